@@ -1,0 +1,389 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each checks a closed form, an
+exact invariant, a limit, a symmetry or a finite-difference derivative, chosen
+so that a dropped term, a wrong sign or a wrong index in the oracle fails one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.cellmodel import FARADAY, GAS_R, Geometry, Model, f_pre, newton_step, ocp
+from paper_1704_04139_amd import inputs as I
+
+
+def column(a, s, m):
+    """1 x 1 x (a+s+m) column: anode solid | pore | cathode solid."""
+    lab = np.zeros((a + s + m, 1, 1), dtype=np.uint8)
+    lab[:a] = I.ANODE
+    lab[a + s:] = I.CATHODE
+    return lab
+
+
+def params(**kw):
+    p = I.CellParams().as_dict()
+    p.update(kw)
+    return p
+
+
+def run(lab, prm, dt, steps, u0=None):
+    model = Model(Geometry(lab), prm)
+    u = model.initial_state() if u0 is None else u0
+    states = [u]
+    for _ in range(steps):
+        u, _ = newton_step(model, u, dt)
+        states.append(u)
+    return model, states
+
+
+def neumann_modes(n):
+    """Eigenpairs of the 1D cell-centred Neumann Laplacian (L c)_p = sum_q (c_p - c_q):
+    cosine (DCT-II) vectors cos(pi m (p + 1/2)/n), eigenvalues 4 sin^2(pi m / (2n))."""
+    p = np.arange(n) + 0.5
+    m = np.arange(n)
+    Q = np.cos(np.pi * np.outer(p, m) / n)
+    Q /= np.linalg.norm(Q, axis=0)
+    lam = 4.0 * np.sin(np.pi * m / (2 * n)) ** 2
+    return Q, lam
+
+
+def implicit_euler_modes(c0, src, coef, dt, steps, V):
+    """Exact implicit-Euler iterates of V dc/dt + coef L c = src, mode by mode."""
+    n = c0.size
+    Q, lam = neumann_modes(n)
+    a = Q.T @ c0
+    b = Q.T @ src
+    out = []
+    for _ in range(steps):
+        a = (V / dt * a + b) / (V / dt + coef * lam)
+        out.append(Q @ a)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# C-P7 unit conventions (Sec. 3.2): 2.5 A/m^2 on a 100 x 100 voxel face of
+# h = 0.44 um is 4.84 nA; 250 A/m^2 is 484 nA.
+# ---------------------------------------------------------------------------
+def test_current_density_convention():
+    lab = np.zeros((3, 100, 100), dtype=np.uint8)
+    lab[0] = I.ANODE
+    lab[2] = I.CATHODE
+    g = Geometry(lab)
+    for mu, nA in ((2.5, 4.84), (250.0, 484.0)):
+        I_app = mu * (44e-6) ** 2
+        m = Model(g, params(I_app=I_app))
+        assert m.mu == pytest.approx(mu, rel=1e-12)
+        assert I_app * 1e9 == pytest.approx(nA, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# C-P2: the zero-current equilibrium (every interface flux vanishes, plated
+# amount at its reversible value) is a fixed point of the implicit step.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("plating", [0, 1])
+def test_equilibrium_is_fixed(plating):
+    w = I.config0()
+    prm = params(I_app=0.0, plating=plating)
+    model = Model(Geometry(w.labels), prm)
+    u0 = model.initial_state()
+    R = model.residual(u0, u0, 10.0)
+    # every term that could be nonzero at equilibrium is a product of
+    # quantities of order 1e-13..1e-6; the residual is at rounding level
+    assert np.max(np.abs(model.scaled_residual(R, 10.0))) < 1e-12
+    u = u0
+    for _ in range(3):
+        u, info = newton_step(model, u, 10.0)
+    N = model.N
+    assert np.max(np.abs(u[:N] - u0[:N]) / u0[:N]) < 1e-14
+    assert np.max(np.abs(u[N:2 * N] - u0[N:2 * N])) < 1e-14       # volts
+    if plating:
+        nn = u[2 * model.N:]
+        assert np.max(np.abs(nn - u0[2 * model.N:]) / prm["n_c"]) < 1e-13
+
+
+def test_plating_equilibrium_amount():
+    """At equilibrium i_pl = 0, i.e. f_pre(n) = exp(-F U_an(x0)/RT)
+    (eq. 2.8 with eta = phi_s - phi_e = U_an)."""
+    w = I.config0()
+    prm = params(I_app=0.0, T=268.0)
+    model = Model(Geometry(w.labels), prm)
+    u0 = model.initial_state()
+    n = u0[2 * model.N:]
+    U = ocp(prm["U_an"], prm["x0"])
+    np.testing.assert_allclose(f_pre(n, prm["n_c"]), np.exp(-FARADAY * U / (GAS_R * 268.0)), rtol=1e-12)
+    _, i_pl = model.interface_currents(u0)
+    assert np.max(np.abs(i_pl)) < 1e-14 * prm["i00_pl"] * np.sqrt(prm["c0"])
+
+
+# ---------------------------------------------------------------------------
+# C-P1: lithium conservation (conservative FV, Sec. 2.4; interface conditions
+# eq. 2.4): electrolyte Li constant, anode + plated gains I dt/F, cathode loses it.
+# ---------------------------------------------------------------------------
+def test_lithium_conservation_3d():
+    w = I.config0()
+    prm = w.params.as_dict()
+    prm["I_app"] *= 3.0
+    model, states = run(w.labels, prm, 10.0, 3)
+    q = prm["I_app"] * 10.0 / FARADAY
+    for k in range(1, 4):
+        a = model.inventories(states[k - 1])
+        b = model.inventories(states[k])
+        assert abs(b["electrolyte"] - a["electrolyte"]) < 1e-9 * q
+        assert (b["anode"] - a["anode"]) + (b["plated"] - a["plated"]) == pytest.approx(q, rel=1e-9)
+        assert b["cathode"] - a["cathode"] == pytest.approx(-q, rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# C-P3 (Sec. 3.1: without Li sources the separator develops a linear
+# gradient): in a 1D column the pore concentration obeys exactly
+#   V dc/dt + A De/h L c = A (1-t+) J/F (e_last - e_first),
+# whose implicit-Euler iterates are known mode by mode (cosine basis).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("plating", [0, 1])
+def test_separator_concentration_closed_form(plating):
+    a, s, m = 3, 10, 3
+    lab = column(a, s, m)
+    I_app = 4.0 * (0.44e-6) ** 2      # 4 A/m^2 through the column
+    prm = params(I_app=I_app, plating=plating)
+    dt, steps = 0.02, 6
+    model, states = run(lab, prm, dt, steps)
+    h = prm["h"]
+    A, V = h * h, h ** 3
+    J = I_app / A
+    src = np.zeros(s)
+    src[0] = -A * (1 - prm["tplus"]) * J / FARADAY
+    src[-1] = +A * (1 - prm["tplus"]) * J / FARADAY
+    exact = implicit_euler_modes(np.full(s, prm["c0"]), src, A * prm["De"] / h, dt, steps, V)
+    for k in range(steps):
+        ce = states[k + 1][a:a + s]
+        np.testing.assert_allclose(ce, exact[k], rtol=1e-11, atol=0)
+    # quasi-steady slope after long times: (1-t+) J h/(F De) per voxel, mean c0
+    model, st = run(lab, prm, 50.0, 4)
+    ce = st[-1][a:a + s]
+    np.testing.assert_allclose(np.diff(ce), (1 - prm["tplus"]) * J * h / (FARADAY * prm["De"]), rtol=1e-6)
+    assert np.mean(ce) == pytest.approx(prm["c0"], rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# C-P4: solid slab under the constant interface flux J/F (1D charge
+# conservation makes the intercalation current exactly -J when plating is
+# off): V dc/dt + A Ds/h L c = A J/F e_top; mean rises by J dt/(F a h).
+# ---------------------------------------------------------------------------
+def test_solid_slab_closed_form():
+    a, s, m = 6, 4, 6
+    lab = column(a, s, m)
+    I_app = 2.0 * (0.44e-6) ** 2
+    prm = params(I_app=I_app, plating=0)
+    dt, steps = 1.0, 5
+    model, states = run(lab, prm, dt, steps)
+    h = prm["h"]
+    A, V = h * h, h ** 3
+    J = I_app / A
+    src = np.zeros(a)
+    src[-1] = A * J / FARADAY
+    c0 = np.full(a, prm["x0"] * prm["cmax_an"])
+    exact = implicit_euler_modes(c0, src, A * prm["Ds_an"] / h, dt, steps, V)
+    for k in range(steps):
+        np.testing.assert_allclose(states[k + 1][:a], exact[k], rtol=1e-12)
+        assert np.mean(states[k + 1][:a]) - c0[0] == pytest.approx(J * (k + 1) * dt / (FARADAY * a * h), rel=1e-10)
+    # the cathode column loses Li at the same rate from its bottom face
+    src_c = np.zeros(m)
+    src_c[0] = -A * J / FARADAY
+    exact_c = implicit_euler_modes(np.full(m, prm["y0"] * prm["cmax_ca"]), src_c, A * prm["Ds_ca"] / h, dt, steps, V)
+    np.testing.assert_allclose(states[-1][a + s:a + s + m], exact_c[-1], rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# C-P5 + C-P6: 1D potentials.  Electrolyte: j = -kappa dphi/dz + kappa (1-t+)
+# theta RT/F dln c/dz carries -J on every pore face, so the drop across the
+# pore is J L/kappa + (1-t+) theta RT/F ln(c_last/c_first).  The cell voltage
+# is then the chain collector -> anode ohmic -> anode BV overpotential (asinh
+# inversion of eq. 2.5) -> electrolyte -> cathode BV -> cathode ohmic ->
+# collector.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("thermo,T", [(1.0, 298.15), (1.7, 268.0)])
+def test_column_voltage_closed_form(thermo, T):
+    a, s, m = 4, 6, 5
+    lab = column(a, s, m)
+    mu = 30.0
+    I_app = mu * (0.44e-6) ** 2
+    prm = params(I_app=I_app, plating=0, thermo=thermo, T=T, sigma_an=3.0, sigma_ca=0.7, kappa=0.2)
+    model, states = run(lab, prm, 2.0, 3)
+    u = states[-1]
+    N = model.N
+    c, phi = u[:N], u[N:2 * N]
+    h, J = prm["h"], mu
+    RT = GAS_R * T
+    # electrolyte drop (C-P5)
+    pe = phi[a:a + s]
+    ce = c[a:a + s]
+    drop = J * (s - 1) * h / prm["kappa"] + (1 - prm["tplus"]) * thermo * RT / FARADAY * np.log(ce[-1] / ce[0])
+    assert pe[-1] - pe[0] == pytest.approx(drop, rel=1e-10, abs=1e-13)
+    # full chain (C-P6)
+    phi_an_top = J * h / (2 * prm["sigma_an"]) + (a - 1) * J * h / prm["sigma_an"]
+    cs_an, ce0 = c[a - 1], ce[0]
+    eta_an = 2 * RT / FARADAY * np.arcsinh(-J / (2 * prm["i00_an"] * np.sqrt(cs_an * ce0)))
+    phi_e0 = phi_an_top - ocp(prm["U_an"], cs_an / prm["cmax_an"]) - eta_an
+    phi_el = phi_e0 + drop
+    cs_ca, ce1 = c[a + s], ce[-1]
+    eta_ca = 2 * RT / FARADAY * np.arcsinh(J / (2 * prm["i00_ca"] * np.sqrt(cs_ca * ce1)))
+    phi_ca_bot = phi_el + ocp(prm["U_ca"], cs_ca / prm["cmax_ca"]) + eta_ca
+    V = phi_ca_bot + (m - 1) * J * h / prm["sigma_ca"] + J * h / (2 * prm["sigma_ca"])
+    assert model.voltage(u) == pytest.approx(V, abs=1e-12)
+    assert phi[0] == pytest.approx(J * h / (2 * prm["sigma_an"]), rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Plating (Sec. 2.3): the plating law clamps the anode/electrolyte potential
+# difference at the metal's reversible value, -(RT/F) ln f_pre(n), when its
+# rate constant is large (plating iff eta_Pl < 0, eq. 2.10; f_pre multiplies
+# the stripping branch of eq. 2.8).  At n = n_c that is +(RT/F) ln 2.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_plating_clamps_reversible_potential(sign):
+    a, s, m = 3, 4, 3
+    lab = column(a, s, m)
+    mu = 5.0 * sign
+    prm = params(I_app=mu * (0.44e-6) ** 2, i00_pl=1e6, plating=1)
+    model = Model(Geometry(lab), prm)
+    u0 = model.initial_state()
+    u0[2 * model.N:] = prm["n_c"]          # one n_c of plated metal on the face
+    u, _ = newton_step(model, u0, 1e-3)
+    N = model.N
+    dphi = u[N + a - 1] - u[N + a]         # phi_s - phi_e across the anode face
+    n = u[2 * N]
+    RT = GAS_R * prm["T"]
+    target = -RT / FARADAY * np.log(f_pre(n, prm["n_c"]))
+    assert dphi == pytest.approx(target, abs=2e-7)
+    assert target == pytest.approx(RT / FARADAY * np.log(2.0), abs=1e-3)
+    # the face current splits between the two reactions and sums to -J; the
+    # plated amount changes by -i_pl dt/F
+    i_int, i_pl = model.interface_currents(u)
+    J = mu
+    assert abs(i_pl[0] + i_int[0] + J) < 1e-9 * abs(J)
+    assert n - prm["n_c"] == pytest.approx(-i_pl[0] * 1e-3 / FARADAY, rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# C-P8: analytic Jacobian against central differences on tiny grids, at
+# perturbed states with little (n << n_c) and much (n >> n_c) plated metal.
+# ---------------------------------------------------------------------------
+def tiny_labels(nx, ny, nz, seed):
+    rng = np.random.default_rng(seed)
+    lab = np.zeros((nz, ny, nx), dtype=np.uint8)
+    a = nz * 2 // 5
+    s = nz // 5
+    lab[:a] = np.where(rng.random((a, ny, nx)) < 0.6, I.ANODE, I.PORE)
+    lab[a + s:] = np.where(rng.random((nz - a - s, ny, nx)) < 0.6, I.CATHODE, I.PORE)
+    lab[0, 0, 0] = I.ANODE
+    lab[-1, 0, 0] = I.CATHODE
+    return lab
+
+
+@pytest.mark.parametrize("shape,seed,nscale", [((2, 2, 6), 3, 0.05), ((2, 2, 6), 4, 20.0),
+                                               ((4, 4, 10), 5, 1.0), ((3, 2, 10), 6, 3.0)])
+def test_jacobian_matches_finite_differences(shape, seed, nscale):
+    lab = tiny_labels(*shape, seed)
+    prm = params(I_app=20.0 * shape[0] * shape[1] * (0.44e-6) ** 2, thermo=1.3)
+    model = Model(Geometry(lab), prm)
+    rng = np.random.default_rng(seed)
+    u_old = model.initial_state()
+    N = model.N
+    u = u_old.copy()
+    u[:N] *= 1.0 + 0.03 * np.clip(rng.standard_normal(N), -1.5, 1.5)
+    u[N:2 * N] += 0.02 * rng.standard_normal(N)
+    u[2 * N:] = prm["n_c"] * nscale * (1.0 + 0.3 * rng.random(model.g.F_pl))
+    dt = 3.0
+    J = model.jacobian(u, dt).toarray()
+    scale = np.concatenate([np.maximum(np.abs(u[:N]), 1.0) * 1e-6, np.full(N, 1e-7),
+                            np.full(model.g.F_pl, prm["n_c"] * 1e-6 * max(nscale, 0.1))])
+    Jfd = np.zeros_like(J)
+    for k in range(u.size):
+        e = np.zeros(u.size)
+        e[k] = scale[k]
+        Jfd[:, k] = (model.residual(u + e, u_old, dt) - model.residual(u - e, u_old, dt)) / (2 * scale[k])
+    # compare column-scaled entries against the row's largest entry
+    rowmax = np.maximum(np.max(np.abs(J), axis=1, keepdims=True), 1e-300)
+    err = np.abs(J - Jfd) / rowmax
+    assert np.max(err) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Symmetry: mirroring or transposing the microstructure in x/y mirrors the
+# solution exactly (catches direction and neighbour-index mistakes).
+# ---------------------------------------------------------------------------
+def _face_key(g):
+    z, rem = np.divmod(g.if_s, g.nx * g.ny)
+    y, x = np.divmod(rem, g.nx)
+    return z, y, x, g.if_dir
+
+
+@pytest.mark.parametrize("op", ["flipx", "flipy", "transpose"])
+def test_mirror_symmetry(op):
+    lab = tiny_labels(5, 4, 12, 11)
+    prm = params(I_app=10.0 * 20 * (0.44e-6) ** 2)
+    if op == "flipx":
+        lab2 = lab[:, :, ::-1].copy()
+    elif op == "flipy":
+        lab2 = lab[:, ::-1, :].copy()
+    else:
+        lab2 = np.ascontiguousarray(lab.transpose(0, 2, 1))
+    m1, s1 = run(lab, prm, 2.0, 2)
+    m2, s2 = run(lab2, prm, 2.0, 2)
+    N = m1.N
+    u1, u2 = s1[-1], s2[-1]
+    for blk in (slice(0, N), slice(N, 2 * N)):
+        f1 = u1[blk].reshape(lab.shape)
+        f2 = u2[blk].reshape(lab2.shape)
+        if op == "flipx":
+            f1 = f1[:, :, ::-1]
+        elif op == "flipy":
+            f1 = f1[:, ::-1, :]
+        else:
+            f1 = f1.transpose(0, 2, 1)
+        np.testing.assert_allclose(f2, f1, rtol=1e-11, atol=1e-13)
+    # plated amounts: match faces by their mirrored (voxel, direction)
+    z, y, x, d = _face_key(m1.g)
+    swap = {"flipx": {0: 1, 1: 0}, "flipy": {2: 3, 3: 2}, "transpose": {0: 2, 1: 3, 2: 0, 3: 1}}[op]
+    d2 = np.array([swap.get(int(v), int(v)) for v in d])
+    if op == "flipx":
+        x = lab.shape[2] - 1 - x
+    elif op == "flipy":
+        y = lab.shape[1] - 1 - y
+    else:
+        x, y = y, x
+    key1 = {(int(a), int(b), int(c), int(e)): k for k, (a, b, c, e) in enumerate(zip(z, y, x, d2))}
+    z2, y2, x2, dd2 = _face_key(m2.g)
+    n1 = u1[2 * N:]
+    pl1 = {k: v for k, v in key1.items() if m1.g.if_phase[v] == I.ANODE}
+    idx_in_pl1 = {f: i for i, f in enumerate(m1.g.pl_face)}
+    for j, f in enumerate(m2.g.pl_face):
+        k = (int(z2[f]), int(y2[f]), int(x2[f]), int(dd2[f]))
+        assert abs(u2[2 * N + j] - n1[idx_in_pl1[pl1[k]]]) <= 1e-11 * prm["n_c"]
+
+
+# ---------------------------------------------------------------------------
+# Brute force: the SuperLU Newton iteration and a dense numpy.linalg.solve
+# Newton iteration reach the same root on a 2 x 2 x 6 grid.
+# ---------------------------------------------------------------------------
+def test_dense_newton_agrees():
+    lab = tiny_labels(2, 2, 6, 3)
+    prm = params(I_app=40.0 * 4 * (0.44e-6) ** 2)
+    model = Model(Geometry(lab), prm)
+    u0 = model.initial_state()
+    ua, _ = newton_step(model, u0, 5.0)
+    ub, _ = newton_step(model, u0, 5.0, solve=lambda J, r: np.linalg.solve(J.toarray(), r))
+    N = model.N
+    np.testing.assert_allclose(ua[:N], ub[:N], rtol=1e-13)
+    np.testing.assert_allclose(ua[N:2 * N], ub[N:2 * N], rtol=1e-11, atol=1e-13)
+
+
+def test_geometry_validation():
+    lab = column(2, 1, 2)
+    lab[2] = I.CATHODE                      # cathode now touches the anode
+    with pytest.raises(ValueError):
+        Geometry(lab)
+    lab = column(2, 2, 2)
+    lab[0] = I.PORE                         # no anode solid on the collector plane
+    with pytest.raises(ValueError):
+        Geometry(lab)
