@@ -1,0 +1,203 @@
+/* mbx.h — C ABI of the MI355X full-order implicit cell-step library.
+ *
+ * The library advances the voxel-resolved full-cell lithium-ion model of
+ * arXiv 1704.04139 (MULTIBAT), Sec. 2.2-2.4, one implicit Euler step at a
+ * time on one AMD Instinct MI355X (gfx950):
+ *   - unknowns (Sec. 2.4, eq. 2.13): one concentration c and one potential
+ *     phi per voxel (electrolyte c_e, phi_e in pore voxels; solid c_s, Phi_s in
+ *     anode/cathode voxels) and one plated-lithium amount n_f (mol/m^2) per
+ *     anode/pore face;
+ *   - fluxes: solid diffusion and conduction (eqs. 2.1-2.2), electrolyte
+ *     diffusion, migration and the dmu/dc term (eqs. 2.3-2.4), Butler-Volmer
+ *     intercalation on every solid/pore face (eq. 2.5 with the interface
+ *     conditions of eq. 2.4), plating/stripping with the f_pre regularisation
+ *     on every anode/pore face (eqs. 2.8-2.12, Sec. 2.3);
+ *   - collectors: the z = 0 plane holds the anode at phi = 0 (across half a
+ *     voxel); the z = L plane feeds the applied current uniformly into the
+ *     cathode solid faces it touches.  Lateral sides carry no flux.
+ *   - solve: Newton's method on the FP64 residual with a preconditioned
+ *     Krylov method (GMRES) for the corrections; FP64 throughout, or FP32
+ *     Krylov/preconditioner with FP64 residual and refinement (MBX_MIXED).
+ *
+ * Conventions
+ *   - SI units everywhere (m, s, mol, A, V, K).
+ *   - Labels: uint8, 0 = pore/electrolyte, 1 = anode active material,
+ *     2 = cathode active material.  Voxel (i, j, k) has flat index
+ *     i + nx*(j + ny*k); k = 0 touches the anode collector, k = nz-1 the
+ *     cathode collector.
+ *   - Interface faces are numbered per phase in canonical order: by solid
+ *     voxel flat index, then by direction 0:-x 1:+x 2:-y 3:+y 4:-z 5:+z as
+ *     seen from the solid voxel.  Plated amounts n_pl[] follow the anode
+ *     face order.
+ *   - Every function returns 0 on success or a negative MBX_E* code; no
+ *     exception crosses the ABI.  mbx_last_error() returns a thread-local
+ *     message for the last failure on the calling thread.
+ *   - A cell is not thread-safe: calls on one cell must not overlap.
+ *   - Pointers marked "device" are HIP device (or managed) addresses; all
+ *     others are host addresses.  The library never takes ownership of
+ *     caller memory; it copies what it needs.
+ */
+#ifndef MBX_H
+#define MBX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MBX_OK = 0,
+  MBX_EINVAL = -1,   /* bad argument (null pointer, size, parameter out of range) */
+  MBX_ELABEL = -2,   /* labels invalid: anode touches cathode, or a collector plane holds no solid of its electrode */
+  MBX_ENEWTON = -3,  /* Newton did not converge within newton_max iterations */
+  MBX_ENAN = -4,     /* non-finite value in the state or residual */
+  MBX_ENOMEM = -5,   /* device allocation failed */
+  MBX_EBUDGET = -6,  /* request does not fit the server's memory budget */
+  MBX_EHIP = -7,     /* HIP runtime error */
+  MBX_ESTATE = -8    /* call not valid in the object's current state */
+};
+
+enum { MBX_FP64 = 0, MBX_MIXED = 1 };
+
+/* Physical and numerical parameters (SI units).  Physical meaning follows
+ * Sec. 2.2-2.3: intercalation i = 2 i00 sqrt(c_s c_e) sinh(F eta/(2RT)),
+ * eta = Phi_s - U(c_s/c_max) - phi_e, U(x) = U0 + U1 ln((1-x)/x);
+ * plating i_pl = i00_pl sqrt(c_e) (f_pre(n) e^{F eta_pl/2RT} - e^{-F eta_pl/2RT}),
+ * eta_pl = Phi_s - phi_e, f_pre(n) = n^4/(n_c^4 + n^4). */
+typedef struct {
+  double T;              /* temperature, K (isothermal, Sec. 2.2) */
+  double I_app;          /* applied current, A; > 0 charges (anode lithiates) */
+  double h;              /* voxel edge, m */
+  double c0;             /* initial electrolyte concentration, mol/m^3 */
+  double x0, y0;         /* initial anode / cathode stoichiometry c_s/c_max */
+  double De, kappa, tplus, thermo;   /* electrolyte diffusivity m^2/s, conductivity S/m,
+                                        transference number, thermodynamic factor */
+  double Ds[2];          /* solid diffusivity, [0] anode, [1] cathode, m^2/s */
+  double sigma[2];       /* solid conductivity, S/m */
+  double cmax[2];        /* maximum solid concentration, mol/m^3 */
+  double i00[2];         /* intercalation rate constant, A m/mol */
+  double U0[2], U1[2];   /* open-circuit potential coefficients, V */
+  double i00_pl;         /* plating rate constant, A m^-1/2 mol^-1/2 */
+  double n_c;            /* f_pre constant, mol/m^2 */
+  int plating;           /* 0: no plating reaction, 1: plating/stripping on */
+  int precision;         /* MBX_FP64 or MBX_MIXED */
+  double newton_tol;     /* scaled update tolerance (default 1e-9 if <= 0) */
+  double res_tol;        /* scaled residual tolerance (default 1e-6 if <= 0) */
+  double krylov_rtol;    /* GMRES relative tolerance floor (default 1e-8 if <= 0) */
+  int newton_max;        /* Newton iteration cap (default 30 if <= 0) */
+  int krylov_max;        /* GMRES iteration cap per Newton iteration (default 2000 if <= 0) */
+} mbx_params;
+
+typedef struct {
+  int newton_iters;      /* Newton iterations taken */
+  int krylov_iters;      /* total GMRES iterations in the step */
+  double res0;           /* scaled residual max-norm at the start of the step */
+  double res_final;      /* scaled residual max-norm at acceptance */
+  double du_final;       /* scaled max-norm of the last Newton update */
+  double V;              /* cell voltage after the step, V */
+  double wall_s;         /* wall time of the step, s */
+} mbx_step_info;
+
+typedef struct mbx_cell mbx_cell;
+
+/* Fill *p with the library's defaults for the numerical knobs and zeros for
+ * the physical fields.  Returns MBX_EINVAL on a null pointer. */
+int mbx_params_default(mbx_params *p);
+
+/* Create a cell from voxel labels (Sec. 2.4: the voxel image defines the
+ * finite-volume mesh; Sec. 2.6: image plus parameters define a simulation).
+ *   labels : host, nx*ny*nz bytes, layout above; copied, caller keeps ownership
+ *   p      : host; copied
+ *   stream : hipStream_t to run on (NULL = the default stream)
+ *   out    : receives the handle; the cell owns its device memory
+ * The state is set to the zero-current equilibrium: c = c0 in pores,
+ * x0*c_max / y0*c_max in the solids, phi_anode = 0, phi_e = -U_an(x0),
+ * phi_cathode = U_ca(y0) - U_an(x0), n_f = n_c (f/(1-f))^(1/4) with
+ * f = exp(-F U_an(x0)/RT), which makes every interface current vanish.
+ * Errors: MBX_EINVAL (bad sizes/parameters), MBX_ELABEL, MBX_ENOMEM, MBX_EHIP. */
+int mbx_cell_create(const uint8_t *labels, int nx, int ny, int nz,
+                    const mbx_params *p, void *stream, mbx_cell **out);
+
+/* Release all device memory of the cell (null is ignored). */
+void mbx_cell_destroy(mbx_cell *c);
+
+/* Advance one implicit Euler step of size dt (s), eq. 2.13: solve
+ * F(u^{n+1}; u^n) = 0 by Newton + preconditioned GMRES.  Transactional: on
+ * any error (MBX_ENEWTON, MBX_ENAN, MBX_EHIP) the state stays at u^n.
+ * info may be null.  Blocks until the step is complete. */
+int mbx_cell_step(mbx_cell *c, double dt, mbx_step_info *info);
+
+/* Change the applied current (A) for the following steps (parameter mu of
+ * Sec. 2.5 enters affinely through the boundary term). */
+int mbx_cell_set_current(mbx_cell *c, double I_app);
+
+/* Sizes: voxels, anode interface faces (= plated-amount entries), cathode
+ * interface faces, cathode collector faces.  Any pointer may be null. */
+int mbx_cell_counts(const mbx_cell *c, int64_t *n_vox, int64_t *n_an_faces,
+                    int64_t *n_ca_faces, int64_t *n_top);
+
+/* Copy the state out.  cfield, phi: N doubles each; n_pl: n_an_faces doubles
+ * (anode face order above).  device_ptrs = 1: the three pointers are device
+ * addresses (copied device-to-device on the cell's stream), 0: host.  Any of
+ * the three pointers may be null to skip that field. */
+int mbx_cell_get_state(const mbx_cell *c, double *cfield, double *phi, double *n_pl,
+                       int device_ptrs);
+
+/* Overwrite the state (both u^n and the Newton iterate); same layouts as
+ * mbx_cell_get_state.  All three pointers are required. */
+int mbx_cell_set_state(mbx_cell *c, const double *cfield, const double *phi,
+                       const double *n_pl, int device_ptrs);
+
+/* Cell voltage (Sec. 2.5 output functional s_cp): mean over the cathode
+ * collector faces of the solid potential extrapolated across half a voxel
+ * with the applied flux; the anode collector is the 0 V reference. */
+int mbx_cell_voltage(const mbx_cell *c, double *V);
+
+/* Lithium inventories (mol) in electrolyte, anode solid, cathode solid and
+ * the plated layer (Sec. 2.4 conservative scheme: at convergence the total
+ * changes only through the applied current).  out[4]. */
+int mbx_cell_inventory(const mbx_cell *c, double out[4]);
+
+/* FP64 residual F(u; u_old) of eq. 2.13 for caller-given u = (c_u, phi_u,
+ * n_u) and u_old = (c_old, n_old) (host arrays, layouts as get_state) and
+ * step dt, on the cell's geometry and parameters.  Writes the raw rows
+ * (mol/s for c and n rows, A for phi rows) to Rc[N], Rphi[N],
+ * Rn[n_an_faces] (host).  Does not change the cell's state.  Used to check
+ * the operator against a reference implementation. */
+int mbx_cell_residual(mbx_cell *c, const double *c_u, const double *phi_u, const double *n_u,
+                      const double *c_old, const double *n_old, double dt,
+                      double *Rc, double *Rphi, double *Rn);
+
+/* Jacobian-vector product of the Newton system the solver hands to GMRES,
+ * at state u = (c_u, phi_u, n_u) with u_old = (c_old, n_old) and step dt
+ * (host arrays as for mbx_cell_residual), applied to v (host, 2N doubles:
+ * [0,N) concentration, [N,2N) potential entries).  The operator is
+ *   J_hat = D_r (J_uu - J_un J_nn^-1 J_nu) D_u,
+ * the Jacobian of eq. 2.13 with the plated unknowns eliminated face by face
+ * (J_nn is diagonal) and scaled by D_u = diag(c_ref, RT/F) (c_ref = c0 in
+ * pores, c_max in solids) and D_r = diag(dt/(h^3 c_ref), 1/(h^2 mu_ref)),
+ * mu_ref = max(|I_app|/(nx ny h^2), 1 A/m^2).  Computed by the solver's own
+ * linearisation and matrix-free kernel in the cell's precision mode.
+ * Writes y (host, 2N doubles).  Does not change the cell's state. */
+int mbx_cell_jvp(mbx_cell *c, const double *c_u, const double *phi_u, const double *n_u,
+                 const double *c_old, const double *n_old, double dt, const double *v, double *y);
+
+/* Batched stepping: advance n cells (all of one precision mode) by one step
+ * of dt each, sharing every kernel launch across the cells.  status_out[i]
+ * receives each cell's own result code (as mbx_cell_step); the function
+ * returns MBX_OK if the batch ran (cells may still have failed individually)
+ * or an error for invalid arguments.  infos may be null. */
+int mbx_batch_step(mbx_cell *const *cells, int n, double dt, int *status_out,
+                   mbx_step_info *infos);
+
+/* Device bytes a cell of this size would allocate (for admission control). */
+int64_t mbx_cell_footprint(int nx, int ny, int nz, int precision, int n_an_faces, int n_ca_faces);
+
+/* Message for the last failure on this thread ("" if none). */
+const char *mbx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBX_H */

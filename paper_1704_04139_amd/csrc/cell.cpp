@@ -1,0 +1,816 @@
+// cell.cpp — cell lifecycle, batched Newton-GMRES orchestration and the C ABI.
+//
+// One implicit Euler step (eq. 2.13) is a damped Newton iteration on the FP64
+// residual; each Newton correction solves the condensed, scaled Jacobian
+// system with restarted GMRES (right preconditioned, classical Gram-Schmidt
+// with one re-orthogonalisation).  Every kernel launch covers all cells of a
+// batch; the host only reads a few per-cell scalars at sync points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mbx.h"
+#include "mbx_dev.h"
+#include "mbx_kernels.h"
+
+using namespace mbx;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(MBX_EHIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+constexpr int kRestart = 30;
+constexpr int kGather = RED_NSLOT + CTL_NSLOT;
+uint64_t g_next_id = 1;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t off[64];
+  int n = 0;
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    size_t o = total;
+    off[n++] = o;
+    total += align256(bytes);
+    return o;
+  }
+};
+
+}  // namespace
+
+struct mbx_cell {
+  uint64_t id;
+  mbx_params p;
+  int nx, ny, nz, N, F_an, F_ca, n_top, nblk, m;
+  bool mixed;
+  hipStream_t s;
+  char* dmem = nullptr;
+  CellDev h{};                 // host mirror of the descriptor
+  CellDev* d_desc = nullptr;   // device descriptor (single-cell launches)
+  int2* d_blk = nullptr;       // device block table
+  double* d_gather = nullptr;
+  double* h_gather = nullptr;  // pinned
+  CellDev* h_desc_pinned = nullptr;
+  int* faces_an = nullptr;
+  int* faces_ca = nullptr;
+};
+
+namespace {
+
+size_t kt_size(int precision) { return precision == MBX_MIXED ? sizeof(float) : sizeof(double); }
+
+Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt) {
+  Layout L;
+  L.add(4 * (size_t)N);                       // 0 meta
+  for (int k = 0; k < 8; ++k) L.add(8 * (size_t)N);   // 1..8 c phi c_try phi_try c_old phi_old Rc Rp
+  L.add(16 * (size_t)N);                      // 9 dc | dp (contiguous)
+  for (int k = 0; k < 7; ++k) L.add(8 * (size_t)std::max(F_an, 1));  // 10..16 n n_try n_old Rn dn rn_jnn sq
+  L.add(5 * kt * std::max(F_an, 1));          // 17 coef_an
+  L.add(3 * kt * std::max(F_ca, 1));          // 18 coef_ca
+  L.add(kt * (size_t)N);                      // 19 wpore
+  L.add(4 * kt * (size_t)N);                  // 20 dinv
+  L.add((size_t)(m + 1) * 2 * N * kt);        // 21 Vb
+  for (int k = 0; k < 4; ++k) L.add(2 * (size_t)N * kt);  // 22..25 w z b x
+  L.add((size_t)nblk * kPartStride * 8);      // 26 part
+  L.add(64);                                  // 27 ticket
+  L.add(8 * RED_NSLOT);                       // 28 red
+  L.add(4 * CTL_NSLOT);                       // 29 ictl
+  L.add(8 * (size_t)gm_size(m));              // 30 gm
+  L.add(4 * (size_t)std::max(F_an, 1));       // 31 faces_an
+  L.add(4 * (size_t)std::max(F_ca, 1));       // 32 faces_ca
+  L.add(sizeof(CellDev));                     // 33 desc
+  L.add(sizeof(int2) * (size_t)nblk);         // 34 blk
+  L.add(8 * kGather);                         // 35 gather
+  return L;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_params(const mbx_params* p) {
+  if (!p) return fail(MBX_EINVAL, "null parameter struct");
+  if (!finite_pos(p->T) || !finite_pos(p->h) || !finite_pos(p->c0) || !finite_pos(p->De) ||
+      !finite_pos(p->kappa) || !finite_pos(p->thermo) || !finite_pos(p->n_c) || !std::isfinite(p->I_app))
+    return fail(MBX_EINVAL, "T, h, c0, De, kappa, thermo, n_c must be finite and > 0; I_app finite");
+  if (!(p->x0 > 0.0 && p->x0 < 1.0) || !(p->y0 > 0.0 && p->y0 < 1.0))
+    return fail(MBX_EINVAL, "initial stoichiometries must lie in (0, 1)");
+  if (!(p->tplus >= 0.0 && p->tplus < 1.0)) return fail(MBX_EINVAL, "tplus must lie in [0, 1)");
+  for (int s = 0; s < 2; ++s) {
+    if (!finite_pos(p->Ds[s]) || !finite_pos(p->sigma[s]) || !finite_pos(p->cmax[s]) || !finite_pos(p->i00[s]) ||
+        !std::isfinite(p->U0[s]) || !std::isfinite(p->U1[s]))
+      return fail(MBX_EINVAL, "solid parameters must be finite and > 0 (U0, U1 finite)");
+  }
+  if (!(std::isfinite(p->i00_pl) && p->i00_pl >= 0.0)) return fail(MBX_EINVAL, "i00_pl must be finite and >= 0");
+  if (p->precision != MBX_FP64 && p->precision != MBX_MIXED) return fail(MBX_EINVAL, "unknown precision mode");
+  if (p->plating != 0 && p->plating != 1) return fail(MBX_EINVAL, "plating must be 0 or 1");
+  return MBX_OK;
+}
+
+void fill_constants(CellDev& h, const mbx_params& p, int nx, int ny) {
+  h.h = p.h;
+  h.A = p.h * p.h;
+  h.Vol = p.h * p.h * p.h;
+  h.RT = kGasR * p.T;
+  h.VT = h.RT / kFaraday;
+  h.beta = kFaraday / (2.0 * h.RT);
+  h.c0 = p.c0;
+  h.x0 = p.x0;
+  h.y0 = p.y0;
+  h.De = p.De;
+  h.kappa = p.kappa;
+  h.tplus = p.tplus;
+  h.thermo = p.thermo;
+  for (int s = 0; s < 2; ++s) {
+    h.Ds[s] = p.Ds[s];
+    h.sigma[s] = p.sigma[s];
+    h.cmax[s] = p.cmax[s];
+    h.i00[s] = p.i00[s];
+    h.U0[s] = p.U0[s];
+    h.U1[s] = p.U1[s];
+  }
+  h.i00_pl = p.i00_pl;
+  h.n_c = p.n_c;
+  h.I_app = p.I_app;
+  h.plating = p.plating;
+  h.mu_ref = std::max(std::fabs(p.I_app) / (nx * (double)ny * h.A), 1.0);
+  h.Kd = p.kappa * (1.0 - p.tplus) * p.thermo * h.RT / (kFaraday * p.h);
+}
+
+// Constants of the scaled operator that depend on the step size.
+void fill_step_constants(CellDev& h, double dt) {
+  const double hh = h.h, mu = h.mu_ref;
+  h.dt = dt;
+  h.Gk = h.kappa * h.VT / (hh * mu);
+  h.tth = (1.0 - h.tplus) * h.thermo;
+  h.Dh = h.De * dt / (hh * hh);
+  h.tau = h.tplus * dt * mu / (kFaraday * hh * h.c0);
+  h.Ke = dt * mu / (hh * kFaraday * h.c0);
+  h.Gcol = 2.0 * h.sigma[0] * h.VT / (hh * mu);
+  for (int s = 0; s < 2; ++s) {
+    h.Dsh[s] = h.Ds[s] * dt / (hh * hh);
+    h.Gs[s] = h.sigma[s] * h.VT / (hh * mu);
+    h.Ks[s] = dt * mu / (hh * kFaraday * h.cmax[s]);
+  }
+}
+
+// A batch of cells sharing every launch.
+struct Batch {
+  std::vector<mbx_cell*> cells;
+  hipStream_t s = nullptr;
+  CellDev* d_desc = nullptr;
+  CellDev* h_desc = nullptr;   // pinned
+  int2* d_blk = nullptr;
+  double* d_gather = nullptr;
+  double* h_gather = nullptr;  // pinned
+  int nblk = 0;
+  bool owned = false;
+  bool mixed = false;
+  int m = kRestart;
+  BatchLaunch bl() const { return BatchLaunch{d_desc, d_blk, nblk, (int)cells.size()}; }
+  int upload() {
+    for (size_t c = 0; c < cells.size(); ++c) h_desc[c] = cells[c]->h;
+    HIPCHK(hipMemcpyAsync(d_desc, h_desc, sizeof(CellDev) * cells.size(), hipMemcpyHostToDevice, s));
+    // the pinned staging buffer is rewritten by the next upload
+    HIPCHK(hipStreamSynchronize(s));
+    return MBX_OK;
+  }
+  int gather() {
+    launch_gather_ctl(bl(), d_gather, s);
+    HIPCHK(hipMemcpyAsync(h_gather, d_gather, sizeof(double) * kGather * cells.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MBX_OK;
+  }
+  double red(int c, int slot) const { return h_gather[(size_t)c * kGather + slot]; }
+  int ctl(int c, int slot) const { return (int)h_gather[(size_t)c * kGather + RED_NSLOT + slot]; }
+  void release() {
+    if (!owned) return;
+    hipFree(d_desc);
+    hipFree(d_blk);
+    hipFree(d_gather);
+    hipHostFree(h_desc);
+    hipHostFree(h_gather);
+    owned = false;
+  }
+};
+
+Batch single(mbx_cell* c) {
+  Batch b;
+  b.cells = {c};
+  b.s = c->s;
+  b.d_desc = c->d_desc;
+  b.h_desc = c->h_desc_pinned;
+  b.d_blk = c->d_blk;
+  b.d_gather = c->d_gather;
+  b.h_gather = c->h_gather;
+  b.nblk = c->nblk;
+  b.mixed = c->mixed;
+  b.m = c->m;
+  return b;
+}
+
+// Cached multi-cell batch (re-used while the same cells are stepped together).
+struct BatchCache {
+  std::vector<uint64_t> ids;
+  Batch b;
+} g_batch_cache;
+
+int make_batch(mbx_cell* const* cells, int n, Batch& out) {
+  std::vector<uint64_t> ids(n);
+  for (int i = 0; i < n; ++i) ids[i] = cells[i]->id;
+  if (g_batch_cache.b.owned && g_batch_cache.ids == ids) {
+    out = g_batch_cache.b;
+    return MBX_OK;
+  }
+  g_batch_cache.b.release();
+  Batch b;
+  b.cells.assign(cells, cells + n);
+  b.s = cells[0]->s;
+  b.mixed = cells[0]->mixed;
+  b.m = cells[0]->m;
+  std::vector<int2> tab;
+  for (int c = 0; c < n; ++c)
+    for (int k = 0; k < cells[c]->nblk; ++k) tab.push_back(make_int2(c, k));
+  b.nblk = (int)tab.size();
+  HIPCHK(hipMalloc(&b.d_desc, sizeof(CellDev) * n));
+  HIPCHK(hipMalloc(&b.d_blk, sizeof(int2) * tab.size()));
+  HIPCHK(hipMalloc(&b.d_gather, sizeof(double) * kGather * n));
+  HIPCHK(hipHostMalloc(&b.h_desc, sizeof(CellDev) * n, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&b.h_gather, sizeof(double) * kGather * n, hipHostMallocDefault));
+  HIPCHK(hipMemcpyAsync(b.d_blk, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice, b.s));
+  HIPCHK(hipStreamSynchronize(b.s));
+  b.owned = true;
+  g_batch_cache.ids = ids;
+  g_batch_cache.b = b;
+  out = b;
+  return MBX_OK;
+}
+
+// ------------------------------------------------------------------ GMRES
+template <typename KT>
+int gmres(Batch& B, int max_iters, int* iters_out) {
+  const BatchLaunch bl = B.bl();
+  const int m = B.m;
+  const int check = 4;
+  int total = 0;
+  launch_gm_start<KT>(bl, 1, B.s);
+  launch_gm_flags(bl, 1, B.s);
+  for (int cyc = 0; total < max_iters; ++cyc) {
+    int k = 0;
+    for (; k < m; ++k) {
+      launch_jacobi<KT>(bl, k, VEC_Z, 0, B.s);
+      launch_matvec<KT>(bl, VEC_Z, VEC_W, 0, B.s);
+      launch_multidot<KT>(bl, k, 0, B.s);
+      launch_orth<KT>(bl, k, 0, B.s);
+      launch_multidot<KT>(bl, k, 1, B.s);
+      launch_orth<KT>(bl, k, 1, B.s);
+      launch_scale_next<KT>(bl, k, B.s);
+      launch_givens(bl, k, B.s);
+      if ((k + 1) % check == 0 || k + 1 == m) {
+        if (int e = B.gather()) return e;
+        bool running = false;
+        for (size_t c = 0; c < B.cells.size(); ++c)
+          if (B.cells[c]->h.active && B.ctl(c, CTL_DONE) == 0) running = true;
+        if (!running) {
+          ++k;
+          break;
+        }
+      }
+    }
+    total += k;
+    launch_backsolve(bl, B.s);
+    launch_combine<KT>(bl, B.s);
+    launch_update_x_jacobi<KT>(bl, B.s);
+    launch_matvec<KT>(bl, VEC_X, VEC_W, 2, B.s);
+    launch_true_residual<KT>(bl, B.s);
+    launch_gm_start<KT>(bl, 0, B.s);
+    launch_gm_flags(bl, 0, B.s);
+    if (int e = B.gather()) return e;
+    bool all = true;
+    for (size_t c = 0; c < B.cells.size(); ++c)
+      if (B.cells[c]->h.active && B.ctl(c, CTL_DONE) != 3) all = false;
+    if (all) break;
+  }
+  if (iters_out) *iters_out = total;
+  return MBX_OK;
+}
+
+// ------------------------------------------------------------------ Newton
+template <typename KT>
+int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
+  const int nc = (int)B.cells.size();
+  const BatchLaunch bl = B.bl();
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<int> st(nc, 1);   // 1 running, 0 converged, < 0 failed
+  std::vector<double> rn(nc), rmax(nc), res0(nc), eta(nc, 1e-4), du(nc, 0.0), lam(nc, 1.0);
+  std::vector<int> nit(nc, 0), kit(nc, 0);
+  for (int c = 0; c < nc; ++c) {
+    mbx_cell* cl = B.cells[c];
+    fill_step_constants(cl->h, dt);
+    cl->h.active = 1;
+    cl->h.lam = 1.0;
+    cl->h.m = B.m;
+  }
+  if (int e = B.upload()) return e;
+  launch_copy_state(bl, 2, B.s);   // u^n <- state
+  launch_copy_state(bl, 1, B.s);   // trial <- state
+  launch_residual<KT>(bl, true, B.s);
+  if (int e = B.gather()) return e;
+  for (int c = 0; c < nc; ++c) {
+    rn[c] = std::sqrt(B.red(c, RED_RSQ));
+    rmax[c] = B.red(c, RED_RMAX);
+    res0[c] = rmax[c];
+    if (!std::isfinite(rn[c])) st[c] = MBX_ENAN;
+  }
+  int newton_max = B.cells[0]->p.newton_max;
+  for (int it = 1; it <= newton_max; ++it) {
+    bool any = false;
+    for (int c = 0; c < nc; ++c) {
+      mbx_cell* cl = B.cells[c];
+      cl->h.active = st[c] == 1;
+      cl->h.rtol = eta[c];
+      any = any || st[c] == 1;
+    }
+    if (!any) break;
+    if (int e = B.upload()) return e;
+    launch_rhs<KT>(bl, B.s);
+    int kits = 0;
+    if (int e = gmres<KT>(B, B.cells[0]->p.krylov_max, &kits)) return e;
+    if (int e = B.gather()) return e;
+    for (int c = 0; c < nc; ++c)
+      if (st[c] == 1) kit[c] += B.ctl(c, CTL_ITERS);
+    launch_direction<KT>(bl, B.s);
+    // line search: halve until admissible and the scaled residual does not grow
+    std::vector<int> searching(nc, 0);
+    for (int c = 0; c < nc; ++c) {
+      searching[c] = st[c] == 1;
+      lam[c] = 1.0;
+    }
+    for (int hlv = 0; hlv <= 20; ++hlv) {
+      bool anys = false;
+      for (int c = 0; c < nc; ++c) {
+        B.cells[c]->h.active = searching[c];
+        B.cells[c]->h.lam = lam[c];
+        anys = anys || searching[c];
+      }
+      if (!anys) break;
+      if (int e = B.upload()) return e;
+      launch_trial(bl, B.s);
+      if (int e = B.gather()) return e;
+      std::vector<double> dmax(nc, 0.0);
+      for (int c = 0; c < nc; ++c) {
+        if (!searching[c]) continue;
+        dmax[c] = B.red(c, RED_DUMAX);
+        if (B.red(c, RED_BAD) > 0.0) {
+          B.cells[c]->h.active = 0;
+          lam[c] *= 0.5;
+        }
+      }
+      if (int e = B.upload()) return e;
+      launch_residual<KT>(bl, true, B.s);
+      if (int e = B.gather()) return e;
+      for (int c = 0; c < nc; ++c) {
+        if (!searching[c] || !B.cells[c]->h.active) continue;
+        const double r1 = std::sqrt(B.red(c, RED_RSQ));
+        const bool ok = std::isfinite(r1) && (r1 <= rn[c] || hlv == 20);
+        if (ok) {
+          searching[c] = 0;
+          du[c] = dmax[c] / lam[c];
+          const double rprev = rn[c];
+          rn[c] = r1;
+          rmax[c] = B.red(c, RED_RMAX);
+          const double ratio = rprev > 0.0 ? r1 / rprev : 0.0;
+          eta[c] = std::max(B.cells[c]->p.krylov_rtol, std::min(1e-4, 0.5 * ratio * ratio));
+        } else {
+          lam[c] *= 0.5;
+        }
+      }
+    }
+    for (int c = 0; c < nc; ++c) {
+      B.cells[c]->h.active = 0;
+      if (st[c] != 1) continue;
+      if (searching[c]) {
+        st[c] = MBX_ENEWTON;
+        continue;
+      }
+      B.cells[c]->h.active = 1;
+      nit[c] = it;
+    }
+    if (int e = B.upload()) return e;
+    launch_copy_state(bl, 0, B.s);   // accept: state <- trial
+    for (int c = 0; c < nc; ++c) {
+      if (st[c] != 1) continue;
+      const mbx_params& p = B.cells[c]->p;
+      if (du[c] <= p.newton_tol && rmax[c] <= p.res_tol) st[c] = 0;
+    }
+  }
+  // roll back failures, outputs for the converged cells
+  for (int c = 0; c < nc; ++c) {
+    if (st[c] == 1) st[c] = MBX_ENEWTON;
+    B.cells[c]->h.active = st[c] < 0;
+  }
+  if (int e = B.upload()) return e;
+  launch_copy_state(bl, 3, B.s);
+  for (int c = 0; c < nc; ++c) B.cells[c]->h.active = 1;
+  if (int e = B.upload()) return e;
+  launch_outputs(bl, B.s);
+  if (int e = B.gather()) return e;
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int c = 0; c < nc; ++c) {
+    status[c] = st[c];
+    if (infos) {
+      mbx_step_info& in = infos[c];
+      in.newton_iters = nit[c];
+      in.krylov_iters = kit[c];
+      in.res0 = res0[c];
+      in.res_final = rmax[c];
+      in.du_final = du[c];
+      in.V = B.red(c, RED_VSUM) / B.cells[c]->n_top;
+      in.wall_s = wall;
+    }
+  }
+  return MBX_OK;
+}
+
+int run_step(Batch& B, double dt, int* status, mbx_step_info* infos) {
+  return B.mixed ? newton<float>(B, dt, status, infos) : newton<double>(B, dt, status, infos);
+}
+
+int sync_outputs(mbx_cell* c) {
+  Batch b = single(c);
+  c->h.active = 1;
+  if (int e = b.upload()) return e;
+  launch_outputs(b.bl(), c->s);
+  return b.gather();
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* mbx_last_error(void) { return g_err.c_str(); }
+
+int mbx_params_default(mbx_params* p) {
+  if (!p) return fail(MBX_EINVAL, "null parameter struct");
+  std::memset(p, 0, sizeof *p);
+  p->newton_tol = 1e-9;
+  p->res_tol = 1e-6;
+  p->krylov_rtol = 1e-8;
+  p->newton_max = 30;
+  p->krylov_max = 2000;
+  p->thermo = 1.0;
+  return MBX_OK;
+}
+
+int64_t mbx_cell_footprint(int nx, int ny, int nz, int precision, int n_an_faces, int n_ca_faces) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (N <= 0 || N > (1 << 28)) return -1;
+  const int nblk = (int)((N + kBlock - 1) / kBlock);
+  Layout L = make_layout((int)N, n_an_faces, n_ca_faces, nblk, kRestart, kt_size(precision));
+  return (int64_t)L.total;
+}
+
+int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_params* pin, void* stream,
+                    mbx_cell** out) {
+  if (!labels || !out) return fail(MBX_EINVAL, "null labels or output pointer");
+  *out = nullptr;
+  if (nx < 1 || ny < 1 || nz < 2) return fail(MBX_EINVAL, "grid must be at least 1 x 1 x 2");
+  const int64_t N64 = (int64_t)nx * ny * nz;
+  if (N64 > (1 << 28)) return fail(MBX_EINVAL, "grid too large (more than 2^28 voxels)");
+  if (int e = check_params(pin)) return e;
+  mbx_params p = *pin;
+  if (p.newton_tol <= 0) p.newton_tol = 1e-9;
+  if (p.res_tol <= 0) p.res_tol = 1e-6;
+  if (p.krylov_rtol <= 0) p.krylov_rtol = 1e-8;
+  if (p.newton_max <= 0) p.newton_max = 30;
+  if (p.krylov_max <= 0) p.krylov_max = 2000;
+  const int N = (int)N64;
+  hipStream_t s = (hipStream_t)stream;
+
+  // ---- phase 1: labels -> masks, face counts, prefix sums (device)
+  size_t scan_bytes = 0;
+  if (exclusive_scan(nullptr, scan_bytes, nullptr, nullptr, N, s) != hipSuccess)
+    return fail(MBX_EHIP, "scan size query failed");
+  Layout T;
+  const size_t o_lab = T.add(N), o_meta = T.add(4 * (size_t)N), o_ca = T.add(4 * (size_t)N),
+               o_cc = T.add(4 * (size_t)N), o_oa = T.add(4 * (size_t)N), o_oc = T.add(4 * (size_t)N),
+               o_fl = T.add(64), o_scan = T.add(scan_bytes);
+  char* tmp = nullptr;
+  if (hipMalloc(&tmp, T.total) != hipSuccess) return fail(MBX_ENOMEM, "device allocation of %zu bytes failed", T.total);
+  auto cleanup_tmp = [&]() { hipFree(tmp); };
+  int* flags = (int*)(tmp + o_fl);
+  int hflags[4] = {0, 0, 0, 0};
+  int tail[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(tmp + o_lab, labels, N, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(flags, 0, 16, s);
+  if (e == hipSuccess) {
+    launch_build_meta((const uint8_t*)(tmp + o_lab), nx, ny, nz, (uint32_t*)(tmp + o_meta), (int*)(tmp + o_ca),
+                      (int*)(tmp + o_cc), flags, s);
+    size_t sb = scan_bytes;
+    e = exclusive_scan(tmp + o_scan, sb, (const int*)(tmp + o_ca), (int*)(tmp + o_oa), N, s);
+    if (e == hipSuccess) {
+      sb = scan_bytes;
+      e = exclusive_scan(tmp + o_scan, sb, (const int*)(tmp + o_cc), (int*)(tmp + o_oc), N, s);
+    }
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(hflags, flags, 16, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&tail[0], tmp + o_ca + 4 * (size_t)(N - 1), 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&tail[1], tmp + o_oa + 4 * (size_t)(N - 1), 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&tail[2], tmp + o_cc + 4 * (size_t)(N - 1), 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&tail[3], tmp + o_oc + 4 * (size_t)(N - 1), 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    cleanup_tmp();
+    return fail(MBX_EHIP, "cell setup: %s", hipGetErrorString(e));
+  }
+  if (hflags[0] & 1) {
+    cleanup_tmp();
+    return fail(MBX_EINVAL, "labels must be 0 (pore), 1 (anode) or 2 (cathode)");
+  }
+  if (hflags[0] & 2) {
+    cleanup_tmp();
+    return fail(MBX_ELABEL, "an anode voxel shares a face with a cathode voxel");
+  }
+  if (hflags[1] == 0 || hflags[2] == 0) {
+    cleanup_tmp();
+    return fail(MBX_ELABEL, "the z=0 plane needs anode solid and the z=nz-1 plane cathode solid");
+  }
+  const int F_an = tail[0] + tail[1], F_ca = tail[2] + tail[3];
+  if (F_an >= (1 << 24) || F_ca >= (1 << 24)) {
+    cleanup_tmp();
+    return fail(MBX_EINVAL, "too many interface faces for the 24-bit face index");
+  }
+
+  // ---- phase 2: the cell's memory
+  mbx_cell* c = new mbx_cell();
+  c->id = g_next_id++;
+  c->p = p;
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->N = N;
+  c->F_an = F_an;
+  c->F_ca = F_ca;
+  c->n_top = hflags[2];
+  c->nblk = (N + kBlock - 1) / kBlock;
+  c->m = kRestart;
+  c->mixed = p.precision == MBX_MIXED;
+  c->s = s;
+  const size_t kt = kt_size(p.precision);
+  Layout L = make_layout(N, F_an, F_ca, c->nblk, c->m, kt);
+  if (hipMalloc(&c->dmem, L.total) != hipSuccess) {
+    cleanup_tmp();
+    delete c;
+    return fail(MBX_ENOMEM, "device allocation of %zu bytes failed", L.total);
+  }
+  char* b = c->dmem;
+  CellDev& h = c->h;
+  h.nx = nx;
+  h.ny = ny;
+  h.nz = nz;
+  h.N = N;
+  h.F_an = F_an;
+  h.F_ca = F_ca;
+  h.n_top = c->n_top;
+  h.nblk = c->nblk;
+  h.active = 1;
+  h.meta = (const uint32_t*)(b + L.off[0]);
+  double** d8[8] = {&h.c, &h.phi, &h.c_try, &h.phi_try, &h.c_old, &h.phi_old, &h.Rc, &h.Rp};
+  for (int k = 0; k < 8; ++k) *d8[k] = (double*)(b + L.off[1 + k]);
+  h.dc = (double*)(b + L.off[9]);
+  h.dp = h.dc + N;
+  double** f8[7] = {&h.n, &h.n_try, &h.n_old, &h.Rn, &h.dn, &h.rn_jnn, &h.sq};
+  for (int k = 0; k < 7; ++k) *f8[k] = (double*)(b + L.off[10 + k]);
+  h.coef_an = b + L.off[17];
+  h.coef_ca = b + L.off[18];
+  h.wpore = b + L.off[19];
+  h.dinv = b + L.off[20];
+  h.Vb = b + L.off[21];
+  h.w = b + L.off[22];
+  h.z = b + L.off[23];
+  h.b = b + L.off[24];
+  h.x = b + L.off[25];
+  h.part = (double*)(b + L.off[26]);
+  h.ticket = (unsigned*)(b + L.off[27]);
+  h.red = (double*)(b + L.off[28]);
+  h.ictl = (int*)(b + L.off[29]);
+  h.gm = (double*)(b + L.off[30]);
+  c->faces_an = (int*)(b + L.off[31]);
+  c->faces_ca = (int*)(b + L.off[32]);
+  c->d_desc = (CellDev*)(b + L.off[33]);
+  c->d_blk = (int2*)(b + L.off[34]);
+  c->d_gather = (double*)(b + L.off[35]);
+  h.m = c->m;
+  h.lam = 1.0;
+  h.rtol = 1e-6;
+  fill_constants(h, p, nx, ny);
+  fill_step_constants(h, 1.0);
+  std::vector<int2> tab(c->nblk);
+  for (int k = 0; k < c->nblk; ++k) tab[k] = make_int2(0, k);
+  int rc = MBX_OK;
+  e = hipHostMalloc(&c->h_gather, sizeof(double) * kGather, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&c->h_desc_pinned, sizeof(CellDev), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)h.meta, tmp + o_meta, 4 * (size_t)N, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) {
+    launch_finish_meta(N, (uint32_t*)h.meta, (const int*)(tmp + o_oa), (const int*)(tmp + o_oc), c->faces_an,
+                       c->faces_ca, s);
+    e = hipMemsetAsync(h.ticket, 0, 64, s);
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(h.ictl, 0, 4 * CTL_NSLOT, s);
+  if (e == hipSuccess) e = hipMemsetAsync(h.red, 0, 8 * RED_NSLOT, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_blk, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup_tmp();
+  if (e != hipSuccess) {
+    rc = fail(MBX_EHIP, "cell setup: %s", hipGetErrorString(e));
+  } else {
+    Batch bt = single(c);
+    rc = bt.upload();
+    if (rc == MBX_OK) {
+      launch_init_state(bt.bl(), s);
+      rc = sync_outputs(c);
+    }
+  }
+  if (rc != MBX_OK) {
+    mbx_cell_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return MBX_OK;
+}
+
+void mbx_cell_destroy(mbx_cell* c) {
+  if (!c) return;
+  if (c->s) hipStreamSynchronize(c->s);
+  else hipDeviceSynchronize();
+  for (size_t k = 0; k < g_batch_cache.ids.size(); ++k)
+    if (g_batch_cache.ids[k] == c->id) {
+      g_batch_cache.b.release();
+      g_batch_cache.ids.clear();
+      break;
+    }
+  hipFree(c->dmem);
+  hipHostFree(c->h_gather);
+  hipHostFree(c->h_desc_pinned);
+  delete c;
+}
+
+int mbx_cell_step(mbx_cell* c, double dt, mbx_step_info* info) {
+  if (!c) return fail(MBX_EINVAL, "null cell");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(MBX_EINVAL, "dt must be finite and > 0");
+  Batch b = single(c);
+  int st = 0;
+  if (int e = run_step(b, dt, &st, info)) return e;
+  if (st == MBX_ENEWTON) return fail(MBX_ENEWTON, "Newton did not converge; state left at u^n");
+  if (st == MBX_ENAN) return fail(MBX_ENAN, "non-finite residual; state left at u^n");
+  return st;
+}
+
+int mbx_batch_step(mbx_cell* const* cells, int n, double dt, int* status_out, mbx_step_info* infos) {
+  if (!cells || n < 1 || !status_out) return fail(MBX_EINVAL, "null cells/status or n < 1");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(MBX_EINVAL, "dt must be finite and > 0");
+  for (int i = 0; i < n; ++i) {
+    if (!cells[i]) return fail(MBX_EINVAL, "null cell %d", i);
+    if (cells[i]->mixed != cells[0]->mixed) return fail(MBX_EINVAL, "cells of one batch must share a precision mode");
+    if (cells[i]->s != cells[0]->s) return fail(MBX_EINVAL, "cells of one batch must share a stream");
+    for (int j = 0; j < i; ++j)
+      if (cells[j] == cells[i]) return fail(MBX_EINVAL, "cell %d appears twice", i);
+  }
+  Batch b;
+  if (int e = make_batch(cells, n, b)) return e;
+  return run_step(b, dt, status_out, infos);
+}
+
+int mbx_cell_set_current(mbx_cell* c, double I_app) {
+  if (!c) return fail(MBX_EINVAL, "null cell");
+  if (!std::isfinite(I_app)) return fail(MBX_EINVAL, "I_app must be finite");
+  c->p.I_app = I_app;
+  fill_constants(c->h, c->p, c->nx, c->ny);
+  return MBX_OK;
+}
+
+int mbx_cell_counts(const mbx_cell* c, int64_t* n_vox, int64_t* n_an, int64_t* n_ca, int64_t* n_top) {
+  if (!c) return fail(MBX_EINVAL, "null cell");
+  if (n_vox) *n_vox = c->N;
+  if (n_an) *n_an = c->F_an;
+  if (n_ca) *n_ca = c->F_ca;
+  if (n_top) *n_top = c->n_top;
+  return MBX_OK;
+}
+
+int mbx_cell_get_state(const mbx_cell* c, double* cf, double* phi, double* n_pl, int device_ptrs) {
+  if (!c) return fail(MBX_EINVAL, "null cell");
+  const hipMemcpyKind k = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (cf) HIPCHK(hipMemcpyAsync(cf, c->h.c, 8 * (size_t)c->N, k, c->s));
+  if (phi) HIPCHK(hipMemcpyAsync(phi, c->h.phi, 8 * (size_t)c->N, k, c->s));
+  if (n_pl && c->F_an) HIPCHK(hipMemcpyAsync(n_pl, c->h.n, 8 * (size_t)c->F_an, k, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return MBX_OK;
+}
+
+int mbx_cell_set_state(mbx_cell* c, const double* cf, const double* phi, const double* n_pl, int device_ptrs) {
+  if (!c || !cf || !phi || (!n_pl && c->F_an)) return fail(MBX_EINVAL, "null argument");
+  const hipMemcpyKind k = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIPCHK(hipMemcpyAsync(c->h.c, cf, 8 * (size_t)c->N, k, c->s));
+  HIPCHK(hipMemcpyAsync(c->h.phi, phi, 8 * (size_t)c->N, k, c->s));
+  if (c->F_an) HIPCHK(hipMemcpyAsync(c->h.n, n_pl, 8 * (size_t)c->F_an, k, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return MBX_OK;
+}
+
+int mbx_cell_voltage(const mbx_cell* cc, double* V) {
+  if (!cc || !V) return fail(MBX_EINVAL, "null argument");
+  mbx_cell* c = const_cast<mbx_cell*>(cc);
+  if (int e = sync_outputs(c)) return e;
+  *V = c->h_gather[RED_VSUM] / c->n_top;
+  return MBX_OK;
+}
+
+int mbx_cell_inventory(const mbx_cell* cc, double out[4]) {
+  if (!cc || !out) return fail(MBX_EINVAL, "null argument");
+  mbx_cell* c = const_cast<mbx_cell*>(cc);
+  if (int e = sync_outputs(c)) return e;
+  for (int k = 0; k < 4; ++k) out[k] = c->h_gather[RED_INV0 + k];
+  return MBX_OK;
+}
+
+static int load_eval_state(mbx_cell* c, const double* cu, const double* pu, const double* nu, const double* cold,
+                           const double* nold, double dt) {
+  if (!cu || !pu || !cold || (c->F_an && (!nu || !nold))) return fail(MBX_EINVAL, "null argument");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(MBX_EINVAL, "dt must be finite and > 0");
+  const size_t N8 = 8 * (size_t)c->N, F8 = 8 * (size_t)c->F_an;
+  HIPCHK(hipMemcpyAsync(c->h.c_try, cu, N8, hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(c->h.phi_try, pu, N8, hipMemcpyHostToDevice, c->s));
+  HIPCHK(hipMemcpyAsync(c->h.c_old, cold, N8, hipMemcpyHostToDevice, c->s));
+  if (c->F_an) {
+    HIPCHK(hipMemcpyAsync(c->h.n_try, nu, F8, hipMemcpyHostToDevice, c->s));
+    HIPCHK(hipMemcpyAsync(c->h.n_old, nold, F8, hipMemcpyHostToDevice, c->s));
+  }
+  fill_step_constants(c->h, dt);
+  c->h.active = 1;
+  Batch b = single(c);
+  return b.upload();
+}
+
+int mbx_cell_residual(mbx_cell* c, const double* cu, const double* pu, const double* nu, const double* cold,
+                      const double* nold, double dt, double* Rc, double* Rphi, double* Rn) {
+  if (!c || !Rc || !Rphi || (c->F_an && !Rn)) return fail(MBX_EINVAL, "null argument");
+  if (int e = load_eval_state(c, cu, pu, nu, cold, nold, dt)) return e;
+  Batch b = single(c);
+  if (c->mixed) launch_residual<float>(b.bl(), false, c->s);
+  else launch_residual<double>(b.bl(), false, c->s);
+  HIPCHK(hipMemcpyAsync(Rc, c->h.Rc, 8 * (size_t)c->N, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipMemcpyAsync(Rphi, c->h.Rp, 8 * (size_t)c->N, hipMemcpyDeviceToHost, c->s));
+  if (c->F_an) HIPCHK(hipMemcpyAsync(Rn, c->h.Rn, 8 * (size_t)c->F_an, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return MBX_OK;
+}
+
+int mbx_cell_jvp(mbx_cell* c, const double* cu, const double* pu, const double* nu, const double* cold,
+                 const double* nold, double dt, const double* v, double* y) {
+  if (!c || !v || !y) return fail(MBX_EINVAL, "null argument");
+  if (int e = load_eval_state(c, cu, pu, nu, cold, nold, dt)) return e;
+  Batch b = single(c);
+  const size_t N16 = 16 * (size_t)c->N;
+  HIPCHK(hipMemsetAsync(c->h.ictl, 0, 4 * CTL_NSLOT, c->s));
+  if (c->mixed) launch_residual<float>(b.bl(), true, c->s);
+  else launch_residual<double>(b.bl(), true, c->s);
+  HIPCHK(hipMemcpyAsync(c->h.dc, v, N16, hipMemcpyHostToDevice, c->s));
+  if (c->mixed) {
+    launch_convert<float>(b.bl(), VEC_Z, 0, c->s);
+    launch_matvec<float>(b.bl(), VEC_Z, VEC_W, 0, c->s);
+    launch_convert<float>(b.bl(), VEC_W, 1, c->s);
+  } else {
+    launch_convert<double>(b.bl(), VEC_Z, 0, c->s);
+    launch_matvec<double>(b.bl(), VEC_Z, VEC_W, 0, c->s);
+    launch_convert<double>(b.bl(), VEC_W, 1, c->s);
+  }
+  HIPCHK(hipMemcpyAsync(y, c->h.dc, N16, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return MBX_OK;
+}
+
+}  // extern "C"

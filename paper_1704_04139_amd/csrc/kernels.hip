@@ -1,0 +1,1022 @@
+// kernels.hip — HIP kernels of the implicit cell step for gfx950.
+//
+// Every voxel kernel is launched over the blocks of a batch of cells: block
+// b works on cell blk[b].x, voxels [blk[b].y*256, +256).  One cell is a batch
+// of one.  Kernels skip cells whose descriptor has active == 0, and the
+// Krylov kernels also skip cells whose GMRES solve has converged.
+#include <hip/hip_runtime.h>
+
+#include "mbx_dev.h"
+#include "mbx_kernels.h"
+#include "reduce.h"
+
+#include <hipcub/hipcub.hpp>
+
+namespace mbx {
+
+struct VoxCoord {
+  int x, y, z;
+};
+__device__ inline VoxCoord coord_of(const CellDev& cd, int i) {
+  VoxCoord v;
+  v.x = i % cd.nx;
+  const int t = i / cd.nx;
+  v.y = t % cd.ny;
+  v.z = t / cd.ny;
+  return v;
+}
+
+template <typename KT>
+__device__ inline KT* vec(const CellDev& cd, int sel) {
+  const size_t n2 = 2 * (size_t)cd.N;
+  switch (sel) {
+    case VEC_Z: return (KT*)cd.z;
+    case VEC_W: return (KT*)cd.w;
+    case VEC_B: return (KT*)cd.b;
+    case VEC_X: return (KT*)cd.x;
+    default: return (KT*)cd.Vb + (size_t)sel * n2;
+  }
+}
+
+__device__ inline double cref_of(const CellDev& cd, int L) { return L == PORE ? cd.c0 : cd.cmax[L - 1]; }
+
+// ------------------------------------------------------------------ setup
+// Label validation and interface masks (Sec. 2.4: each face of the voxel
+// grid is either a same-phase transport face or a solid/pore interface
+// carrying the Butler-Volmer flux; the paper's interface table has no
+// anode/cathode interface, so such faces are rejected).
+__global__ void __launch_bounds__(kBlock) k_build_meta(const uint8_t* __restrict__ lab, int nx, int ny, int nz,
+                                                       uint32_t* __restrict__ meta, int* __restrict__ cnt_an,
+                                                       int* __restrict__ cnt_ca, int* __restrict__ flags) {
+  const int N = nx * ny * nz;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= N) return;
+  const int L = lab[i];
+  if (L > 2) {
+    atomicOr(&flags[0], 1);
+    meta[i] = 0;
+    cnt_an[i] = cnt_ca[i] = 0;
+    return;
+  }
+  const int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+  const int nb[6] = {x > 0 ? i - 1 : -1,      x < nx - 1 ? i + 1 : -1,      y > 0 ? i - nx : -1,
+                     y < ny - 1 ? i + nx : -1, z > 0 ? i - nx * ny : -1, z < nz - 1 ? i + nx * ny : -1};
+  uint32_t mask = 0;
+  for (int d = 0; d < 6; ++d) {
+    if (nb[d] < 0) continue;
+    const int Lk = lab[nb[d]];
+    if ((L == PORE) != (Lk == PORE)) mask |= 1u << d;
+    if ((L == ANODE && Lk == CATHODE) || (L == CATHODE && Lk == ANODE)) atomicOr(&flags[0], 2);
+  }
+  if (z == 0 && L == ANODE) atomicOr(&flags[1], 1);
+  if (z == nz - 1 && L == CATHODE) atomicAdd(&flags[2], 1);
+  meta[i] = (uint32_t)L | (mask << 2);
+  const int cnt = __popc(mask);
+  cnt_an[i] = (L == ANODE) ? cnt : 0;
+  cnt_ca[i] = (L == CATHODE) ? cnt : 0;
+}
+
+// Stores each solid voxel's first face index (exclusive prefix sums of the
+// per-voxel face counts, one scan per phase) and the compacted face lists
+// (voxel index * 8 + direction) in canonical order.
+__global__ void __launch_bounds__(kBlock) k_finish_meta(int N, uint32_t* __restrict__ meta,
+                                                        const int* __restrict__ off_an,
+                                                        const int* __restrict__ off_ca,
+                                                        int* __restrict__ faces_an, int* __restrict__ faces_ca) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= N) return;
+  const uint32_t m = meta[i];
+  const int L = lab_of(m);
+  if (L == PORE) return;
+  const int base = (L == ANODE) ? off_an[i] : off_ca[i];
+  meta[i] = m | ((uint32_t)base << 8);
+  int* fl = (L == ANODE) ? faces_an : faces_ca;
+  int r = 0;
+  for (int d = 0; d < 6; ++d)
+    if ((mask_of(m) >> d) & 1u) fl[base + r++] = i * 8 + d;
+}
+
+// Zero-current equilibrium (every interface current vanishes; the plated
+// amount makes the plating current zero: f_pre(n) = exp(-F U_an(x0)/RT)).
+__global__ void __launch_bounds__(kBlock) k_init_state(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const uint32_t m = cd.meta[i];
+  const int L = lab_of(m);
+  const double Uan = cd.U0[0] + cd.U1[0] * log((1.0 - cd.x0) / cd.x0);
+  const double Uca = cd.U0[1] + cd.U1[1] * log((1.0 - cd.y0) / cd.y0);
+  double c, p;
+  if (L == PORE) {
+    c = cd.c0;
+    p = -Uan;
+  } else if (L == ANODE) {
+    c = cd.x0 * cd.cmax[0];
+    p = 0.0;
+  } else {
+    c = cd.y0 * cd.cmax[1];
+    p = Uca - Uan;
+  }
+  cd.c[i] = c;
+  cd.phi[i] = p;
+  if (L == ANODE) {
+    const double f = exp(-kFaraday * Uan / cd.RT);
+    const double neq = cd.n_c * pow(f / (1.0 - f), 0.25);
+    const uint32_t cnt = __popc(mask_of(m));
+    for (uint32_t r = 0; r < cnt; ++r) cd.n[base_of(m) + r] = neq;
+  }
+}
+
+// --------------------------------------------------------------- residual
+// FP64 residual of the implicit Euler system (eq. 2.13) at the trial state,
+// with every face flux evaluated from the two adjacent voxels in the same
+// order on both sides (so the scatter conserves Li to rounding):
+//   pore/pore   j = -kappa dphi/h + kappa (1-t+) theta RT/F dln c/h,
+//               N = -De dc/h + t+/F j                     (eqs. 2.3-2.4, 2.6)
+//   solid/solid N = -Ds dc/h, j = -sigma dphi/h            (eqs. 2.1-2.2)
+//   solid/pore  Butler-Volmer intercalation (2.5) and, on anode faces,
+//               plating/stripping (2.8) as the numerical flux (eq. 2.4)
+//   collectors  anode at phi = 0 across h/2; cathode galvanostatic.
+// With LIN it also writes the linearisation used by the Krylov solve: the
+// scaled face coefficients (plating condensed onto the voxel unknowns),
+// the pore 1/c coefficient and the inverse 2x2 diagonal blocks.
+template <bool LIN, typename KT>
+__global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  CellDev* cdp = cells + bb.x;
+  const CellDev& cd = *cdp;
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  double rsq = 0.0, rmax = 0.0;
+  if (i < cd.N) {
+    const VoxCoord v = coord_of(cd, i);
+    const uint32_t mi = cd.meta[i];
+    const int L = lab_of(mi);
+    const double ci = cd.c_try[i], pi = cd.phi_try[i];
+    const double A = cd.A, h = cd.h, dt = cd.dt;
+    const bool plate = cd.plating != 0;
+    double Rc = cd.Vol * (ci - cd.c_old[i]) / dt;
+    double Rp = 0.0;
+    double bcc = cd.Vol / dt, bcp = 0.0, bpc = 0.0, bpp = 0.0;
+    for (int d = 0; d < 6; ++d) {
+      const int k = neighbour(cd, i, v.x, v.y, v.z, d);
+      if (k < 0) {
+        if (d == 4 && L == ANODE) {
+          Rp += 2.0 * A * cd.sigma[0] * pi / h;
+          bpp += 2.0 * A * cd.sigma[0] / h;
+        } else if (d == 5 && L == CATHODE) {
+          Rp += -cd.I_app / cd.n_top;
+        }
+        continue;
+      }
+      const uint32_t mk = cd.meta[k];
+      const int Lk = lab_of(mk);
+      const double ck = cd.c_try[k], pk = cd.phi_try[k];
+      const bool lo = i < k;
+      const double sgn = lo ? 1.0 : -1.0;
+      const double ca = lo ? ci : ck, cb = lo ? ck : ci;
+      const double pa = lo ? pi : pk, pb = lo ? pk : pi;
+      if (L == PORE && Lk == PORE) {
+        const double j = -cd.kappa * (pb - pa) / h + cd.Kd * (log(cb) - log(ca));
+        const double Nf = -cd.De * (cb - ca) / h + cd.tplus / kFaraday * j;
+        Rc += sgn * (A * Nf);
+        Rp += sgn * (A * j);
+        if (LIN) {
+          bcc += A * (cd.De / h - cd.tplus / kFaraday * cd.Kd / ci);
+          bcp += A * (cd.tplus / kFaraday * cd.kappa / h);
+          bpc += -A * cd.Kd / ci;
+          bpp += A * cd.kappa / h;
+        }
+      } else if (L == Lk) {
+        const int s = L - 1;
+        const double Nf = -cd.Ds[s] * (cb - ca) / h;
+        const double j = -cd.sigma[s] * (pb - pa) / h;
+        Rc += sgn * (A * Nf);
+        Rp += sgn * (A * j);
+        if (LIN) {
+          bcc += A * cd.Ds[s] / h;
+          bpp += A * cd.sigma[s] / h;
+        }
+      } else if (L == PORE) {
+        const bool an = Lk == ANODE;
+        const uint32_t f = face_rank(mk, d ^ 1);
+        const double nf = an ? cd.n_try[f] : 0.0;
+        const Kin q = interface_kinetics(cd, Lk, ck, ci, pk, pi, nf, an && plate, LIN);
+        const double it = q.ii + q.ip;
+        Rc -= A * it / kFaraday;
+        Rp -= A * it;
+        if (LIN) {
+          double kap = 0.0;
+          if (an && plate) kap = (A / dt) / (A / dt + A * q.p_n / kFaraday);
+          const double dce = q.d_ce + kap * q.p_ce, gg = q.g + kap * q.g_p;
+          bcc += -A * dce / kFaraday;
+          bcp += A * gg / kFaraday;
+          bpc += -A * dce;
+          bpp += A * gg;
+        }
+      } else {
+        const bool an = L == ANODE;
+        const uint32_t f = face_rank(mi, d);
+        const double nf = an ? cd.n_try[f] : 0.0;
+        const Kin q = interface_kinetics(cd, L, ci, ck, pi, pk, nf, an && plate, LIN);
+        Rc += A * q.ii / kFaraday;
+        Rp += A * (q.ii + q.ip);
+        double kap = 0.0;
+        if (an) {
+          const double Rn = A * (nf - cd.n_old[f]) / dt + A * q.ip / kFaraday;
+          cd.Rn[f] = Rn;
+          const double rs = Rn * dt / (A * cd.n_c);
+          rsq += rs * rs;
+          rmax = fmax(rmax, fabs(rs));
+          if (LIN) {
+            const double jnn = A / dt + A * q.p_n / kFaraday;
+            kap = (A / dt) / jnn;
+            const double mu = cd.mu_ref;
+            KT* co = (KT*)cd.coef_an + 5 * (size_t)f;
+            co[0] = (KT)(q.d_cs * cd.cmax[0] / mu);
+            co[1] = (KT)(q.d_ce * cd.c0 / mu);
+            co[2] = (KT)(q.g * cd.VT / mu);
+            co[3] = (KT)(kap * q.p_ce * cd.c0 / mu);
+            co[4] = (KT)(kap * q.g_p * cd.VT / mu);
+            cd.rn_jnn[f] = Rn / jnn;
+            cd.sq[f] = q.p_n * Rn / (jnn * mu);
+          }
+        } else if (LIN) {
+          const double mu = cd.mu_ref;
+          KT* co = (KT*)cd.coef_ca + 3 * (size_t)f;
+          co[0] = (KT)(q.d_cs * cd.cmax[1] / mu);
+          co[1] = (KT)(q.d_ce * cd.c0 / mu);
+          co[2] = (KT)(q.g * cd.VT / mu);
+        }
+        if (LIN) {
+          bcc += A * q.d_cs / kFaraday;
+          bcp += A * q.g / kFaraday;
+          bpc += A * q.d_cs;
+          bpp += A * (q.g + kap * q.g_p);
+        }
+      }
+    }
+    cd.Rc[i] = Rc;
+    cd.Rp[i] = Rp;
+    const double cref = cref_of(cd, L);
+    const double sc = dt / (cd.Vol * cref), sp = 1.0 / (A * cd.mu_ref);
+    const double rc = Rc * sc, rp = Rp * sp;
+    rsq += rc * rc + rp * rp;
+    rmax = fmax(rmax, fmax(fabs(rc), fabs(rp)));
+    if (LIN) {
+      const double Bcc = sc * bcc * cref, Bcp = sc * bcp * cd.VT;
+      const double Bpc = sp * bpc * cref, Bpp = sp * bpp * cd.VT;
+      const double det = Bcc * Bpp - Bcp * Bpc;
+      KT* di = (KT*)cd.dinv + 4 * (size_t)i;
+      di[0] = (KT)(Bpp / det);
+      di[1] = (KT)(-Bcp / det);
+      di[2] = (KT)(-Bpc / det);
+      di[3] = (KT)(Bcc / det);
+      ((KT*)cd.wpore)[i] = (KT)(L == PORE ? cd.c0 / ci : 0.0);
+    }
+  }
+  const double vals[2] = {rsq, rmax};
+  reduce_cell<2>(cdp, bb.y, vals, 0x2u, cd.red + RED_RSQ);
+}
+
+// Right-hand side of the condensed, scaled Newton system:
+//   b = D_r (-R_u + J_un J_nn^-1 R_n),
+// also copied to w (the first GMRES residual, x = 0), with ||b||^2.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  CellDev* cdp = cells + bb.x;
+  const CellDev& cd = *cdp;
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  double ss = 0.0;
+  if (i < cd.N) {
+    const VoxCoord v = coord_of(cd, i);
+    const uint32_t mi = cd.meta[i];
+    const int L = lab_of(mi);
+    const double cref = cref_of(cd, L);
+    double bc = -cd.Rc[i] * cd.dt / (cd.Vol * cref);
+    double bp = -cd.Rp[i] / (cd.A * cd.mu_ref);
+    if (cd.plating) {
+      const uint32_t msk = mask_of(mi);
+      if (L == ANODE) {
+        for (int d = 0; d < 6; ++d)
+          if ((msk >> d) & 1u) bp += cd.sq[face_rank(mi, d)];
+      } else if (L == PORE && msk) {
+        for (int d = 0; d < 6; ++d) {
+          if (!((msk >> d) & 1u)) continue;
+          const int k = neighbour(cd, i, v.x, v.y, v.z, d);
+          const uint32_t mk = cd.meta[k];
+          if (lab_of(mk) != ANODE) continue;
+          const double s = cd.sq[face_rank(mk, d ^ 1)];
+          bc -= cd.Ke * s;
+          bp -= s;
+        }
+      }
+    }
+    const size_t N = cd.N;
+    KT* b = (KT*)cd.b;
+    KT* w = (KT*)cd.w;
+    KT* x = (KT*)cd.x;
+    b[i] = (KT)bc;
+    b[N + i] = (KT)bp;
+    w[i] = (KT)bc;
+    w[N + i] = (KT)bp;
+    x[i] = (KT)0;
+    x[N + i] = (KT)0;
+    const double bcr = (double)(KT)bc, bpr = (double)(KT)bp;
+    ss = bcr * bcr + bpr * bpr;
+  }
+  const double vals[1] = {ss};
+  reduce_cell<1>(cdp, bb.y, vals, 0u, cd.red + RED_BSQ);
+}
+
+// ---------------------------------------------------------- preconditioner
+// Block Jacobi: z = D^-1 v with the inverse 2x2 (c, phi) voxel blocks.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_jacobi(CellDev* cells, const int2* __restrict__ blk, int src, int dst,
+                                                   int need) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active || cd.ictl[CTL_DONE] != need) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const size_t N = cd.N;
+  const KT* v = vec<KT>(cd, src);
+  KT* z = vec<KT>(cd, dst);
+  const KT* di = (const KT*)cd.dinv + 4 * (size_t)i;
+  const KT vc = v[i], vp = v[N + i];
+  z[i] = di[0] * vc + di[1] * vp;
+  z[N + i] = di[2] * vc + di[3] * vp;
+}
+
+// ----------------------------------------------------------------- J * v
+// Matrix-free product with the scaled, condensed Jacobian of the residual:
+// same stencil as k_residual, linear in v, coefficients from the last
+// linearisation.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* __restrict__ blk, int src, int dst,
+                                                   int need) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active || cd.ictl[CTL_DONE] != need) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const size_t N = cd.N;
+  const KT* v = vec<KT>(cd, src);
+  KT* y = vec<KT>(cd, dst);
+  const KT* wpo = (const KT*)cd.wpore;
+  const KT* can = (const KT*)cd.coef_an;
+  const KT* cca = (const KT*)cd.coef_ca;
+  const VoxCoord c3 = coord_of(cd, i);
+  const uint32_t mi = cd.meta[i];
+  const int L = lab_of(mi);
+  const KT vc = v[i], vp = v[N + i];
+  const KT wi = (L == PORE) ? wpo[i] : (KT)0;
+  const KT Gk = (KT)cd.Gk, tth = (KT)cd.tth, Dh = (KT)cd.Dh, tau = (KT)cd.tau, Ke = (KT)cd.Ke;
+  KT yc = vc, yp = (KT)0;
+  for (int d = 0; d < 6; ++d) {
+    const int k = neighbour(cd, i, c3.x, c3.y, c3.z, d);
+    if (k < 0) {
+      if (d == 4 && L == ANODE) yp += (KT)cd.Gcol * vp;
+      continue;
+    }
+    const uint32_t mk = cd.meta[k];
+    const int Lk = lab_of(mk);
+    const KT vck = v[k], vpk = v[N + k];
+    const bool lo = i < k;
+    if (L == PORE && Lk == PORE) {
+      const KT wk = wpo[k];
+      const KT vca = lo ? vc : vck, vcb = lo ? vck : vc;
+      const KT vpa = lo ? vp : vpk, vpb = lo ? vpk : vp;
+      const KT wa = lo ? wi : wk, wb = lo ? wk : wi;
+      const KT dj = Gk * (-(vpb - vpa) + tth * (wb * vcb - wa * vca));
+      const KT dN = -Dh * (vcb - vca) + tau * dj;
+      if (lo) {
+        yc += dN;
+        yp += dj;
+      } else {
+        yc -= dN;
+        yp -= dj;
+      }
+    } else if (L == Lk) {
+      const int s = L - 1;
+      // -D (v_k - v_i) seen from voxel i, in either orientation
+      yc += (KT)cd.Dsh[s] * (vc - vck);
+      yp += (KT)cd.Gs[s] * (vp - vpk);
+    } else if (L == PORE) {
+      const uint32_t f = face_rank(mk, d ^ 1);
+      KT q, qp = (KT)0;
+      if (Lk == ANODE) {
+        const KT* co = can + 5 * (size_t)f;
+        q = co[0] * vck + co[1] * vc + co[2] * (vpk - vp);
+        qp = co[3] * vc + co[4] * (vpk - vp);
+      } else {
+        const KT* co = cca + 3 * (size_t)f;
+        q = co[0] * vck + co[1] * vc + co[2] * (vpk - vp);
+      }
+      yc -= Ke * (q + qp);
+      yp -= q + qp;
+    } else {
+      const uint32_t f = face_rank(mi, d);
+      KT q, qp = (KT)0;
+      if (L == ANODE) {
+        const KT* co = can + 5 * (size_t)f;
+        q = co[0] * vc + co[1] * vck + co[2] * (vp - vpk);
+        qp = co[3] * vck + co[4] * (vp - vpk);
+      } else {
+        const KT* co = cca + 3 * (size_t)f;
+        q = co[0] * vc + co[1] * vck + co[2] * (vp - vpk);
+      }
+      yc += (KT)cd.Ks[L - 1] * q;
+      yp += q + qp;
+    }
+  }
+  y[i] = yc;
+  y[N + i] = yp;
+}
+
+// ------------------------------------------------------------------- GMRES
+// Dots of w with basis vectors 0..k into H(:,k) (tgt = 0) or tmp (tgt = 1).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_multidot(CellDev* cells, const int2* __restrict__ blk, int k, int tgt) {
+  const int2 bb = blk[blockIdx.x];
+  CellDev* cdp = cells + bb.x;
+  const CellDev& cd = *cdp;
+  if (!cd.active || cd.ictl[CTL_DONE]) return;
+  __shared__ double lds4[4];
+  __shared__ bool flag;
+  const int i = bb.y * kBlock + threadIdx.x;
+  const size_t N = cd.N;
+  double wc = 0.0, wp = 0.0;
+  if (i < cd.N) {
+    const KT* w = (const KT*)cd.w;
+    wc = (double)w[i];
+    wp = (double)w[N + i];
+  }
+  for (int j = 0; j <= k; ++j) {
+    double s = 0.0;
+    if (i < cd.N) {
+      const KT* vj = vec<KT>(cd, j);
+      s = (double)vj[i] * wc + (double)vj[N + i] * wp;
+    }
+    const double r = block_sum(s, lds4);
+    if (threadIdx.x == 0) part_store(&cd.part[(size_t)bb.y * kPartStride + j], r);
+  }
+  if (!take_ticket(cdp, &flag)) return;
+  const int m = cd.m;
+  double* out = tgt == 0 ? cd.gm + gm_H(m) + (size_t)(m + 1) * k : cd.gm + gm_tmp(m);
+  for (int j = 0; j <= k; ++j) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < cd.nblk; b += kBlock) acc += part_load(&cd.part[(size_t)b * kPartStride + j]);
+    acc = block_sum(acc, lds4);
+    if (threadIdx.x == 0) out[j] = acc;
+  }
+  release_ticket(cdp);
+}
+
+// w -= sum_j h_j V_j with h = H(:,k) (src = 0) or tmp (src = 1; then H(:,k)
+// += tmp); ||w||^2 into H(k+1,k).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_orth(CellDev* cells, const int2* __restrict__ blk, int k, int src) {
+  const int2 bb = blk[blockIdx.x];
+  CellDev* cdp = cells + bb.x;
+  const CellDev& cd = *cdp;
+  if (!cd.active || cd.ictl[CTL_DONE]) return;
+  __shared__ double lds4[4];
+  __shared__ bool flag;
+  const int m = cd.m;
+  const double* hc = src == 0 ? cd.gm + gm_H(m) + (size_t)(m + 1) * k : cd.gm + gm_tmp(m);
+  const int i = bb.y * kBlock + threadIdx.x;
+  const size_t N = cd.N;
+  double ss = 0.0;
+  if (i < cd.N) {
+    KT* w = (KT*)cd.w;
+    KT wc = w[i], wp = w[N + i];
+    for (int j = 0; j <= k; ++j) {
+      const KT* vj = vec<KT>(cd, j);
+      const KT hj = (KT)hc[j];
+      wc -= hj * vj[i];
+      wp -= hj * vj[N + i];
+    }
+    w[i] = wc;
+    w[N + i] = wp;
+    ss = (double)wc * (double)wc + (double)wp * (double)wp;
+  }
+  const double r = block_sum(ss, lds4);
+  if (threadIdx.x == 0) part_store(&cd.part[(size_t)bb.y * kPartStride], r);
+  if (!take_ticket(cdp, &flag)) return;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < cd.nblk; b += kBlock) acc += part_load(&cd.part[(size_t)b * kPartStride]);
+  acc = block_sum(acc, lds4);
+  if (threadIdx.x == 0) {
+    double* H = cd.gm + gm_H(m) + (size_t)(m + 1) * k;
+    if (src == 1)
+      for (int j = 0; j <= k; ++j) H[j] += hc[j];
+    H[k + 1] = sqrt(acc);
+  }
+  release_ticket(cdp);
+}
+
+// V_{k+1} = w / H(k+1,k)
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_scale_next(CellDev* cells, const int2* __restrict__ blk, int k) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active || cd.ictl[CTL_DONE]) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const int m = cd.m;
+  const double hn = cd.gm[gm_H(m) + (size_t)(m + 1) * k + k + 1];
+  const KT inv = hn > 0.0 ? (KT)(1.0 / hn) : (KT)0;
+  const size_t N = cd.N;
+  const KT* w = (const KT*)cd.w;
+  KT* vn = vec<KT>(cd, k + 1);
+  vn[i] = w[i] * inv;
+  vn[N + i] = w[N + i] * inv;
+}
+
+// Givens rotations of the Hessenberg column k (one thread per cell).
+__global__ void k_givens(CellDev* cells, int ncell, int k) {
+  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= ncell) return;
+  const CellDev& cd = cells[ci];
+  if (!cd.active || cd.ictl[CTL_DONE]) return;
+  const int m = cd.m;
+  double* H = cd.gm + gm_H(m) + (size_t)(m + 1) * k;
+  double* g = cd.gm + gm_g(m);
+  double* cs = cd.gm + gm_cs(m);
+  double* sn = cd.gm + gm_sn(m);
+  for (int j = 0; j < k; ++j) {
+    const double t = cs[j] * H[j] + sn[j] * H[j + 1];
+    H[j + 1] = -sn[j] * H[j] + cs[j] * H[j + 1];
+    H[j] = t;
+  }
+  const double a = H[k], b = H[k + 1];
+  const double r = hypot(a, b);
+  double c = 1.0, s = 0.0;
+  if (r > 0.0) {
+    c = a / r;
+    s = b / r;
+  }
+  cs[k] = c;
+  sn[k] = s;
+  H[k] = r;
+  H[k + 1] = 0.0;
+  g[k + 1] = -s * g[k];
+  g[k] = c * g[k];
+  cd.ictl[CTL_K] = k + 1;
+  cd.ictl[CTL_ITERS] += 1;
+  if (fabs(g[k + 1]) <= cd.red[RED_TOL] || b == 0.0)
+    cd.ictl[CTL_DONE] = 1;          // converged (or exact breakdown)
+  else if (k + 1 >= m)
+    cd.ictl[CTL_DONE] = 2;          // cycle full: restart needed
+}
+
+// Back substitution R y = g for the iterations of the current cycle.
+__global__ void k_backsolve(CellDev* cells, int ncell) {
+  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= ncell) return;
+  const CellDev& cd = cells[ci];
+  if (!cd.active) return;
+  const int st = cd.ictl[CTL_DONE];
+  if (st != 1 && st != 2) return;
+  const int m = cd.m;
+  const int kk = cd.ictl[CTL_K];
+  const double* H = cd.gm + gm_H(m);
+  const double* g = cd.gm + gm_g(m);
+  double* y = cd.gm + gm_y(m);
+  for (int r = kk - 1; r >= 0; --r) {
+    double s = g[r];
+    for (int j = r + 1; j < kk; ++j) s -= H[r + (size_t)(m + 1) * j] * y[j];
+    const double dgl = H[r + (size_t)(m + 1) * r];
+    y[r] = dgl != 0.0 ? s / dgl : 0.0;
+  }
+}
+
+// w = sum_{j<k} y_j V_j (cycle end; runs for converged cells too)
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_combine(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  {
+    const int st = cd.ictl[CTL_DONE];
+    if (st != 1 && st != 2) return;
+  }
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const int m = cd.m;
+  const int kk = cd.ictl[CTL_K];
+  const double* y = cd.gm + gm_y(m);
+  const size_t N = cd.N;
+  KT ac = (KT)0, ap = (KT)0;
+  for (int j = 0; j < kk; ++j) {
+    const KT* vj = vec<KT>(cd, j);
+    const KT yj = (KT)y[j];
+    ac += yj * vj[i];
+    ap += yj * vj[N + i];
+  }
+  KT* w = (KT*)cd.w;
+  w[i] = ac;
+  w[N + i] = ap;
+}
+
+// Cycle end: z = M^-1 w (block Jacobi) and x += z, fused.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_update_x_jacobi(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  {
+    const int st = cd.ictl[CTL_DONE];
+    if (st != 1 && st != 2) return;
+  }
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const size_t N = cd.N;
+  const KT* w = (const KT*)cd.w;
+  KT* x = (KT*)cd.x;
+  const KT* di = (const KT*)cd.dinv + 4 * (size_t)i;
+  const KT vc = w[i], vp = w[N + i];
+  x[i] += di[0] * vc + di[1] * vp;
+  x[N + i] += di[2] * vc + di[3] * vp;
+}
+
+// x += z
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_add_z_to_x(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  {
+    const int st = cd.ictl[CTL_DONE];
+    if (st != 1 && st != 2) return;
+  }
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const size_t N = cd.N;
+  const KT* z = (const KT*)cd.z;
+  KT* x = (KT*)cd.x;
+  x[i] += z[i];
+  x[N + i] += z[N + i];
+}
+
+// Restart: w = b - w (w holds J x) with ||w||^2.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_true_residual(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  CellDev* cdp = cells + bb.x;
+  const CellDev& cd = *cdp;
+  if (!cd.active || cd.ictl[CTL_DONE] != 2) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  double ss = 0.0;
+  if (i < cd.N) {
+    const size_t N = cd.N;
+    const KT* b = (const KT*)cd.b;
+    KT* w = (KT*)cd.w;
+    const KT rc = b[i] - w[i], rp = b[N + i] - w[N + i];
+    w[i] = rc;
+    w[N + i] = rp;
+    ss = (double)rc * (double)rc + (double)rp * (double)rp;
+  }
+  const double vals[1] = {ss};
+  reduce_cell<1>(cdp, bb.y, vals, 0u, cd.red + RED_BSQ);
+}
+
+// Start a GMRES cycle from the residual in w: V_0 = w/beta (all cells on
+// the first cycle of a solve, otherwise only cells that must restart).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_gm_start(CellDev* cells, const int2* __restrict__ blk, int first) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  if (!first && cd.ictl[CTL_DONE] != 2) return;
+  const double beta = sqrt(cd.red[RED_BSQ]);
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const size_t N = cd.N;
+  const KT inv = beta > 0.0 ? (KT)(1.0 / beta) : (KT)0;
+  const KT* w = (const KT*)cd.w;
+  KT* v0 = vec<KT>(cd, 0);
+  v0[i] = w[i] * inv;
+  v0[N + i] = w[N + i] * inv;
+}
+
+// Per-cell GMRES bookkeeping after k_gm_start (one thread per cell):
+// first cycle: tolerance = rtol * beta0; later: a cell that converged in the
+// cycle just closed is finished (state 3), a cell that ran out of basis
+// restarts from the true residual.
+__global__ void k_gm_flags(CellDev* cells, int ncell, int first) {
+  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= ncell) return;
+  const CellDev& cd = cells[ci];
+  if (!cd.active) return;
+  const int m = cd.m;
+  const double beta = sqrt(cd.red[RED_BSQ]);
+  double* g = cd.gm + gm_g(m);
+  if (first) {
+    cd.red[RED_BETA0] = beta;
+    cd.red[RED_TOL] = cd.rtol * beta;
+    cd.ictl[CTL_ITERS] = 0;
+  } else {
+    const int st = cd.ictl[CTL_DONE];
+    if (st == 1 || st == 3) {
+      cd.ictl[CTL_DONE] = 3;
+      return;
+    }
+    if (st != 2) return;
+  }
+  for (int j = 0; j <= m; ++j) g[j] = 0.0;
+  g[0] = beta;
+  cd.ictl[CTL_K] = 0;
+  cd.ictl[CTL_DONE] = (beta <= cd.red[RED_TOL]) ? 1 : 0;
+}
+
+// Gathers every cell's reduction slots and flags for one host read.
+__global__ void k_gather_ctl(CellDev* cells, int ncell, double* out) {
+  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= ncell) return;
+  const CellDev& cd = cells[ci];
+  double* o = out + (size_t)ci * (RED_NSLOT + CTL_NSLOT);
+  for (int j = 0; j < RED_NSLOT; ++j) o[j] = cd.red[j];
+  for (int j = 0; j < CTL_NSLOT; ++j) o[RED_NSLOT + j] = (double)cd.ictl[j];
+}
+
+// ------------------------------------------------------------------ Newton
+// Raw Newton direction from the Krylov solution x: dc = c_ref x_c,
+// dphi = (RT/F) x_phi, and the condensed plated unknowns
+// dn = -R^n/J_nn - (dt/F) (d i_pl, condensed).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_direction(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const size_t N = cd.N;
+  const KT* x = (const KT*)cd.x;
+  const uint32_t mi = cd.meta[i];
+  const int L = lab_of(mi);
+  const double xc = (double)x[i], xp = (double)x[N + i];
+  cd.dc[i] = cref_of(cd, L) * xc;
+  cd.dp[i] = cd.VT * xp;
+  if (L == ANODE) {
+    const VoxCoord v = coord_of(cd, i);
+    const uint32_t msk = mask_of(mi);
+    const KT* can = (const KT*)cd.coef_an;
+    for (int d = 0; d < 6; ++d) {
+      if (!((msk >> d) & 1u)) continue;
+      const int k = neighbour(cd, i, v.x, v.y, v.z, d);
+      const uint32_t f = face_rank(mi, d);
+      double dn = -cd.rn_jnn[f];
+      if (cd.plating) {
+        const KT* co = can + 5 * (size_t)f;
+        const double qp = (double)co[3] * (double)x[k] + (double)co[4] * (xp - (double)x[N + k]);
+        dn -= cd.dt * cd.mu_ref / kFaraday * qp;
+      }
+      cd.dn[f] = dn;
+    }
+  }
+}
+
+// Trial state u + lam du; counts inadmissible entries (c <= 0, c_s >= c_max,
+// n < 0, non-finite) and the scaled max-norm of the step.
+__global__ void __launch_bounds__(kBlock) k_trial(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  CellDev* cdp = cells + bb.x;
+  const CellDev& cd = *cdp;
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  double bad = 0.0, dmax = 0.0;
+  if (i < cd.N) {
+    const uint32_t mi = cd.meta[i];
+    const int L = lab_of(mi);
+    const double lam = cd.lam;
+    const double c = cd.c[i] + lam * cd.dc[i];
+    const double p = cd.phi[i] + lam * cd.dp[i];
+    cd.c_try[i] = c;
+    cd.phi_try[i] = p;
+    const double cref = cref_of(cd, L);
+    if (!(c > 0.0) || !isfinite(p) || (L != PORE && !(c < cref))) bad += 1.0;
+    dmax = fmax(fabs(lam * cd.dc[i]) / cref, fabs(lam * cd.dp[i]) / cd.VT);
+    if (!isfinite(dmax)) bad += 1.0;
+    if (L == ANODE) {
+      const uint32_t cnt = __popc(mask_of(mi));
+      for (uint32_t r = 0; r < cnt; ++r) {
+        const uint32_t f = base_of(mi) + r;
+        const double nn = cd.n[f] + lam * cd.dn[f];
+        cd.n_try[f] = nn;
+        if (!(nn >= 0.0)) bad += 1.0;
+        dmax = fmax(dmax, fabs(lam * cd.dn[f]) / cd.n_c);
+      }
+    }
+  }
+  const double vals[2] = {bad, dmax};
+  reduce_cell<2>(cdp, bb.y, vals, 0x2u, cd.red + RED_BAD);
+}
+
+// State copies: 0 try -> iterate, 1 iterate -> try, 2 iterate -> old (step
+// start), 3 old -> iterate and try (rollback), 4 old -> try (step start).
+__global__ void __launch_bounds__(kBlock) k_copy_state(CellDev* cells, const int2* __restrict__ blk, int mode) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const uint32_t mi = cd.meta[i];
+  const int L = lab_of(mi);
+  const uint32_t cnt = (L == ANODE) ? __popc(mask_of(mi)) : 0u;
+  const uint32_t f0 = base_of(mi);
+  const double *sc, *sp, *sn;
+  double *dc, *dp, *dn;
+  double *dc2 = nullptr, *dp2 = nullptr, *dn2 = nullptr;
+  switch (mode) {
+    case 0: sc = cd.c_try; sp = cd.phi_try; sn = cd.n_try; dc = cd.c; dp = cd.phi; dn = cd.n; break;
+    case 1: sc = cd.c; sp = cd.phi; sn = cd.n; dc = cd.c_try; dp = cd.phi_try; dn = cd.n_try; break;
+    case 2: sc = cd.c; sp = cd.phi; sn = cd.n; dc = cd.c_old; dp = cd.phi_old; dn = cd.n_old; break;
+    case 3:
+      sc = cd.c_old; sp = cd.phi_old; sn = cd.n_old; dc = cd.c; dp = cd.phi; dn = cd.n;
+      dc2 = cd.c_try; dp2 = cd.phi_try; dn2 = cd.n_try;
+      break;
+    default: sc = cd.c_old; sp = cd.phi_old; sn = cd.n_old; dc = cd.c_try; dp = cd.phi_try; dn = cd.n_try; break;
+  }
+  dc[i] = sc[i];
+  dp[i] = sp[i];
+  if (dc2) {
+    dc2[i] = sc[i];
+    dp2[i] = sp[i];
+  }
+  for (uint32_t r = 0; r < cnt; ++r) {
+    dn[f0 + r] = sn[f0 + r];
+    if (dn2) dn2[f0 + r] = sn[f0 + r];
+  }
+}
+
+// Output functionals of the iterate (Sec. 2.5: linear functionals of the
+// state): Li inventories per phase and the plated layer, and the sum over
+// cathode collector faces of the extrapolated collector potential.
+__global__ void __launch_bounds__(kBlock) k_outputs(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  CellDev* cdp = cells + bb.x;
+  const CellDev& cd = *cdp;
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i < cd.N) {
+    const uint32_t mi = cd.meta[i];
+    const int L = lab_of(mi);
+    v[L] = cd.c[i] * cd.Vol;
+    if (L == ANODE) {
+      const uint32_t cnt = __popc(mask_of(mi));
+      double s = 0.0;
+      for (uint32_t r = 0; r < cnt; ++r) s += cd.n[base_of(mi) + r];
+      v[3] = s * cd.A;
+    }
+    const int z = i / (cd.nx * cd.ny);
+    if (L == CATHODE && z == cd.nz - 1) {
+      const double jout = -cd.I_app / (cd.n_top * cd.A);
+      v[4] = cd.phi[i] - jout * cd.h / (2.0 * cd.sigma[1]);
+    }
+  }
+  reduce_cell<5>(cdp, bb.y, v, 0u, cd.red + RED_INV0);
+}
+
+// Conversions between the raw FP64 scratch pair (dc, dp: 2N contiguous
+// doubles) and a Krylov vector: dir 0 doubles -> KT vector, 1 KT -> doubles.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_convert(CellDev* cells, const int2* __restrict__ blk, int sel, int dir) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const size_t N = cd.N;
+  KT* v = vec<KT>(cd, sel);
+  if (dir == 0) {
+    v[i] = (KT)cd.dc[i];
+    v[N + i] = (KT)cd.dp[i];
+  } else {
+    cd.dc[i] = (double)v[i];
+    cd.dp[i] = (double)v[N + i];
+  }
+}
+
+// --------------------------------------------------------------- launchers
+static inline dim3 grid_of(int nblk) { return dim3((unsigned)nblk); }
+
+void launch_build_meta(const uint8_t* lab, int nx, int ny, int nz, uint32_t* meta, int* cnt_an, int* cnt_ca,
+                       int* flags, hipStream_t s) {
+  const int N = nx * ny * nz;
+  k_build_meta<<<(N + kBlock - 1) / kBlock, kBlock, 0, s>>>(lab, nx, ny, nz, meta, cnt_an, cnt_ca, flags);
+}
+void launch_finish_meta(int N, uint32_t* meta, const int* off_an, const int* off_ca, int* faces_an, int* faces_ca,
+                        hipStream_t s) {
+  k_finish_meta<<<(N + kBlock - 1) / kBlock, kBlock, 0, s>>>(N, meta, off_an, off_ca, faces_an, faces_ca);
+}
+hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* out, int n, hipStream_t s) {
+  return hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, in, out, n, s);
+}
+void launch_init_state(const BatchLaunch& b, hipStream_t s) {
+  k_init_state<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+
+template <typename KT>
+void launch_residual(const BatchLaunch& b, bool lin, hipStream_t s) {
+  if (lin)
+    k_residual<true, KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+  else
+    k_residual<false, KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+template <typename KT>
+void launch_rhs(const BatchLaunch& b, hipStream_t s) {
+  k_rhs<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+template <typename KT>
+void launch_jacobi(const BatchLaunch& b, int src, int dst, int need, hipStream_t s) {
+  k_jacobi<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need);
+}
+template <typename KT>
+void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t s) {
+  k_matvec<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need);
+}
+template <typename KT>
+void launch_multidot(const BatchLaunch& b, int k, int tgt, hipStream_t s) {
+  k_multidot<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, k, tgt);
+}
+template <typename KT>
+void launch_orth(const BatchLaunch& b, int k, int src, hipStream_t s) {
+  k_orth<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, k, src);
+}
+template <typename KT>
+void launch_scale_next(const BatchLaunch& b, int k, hipStream_t s) {
+  k_scale_next<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, k);
+}
+void launch_givens(const BatchLaunch& b, int k, hipStream_t s) {
+  k_givens<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell, k);
+}
+void launch_backsolve(const BatchLaunch& b, hipStream_t s) {
+  k_backsolve<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell);
+}
+template <typename KT>
+void launch_combine(const BatchLaunch& b, hipStream_t s) {
+  k_combine<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+template <typename KT>
+void launch_update_x_jacobi(const BatchLaunch& b, hipStream_t s) {
+  k_update_x_jacobi<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+template <typename KT>
+void launch_add_z_to_x(const BatchLaunch& b, hipStream_t s) {
+  k_add_z_to_x<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+template <typename KT>
+void launch_true_residual(const BatchLaunch& b, hipStream_t s) {
+  k_true_residual<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+template <typename KT>
+void launch_gm_start(const BatchLaunch& b, int first, hipStream_t s) {
+  k_gm_start<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, first);
+}
+void launch_gm_flags(const BatchLaunch& b, int first, hipStream_t s) {
+  k_gm_flags<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell, first);
+}
+void launch_gather_ctl(const BatchLaunch& b, double* out, hipStream_t s) {
+  k_gather_ctl<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell, out);
+}
+template <typename KT>
+void launch_convert(const BatchLaunch& b, int sel, int dir, hipStream_t s) {
+  k_convert<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, sel, dir);
+}
+template <typename KT>
+void launch_direction(const BatchLaunch& b, hipStream_t s) {
+  k_direction<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+void launch_trial(const BatchLaunch& b, hipStream_t s) { k_trial<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk); }
+void launch_copy_state(const BatchLaunch& b, int mode, hipStream_t s) {
+  k_copy_state<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, mode);
+}
+void launch_outputs(const BatchLaunch& b, hipStream_t s) {
+  k_outputs<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+
+#define MBX_INST(KT)                                                             \
+  template void launch_residual<KT>(const BatchLaunch&, bool, hipStream_t);      \
+  template void launch_rhs<KT>(const BatchLaunch&, hipStream_t);                 \
+  template void launch_jacobi<KT>(const BatchLaunch&, int, int, int, hipStream_t);  \
+  template void launch_matvec<KT>(const BatchLaunch&, int, int, int, hipStream_t);  \
+  template void launch_convert<KT>(const BatchLaunch&, int, int, hipStream_t);      \
+  template void launch_multidot<KT>(const BatchLaunch&, int, int, hipStream_t);  \
+  template void launch_orth<KT>(const BatchLaunch&, int, int, hipStream_t);      \
+  template void launch_scale_next<KT>(const BatchLaunch&, int, hipStream_t);     \
+  template void launch_combine<KT>(const BatchLaunch&, hipStream_t);             \
+  template void launch_update_x_jacobi<KT>(const BatchLaunch&, hipStream_t);     \
+  template void launch_add_z_to_x<KT>(const BatchLaunch&, hipStream_t);          \
+  template void launch_true_residual<KT>(const BatchLaunch&, hipStream_t);       \
+  template void launch_gm_start<KT>(const BatchLaunch&, int, hipStream_t);       \
+  template void launch_direction<KT>(const BatchLaunch&, hipStream_t);
+MBX_INST(float)
+MBX_INST(double)
+#undef MBX_INST
+
+}  // namespace mbx

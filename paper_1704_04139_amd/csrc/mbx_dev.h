@@ -1,0 +1,195 @@
+// mbx_dev.h — device-side data layout and pointwise laws of the cell model.
+//
+// Layout in HBM (per cell, structure of arrays, voxel flat index
+// i + nx*(j + ny*k)):
+//   meta[N]   uint32: bits 0-1 label (0 pore, 1 anode, 2 cathode), bits 2-7
+//             interface mask (bit d set when the neighbour in direction d is
+//             of the other kind: pore<->solid), bits 8-31 the voxel's first
+//             interface-face index in its phase's face list (solid voxels).
+//   c, phi    double[N] state; n double[F_an] plated amount per anode face.
+//   face coefficient arrays (per phase, canonical face order), per-voxel
+//   pore coefficient and 2x2 inverse diagonal blocks in the Krylov type KT.
+//   Krylov vectors: 2N entries, [0,N) concentration rows/unknowns, [N,2N)
+//   potential rows/unknowns, in scaled (dimensionless) units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbx {
+
+constexpr double kFaraday = 96485.33212;   // C/mol
+constexpr double kGasR = 8.314462618;      // J/(mol K)
+constexpr int kBlock = 256;                // threads per voxel block (4 wavefronts)
+constexpr int kMaxRestart = 40;            // GMRES restart length bound
+constexpr int kPartStride = kMaxRestart + 2;
+
+enum { PORE = 0, ANODE = 1, CATHODE = 2 };
+
+__host__ __device__ inline int lab_of(uint32_t m) { return int(m & 3u); }
+__host__ __device__ inline uint32_t mask_of(uint32_t m) { return (m >> 2) & 63u; }
+__host__ __device__ inline uint32_t base_of(uint32_t m) { return m >> 8; }
+__device__ inline uint32_t face_rank(uint32_t m, int d) {
+  return base_of(m) + (uint32_t)__popc(mask_of(m) & ((1u << d) - 1u));
+}
+
+// Slots of the per-cell reduction output array `red`.
+enum {
+  RED_RSQ = 0,     // sum of squared scaled residual
+  RED_RMAX = 1,    // max |scaled residual|
+  RED_BAD = 2,     // infeasible entries in a trial state
+  RED_DUMAX = 3,   // max |scaled update|
+  RED_BSQ = 4,     // sum of squares of a Krylov vector (rhs / true residual)
+  RED_INV0 = 5,    // inventories: electrolyte, anode, cathode, plated (4 slots)
+  RED_VSUM = 9,    // sum over cathode top voxels of phi
+  RED_TOL = 10,    // GMRES absolute tolerance of the current solve
+  RED_BETA0 = 11,  // norm of the first GMRES residual of the current solve
+  RED_NSLOT = 12
+};
+// Slots of the per-cell device-written integer array `ictl`.
+enum { CTL_DONE = 0, CTL_K = 1, CTL_ITERS = 2, CTL_NSLOT = 4 };
+
+// Per-cell descriptor.  The host keeps a mirror and uploads the array of
+// descriptors of a batch whenever a field changes.
+struct CellDev {
+  int nx, ny, nz, N;
+  int F_an, F_ca, n_top, nblk;
+  int active;         // 0: every kernel skips this cell
+  int pad0;
+  const uint32_t* meta;
+  double *c, *phi, *n;               // Newton iterate
+  double *c_try, *phi_try, *n_try;   // trial state (residual kernels read these)
+  double *c_old, *phi_old, *n_old;   // u^n
+  double *Rc, *Rp, *Rn;              // residual rows at the trial state
+  double *dc, *dp, *dn;              // Newton direction (raw units)
+  double *rn_jnn, *sq;               // per anode face: R^n/J_nn, condensation term
+  void *coef_an, *coef_ca;           // KT: 5 per anode face, 3 per cathode face
+  void *wpore;                       // KT: c0/c on pore voxels
+  void *dinv;                        // KT: 4 per voxel (row-major inverse 2x2 block)
+  void *Vb;                          // KT: (m+1) Krylov basis vectors of 2N
+  void *w, *z, *b, *x;               // KT: 2N each
+  double *part;                      // nblk * kPartStride partial sums
+  unsigned *ticket;                  // one reduction ticket
+  double *red;                       // RED_NSLOT outputs (device-written)
+  int *ictl;                         // CTL_NSLOT flags (device-written)
+  double *gm;                        // GMRES small arrays (see gm_* offsets)
+  // step data (host-written)
+  double dt, lam, rtol;
+  int m;                             // GMRES restart length
+  int pad3;
+  // parameters and derived constants
+  double h, A, Vol, RT, VT, beta;
+  double c0, x0, y0, De, kappa, tplus, thermo;
+  double Ds[2], sigma[2], cmax[2], i00[2], U0[2], U1[2];
+  double i00_pl, n_c, I_app, mu_ref;
+  int plating, pad2;
+  // scaled-operator constants
+  double Kd;                         // kappa (1-t+) theta RT/(F h)
+  double Gk, tth, Dh, tau, Ke, Gcol;
+  double Dsh[2], Gs[2], Ks[2];
+};
+
+// gm layout: H[(m+1)*m] column-major, g[m+1], cs[m], sn[m], y[m], tmp[m+1]
+__host__ __device__ inline int gm_H(int m) { return 0; }
+__host__ __device__ inline int gm_g(int m) { return (m + 1) * m; }
+__host__ __device__ inline int gm_cs(int m) { return (m + 1) * m + (m + 1); }
+__host__ __device__ inline int gm_sn(int m) { return (m + 1) * m + (m + 1) + m; }
+__host__ __device__ inline int gm_y(int m) { return (m + 1) * m + (m + 1) + 2 * m; }
+__host__ __device__ inline int gm_tmp(int m) { return (m + 1) * m + (m + 1) + 3 * m; }
+__host__ __device__ inline int gm_size(int m) { return (m + 1) * m + 2 * (m + 1) + 3 * m; }
+
+// Neighbour of voxel (x,y,z) in direction d, or -1 outside the box.
+__device__ inline int neighbour(const CellDev& cd, int i, int x, int y, int z, int d) {
+  switch (d) {
+    case 0: return x > 0 ? i - 1 : -1;
+    case 1: return x < cd.nx - 1 ? i + 1 : -1;
+    case 2: return y > 0 ? i - cd.nx : -1;
+    case 3: return y < cd.ny - 1 ? i + cd.nx : -1;
+    case 4: return z > 0 ? i - cd.nx * cd.ny : -1;
+    default: return z < cd.nz - 1 ? i + cd.nx * cd.ny : -1;
+  }
+}
+
+// Interface kinetics on one solid/pore face (Sec. 2.2 eq. 2.5, Sec. 2.3
+// eq. 2.8).  Every caller passes the same arguments in the same order, so
+// the two voxels sharing a face evaluate bit-identical currents.
+struct Kin {
+  double ii, ip;                 // intercalation and plating current, A/m^2 (solid -> pore > 0)
+  double d_cs, d_ce, g;          // d ii / d(cs, ce, phi_s); d/dphi_e = -g
+  double p_ce, g_p, p_n;         // d ip / d(ce, phi_s, n); d/dphi_e = -g_p
+};
+
+__device__ inline Kin interface_kinetics(const CellDev& cd, int ph, double cs, double ce, double ps,
+                                         double pe, double nf, bool plate, bool lin) {
+  Kin k;
+  const int s = ph - 1;
+  const double cm = cd.cmax[s];
+  const double xs = cs / cm;
+  const double U = cd.U0[s] + cd.U1[s] * log((1.0 - xs) / xs);
+  const double eta = ps - U - pe;
+  const double sq = sqrt(cs * ce);
+  const double pre = 2.0 * cd.i00[s] * sq;
+  const double be = cd.beta * eta;
+  k.ii = pre * sinh(be);
+  k.ip = 0.0;
+  k.p_ce = k.g_p = k.p_n = 0.0;
+  if (lin) {
+    const double dU = -cd.U1[s] / (xs * (1.0 - xs)) / cm;
+    k.g = pre * cd.beta * cosh(be);
+    k.d_cs = k.ii / (2.0 * cs) - k.g * dU;
+    k.d_ce = k.ii / (2.0 * ce);
+  } else {
+    k.g = k.d_cs = k.d_ce = 0.0;
+  }
+  if (plate) {
+    const double a = cd.beta * (ps - pe);
+    const double ea = exp(a), ema = exp(-a);
+    const double n2 = nf * nf, n4 = n2 * n2;
+    const double nc2 = cd.n_c * cd.n_c, nc4 = nc2 * nc2;
+    const double fp = n4 / (nc4 + n4);
+    const double sqe = sqrt(ce);
+    k.ip = cd.i00_pl * sqe * (fp * ea - ema);
+    if (lin) {
+      const double den = nc4 + n4;
+      const double dfp = 4.0 * n2 * nf * nc4 / (den * den);
+      k.p_ce = k.ip / (2.0 * ce);
+      k.g_p = cd.i00_pl * sqe * cd.beta * (fp * ea + ema);
+      k.p_n = cd.i00_pl * sqe * ea * dfp;
+    }
+  }
+  return k;
+}
+
+// ---------------------------------------------------------------- reductions
+// Block-wide sum / max of one double over 256 threads (4 wavefronts of 64):
+// wavefront shuffle tree, then the four wave results in fixed order.
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+// Result valid in thread 0.
+__device__ inline double block_sum(double v, double* lds4) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds4[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+  return r;
+}
+__device__ inline double block_max(double v, double* lds4) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds4[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = fmax(fmax(lds4[0], lds4[1]), fmax(lds4[2], lds4[3]));
+  return r;
+}
+
+}  // namespace mbx

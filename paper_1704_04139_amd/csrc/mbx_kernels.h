@@ -1,0 +1,52 @@
+// mbx_kernels.h — host-side launchers of the kernels in kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mbx_dev.h"
+
+namespace mbx {
+
+// Krylov vector selectors (>= 0: basis vector j).
+enum { VEC_Z = -1, VEC_W = -2, VEC_B = -3, VEC_X = -4 };
+
+// One launch over a batch: device descriptor array and block table
+// (blk[b] = {cell index, block index within the cell}).
+struct BatchLaunch {
+  CellDev* cells;
+  const int2* blk;
+  int nblk;
+  int ncell;
+};
+
+void launch_build_meta(const uint8_t* lab, int nx, int ny, int nz, uint32_t* meta, int* cnt_an, int* cnt_ca,
+                       int* flags, hipStream_t s);
+void launch_finish_meta(int N, uint32_t* meta, const int* off_an, const int* off_ca, int* faces_an, int* faces_ca,
+                        hipStream_t s);
+void launch_init_state(const BatchLaunch& b, hipStream_t s);
+// hipCUB exclusive prefix sum (temp == nullptr: query temp_bytes)
+hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* out, int n, hipStream_t s);
+
+template <typename KT> void launch_residual(const BatchLaunch& b, bool lin, hipStream_t s);
+template <typename KT> void launch_rhs(const BatchLaunch& b, hipStream_t s);
+template <typename KT> void launch_jacobi(const BatchLaunch& b, int src, int dst, int need, hipStream_t s);
+template <typename KT> void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t s);
+template <typename KT> void launch_convert(const BatchLaunch& b, int sel, int dir, hipStream_t s);
+template <typename KT> void launch_multidot(const BatchLaunch& b, int k, int tgt, hipStream_t s);
+template <typename KT> void launch_orth(const BatchLaunch& b, int k, int src, hipStream_t s);
+template <typename KT> void launch_scale_next(const BatchLaunch& b, int k, hipStream_t s);
+void launch_givens(const BatchLaunch& b, int k, hipStream_t s);
+void launch_backsolve(const BatchLaunch& b, hipStream_t s);
+template <typename KT> void launch_combine(const BatchLaunch& b, hipStream_t s);
+template <typename KT> void launch_update_x_jacobi(const BatchLaunch& b, hipStream_t s);
+template <typename KT> void launch_add_z_to_x(const BatchLaunch& b, hipStream_t s);
+template <typename KT> void launch_true_residual(const BatchLaunch& b, hipStream_t s);
+template <typename KT> void launch_gm_start(const BatchLaunch& b, int first, hipStream_t s);
+void launch_gm_flags(const BatchLaunch& b, int first, hipStream_t s);
+void launch_gather_ctl(const BatchLaunch& b, double* out, hipStream_t s);
+template <typename KT> void launch_direction(const BatchLaunch& b, hipStream_t s);
+void launch_trial(const BatchLaunch& b, hipStream_t s);
+void launch_copy_state(const BatchLaunch& b, int mode, hipStream_t s);
+void launch_outputs(const BatchLaunch& b, hipStream_t s);
+
+}  // namespace mbx

@@ -1,0 +1,231 @@
+"""Python binding of the C ABI in include/mbx.h (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library libmbx.so built in this package
+directory.  Loading fails loudly when the library is missing: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbx.so")
+
+MBX_OK, MBX_EINVAL, MBX_ELABEL, MBX_ENEWTON, MBX_ENAN, MBX_ENOMEM, MBX_EBUDGET, MBX_EHIP, MBX_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+MBX_FP64, MBX_MIXED = 0, 1
+ERR_NAMES = {0: "MBX_OK", -1: "MBX_EINVAL", -2: "MBX_ELABEL", -3: "MBX_ENEWTON", -4: "MBX_ENAN",
+             -5: "MBX_ENOMEM", -6: "MBX_EBUDGET", -7: "MBX_EHIP", -8: "MBX_ESTATE"}
+
+_d = ctypes.c_double
+_i = ctypes.c_int
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("T", _d), ("I_app", _d), ("h", _d), ("c0", _d), ("x0", _d), ("y0", _d),
+                ("De", _d), ("kappa", _d), ("tplus", _d), ("thermo", _d),
+                ("Ds", _d * 2), ("sigma", _d * 2), ("cmax", _d * 2), ("i00", _d * 2),
+                ("U0", _d * 2), ("U1", _d * 2), ("i00_pl", _d), ("n_c", _d),
+                ("plating", _i), ("precision", _i), ("newton_tol", _d), ("res_tol", _d),
+                ("krylov_rtol", _d), ("newton_max", _i), ("krylov_max", _i)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("newton_iters", _i), ("krylov_iters", _i), ("res0", _d), ("res_final", _d),
+                ("du_final", _d), ("V", _d), ("wall_s", _d)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MbxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# exported entry points: name -> (restype, argtypes)
+SIGNATURES = {
+    "mbx_params_default": (_i, [ctypes.POINTER(Params)]),
+    "mbx_cell_create": (_i, [_vp, _i, _i, _i, ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)]),
+    "mbx_cell_destroy": (None, [_vp]),
+    "mbx_cell_step": (_i, [_vp, _d, ctypes.POINTER(StepInfo)]),
+    "mbx_cell_set_current": (_i, [_vp, _d]),
+    "mbx_cell_counts": (_i, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "mbx_cell_get_state": (_i, [_vp, _vp, _vp, _vp, _i]),
+    "mbx_cell_set_state": (_i, [_vp, _vp, _vp, _vp, _i]),
+    "mbx_cell_voltage": (_i, [_vp, _dp]),
+    "mbx_cell_inventory": (_i, [_vp, _dp]),
+    "mbx_cell_residual": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp]),
+    "mbx_cell_jvp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]),
+    "mbx_batch_step": (_i, [ctypes.POINTER(_vp), _i, _d, ctypes.POINTER(_i), ctypes.POINTER(StepInfo)]),
+    "mbx_cell_footprint": (ctypes.c_int64, [_i, _i, _i, _i, _i, _i]),
+    "mbx_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libmbx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: run python -m paper_1704_04139_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != MBX_OK:
+        raise MbxError(code, load().mbx_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_vp)
+
+
+def make_params(cp, precision: str = "fp64", **knobs) -> Params:
+    """Params from an inputs.CellParams (physical values) plus solver knobs."""
+    lib = load()
+    p = Params()
+    _check(lib.mbx_params_default(ctypes.byref(p)))
+    p.T, p.I_app, p.h, p.c0, p.x0, p.y0 = cp.T, cp.I_app, cp.h, cp.c0, cp.x0, cp.y0
+    p.De, p.kappa, p.tplus, p.thermo = cp.De, cp.kappa, cp.tplus, cp.thermo
+    p.Ds[0], p.Ds[1] = cp.Ds_an, cp.Ds_ca
+    p.sigma[0], p.sigma[1] = cp.sigma_an, cp.sigma_ca
+    p.cmax[0], p.cmax[1] = cp.cmax_an, cp.cmax_ca
+    p.i00[0], p.i00[1] = cp.i00_an, cp.i00_ca
+    p.U0[0], p.U1[0] = cp.U_an
+    p.U0[1], p.U1[1] = cp.U_ca
+    p.i00_pl, p.n_c, p.plating = cp.i00_pl, cp.n_c, int(cp.plating)
+    p.precision = MBX_MIXED if precision == "mixed" else MBX_FP64
+    for k, v in knobs.items():
+        setattr(p, k, v)
+    return p
+
+
+@dataclass
+class Counts:
+    n_vox: int
+    n_an_faces: int
+    n_ca_faces: int
+    n_top: int
+
+
+class Cell:
+    """One cell on the GPU (owns its device memory)."""
+
+    def __init__(self, labels: np.ndarray, params, precision: str = "fp64", stream=None, **knobs):
+        lib = load()
+        lab = np.ascontiguousarray(labels, dtype=np.uint8)
+        nz, ny, nx = lab.shape
+        self.shape = (nx, ny, nz)
+        self.params = params if isinstance(params, Params) else make_params(params, precision, **knobs)
+        h = _vp()
+        s = _vp(stream) if stream else None
+        _check(lib.mbx_cell_create(_ptr(lab), nx, ny, nz, ctypes.byref(self.params), s, ctypes.byref(h)))
+        self._h = h
+        self.counts = self._counts()
+
+    def _counts(self) -> Counts:
+        a, b, c, d = (ctypes.c_int64() for _ in range(4))
+        _check(load().mbx_cell_counts(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        return Counts(a.value, b.value, c.value, d.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().mbx_cell_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, dt: float) -> dict:
+        info = StepInfo()
+        _check(load().mbx_cell_step(self._h, float(dt), ctypes.byref(info)))
+        return info.as_dict()
+
+    def try_step(self, dt: float):
+        """Step without raising: returns (code, info dict)."""
+        info = StepInfo()
+        code = load().mbx_cell_step(self._h, float(dt), ctypes.byref(info))
+        return code, info.as_dict()
+
+    def set_current(self, I_app: float):
+        _check(load().mbx_cell_set_current(self._h, float(I_app)))
+
+    def get_state(self):
+        c = np.empty(self.counts.n_vox)
+        p = np.empty(self.counts.n_vox)
+        n = np.empty(self.counts.n_an_faces)
+        _check(load().mbx_cell_get_state(self._h, _ptr(c), _ptr(p), _ptr(n), 0))
+        return c, p, n
+
+    def get_state_device(self, c_ptr: int, p_ptr: int, n_ptr: int):
+        _check(load().mbx_cell_get_state(self._h, _vp(c_ptr), _vp(p_ptr), _vp(n_ptr), 1))
+
+    def set_state(self, c, p, n):
+        c, p, n = (np.ascontiguousarray(a, dtype=np.float64) for a in (c, p, n))
+        _check(load().mbx_cell_set_state(self._h, _ptr(c), _ptr(p), _ptr(n), 0))
+
+    def voltage(self) -> float:
+        v = ctypes.c_double()
+        _check(load().mbx_cell_voltage(self._h, ctypes.byref(v)))
+        return v.value
+
+    def inventory(self):
+        out = (ctypes.c_double * 4)()
+        _check(load().mbx_cell_inventory(self._h, out))
+        return {"electrolyte": out[0], "anode": out[1], "cathode": out[2], "plated": out[3]}
+
+    def residual(self, c, p, n, c_old, n_old, dt):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (c, p, n, c_old, n_old)]
+        Rc = np.empty(self.counts.n_vox)
+        Rp = np.empty(self.counts.n_vox)
+        Rn = np.empty(self.counts.n_an_faces)
+        _check(load().mbx_cell_residual(self._h, *[_ptr(a) for a in arrs], float(dt), _ptr(Rc), _ptr(Rp), _ptr(Rn)))
+        return Rc, Rp, Rn
+
+    def jvp(self, c, p, n, c_old, n_old, dt, v):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (c, p, n, c_old, n_old)]
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        y = np.empty(2 * self.counts.n_vox)
+        _check(load().mbx_cell_jvp(self._h, *[_ptr(a) for a in arrs], float(dt), _ptr(v), _ptr(y)))
+        return y
+
+
+def batch_step(cells, dt: float):
+    """Step several cells in shared launches; returns (status list, info dicts)."""
+    lib = load()
+    n = len(cells)
+    hs = (_vp * n)(*[c.handle.value for c in cells])
+    st = (_i * n)()
+    infos = (StepInfo * n)()
+    _check(lib.mbx_batch_step(hs, n, float(dt), st, infos))
+    return list(st), [infos[k].as_dict() for k in range(n)]
+
+
+def footprint(nx, ny, nz, precision="fp64", n_an_faces=0, n_ca_faces=0) -> int:
+    return int(load().mbx_cell_footprint(nx, ny, nz, MBX_MIXED if precision == "mixed" else MBX_FP64,
+                                         n_an_faces, n_ca_faces))

@@ -1,0 +1,52 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point that include/mbx.h declares, and the binding knows them."""
+import os
+import re
+
+import pytest
+
+from paper_1704_04139_amd import mbx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(mbx_[a-z_0-9]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mbx.load()
+    decl = declared_functions()
+    assert len(decl) >= 15
+    for name in sorted(decl):
+        assert hasattr(lib, name), name
+        assert name in mbx.SIGNATURES, name
+
+
+def test_params_default_and_footprint():
+    import ctypes
+    lib = mbx.load()
+    p = mbx.Params()
+    assert lib.mbx_params_default(ctypes.byref(p)) == 0
+    assert p.newton_tol == 1e-9 and p.newton_max == 30 and p.thermo == 1.0
+    assert lib.mbx_params_default(None) == mbx.MBX_EINVAL
+    f64 = mbx.footprint(64, 64, 160, "fp64", 90000, 90000)
+    f32 = mbx.footprint(64, 64, 160, "mixed", 90000, 90000)
+    assert 0 < f32 < f64 < 2e9
+    assert mbx.footprint(0, 4, 4) == -1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(RuntimeError):
+        mbx._lib, saved = None, mbx._lib
+        try:
+            mbx.load(str(tmp_path / "nope.so"))
+        finally:
+            mbx._lib = saved

@@ -1,0 +1,67 @@
+"""The seeded workload generator: determinism, connectivity rules, C-rate."""
+import numpy as np
+import scipy.ndimage as ndi
+
+from paper_1704_04139_amd import inputs as I
+
+
+def test_stream_is_deterministic_and_keyed():
+    a = I.Stream(5, 1).uniform(100)
+    b = I.Stream(5, 1).uniform(100)
+    c = I.Stream(5, 2).uniform(100)
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, c)
+    assert 0.0 <= a.min() and a.max() < 1.0
+    assert abs(a.mean() - 0.5) < 0.1
+    # counter-based: the k-th draw does not depend on how the draws are chunked
+    s = I.Stream(9, 3)
+    chunks = np.concatenate([s.uniform(7), s.uniform(13)])
+    assert np.array_equal(chunks, I.Stream(9, 3).uniform(20))
+
+
+def test_sphere_cell_rules():
+    lab = I.sphere_cell(24, 20, 60, 7, 2.0, 4.0, 0.35, 0.30)
+    nz = lab.shape[0]
+    a, s = int(round(0.4 * nz)), int(round(0.2 * nz))
+    assert np.all(lab[a:a + s] == I.PORE)                  # separator all pore
+    assert np.all(lab[:a] != I.CATHODE) and np.all(lab[a + s:] != I.ANODE)
+    assert np.any(lab[0] == I.ANODE) and np.any(lab[-1] == I.CATHODE)
+    st = ndi.generate_binary_structure(3, 1)
+    for ph, plane in ((I.ANODE, 0), (I.CATHODE, nz - 1)):
+        comp, n = ndi.label(lab == ph, structure=st)
+        on_plane = set(np.unique(comp[plane])) - {0}
+        assert set(range(1, n + 1)) == on_plane            # every solid cluster reaches its collector
+    comp, n = ndi.label(lab == I.PORE, structure=st)
+    assert n == 1                                          # no closed pores
+    por = np.mean(lab[:a] == I.PORE)
+    assert 0.2 < por < 0.45
+    assert np.array_equal(lab, I.sphere_cell(24, 20, 60, 7, 2.0, 4.0, 0.35, 0.30))
+
+
+def test_config0_and_crate():
+    w = I.config0()
+    assert w.labels.shape == (40, 12, 12)
+    assert w.steps == 20 and w.dt == 10.0
+    p = w.params
+    cap = min(np.sum(w.labels == 1), np.sum(w.labels == 2)) * p.h ** 3 * p.cmax_an * I.FARADAY_FOR_CRATE
+    assert abs(p.I_app - cap / 3600.0) < 1e-12 * p.I_app
+
+
+def test_paper_capacity_convention():
+    """Sec. 3.3: a 49 nAh electrode; 250 A/m^2 on (44 um)^2 is 484 nA, i.e. ~10C."""
+    I_max = 250.0 * (44e-6) ** 2
+    one_c = 49e-9            # A for 49 nAh over one hour
+    assert abs(I_max / one_c - 10.0) < 0.2
+
+
+def test_sampled_queries_ranges():
+    qs = I.config3(n_cells=6, scale=1)
+    for q in qs:
+        nx, ny, nz = q.shape
+        assert 32 <= nx <= 96 and nx % 8 == 0 and ny == nx and nz == int(round(2.5 * nx))
+        assert 268.0 <= q.params.T <= 308.0
+        assert 1e-4 <= q.params.i00_pl <= 1.0
+        assert 0.5 <= q.meta["crate"] <= 4.0
+    t = I.poisson_arrivals(20.0, 2000)
+    assert np.all(np.diff(t) > 0)
+    assert abs(len(t) / t[-1] - 20.0) < 2.0
