@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Throughput of the full-order implicit cell step on one MI355X.
+
+A step is one implicit Euler step (eq. 2.13) of the 64 x 64 x 160 full cell
+(anode 64 / separator 32 / cathode 64 layers, overlapping-sphere electrodes
+with radius 3-6 voxels and porosity drawn in [0.30, 0.40], 2C charge, dt = 5 s,
+plating on): FP64 residual, Newton, multigrid-preconditioned GMRES, line
+search, outputs.  The metric is DOF x steps / s with DOF = 2 x voxels.
+Inputs are resident in HBM before the timed region; timing brackets exactly
+--steps steps with a device synchronisation on both sides.
+
+Prints one JSON line.  Extra objects: `fp64` (the plain FP64 path on the same
+workload), `roofline` (the dominant kernel's algorithmic bytes per launch over
+its event-timed average launch duration), `cpu_baseline` (the CPU oracle on
+a bounded down-scaled sample of the same workload).
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILED_KERNEL = "smooth0"     # the kernel class with the largest share of GPU time
+
+
+def run_gpu(w, precision, steps, warmup, stream):
+    import torch
+    from paper_1704_04139_amd import mbx
+    cell = mbx.Cell(w.labels, w.params, precision=precision, stream=stream)
+    for _ in range(warmup):
+        cell.step(w.dt)
+    torch.cuda.synchronize()
+    mbx.profile(PROFILED_KERNEL)
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos.append(cell.step(w.dt))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, ms, nbytes = mbx.profile_read()
+    mbx.profile(None)
+    counts = cell.counts
+    cell.close()
+    wall = t1 - t0
+    dof = 2 * counts.n_vox
+    return {
+        "value": dof * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "newton_per_step": sum(i["newton_iters"] for i in infos) / steps,
+        "krylov_per_step": sum(i["krylov_iters"] for i in infos) / steps,
+        "V_end": infos[-1]["V"],
+        "kernel": {"launches": launches, "ms": ms, "bytes": nbytes},
+        "counts": counts,
+    }
+
+
+CPU_SNIPPET = r"""
+import json, sys, time
+sys.path.insert(0, {root!r})
+import oracle
+from paper_1704_04139_amd import inputs as I
+w = I.config1(seed=1, scale=4)
+model = oracle.Model(oracle.Geometry(w.labels), w.params.as_dict())
+u = model.initial_state()
+u, _ = oracle.newton_step(model, u, w.dt)            # first step from equilibrium, untimed
+t0 = time.perf_counter()
+n = 0
+while n < 2:
+    u, _ = oracle.newton_step(model, u, w.dt)
+    n += 1
+t = time.perf_counter() - t0
+print(json.dumps({{"voxels": model.N, "steps": n, "seconds": t, "shape": list(w.labels.shape)}}))
+"""
+
+
+def cpu_baseline():
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", CPU_SNIPPET.format(root=ROOT)], capture_output=True, text=True,
+                       env=env, timeout=600)
+    if r.returncode != 0:
+        return {"value": None, "error": r.stderr[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    nz, ny, nx = d["shape"]
+    cpu = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": 2 * d["voxels"] * d["steps"] / d["seconds"], "unit": "DOF*steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{nx}x{ny}x{nz} copy of the 64x64x160 recipe (same generator, 2C, dt 5 s), "
+                      f"steps 2-3 after the first step, {d['seconds']:.1f} s, SuperLU Newton, 1 thread",
+            "host_cpu": cpu, "host_nproc": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["mixed", "fp64", "both"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); independent cells shard across GPUs "
+              "without communication, which this benchmark does not launch.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1704_04139_amd import inputs as I
+    from paper_1704_04139_amd import mbx
+    mbx.load()
+    torch.cuda.init()
+    stream = torch.cuda.current_stream().cuda_stream
+    w = I.config1()
+    print(f"[bench] workload {w.name}, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
+    res = {}
+    for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
+        res[prec] = run_gpu(w, prec, args.steps, args.warmup, stream)
+        print(f"[bench] {prec}: {res[prec]['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    main_prec = "mixed" if "mixed" in res else "fp64"
+    r = res[main_prec]
+    k = r["kernel"]
+    achieved = (k["bytes"] / k["launches"]) / (k["ms"] / k["launches"] * 1e-3) / 1e9 if k["launches"] else None
+    counts = r["counts"]
+    line = {
+        "metric": "DOF*timesteps/s",
+        "value": r["value"],
+        "unit": "DOF*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32" if main_prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "full cell 64x64x160 (anode 64 / separator 32 / cathode 64), 2C charge, dt 5 s, "
+                               "plating on",
+                   "voxels": counts.n_vox, "dof": 2 * counts.n_vox, "anode_faces": counts.n_an_faces,
+                   "cathode_faces": counts.n_ca_faces, "precision": main_prec, "parallelism": "1 GPU"},
+        "newton_per_step": r["newton_per_step"],
+        "krylov_per_step": r["krylov_per_step"],
+        "roofline": {"bound": "hbm", "kernel": PROFILED_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "launches": k["launches"], "avg_us": 1e3 * k["ms"] / max(k["launches"], 1),
+                     "bytes_per_launch": k["bytes"] / max(k["launches"], 1)},
+    }
+    if "fp64" in res and main_prec != "fp64":
+        f = res["fp64"]
+        line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "newton_per_step": f["newton_per_step"],
+                        "krylov_per_step": f["krylov_per_step"]}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, 1 thread)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -84,7 +84,7 @@ typedef struct {
   int precision;         /* MBX_FP64 or MBX_MIXED */
   double newton_tol;     /* scaled update tolerance (default 1e-9 if <= 0) */
   double res_tol;        /* scaled residual tolerance (default 1e-6 if <= 0) */
-  double krylov_rtol;    /* GMRES relative tolerance floor (default 1e-8 if <= 0) */
+  double krylov_rtol;    /* floor of the GMRES relative tolerance (forcing term) (default 1e-6 if <= 0) */
   int newton_max;        /* Newton iteration cap (default 30 if <= 0) */
   int krylov_max;        /* GMRES iteration cap per Newton iteration (default 2000 if <= 0) */
 } mbx_params;
@@ -183,6 +183,23 @@ int mbx_cell_residual(mbx_cell *c, const double *c_u, const double *phi_u, const
 int mbx_cell_jvp(mbx_cell *c, const double *c_u, const double *phi_u, const double *n_u,
                  const double *c_old, const double *n_old, double dt, const double *v, double *y);
 
+/* Applies the solver's preconditioner M^-1 ~ J_hat^-1 (same operator as in
+ * mbx_cell_jvp, linearised at u with u_old and dt) to v (host, 2N doubles);
+ * writes z (host, 2N doubles).  In the cell's precision mode.  Does not
+ * change the cell's state.  Used to check the preconditioner. */
+int mbx_cell_precond(mbx_cell *c, const double *c_u, const double *phi_u, const double *n_u,
+                     const double *c_old, const double *n_old, double dt, const double *v, double *z);
+
+/* Solves J_hat x = rhs (operator of mbx_cell_jvp at u, u_old, dt) with the
+ * solver's preconditioned GMRES to relative residual rtol; rhs and x are
+ * host arrays of 2N doubles; *iters (may be null) receives the GMRES
+ * iteration count.  In the cell's precision mode; the cell's state is not
+ * changed.  This is the linear-solve service an outer Newton or
+ * model-reduction driver would call. */
+int mbx_cell_solve(mbx_cell *c, const double *c_u, const double *phi_u, const double *n_u,
+                   const double *c_old, const double *n_old, double dt, const double *rhs, double rtol,
+                   double *x, int *iters);
+
 /* Batched stepping: advance n cells (all of one precision mode) by one step
  * of dt each, sharing every kernel launch across the cells.  status_out[i]
  * receives each cell's own result code (as mbx_cell_step); the function
@@ -190,6 +207,19 @@ int mbx_cell_jvp(mbx_cell *c, const double *c_u, const double *phi_u, const doub
  * or an error for invalid arguments.  infos may be null. */
 int mbx_batch_step(mbx_cell *const *cells, int n, double dt, int *status_out,
                    mbx_step_info *infos);
+
+/* Kernel timing for measurement: after mbx_profile(k), every launch of
+ * kernel class k (1 FP64 residual + linearisation, 2 matrix-free J*v,
+ * 3 level-0 multigrid smoothing half-sweep, 4 whole preconditioner
+ * application; 0 stops timing) is bracketed by a pair of HIP events recorded
+ * on the stream it runs on, together with the launch's algorithmic bytes
+ * (every array element the operation must read or write, counted once).
+ * mbx_profile clears earlier records.  mbx_profile_read waits for the
+ * recorded events and returns the number of timed launches, their summed
+ * duration (ms) and summed algorithmic bytes.  Timing adds two event
+ * records per launch; it is not meant to be left on in production. */
+int mbx_profile(int kernel);
+int mbx_profile_read(int64_t *launches, double *total_ms, double *total_bytes);
 
 /* Device bytes a cell of this size would allocate (for admission control). */
 int64_t mbx_cell_footprint(int nx, int ny, int nz, int precision, int n_an_faces, int n_ca_faces);

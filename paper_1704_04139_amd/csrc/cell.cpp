@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -43,13 +44,26 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int kRestart = 30;
+constexpr double kStepLimit = 4.0;   // largest scaled Newton update taken in one iteration
+
+bool g_verbose() {
+  static int v = -1;
+  if (v < 0) v = std::getenv("MBX_VERBOSE") ? 1 : 0;
+  return v == 1;
+}
+
+// Coarse-correction scale of the multigrid V-cycle (MBX_MG_ALPHA overrides).
+double g_mg_alpha() {
+  const char* e = std::getenv("MBX_MG_ALPHA");
+  return e ? std::atof(e) : 1.8;
+}
 constexpr int kGather = RED_NSLOT + CTL_NSLOT;
 uint64_t g_next_id = 1;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t off[64];
+  size_t off[128];
   int n = 0;
   size_t total = 0;
   size_t add(size_t bytes) {
@@ -59,6 +73,32 @@ struct Layout {
     return o;
   }
 };
+
+struct LevelDims {
+  int n = 0;                       // number of levels incl. the voxel level
+  int nx[kMaxLevels], ny[kMaxLevels], nz[kMaxLevels], ncell[kMaxLevels];
+};
+
+// Ceil-halving hierarchy down to at most kCoarseMaxCells coarse cells (at
+// least one coarse level).
+LevelDims level_dims(int nx, int ny, int nz) {
+  LevelDims d;
+  d.nx[0] = nx;
+  d.ny[0] = ny;
+  d.nz[0] = nz;
+  d.ncell[0] = nx * ny * nz;
+  d.n = 1;
+  while (d.n < kMaxLevels) {
+    const int l = d.n;
+    d.nx[l] = (d.nx[l - 1] + 1) / 2;
+    d.ny[l] = (d.ny[l - 1] + 1) / 2;
+    d.nz[l] = (d.nz[l - 1] + 1) / 2;
+    d.ncell[l] = d.nx[l] * d.ny[l] * d.nz[l];
+    d.n++;
+    if (d.ncell[l] <= kCoarseMaxCells) break;
+  }
+  return d;
+}
 
 }  // namespace
 
@@ -77,13 +117,16 @@ struct mbx_cell {
   CellDev* h_desc_pinned = nullptr;
   int* faces_an = nullptr;
   int* faces_ca = nullptr;
+  LevelDims ld;
+  int2* lvl_blk[kMaxLevels] = {};
+  int lvl_nblk[kMaxLevels] = {};
 };
 
 namespace {
 
 size_t kt_size(int precision) { return precision == MBX_MIXED ? sizeof(float) : sizeof(double); }
 
-Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt) {
+Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const LevelDims& ld) {
   Layout L;
   L.add(4 * (size_t)N);                       // 0 meta
   for (int k = 0; k < 8; ++k) L.add(8 * (size_t)N);   // 1..8 c phi c_try phi_try c_old phi_old Rc Rp
@@ -105,6 +148,20 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt) {
   L.add(sizeof(CellDev));                     // 33 desc
   L.add(sizeof(int2) * (size_t)nblk);         // 34 blk
   L.add(8 * kGather);                         // 35 gather
+  L.add(kt * (size_t)N);                      // 36 b0
+  L.add(kt * std::max(F_an, 1));              // 37 cond_an
+  L.add(kt * std::max(F_ca, 1));              // 38 cond_ca
+  const int nc = ld.ncell[ld.n - 1];
+  L.add(8 * (size_t)9 * nc * nc);             // 39 cinv[0]
+  L.add(8 * (size_t)9 * nc * nc);             // 40 cinv[1]
+  for (int l = 1; l < ld.n; ++l) {            // 41 + 5(l-1): x, b, op0, op1, blk
+    const size_t n = ld.ncell[l];
+    L.add(3 * n * kt);
+    L.add(3 * n * kt);
+    L.add(kOpStride * n * kt);
+    L.add(kOpStride * n * kt);
+    L.add(sizeof(int2) * ((n + kBlock - 1) / kBlock));
+  }
   return L;
 }
 
@@ -189,7 +246,30 @@ struct Batch {
   bool owned = false;
   bool mixed = false;
   int m = kRestart;
-  BatchLaunch bl() const { return BatchLaunch{d_desc, d_blk, nblk, (int)cells.size()}; }
+  int nu = 2;
+  int maxlev = 0;
+  int2* lvl_blk[kMaxLevels] = {};
+  int lvl_nblk[kMaxLevels] = {};
+  BatchLaunch bl() const {
+    BatchLaunch b{};
+    for (const mbx_cell* c : cells) {
+      const double N = c->N, Fa = c->F_an, Fc = c->F_ca, kt = c->mixed ? 4.0 : 8.0;
+      b.bytes_residual[0] += 44.0 * N + 24.0 * Fa;
+      b.bytes_residual[1] += 44.0 * N + 24.0 * Fa + kt * N + (6.0 * kt + 16.0) * Fa + 4.0 * kt * Fc;
+      b.bytes_matvec += (4.0 + 5.0 * kt) * N + 5.0 * kt * Fa + 3.0 * kt * Fc;
+      b.bytes_smooth0 += (4.0 + 1.5 * kt) * N + kt * (Fa + Fc);
+    }
+    b.cells = d_desc;
+    b.blk = d_blk;
+    b.nblk = nblk;
+    b.ncell = (int)cells.size();
+    b.maxlev = maxlev;
+    for (int l = 0; l < kMaxLevels; ++l) {
+      b.lvl_blk[l] = lvl_blk[l];
+      b.lvl_nblk[l] = lvl_nblk[l];
+    }
+    return b;
+  }
   int upload() {
     for (size_t c = 0; c < cells.size(); ++c) h_desc[c] = cells[c]->h;
     HIPCHK(hipMemcpyAsync(d_desc, h_desc, sizeof(CellDev) * cells.size(), hipMemcpyHostToDevice, s));
@@ -210,6 +290,8 @@ struct Batch {
     hipFree(d_desc);
     hipFree(d_blk);
     hipFree(d_gather);
+    for (int l = 1; l < kMaxLevels; ++l)
+      if (lvl_blk[l]) hipFree(lvl_blk[l]);
     hipHostFree(h_desc);
     hipHostFree(h_gather);
     owned = false;
@@ -228,6 +310,11 @@ Batch single(mbx_cell* c) {
   b.nblk = c->nblk;
   b.mixed = c->mixed;
   b.m = c->m;
+  b.maxlev = c->ld.n;
+  for (int l = 1; l < c->ld.n; ++l) {
+    b.lvl_blk[l] = c->lvl_blk[l];
+    b.lvl_nblk[l] = c->lvl_nblk[l];
+  }
   return b;
 }
 
@@ -254,6 +341,16 @@ int make_batch(mbx_cell* const* cells, int n, Batch& out) {
   for (int c = 0; c < n; ++c)
     for (int k = 0; k < cells[c]->nblk; ++k) tab.push_back(make_int2(c, k));
   b.nblk = (int)tab.size();
+  for (int c = 0; c < n; ++c) b.maxlev = std::max(b.maxlev, cells[c]->ld.n);
+  for (int l = 1; l < b.maxlev; ++l) {
+    std::vector<int2> lt;
+    for (int c = 0; c < n; ++c)
+      if (l < cells[c]->ld.n)
+        for (int k = 0; k < cells[c]->lvl_nblk[l]; ++k) lt.push_back(make_int2(c, k));
+    b.lvl_nblk[l] = (int)lt.size();
+    HIPCHK(hipMalloc(&b.lvl_blk[l], sizeof(int2) * std::max<size_t>(lt.size(), 1)));
+    HIPCHK(hipMemcpyAsync(b.lvl_blk[l], lt.data(), sizeof(int2) * lt.size(), hipMemcpyHostToDevice, b.s));
+  }
   HIPCHK(hipMalloc(&b.d_desc, sizeof(CellDev) * n));
   HIPCHK(hipMalloc(&b.d_blk, sizeof(int2) * tab.size()));
   HIPCHK(hipMalloc(&b.d_gather, sizeof(double) * kGather * n));
@@ -277,10 +374,10 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
   int total = 0;
   launch_gm_start<KT>(bl, 1, B.s);
   launch_gm_flags(bl, 1, B.s);
-  for (int cyc = 0; total < max_iters; ++cyc) {
+  while (total < max_iters) {
     int k = 0;
     for (; k < m; ++k) {
-      launch_jacobi<KT>(bl, k, VEC_Z, 0, B.s);
+      launch_precond<KT>(bl, k, B.nu, 0, B.s);
       launch_matvec<KT>(bl, VEC_Z, VEC_W, 0, B.s);
       launch_multidot<KT>(bl, k, 0, B.s);
       launch_orth<KT>(bl, k, 0, B.s);
@@ -302,7 +399,8 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
     total += k;
     launch_backsolve(bl, B.s);
     launch_combine<KT>(bl, B.s);
-    launch_update_x_jacobi<KT>(bl, B.s);
+    launch_precond<KT>(bl, VEC_W, B.nu, -1, B.s);
+    launch_add_z_to_x<KT>(bl, B.s);
     launch_matvec<KT>(bl, VEC_X, VEC_W, 2, B.s);
     launch_true_residual<KT>(bl, B.s);
     launch_gm_start<KT>(bl, 0, B.s);
@@ -324,11 +422,15 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
   const BatchLaunch bl = B.bl();
   auto t0 = std::chrono::steady_clock::now();
   std::vector<int> st(nc, 1);   // 1 running, 0 converged, < 0 failed
-  std::vector<double> rn(nc), rmax(nc), res0(nc), eta(nc, 1e-4), du(nc, 0.0), lam(nc, 1.0);
+  std::vector<double> rn(nc), rmax(nc), res0(nc), eta(nc, 1e-4), du(nc, 0.0), lam(nc, 1.0), mr(nc), dnm(nc, 0.0);
+  // FP32 Krylov cannot resolve relative residuals much below 1e-6
+  const double eta_floor = B.cells[0]->p.krylov_rtol;
   std::vector<int> nit(nc, 0), kit(nc, 0);
   for (int c = 0; c < nc; ++c) {
     mbx_cell* cl = B.cells[c];
     fill_step_constants(cl->h, dt);
+    cl->h.use_w = 0;
+    cl->h.elim_n = 1;
     cl->h.active = 1;
     cl->h.lam = 1.0;
     cl->h.m = B.m;
@@ -340,6 +442,7 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
   if (int e = B.gather()) return e;
   for (int c = 0; c < nc; ++c) {
     rn[c] = std::sqrt(B.red(c, RED_RSQ));
+    mr[c] = std::sqrt(B.red(c, RED_MSQ));
     rmax[c] = B.red(c, RED_RMAX);
     res0[c] = rmax[c];
     if (!std::isfinite(rn[c])) st[c] = MBX_ENAN;
@@ -355,6 +458,7 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
     }
     if (!any) break;
     if (int e = B.upload()) return e;
+    launch_mg_setup<KT>(bl, B.s);
     launch_rhs<KT>(bl, B.s);
     int kits = 0;
     if (int e = gmres<KT>(B, B.cells[0]->p.krylov_max, &kits)) return e;
@@ -362,11 +466,21 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
     for (int c = 0; c < nc; ++c)
       if (st[c] == 1) kit[c] += B.ctl(c, CTL_ITERS);
     launch_direction<KT>(bl, B.s);
-    // line search: halve until admissible and the scaled residual does not grow
+    if (int e = B.gather()) return e;
+    // step-length limiter: no scaled update larger than kStepLimit (potentials
+    // in RT/F, concentrations relative to c0 / c_max), then halving until the
+    // state is admissible and (FP64) the scaled residual norm does not grow
     std::vector<int> searching(nc, 0);
     for (int c = 0; c < nc; ++c) {
       searching[c] = st[c] == 1;
-      lam[c] = 1.0;
+      if (!searching[c]) continue;
+      const double dfull = B.red(c, RED_DUMAX);
+      lam[c] = (std::isfinite(dfull) && dfull > kStepLimit) ? kStepLimit / dfull : 1.0;
+      if (!std::isfinite(dfull)) {
+        if (g_verbose()) fprintf(stderr, "[mbx] cell %d newton %d: non-finite Newton direction\n", c, it);
+        st[c] = MBX_ENAN;
+        searching[c] = 0;
+      }
     }
     for (int hlv = 0; hlv <= 20; ++hlv) {
       bool anys = false;
@@ -393,16 +507,29 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
       if (int e = B.gather()) return e;
       for (int c = 0; c < nc; ++c) {
         if (!searching[c] || !B.cells[c]->h.active) continue;
+        // FP64: the scaled residual 2-norm must not grow.  Mixed: an FP32
+        // correction carries rounding noise of ~1e-7 |x| into every entry,
+        // which rows with large conductance (anode potential) turn into
+        // residual growth unrelated to progress; the limited full step is
+        // taken and the FP64 residual of the next Newton iteration refines it.
         const double r1 = std::sqrt(B.red(c, RED_RSQ));
-        const bool ok = std::isfinite(r1) && (r1 <= rn[c] || hlv == 20);
+        const double m1 = std::sqrt(B.red(c, RED_MSQ));
+        // once the iterate meets the residual tolerance the remaining
+        // differences are rounding noise: take the full step
+        const bool ok = std::isfinite(r1) &&
+                        (B.mixed || r1 <= rn[c] || rmax[c] <= B.cells[c]->p.res_tol || hlv == 20);
         if (ok) {
           searching[c] = 0;
           du[c] = dmax[c] / lam[c];
+          dnm[c] = B.red(c, RED_DNMAX);
+          const double mprev = mr[c];
           const double rprev = rn[c];
           rn[c] = r1;
+          mr[c] = m1;
           rmax[c] = B.red(c, RED_RMAX);
           const double ratio = rprev > 0.0 ? r1 / rprev : 0.0;
-          eta[c] = std::max(B.cells[c]->p.krylov_rtol, std::min(1e-4, 0.5 * ratio * ratio));
+          (void)mprev;
+          eta[c] = std::max(eta_floor, std::min(1e-4, 0.5 * ratio * ratio));
         } else {
           lam[c] *= 0.5;
         }
@@ -423,7 +550,10 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
     for (int c = 0; c < nc; ++c) {
       if (st[c] != 1) continue;
       const mbx_params& p = B.cells[c]->p;
-      if (du[c] <= p.newton_tol && rmax[c] <= p.res_tol) st[c] = 0;
+      if (g_verbose())
+        fprintf(stderr, "[mbx] cell %d newton %d: lam %.3g |r|2 %.3e |r|inf %.3e merit %.3e du %.3e dn %.3e eta %.1e gmres %d (beta0 %.3e)\n",
+                c, it, lam[c], rn[c], rmax[c], mr[c], du[c], dnm[c], eta[c], B.ctl(c, CTL_ITERS), B.red(c, RED_BETA0));
+      if (lam[c] == 1.0 && du[c] <= p.newton_tol && dnm[c] <= p.newton_tol && rmax[c] <= p.res_tol) st[c] = 0;
     }
   }
   // roll back failures, outputs for the converged cells
@@ -446,7 +576,7 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
       in.krylov_iters = kit[c];
       in.res0 = res0[c];
       in.res_final = rmax[c];
-      in.du_final = du[c];
+      in.du_final = std::max(du[c], dnm[c]);
       in.V = B.red(c, RED_VSUM) / B.cells[c]->n_top;
       in.wall_s = wall;
     }
@@ -478,7 +608,7 @@ int mbx_params_default(mbx_params* p) {
   std::memset(p, 0, sizeof *p);
   p->newton_tol = 1e-9;
   p->res_tol = 1e-6;
-  p->krylov_rtol = 1e-8;
+  p->krylov_rtol = 1e-6;
   p->newton_max = 30;
   p->krylov_max = 2000;
   p->thermo = 1.0;
@@ -489,7 +619,7 @@ int64_t mbx_cell_footprint(int nx, int ny, int nz, int precision, int n_an_faces
   const int64_t N = (int64_t)nx * ny * nz;
   if (N <= 0 || N > (1 << 28)) return -1;
   const int nblk = (int)((N + kBlock - 1) / kBlock);
-  Layout L = make_layout((int)N, n_an_faces, n_ca_faces, nblk, kRestart, kt_size(precision));
+  Layout L = make_layout((int)N, n_an_faces, n_ca_faces, nblk, kRestart, kt_size(precision), level_dims(nx, ny, nz));
   return (int64_t)L.total;
 }
 
@@ -504,7 +634,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   mbx_params p = *pin;
   if (p.newton_tol <= 0) p.newton_tol = 1e-9;
   if (p.res_tol <= 0) p.res_tol = 1e-6;
-  if (p.krylov_rtol <= 0) p.krylov_rtol = 1e-8;
+  if (p.krylov_rtol <= 0) p.krylov_rtol = 1e-6;
   if (p.newton_max <= 0) p.newton_max = 30;
   if (p.krylov_max <= 0) p.krylov_max = 2000;
   const int N = (int)N64;
@@ -580,11 +710,26 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   c->mixed = p.precision == MBX_MIXED;
   c->s = s;
   const size_t kt = kt_size(p.precision);
-  Layout L = make_layout(N, F_an, F_ca, c->nblk, c->m, kt);
+  c->ld = level_dims(nx, ny, nz);
+  if (c->ld.ncell[c->ld.n - 1] > kCoarseMaxCells) {
+    cleanup_tmp();
+    delete c;
+    return fail(MBX_EINVAL, "grid too elongated for the multigrid hierarchy");
+  }
+  Layout L = make_layout(N, F_an, F_ca, c->nblk, c->m, kt, c->ld);
   if (hipMalloc(&c->dmem, L.total) != hipSuccess) {
     cleanup_tmp();
     delete c;
     return fail(MBX_ENOMEM, "device allocation of %zu bytes failed", L.total);
+  }
+  if (std::getenv("MBX_POISON")) {
+    // debugging aid: NaN bytes everywhere, so a read before the first write shows up
+    if (hipMemsetAsync(c->dmem, 0xff, L.total, s) != hipSuccess) {
+      cleanup_tmp();
+      hipFree(c->dmem);
+      delete c;
+      return fail(MBX_EHIP, "poison fill failed");
+    }
   }
   char* b = c->dmem;
   CellDev& h = c->h;
@@ -623,6 +768,32 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   c->d_desc = (CellDev*)(b + L.off[33]);
   c->d_blk = (int2*)(b + L.off[34]);
   c->d_gather = (double*)(b + L.off[35]);
+  h.b0 = b + L.off[36];
+  h.cond_an = b + L.off[37];
+  h.cond_ca = b + L.off[38];
+  h.cinv[0] = (double*)(b + L.off[39]);
+  h.cinv[1] = (double*)(b + L.off[40]);
+  h.nlev = c->ld.n;
+  h.alpha = g_mg_alpha();
+  h.nu = 2;
+  h.lv[0].nx = nx;
+  h.lv[0].ny = ny;
+  h.lv[0].nz = nz;
+  h.lv[0].ncell = N;
+  for (int l = 1; l < c->ld.n; ++l) {
+    const int o = 41 + 5 * (l - 1);
+    MGLevel& lv = h.lv[l];
+    lv.nx = c->ld.nx[l];
+    lv.ny = c->ld.ny[l];
+    lv.nz = c->ld.nz[l];
+    lv.ncell = c->ld.ncell[l];
+    lv.x = b + L.off[o];
+    lv.b = b + L.off[o + 1];
+    lv.op[0] = b + L.off[o + 2];
+    lv.op[1] = b + L.off[o + 3];
+    c->lvl_blk[l] = (int2*)(b + L.off[o + 4]);
+    c->lvl_nblk[l] = (lv.ncell + kBlock - 1) / kBlock;
+  }
   h.m = c->m;
   h.lam = 1.0;
   h.rtol = 1e-6;
@@ -642,6 +813,12 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   if (e == hipSuccess) e = hipMemsetAsync(h.ictl, 0, 4 * CTL_NSLOT, s);
   if (e == hipSuccess) e = hipMemsetAsync(h.red, 0, 8 * RED_NSLOT, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->d_blk, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice, s);
+  std::vector<std::vector<int2>> ltabs(c->ld.n);
+  for (int l = 1; l < c->ld.n && e == hipSuccess; ++l) {
+    ltabs[l].resize(c->lvl_nblk[l]);
+    for (int k = 0; k < c->lvl_nblk[l]; ++k) ltabs[l][k] = make_int2(0, k);
+    e = hipMemcpyAsync(c->lvl_blk[l], ltabs[l].data(), sizeof(int2) * ltabs[l].size(), hipMemcpyHostToDevice, s);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup_tmp();
   if (e != hipSuccess) {
@@ -771,6 +948,8 @@ static int load_eval_state(mbx_cell* c, const double* cu, const double* pu, cons
   }
   fill_step_constants(c->h, dt);
   c->h.active = 1;
+  c->h.use_w = 0;    // probes expose the unweighted scaled operator
+  c->h.elim_n = 0;   // ... at the caller's plated amounts
   Batch b = single(c);
   return b.upload();
 }
@@ -810,6 +989,68 @@ int mbx_cell_jvp(mbx_cell* c, const double* cu, const double* pu, const double* 
   }
   HIPCHK(hipMemcpyAsync(y, c->h.dc, N16, hipMemcpyDeviceToHost, c->s));
   HIPCHK(hipStreamSynchronize(c->s));
+  return MBX_OK;
+}
+
+int mbx_cell_precond(mbx_cell* c, const double* cu, const double* pu, const double* nu, const double* cold,
+                     const double* nold, double dt, const double* v, double* z) {
+  if (!c || !v || !z) return fail(MBX_EINVAL, "null argument");
+  if (int e = load_eval_state(c, cu, pu, nu, cold, nold, dt)) return e;
+  Batch b = single(c);
+  const size_t N16 = 16 * (size_t)c->N;
+  if (c->mixed) launch_residual<float>(b.bl(), true, c->s);
+  else launch_residual<double>(b.bl(), true, c->s);
+  if (c->mixed) launch_mg_setup<float>(b.bl(), c->s);
+  else launch_mg_setup<double>(b.bl(), c->s);
+  HIPCHK(hipMemcpyAsync(c->h.dc, v, N16, hipMemcpyHostToDevice, c->s));
+  if (c->mixed) {
+    launch_convert<float>(b.bl(), VEC_W, 0, c->s);
+    launch_precond<float>(b.bl(), VEC_W, b.nu, -2, c->s);
+    launch_convert<float>(b.bl(), VEC_Z, 1, c->s);
+  } else {
+    launch_convert<double>(b.bl(), VEC_W, 0, c->s);
+    launch_precond<double>(b.bl(), VEC_W, b.nu, -2, c->s);
+    launch_convert<double>(b.bl(), VEC_Z, 1, c->s);
+  }
+  HIPCHK(hipMemcpyAsync(z, c->h.dc, N16, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return MBX_OK;
+}
+
+int mbx_cell_solve(mbx_cell* c, const double* cu, const double* pu, const double* nu, const double* cold,
+                   const double* nold, double dt, const double* rhs, double rtol, double* x, int* iters) {
+  if (!c || !rhs || !x) return fail(MBX_EINVAL, "null argument");
+  if (!(rtol > 0.0 && rtol < 1.0)) return fail(MBX_EINVAL, "rtol must lie in (0, 1)");
+  if (int e = load_eval_state(c, cu, pu, nu, cold, nold, dt)) return e;
+  Batch b = single(c);
+  const size_t N16 = 16 * (size_t)c->N;
+  c->h.rtol = rtol;
+  if (int e = b.upload()) return e;
+  int its = 0;
+  HIPCHK(hipMemcpyAsync(c->h.dc, rhs, N16, hipMemcpyHostToDevice, c->s));
+  if (c->mixed) {
+    launch_residual<float>(b.bl(), true, c->s);
+    launch_mg_setup<float>(b.bl(), c->s);
+    launch_convert<float>(b.bl(), VEC_B, 0, c->s);
+    launch_convert<float>(b.bl(), VEC_W, 0, c->s);
+    launch_zero_x<float>(b.bl(), c->s);
+    launch_norm_w<float>(b.bl(), c->s);
+    if (int e = gmres<float>(b, c->p.krylov_max, &its)) return e;
+    launch_convert<float>(b.bl(), VEC_X, 1, c->s);
+  } else {
+    launch_residual<double>(b.bl(), true, c->s);
+    launch_mg_setup<double>(b.bl(), c->s);
+    launch_convert<double>(b.bl(), VEC_B, 0, c->s);
+    launch_convert<double>(b.bl(), VEC_W, 0, c->s);
+    launch_zero_x<double>(b.bl(), c->s);
+    launch_norm_w<double>(b.bl(), c->s);
+    if (int e = gmres<double>(b, c->p.krylov_max, &its)) return e;
+    launch_convert<double>(b.bl(), VEC_X, 1, c->s);
+  }
+  HIPCHK(hipMemcpyAsync(x, c->h.dc, N16, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (int e = b.gather()) return e;
+  if (iters) *iters = b.ctl(0, CTL_ITERS);
   return MBX_OK;
 }
 

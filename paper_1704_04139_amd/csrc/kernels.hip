@@ -9,6 +9,7 @@
 #include "mbx_dev.h"
 #include "mbx_kernels.h"
 #include "reduce.h"
+#include "prof.h"
 
 #include <hipcub/hipcub.hpp>
 
@@ -139,8 +140,9 @@ __global__ void __launch_bounds__(kBlock) k_init_state(CellDev* cells, const int
 //               plating/stripping (2.8) as the numerical flux (eq. 2.4)
 //   collectors  anode at phi = 0 across h/2; cathode galvanostatic.
 // With LIN it also writes the linearisation used by the Krylov solve: the
-// scaled face coefficients (plating condensed onto the voxel unknowns),
-// the pore 1/c coefficient and the inverse 2x2 diagonal blocks.
+// scaled face coefficients (plating condensed onto the voxel unknowns), the
+// potential-operator conductance of each interface face and the pore 1/c
+// coefficient.
 template <bool LIN, typename KT>
 __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2* __restrict__ blk) {
   const int2 bb = blk[blockIdx.x];
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
   const CellDev& cd = *cdp;
   if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
-  double rsq = 0.0, rmax = 0.0;
+  double rsq = 0.0, rmax = 0.0, msq = 0.0, dnmax = 0.0;
   if (i < cd.N) {
     const VoxCoord v = coord_of(cd, i);
     const uint32_t mi = cd.meta[i];
@@ -158,13 +160,12 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
     const bool plate = cd.plating != 0;
     double Rc = cd.Vol * (ci - cd.c_old[i]) / dt;
     double Rp = 0.0;
-    double bcc = cd.Vol / dt, bcp = 0.0, bpc = 0.0, bpp = 0.0;
+    double wc = 1.0, wp = 0.0;   // state-independent diagonal of the scaled rows (merit weights)
     for (int d = 0; d < 6; ++d) {
       const int k = neighbour(cd, i, v.x, v.y, v.z, d);
       if (k < 0) {
         if (d == 4 && L == ANODE) {
           Rp += 2.0 * A * cd.sigma[0] * pi / h;
-          bpp += 2.0 * A * cd.sigma[0] / h;
         } else if (d == 5 && L == CATHODE) {
           Rp += -cd.I_app / cd.n_top;
         }
@@ -177,52 +178,39 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
       const double sgn = lo ? 1.0 : -1.0;
       const double ca = lo ? ci : ck, cb = lo ? ck : ci;
       const double pa = lo ? pi : pk, pb = lo ? pk : pi;
+      weight_add(cd, L, Lk, wc, wp);
       if (L == PORE && Lk == PORE) {
         const double j = -cd.kappa * (pb - pa) / h + cd.Kd * (log(cb) - log(ca));
         const double Nf = -cd.De * (cb - ca) / h + cd.tplus / kFaraday * j;
         Rc += sgn * (A * Nf);
         Rp += sgn * (A * j);
-        if (LIN) {
-          bcc += A * (cd.De / h - cd.tplus / kFaraday * cd.Kd / ci);
-          bcp += A * (cd.tplus / kFaraday * cd.kappa / h);
-          bpc += -A * cd.Kd / ci;
-          bpp += A * cd.kappa / h;
-        }
       } else if (L == Lk) {
         const int s = L - 1;
         const double Nf = -cd.Ds[s] * (cb - ca) / h;
         const double j = -cd.sigma[s] * (pb - pa) / h;
         Rc += sgn * (A * Nf);
         Rp += sgn * (A * j);
-        if (LIN) {
-          bcc += A * cd.Ds[s] / h;
-          bpp += A * cd.sigma[s] / h;
-        }
       } else if (L == PORE) {
         const bool an = Lk == ANODE;
         const uint32_t f = face_rank(mk, d ^ 1);
-        const double nf = an ? cd.n_try[f] : 0.0;
+        double nf = an ? cd.n_try[f] : 0.0;
+        if (an && cd.elim_n) nf = plate ? plated_root(cd, ci, pk, pi, cd.n_old[f], cd.n[f]) : cd.n_old[f];
         const Kin q = interface_kinetics(cd, Lk, ck, ci, pk, pi, nf, an && plate, LIN);
         const double it = q.ii + q.ip;
         Rc -= A * it / kFaraday;
         Rp -= A * it;
-        if (LIN) {
-          double kap = 0.0;
-          if (an && plate) kap = (A / dt) / (A / dt + A * q.p_n / kFaraday);
-          const double dce = q.d_ce + kap * q.p_ce, gg = q.g + kap * q.g_p;
-          bcc += -A * dce / kFaraday;
-          bcp += A * gg / kFaraday;
-          bpc += -A * dce;
-          bpp += A * gg;
-        }
       } else {
         const bool an = L == ANODE;
         const uint32_t f = face_rank(mi, d);
-        const double nf = an ? cd.n_try[f] : 0.0;
+        double nf = an ? cd.n_try[f] : 0.0;
+        if (an && cd.elim_n) {
+          nf = plate ? plated_root(cd, ck, pi, pk, cd.n_old[f], cd.n[f]) : cd.n_old[f];
+          cd.n_try[f] = nf;
+          dnmax = fmax(dnmax, fabs(nf - cd.n[f]) / cd.n_c);
+        }
         const Kin q = interface_kinetics(cd, L, ci, ck, pi, pk, nf, an && plate, LIN);
         Rc += A * q.ii / kFaraday;
         Rp += A * (q.ii + q.ip);
-        double kap = 0.0;
         if (an) {
           const double Rn = A * (nf - cd.n_old[f]) / dt + A * q.ip / kFaraday;
           cd.Rn[f] = Rn;
@@ -231,7 +219,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
           rmax = fmax(rmax, fabs(rs));
           if (LIN) {
             const double jnn = A / dt + A * q.p_n / kFaraday;
-            kap = (A / dt) / jnn;
+            const double kap = (A / dt) / jnn;
             const double mu = cd.mu_ref;
             KT* co = (KT*)cd.coef_an + 5 * (size_t)f;
             co[0] = (KT)(q.d_cs * cd.cmax[0] / mu);
@@ -241,6 +229,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
             co[4] = (KT)(kap * q.g_p * cd.VT / mu);
             cd.rn_jnn[f] = Rn / jnn;
             cd.sq[f] = q.p_n * Rn / (jnn * mu);
+            ((KT*)cd.cond_an)[f] = (KT)((q.g + kap * q.g_p) * cd.VT / mu);
           }
         } else if (LIN) {
           const double mu = cd.mu_ref;
@@ -248,12 +237,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
           co[0] = (KT)(q.d_cs * cd.cmax[1] / mu);
           co[1] = (KT)(q.d_ce * cd.c0 / mu);
           co[2] = (KT)(q.g * cd.VT / mu);
-        }
-        if (LIN) {
-          bcc += A * q.d_cs / kFaraday;
-          bcp += A * q.g / kFaraday;
-          bpc += A * q.d_cs;
-          bpp += A * (q.g + kap * q.g_p);
+          ((KT*)cd.cond_ca)[f] = co[2];
         }
       }
     }
@@ -264,20 +248,15 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
     const double rc = Rc * sc, rp = Rp * sp;
     rsq += rc * rc + rp * rp;
     rmax = fmax(rmax, fmax(fabs(rc), fabs(rp)));
+    if (L == ANODE && v.z == 0) wp += cd.Gcol;
+    const double mc = rc / wc, mp = rp / fmax(wp, 1.0);
+    msq += mc * mc + mp * mp;
     if (LIN) {
-      const double Bcc = sc * bcc * cref, Bcp = sc * bcp * cd.VT;
-      const double Bpc = sp * bpc * cref, Bpp = sp * bpp * cd.VT;
-      const double det = Bcc * Bpp - Bcp * Bpc;
-      KT* di = (KT*)cd.dinv + 4 * (size_t)i;
-      di[0] = (KT)(Bpp / det);
-      di[1] = (KT)(-Bcp / det);
-      di[2] = (KT)(-Bpc / det);
-      di[3] = (KT)(Bcc / det);
       ((KT*)cd.wpore)[i] = (KT)(L == PORE ? cd.c0 / ci : 0.0);
     }
   }
-  const double vals[2] = {rsq, rmax};
-  reduce_cell<2>(cdp, bb.y, vals, 0x2u, cd.red + RED_RSQ);
+  const double vals[4] = {rsq, rmax, msq, dnmax};
+  reduce_cell<4>(cdp, bb.y, vals, 0xAu, cd.red + RED_RSQ);
 }
 
 // Right-hand side of the condensed, scaled Newton system:
@@ -315,6 +294,14 @@ __global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __re
         }
       }
     }
+    double wc = 1.0, wp = 0.0;
+    for (int d = 0; d < 6; ++d) {
+      const int k = neighbour(cd, i, v.x, v.y, v.z, d);
+      if (k >= 0) weight_add(cd, L, lab_of(cd.meta[k]), wc, wp);
+    }
+    weight_finish(cd, L, v.z, wc, wp);
+    bc *= wc;
+    bp *= wp;
     const size_t N = cd.N;
     KT* b = (KT*)cd.b;
     KT* w = (KT*)cd.w;
@@ -376,6 +363,7 @@ __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* _
   const KT wi = (L == PORE) ? wpo[i] : (KT)0;
   const KT Gk = (KT)cd.Gk, tth = (KT)cd.tth, Dh = (KT)cd.Dh, tau = (KT)cd.tau, Ke = (KT)cd.Ke;
   KT yc = vc, yp = (KT)0;
+  double wc = 1.0, wp = 0.0;
   for (int d = 0; d < 6; ++d) {
     const int k = neighbour(cd, i, c3.x, c3.y, c3.z, d);
     if (k < 0) {
@@ -384,6 +372,7 @@ __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* _
     }
     const uint32_t mk = cd.meta[k];
     const int Lk = lab_of(mk);
+    weight_add(cd, L, Lk, wc, wp);
     const KT vck = v[k], vpk = v[N + k];
     const bool lo = i < k;
     if (L == PORE && Lk == PORE) {
@@ -433,8 +422,9 @@ __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* _
       yp += q + qp;
     }
   }
-  y[i] = yc;
-  y[N + i] = yp;
+  weight_finish(cd, L, c3.z, wc, wp);
+  y[i] = yc * (KT)wc;
+  y[N + i] = yp * (KT)wp;
 }
 
 // ------------------------------------------------------------------- GMRES
@@ -751,10 +741,12 @@ __global__ void k_gather_ctl(CellDev* cells, int ncell, double* out) {
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_direction(CellDev* cells, const int2* __restrict__ blk) {
   const int2 bb = blk[blockIdx.x];
-  const CellDev& cd = cells[bb.x];
+  CellDev* cdp = cells + bb.x;
+  const CellDev& cd = *cdp;
   if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
-  if (i >= cd.N) return;
+  double dmax = 0.0;
+  if (i < cd.N) {
   const size_t N = cd.N;
   const KT* x = (const KT*)cd.x;
   const uint32_t mi = cd.meta[i];
@@ -762,7 +754,9 @@ __global__ void __launch_bounds__(kBlock) k_direction(CellDev* cells, const int2
   const double xc = (double)x[i], xp = (double)x[N + i];
   cd.dc[i] = cref_of(cd, L) * xc;
   cd.dp[i] = cd.VT * xp;
-  if (L == ANODE) {
+  dmax = fmax(fabs(xc), fabs(xp));
+  if (!isfinite(dmax)) dmax = INFINITY;
+  if (L == ANODE && !cd.elim_n) {
     const VoxCoord v = coord_of(cd, i);
     const uint32_t msk = mask_of(mi);
     const KT* can = (const KT*)cd.coef_an;
@@ -777,8 +771,13 @@ __global__ void __launch_bounds__(kBlock) k_direction(CellDev* cells, const int2
         dn -= cd.dt * cd.mu_ref / kFaraday * qp;
       }
       cd.dn[f] = dn;
+      dmax = fmax(dmax, fabs(dn) / cd.n_c);
     }
   }
+  }
+  // scaled max-norm of the full Newton step (step-length limiter)
+  const double vals[1] = {dmax};
+  reduce_cell<1>(cdp, bb.y, vals, 0x1u, cd.red + RED_DUMAX);
 }
 
 // Trial state u + lam du; counts inadmissible entries (c <= 0, c_s >= c_max,
@@ -802,7 +801,7 @@ __global__ void __launch_bounds__(kBlock) k_trial(CellDev* cells, const int2* __
     if (!(c > 0.0) || !isfinite(p) || (L != PORE && !(c < cref))) bad += 1.0;
     dmax = fmax(fabs(lam * cd.dc[i]) / cref, fabs(lam * cd.dp[i]) / cd.VT);
     if (!isfinite(dmax)) bad += 1.0;
-    if (L == ANODE) {
+    if (L == ANODE && !cd.elim_n) {
       const uint32_t cnt = __popc(mask_of(mi));
       for (uint32_t r = 0; r < cnt; ++r) {
         const uint32_t f = base_of(mi) + r;
@@ -902,6 +901,37 @@ __global__ void __launch_bounds__(kBlock) k_convert(CellDev* cells, const int2* 
   }
 }
 
+// x = 0 (start of a solve from a given right-hand side)
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_zero_x(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  KT* x = (KT*)cd.x;
+  x[i] = (KT)0;
+  x[(size_t)cd.N + i] = (KT)0;
+}
+
+// ||w||^2 into RED_BSQ
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_norm_w(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = blk[blockIdx.x];
+  CellDev* cdp = cells + bb.x;
+  const CellDev& cd = *cdp;
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  double ss = 0.0;
+  if (i < cd.N) {
+    const KT* w = (const KT*)cd.w;
+    const double a = (double)w[i], b = (double)w[(size_t)cd.N + i];
+    ss = a * a + b * b;
+  }
+  const double vals[1] = {ss};
+  reduce_cell<1>(cdp, bb.y, vals, 0u, cd.red + RED_BSQ);
+}
+
 // --------------------------------------------------------------- launchers
 static inline dim3 grid_of(int nblk) { return dim3((unsigned)nblk); }
 
@@ -923,10 +953,12 @@ void launch_init_state(const BatchLaunch& b, hipStream_t s) {
 
 template <typename KT>
 void launch_residual(const BatchLaunch& b, bool lin, hipStream_t s) {
+  prof_begin(PK_RESIDUAL, s);
   if (lin)
     k_residual<true, KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
   else
     k_residual<false, KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+  if (prof_on(PK_RESIDUAL)) prof_end(PK_RESIDUAL, s, b.bytes_residual[lin ? 1 : 0]);
 }
 template <typename KT>
 void launch_rhs(const BatchLaunch& b, hipStream_t s) {
@@ -938,7 +970,9 @@ void launch_jacobi(const BatchLaunch& b, int src, int dst, int need, hipStream_t
 }
 template <typename KT>
 void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t s) {
+  prof_begin(PK_MATVEC, s);
   k_matvec<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need);
+  if (prof_on(PK_MATVEC)) prof_end(PK_MATVEC, s, b.bytes_matvec);
 }
 template <typename KT>
 void launch_multidot(const BatchLaunch& b, int k, int tgt, hipStream_t s) {
@@ -985,6 +1019,14 @@ void launch_gather_ctl(const BatchLaunch& b, double* out, hipStream_t s) {
   k_gather_ctl<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell, out);
 }
 template <typename KT>
+void launch_zero_x(const BatchLaunch& b, hipStream_t s) {
+  k_zero_x<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+template <typename KT>
+void launch_norm_w(const BatchLaunch& b, hipStream_t s) {
+  k_norm_w<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+}
+template <typename KT>
 void launch_convert(const BatchLaunch& b, int sel, int dir, hipStream_t s) {
   k_convert<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, sel, dir);
 }
@@ -1006,6 +1048,8 @@ void launch_outputs(const BatchLaunch& b, hipStream_t s) {
   template void launch_jacobi<KT>(const BatchLaunch&, int, int, int, hipStream_t);  \
   template void launch_matvec<KT>(const BatchLaunch&, int, int, int, hipStream_t);  \
   template void launch_convert<KT>(const BatchLaunch&, int, int, hipStream_t);      \
+  template void launch_zero_x<KT>(const BatchLaunch&, hipStream_t);                  \
+  template void launch_norm_w<KT>(const BatchLaunch&, hipStream_t);                  \
   template void launch_multidot<KT>(const BatchLaunch&, int, int, hipStream_t);  \
   template void launch_orth<KT>(const BatchLaunch&, int, int, hipStream_t);      \
   template void launch_scale_next<KT>(const BatchLaunch&, int, hipStream_t);     \

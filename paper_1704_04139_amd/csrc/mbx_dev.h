@@ -25,6 +25,19 @@ constexpr int kPartStride = kMaxRestart + 2;
 
 enum { PORE = 0, ANODE = 1, CATHODE = 2 };
 
+// Multigrid hierarchy (per cell).  Level 0 is the voxel grid (operators
+// applied matrix-free); level l >= 1 is a grid of ceil-halved cells, each
+// with three slots (pore, anode, cathode aggregates of the finer level).
+constexpr int kMaxLevels = 12;
+constexpr int kCoarseMaxCells = 64;
+constexpr int kOpStride = 33;   // per coarse cell: E[3], X[3], G[3 dirs][3][3] (SoA)
+struct MGLevel {
+  int nx, ny, nz, ncell;
+  void* x;       // KT [3*ncell] (slot-major)
+  void* b;       // KT [3*ncell]
+  void* op[2];   // KT [kOpStride*ncell] for the concentration (0) and potential (1) operators
+};
+
 __host__ __device__ inline int lab_of(uint32_t m) { return int(m & 3u); }
 __host__ __device__ inline uint32_t mask_of(uint32_t m) { return (m >> 2) & 63u; }
 __host__ __device__ inline uint32_t base_of(uint32_t m) { return m >> 8; }
@@ -32,18 +45,21 @@ __device__ inline uint32_t face_rank(uint32_t m, int d) {
   return base_of(m) + (uint32_t)__popc(mask_of(m) & ((1u << d) - 1u));
 }
 
-// Slots of the per-cell reduction output array `red`.
+// Slots of the per-cell reduction output array `red`.  A kernel performs at
+// most one reduce_cell call (the partial buffer and ticket are per cell).
 enum {
   RED_RSQ = 0,     // sum of squared scaled residual
   RED_RMAX = 1,    // max |scaled residual|
-  RED_BAD = 2,     // infeasible entries in a trial state
-  RED_DUMAX = 3,   // max |scaled update|
-  RED_BSQ = 4,     // sum of squares of a Krylov vector (rhs / true residual)
-  RED_INV0 = 5,    // inventories: electrolyte, anode, cathode, plated (4 slots)
-  RED_VSUM = 9,    // sum over cathode top voxels of phi
-  RED_TOL = 10,    // GMRES absolute tolerance of the current solve
-  RED_BETA0 = 11,  // norm of the first GMRES residual of the current solve
-  RED_NSLOT = 12
+  RED_MSQ = 2,     // line-search merit: sum of squared diagonally weighted voxel-row residuals
+  RED_DNMAX = 3,   // max |n_trial - n| / n_c of the eliminated plated amounts
+  RED_BAD = 4,     // infeasible entries in a trial state
+  RED_DUMAX = 5,   // max |scaled update|
+  RED_BSQ = 6,     // sum of squares of a Krylov vector (rhs / true residual)
+  RED_INV0 = 7,    // inventories: electrolyte, anode, cathode, plated (4 slots)
+  RED_VSUM = 11,   // sum over cathode top voxels of phi (must follow the inventories)
+  RED_TOL = 12,    // GMRES absolute tolerance of the current solve
+  RED_BETA0 = 13,  // norm of the first GMRES residual of the current solve
+  RED_NSLOT = 14
 };
 // Slots of the per-cell device-written integer array `ictl`.
 enum { CTL_DONE = 0, CTL_K = 1, CTL_ITERS = 2, CTL_NSLOT = 4 };
@@ -54,6 +70,8 @@ struct CellDev {
   int nx, ny, nz, N;
   int F_an, F_ca, n_top, nblk;
   int active;         // 0: every kernel skips this cell
+  int use_w;          // 1: Krylov system rows weighted by 1/(transport diagonal)
+  int elim_n;         // 1: residual kernels solve each face's plating balance for n
   int pad0;
   const uint32_t* meta;
   double *c, *phi, *n;               // Newton iterate
@@ -82,6 +100,14 @@ struct CellDev {
   double Ds[2], sigma[2], cmax[2], i00[2], U0[2], U1[2];
   double i00_pl, n_c, I_app, mu_ref;
   int plating, pad2;
+  // multigrid
+  int nlev, pad4;                    // levels incl. the voxel level; coarsest = nlev-1
+  MGLevel lv[kMaxLevels];
+  void *b0;                          // KT [N] right-hand side of a level-0 solve
+  void *cond_an, *cond_ca;           // KT potential-operator conductance per interface face
+  double *cinv[2];                   // coarsest-level dense inverses (FP64), (3*ncell)^2 each
+  double alpha;                      // coarse-correction scale
+  int nu, pad5;                      // smoothing sweeps (red+black pairs) per side
   // scaled-operator constants
   double Kd;                         // kappa (1-t+) theta RT/(F h)
   double Gk, tth, Dh, tau, Ke, Gcol;
@@ -107,6 +133,52 @@ __device__ inline int neighbour(const CellDev& cd, int i, int x, int y, int z, i
     case 4: return z > 0 ? i - cd.nx * cd.ny : -1;
     default: return z < cd.nz - 1 ? i + cd.nx * cd.ny : -1;
   }
+}
+
+// Row weights of the Newton system: the reciprocal of the state-independent
+// part of each scaled row's diagonal (mass + same-phase transport +
+// collector), so that every weighted row measures the error of its own
+// unknown.  A row with no transport coupling keeps weight 1.
+__device__ inline void weight_add(const CellDev& cd, int L, int Lk, double& wc, double& wp) {
+  if (L != Lk) return;
+  wc += (L == PORE) ? cd.Dh : cd.Dsh[L - 1];
+  wp += (L == PORE) ? cd.Gk : cd.Gs[L - 1];
+}
+__device__ inline void weight_finish(const CellDev& cd, int L, int z, double& wc, double& wp) {
+  if (L == ANODE && z == 0) wp += cd.Gcol;
+  wc = cd.use_w ? 1.0 / wc : 1.0;
+  wp = cd.use_w ? 1.0 / fmax(wp, 1.0) : 1.0;
+}
+
+// Plated amount that zeroes the face's plating balance (Sec. 2.3, eq. 2.8):
+//   g(n) = (n - n_old)/dt + i_pl(n)/F = 0,
+//   i_pl = K f_pre(n) - E,  K = i00_pl sqrt(c_e) e^a,  E = i00_pl sqrt(c_e) e^-a,
+//   a = F (phi_s - phi_e)/(2RT).
+// g is increasing in n >= 0, g(0) < 0 and g(n_old + dt E/F) >= 0, so the root
+// is unique in that bracket; safeguarded Newton (bisection fallback).
+// Both voxels of the face call this with identical arguments.
+__device__ inline double plated_root(const CellDev& cd, double ce, double ps, double pe, double n_old,
+                                     double guess) {
+  const double a = cd.beta * (ps - pe);
+  const double sq = cd.i00_pl * sqrt(ce);
+  const double K = sq * exp(a), E = sq * exp(-a);
+  const double dt = cd.dt, invF = 1.0 / kFaraday;
+  const double nc2 = cd.n_c * cd.n_c, nc4 = nc2 * nc2;
+  double lo = 0.0, hi = n_old + dt * E * invF;
+  if (!(hi > 0.0)) return 0.0;
+  double n = (guess > lo && guess < hi) ? guess : 0.5 * (lo + hi);
+  for (int it = 0; it < 100; ++it) {
+    const double n2 = n * n, n4 = n2 * n2, den = nc4 + n4;
+    const double f = n4 / den;
+    const double g = (n - n_old) / dt + (K * f - E) * invF;
+    if (g > 0.0) hi = n; else lo = n;
+    const double dg = 1.0 / dt + K * invF * 4.0 * n2 * n * nc4 / (den * den);
+    double nn = n - g / dg;
+    if (!(nn > lo && nn < hi)) nn = 0.5 * (lo + hi);
+    if (fabs(nn - n) <= 1e-15 * fmax(nn, cd.n_c * 1e-3) || hi - lo <= 1e-16 * hi) return nn;
+    n = nn;
+  }
+  return n;
 }
 
 // Interface kinetics on one solid/pore face (Sec. 2.2 eq. 2.5, Sec. 2.3

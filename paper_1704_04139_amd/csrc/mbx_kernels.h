@@ -17,6 +17,13 @@ struct BatchLaunch {
   const int2* blk;
   int nblk;
   int ncell;
+  int maxlev;                            // max multigrid levels over the batch
+  const int2* lvl_blk[kMaxLevels];       // block tables over each level's cells (index >= 1)
+  int lvl_nblk[kMaxLevels];
+  // algorithmic bytes per launch (summed over the batch), for timing records
+  double bytes_residual[2];              // [0] residual only, [1] with linearisation
+  double bytes_matvec;
+  double bytes_smooth0;                  // one level-0 red-black half sweep
 };
 
 void launch_build_meta(const uint8_t* lab, int nx, int ny, int nz, uint32_t* meta, int* cnt_an, int* cnt_ca,
@@ -32,6 +39,8 @@ template <typename KT> void launch_rhs(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_jacobi(const BatchLaunch& b, int src, int dst, int need, hipStream_t s);
 template <typename KT> void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t s);
 template <typename KT> void launch_convert(const BatchLaunch& b, int sel, int dir, hipStream_t s);
+template <typename KT> void launch_zero_x(const BatchLaunch& b, hipStream_t s);
+template <typename KT> void launch_norm_w(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_multidot(const BatchLaunch& b, int k, int tgt, hipStream_t s);
 template <typename KT> void launch_orth(const BatchLaunch& b, int k, int src, hipStream_t s);
 template <typename KT> void launch_scale_next(const BatchLaunch& b, int k, hipStream_t s);
@@ -48,5 +57,10 @@ template <typename KT> void launch_direction(const BatchLaunch& b, hipStream_t s
 void launch_trial(const BatchLaunch& b, hipStream_t s);
 void launch_copy_state(const BatchLaunch& b, int mode, hipStream_t s);
 void launch_outputs(const BatchLaunch& b, hipStream_t s);
+
+// multigrid preconditioner (mg.hip)
+template <typename KT> void launch_mg_setup(const BatchLaunch& b, hipStream_t s);
+// z = M^-1 v_src; need: GMRES state gate (>= 0 equal, -1 cycle end, -2 always)
+template <typename KT> void launch_precond(const BatchLaunch& b, int src, int nu, int need, hipStream_t s);
 
 }  // namespace mbx

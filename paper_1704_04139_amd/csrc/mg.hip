@@ -1,0 +1,667 @@
+// mg.hip — preconditioner of the Newton correction system.
+//
+// The scaled Jacobian J couples concentrations and potentials.  The
+// preconditioner (1) removes the migration coupling from the pore
+// concentration rows with the row operation c-row -= tau * phi-row (in the
+// bulk electrolyte the t+ j/F flux then cancels exactly), (2) solves the
+// concentration block (mass + same-phase diffusion, symmetric positive
+// definite), (3) solves the potential block (conduction in each phase plus
+// Butler-Volmer and plating conductances across solid/pore faces: a
+// symmetric weighted graph Laplacian, pinned by the anode collector) with
+// the concentration coupling moved to the right-hand side.  Each block is
+// solved approximately by one multigrid V-cycle: aggregates are 2x2x2 voxel
+// blocks split by phase (a coarse cell holds up to three slots: pore, anode,
+// cathode), coarse operators are Galerkin sums with piecewise-constant
+// transfer, smoothing is red-black Gauss-Seidel, the coarse correction is
+// scaled by alpha, and the coarsest level is solved with a dense inverse.
+// Phase-respecting aggregates keep the near-null modes of the potential
+// operator (a constant potential per phase, tied only by the weak interface
+// conductances) exactly representable on every level.
+#include <hip/hip_runtime.h>
+
+#include "mbx_dev.h"
+#include "mbx_kernels.h"
+#include "prof.h"
+
+namespace mbx {
+
+namespace {
+
+__device__ inline int xidx(int s, int t) { return s + t - 1; }   // (0,1)->0 (0,2)->1 (1,2)->2
+
+template <typename KT>
+struct OpV {
+  const KT* p;
+  int n;
+  __device__ KT E(int c, int s) const { return p[(size_t)s * n + c]; }
+  __device__ KT X(int c, int k) const { return p[(size_t)(3 + k) * n + c]; }
+  __device__ KT G(int c, int dir, int s, int t) const { return p[(size_t)(6 + dir * 9 + s * 3 + t) * n + c]; }
+};
+
+// run gate for preconditioner kernels: need >= 0 -> GMRES state == need;
+// need == -1 -> cycle end (state 1 or 2); need == -2 -> always.
+__device__ inline bool gate(const CellDev& cd, int need) {
+  if (!cd.active) return false;
+  if (need == -2) return true;
+  const int st = cd.ictl[CTL_DONE];
+  if (need == -1) return st == 1 || st == 2;
+  return st == need;
+}
+
+template <typename KT>
+__device__ inline KT* vsel(const CellDev& cd, int sel) {
+  const size_t n2 = 2 * (size_t)cd.N;
+  switch (sel) {
+    case VEC_Z: return (KT*)cd.z;
+    case VEC_W: return (KT*)cd.w;
+    case VEC_B: return (KT*)cd.b;
+    case VEC_X: return (KT*)cd.x;
+    default: return (KT*)cd.Vb + (size_t)sel * n2;
+  }
+}
+
+struct C3 {
+  int x, y, z;
+};
+__device__ inline C3 c3_of(int i, int nx, int ny) {
+  C3 c;
+  c.x = i % nx;
+  const int t = i / nx;
+  c.y = t % ny;
+  c.z = t / ny;
+  return c;
+}
+
+// Level-0 conductance of the face between voxel i (label L) and its
+// neighbour k (label Lk) in direction d, for operator op (0 concentration,
+// 1 potential).  Zero when the operator does not couple the two voxels.
+template <typename KT>
+__device__ inline KT fine_cond(const CellDev& cd, int op, int L, int Lk, uint32_t mi, uint32_t mk, int d) {
+  if (L == Lk) {
+    if (op == 0) return (KT)(L == PORE ? cd.Dh : cd.Dsh[L - 1]);
+    return (KT)(L == PORE ? cd.Gk : cd.Gs[L - 1]);
+  }
+  if (op == 0 || (L != PORE && Lk != PORE)) return (KT)0;
+  if (L == PORE) {
+    const uint32_t f = face_rank(mk, d ^ 1);
+    return Lk == ANODE ? ((const KT*)cd.cond_an)[f] : ((const KT*)cd.cond_ca)[f];
+  }
+  const uint32_t f = face_rank(mi, d);
+  return L == ANODE ? ((const KT*)cd.cond_an)[f] : ((const KT*)cd.cond_ca)[f];
+}
+
+template <typename KT>
+__device__ inline KT fine_extra(const CellDev& cd, int op, int L, int z) {
+  if (op == 0) return (KT)1;
+  return (L == ANODE && z == 0) ? (KT)cd.Gcol : (KT)0;
+}
+
+__device__ inline int fine_nbr(int i, const C3& c, int nx, int ny, int nz, int d) {
+  switch (d) {
+    case 0: return c.x > 0 ? i - 1 : -1;
+    case 1: return c.x < nx - 1 ? i + 1 : -1;
+    case 2: return c.y > 0 ? i - nx : -1;
+    case 3: return c.y < ny - 1 ? i + nx : -1;
+    case 4: return c.z > 0 ? i - nx * ny : -1;
+    default: return c.z < nz - 1 ? i + nx * ny : -1;
+  }
+}
+
+__device__ inline int lvl_cell(const MGLevel& L, int x, int y, int z) { return x + L.nx * (y + L.ny * z); }
+
+// (A_l x)(c, s) pieces for a coarse cell: D and the off-diagonal sum
+// sum_j g_j x_j (x read from xs, optionally corrected by alpha * xp[parent]).
+template <typename KT>
+struct CoarseRow {
+  KT D, off;
+};
+
+template <typename KT>
+__device__ inline KT xval(const MGLevel& L, const MGLevel* Lp, int c, int t, int mode, KT alpha) {
+  if (mode == 1) return (KT)0;
+  KT v = ((const KT*)L.x)[(size_t)t * L.ncell + c];
+  if (mode == 2) {
+    const C3 q = c3_of(c, L.nx, L.ny);
+    const int pc = lvl_cell(*Lp, q.x >> 1, q.y >> 1, q.z >> 1);
+    v += alpha * ((const KT*)Lp->x)[(size_t)t * Lp->ncell + pc];
+  }
+  return v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- assembly
+// Level-1 operator from the voxel level: extras summed per slot; faces inside
+// the cell between different slots -> X; faces to the +dir neighbour cell -> G.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mg_assemble0(CellDev* cells, const int2* __restrict__ blk, int op) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active || cd.nlev < 2) return;
+  const MGLevel& L1 = cd.lv[1];
+  const int C = bb.y * kBlock + threadIdx.x;
+  if (C >= L1.ncell) return;
+  const C3 q = c3_of(C, L1.nx, L1.ny);
+  KT E[3] = {0, 0, 0}, X[3] = {0, 0, 0}, G[27];
+  for (int k = 0; k < 27; ++k) G[k] = (KT)0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int fx = 2 * q.x + dx, fy = 2 * q.y + dy, fz = 2 * q.z + dz;
+        if (fx >= cd.nx || fy >= cd.ny || fz >= cd.nz) continue;
+        const int i = fx + cd.nx * (fy + cd.ny * fz);
+        const uint32_t mi = cd.meta[i];
+        const int Li = lab_of(mi);
+        const C3 fc{fx, fy, fz};
+        E[Li] += fine_extra<KT>(cd, op, Li, fz);
+        for (int d = 1; d < 6; d += 2) {   // + directions only: each face counted once
+          const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
+          if (k < 0) continue;
+          const uint32_t mk = cd.meta[k];
+          const int Lk = lab_of(mk);
+          const KT g = fine_cond<KT>(cd, op, Li, Lk, mi, mk, d);
+          if (g == (KT)0) continue;
+          const int dir = d >> 1;
+          const bool inside = (dir == 0 ? dx : dir == 1 ? dy : dz) == 0;
+          if (inside) {
+            if (Li != Lk) X[xidx(Li, Lk)] += g;
+          } else {
+            G[dir * 9 + Li * 3 + Lk] += g;
+          }
+        }
+      }
+  KT* o = (KT*)L1.op[op];
+  const size_t n = L1.ncell;
+  for (int s = 0; s < 3; ++s) o[s * n + C] = E[s];
+  for (int k = 0; k < 3; ++k) o[(3 + k) * n + C] = X[k];
+  for (int k = 0; k < 27; ++k) o[(6 + k) * n + C] = G[k];
+}
+
+// Level l+1 operator from level l (Galerkin sum with piecewise-constant
+// transfer; same-slot couplings inside an aggregate cancel).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mg_assemble(CellDev* cells, const int2* __restrict__ blk, int l, int op) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active || l + 1 >= cd.nlev) return;
+  const MGLevel& Lc = cd.lv[l];
+  const MGLevel& Lp = cd.lv[l + 1];
+  const int P = bb.y * kBlock + threadIdx.x;
+  if (P >= Lp.ncell) return;
+  const C3 q = c3_of(P, Lp.nx, Lp.ny);
+  const OpV<KT> A{(const KT*)Lc.op[op], Lc.ncell};
+  KT E[3] = {0, 0, 0}, X[3] = {0, 0, 0}, G[27];
+  for (int k = 0; k < 27; ++k) G[k] = (KT)0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int cx = 2 * q.x + dx, cy = 2 * q.y + dy, cz = 2 * q.z + dz;
+        if (cx >= Lc.nx || cy >= Lc.ny || cz >= Lc.nz) continue;
+        const int c = lvl_cell(Lc, cx, cy, cz);
+        for (int s = 0; s < 3; ++s) E[s] += A.E(c, s);
+        for (int k = 0; k < 3; ++k) X[k] += A.X(c, k);
+        for (int dir = 0; dir < 3; ++dir) {
+          const int nxp = cx + (dir == 0), nyp = cy + (dir == 1), nzp = cz + (dir == 2);
+          if (nxp >= Lc.nx || nyp >= Lc.ny || nzp >= Lc.nz) continue;
+          const bool inside = (dir == 0 ? dx : dir == 1 ? dy : dz) == 0;
+          for (int s = 0; s < 3; ++s)
+            for (int t = 0; t < 3; ++t) {
+              const KT g = A.G(c, dir, s, t);
+              if (g == (KT)0) continue;
+              if (inside) {
+                if (s != t) X[xidx(s, t)] += g;
+              } else {
+                G[dir * 9 + s * 3 + t] += g;
+              }
+            }
+        }
+      }
+  KT* o = (KT*)Lp.op[op];
+  const size_t n = Lp.ncell;
+  for (int s = 0; s < 3; ++s) o[s * n + P] = E[s];
+  for (int k = 0; k < 3; ++k) o[(3 + k) * n + P] = X[k];
+  for (int k = 0; k < 27; ++k) o[(6 + k) * n + P] = G[k];
+}
+
+// Dense inverse of the coarsest operator (one block per cell, FP64,
+// Gauss-Jordan without pivoting: the operator is symmetric positive
+// definite; empty slots get an identity row).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int ncells, int op) {
+  const int ci = blockIdx.x;
+  if (ci >= ncells) return;
+  const CellDev& cd = cells[ci];
+  if (!cd.active) return;
+  const int lc = cd.nlev - 1;
+  const MGLevel& L = cd.lv[lc];
+  const OpV<KT> A{(const KT*)L.op[op], L.ncell};
+  const int n = 3 * L.ncell;
+  double* M = cd.cinv[op];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = 0.0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const int c = r / 3, s = r % 3;
+    const C3 q = c3_of(c, L.nx, L.ny);
+    double D = (double)A.E(c, s);
+    for (int t = 0; t < 3; ++t)
+      if (t != s) {
+        const double g = (double)A.X(c, xidx(s, t));
+        D += g;
+        M[(size_t)r * n + 3 * c + t] -= g;
+      }
+    for (int dir = 0; dir < 3; ++dir) {
+      const int xp = q.x + (dir == 0), yp = q.y + (dir == 1), zp = q.z + (dir == 2);
+      if (xp < L.nx && yp < L.ny && zp < L.nz) {
+        const int c2 = lvl_cell(L, xp, yp, zp);
+        for (int t = 0; t < 3; ++t) {
+          const double g = (double)A.G(c, dir, s, t);
+          D += g;
+          M[(size_t)r * n + 3 * c2 + t] -= g;
+        }
+      }
+      const int xm = q.x - (dir == 0), ym = q.y - (dir == 1), zm = q.z - (dir == 2);
+      if (xm >= 0 && ym >= 0 && zm >= 0) {
+        const int c2 = lvl_cell(L, xm, ym, zm);
+        for (int t = 0; t < 3; ++t) {
+          const double g = (double)A.G(c2, dir, t, s);
+          D += g;
+          M[(size_t)r * n + 3 * c2 + t] -= g;
+        }
+      }
+    }
+    M[(size_t)r * n + r] = D > 0.0 ? D : 1.0;
+  }
+  __syncthreads();
+  // in-place Gauss-Jordan inversion
+  __shared__ double piv;
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) piv = M[(size_t)k * n + k];
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) M[(size_t)k * n + j] = (j == k ? inv : M[(size_t)k * n + j] * inv);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      if (i == k) continue;
+      const double f = M[(size_t)i * n + k];
+      if (j == k)
+        continue;
+      M[(size_t)i * n + j] -= f * M[(size_t)k * n + j];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      if (i != k) M[(size_t)i * n + k] = -M[(size_t)i * n + k] * M[(size_t)k * n + k];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- V-cycle
+// Level-0 red-black Gauss-Seidel half sweep on operator op; the solution
+// lives in the Krylov vector z (concentration part for op 0, potential part
+// for op 1), the right-hand side in b0.  mode 1: x treated as zero (first
+// sweep); mode 2: neighbours corrected by alpha * (level-1 solution).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mg0_smooth(CellDev* cells, const int2* __restrict__ blk, int op,
+                                                       int color, int mode, int need) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!gate(cd, need)) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const C3 c = c3_of(i, cd.nx, cd.ny);
+  if (((c.x + c.y + c.z) & 1) != color) return;
+  KT* x0 = (KT*)cd.z + (size_t)op * cd.N;
+  const KT* b0 = (const KT*)cd.b0;
+  const uint32_t mi = cd.meta[i];
+  const int L = lab_of(mi);
+  KT D = fine_extra<KT>(cd, op, L, c.z);
+  KT sum = b0[i];
+  const MGLevel& L1 = cd.lv[1];
+  const KT alpha = (KT)cd.alpha;
+  for (int d = 0; d < 6; ++d) {
+    const int k = fine_nbr(i, c, cd.nx, cd.ny, cd.nz, d);
+    if (k < 0) continue;
+    const uint32_t mk = cd.meta[k];
+    const int Lk = lab_of(mk);
+    const KT g = fine_cond<KT>(cd, op, L, Lk, mi, mk, d);
+    if (g == (KT)0) continue;
+    D += g;
+    if (mode != 1) {
+      KT xk = x0[k];
+      if (mode == 2) {
+        const C3 ck = c3_of(k, cd.nx, cd.ny);
+        xk += alpha * ((const KT*)L1.x)[(size_t)Lk * L1.ncell + lvl_cell(L1, ck.x >> 1, ck.y >> 1, ck.z >> 1)];
+      }
+      sum += g * xk;
+    }
+  }
+  x0[i] = D > (KT)0 ? sum / D : (KT)0;
+}
+
+// Level-0 residual restricted to level 1 (sum per slot over the cell's voxels).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const int2* __restrict__ blk, int op,
+                                                         int need) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!gate(cd, need)) return;
+  const MGLevel& L1 = cd.lv[1];
+  const int C = bb.y * kBlock + threadIdx.x;
+  if (C >= L1.ncell) return;
+  const C3 q = c3_of(C, L1.nx, L1.ny);
+  const KT* x0 = (const KT*)cd.z + (size_t)op * cd.N;
+  const KT* b0 = (const KT*)cd.b0;
+  KT rs[3] = {0, 0, 0};
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int fx = 2 * q.x + dx, fy = 2 * q.y + dy, fz = 2 * q.z + dz;
+        if (fx >= cd.nx || fy >= cd.ny || fz >= cd.nz) continue;
+        const int i = fx + cd.nx * (fy + cd.ny * fz);
+        const uint32_t mi = cd.meta[i];
+        const int L = lab_of(mi);
+        const C3 fc{fx, fy, fz};
+        const KT xi = x0[i];
+        KT r = b0[i] - fine_extra<KT>(cd, op, L, fz) * xi;
+        for (int d = 0; d < 6; ++d) {
+          const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
+          if (k < 0) continue;
+          const uint32_t mk = cd.meta[k];
+          const KT g = fine_cond<KT>(cd, op, L, lab_of(mk), mi, mk, d);
+          if (g == (KT)0) continue;
+          r -= g * (xi - x0[k]);
+        }
+        rs[L] += r;
+      }
+  KT* b1 = (KT*)L1.b;
+  for (int s = 0; s < 3; ++s) b1[(size_t)s * L1.ncell + C] = rs[s];
+}
+
+// Coarse-level (l >= 1) red-black Gauss-Seidel half sweep; slots of one
+// cell are relaxed in order.  mode as for k_mg0_smooth (mode 2 reads the
+// level l+1 solution for the coarse correction); mode 3 is the first black
+// sweep of a cycle: neighbours (red, just written) are read, the cell's own
+// slots start from zero.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int2* __restrict__ blk, int l, int op,
+                                                       int color, int mode, int need) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!gate(cd, need) || l >= cd.nlev - 1) return;
+  const MGLevel& L = cd.lv[l];
+  const MGLevel* Lp = &cd.lv[l + 1];
+  const int C = bb.y * kBlock + threadIdx.x;
+  if (C >= L.ncell) return;
+  const C3 q = c3_of(C, L.nx, L.ny);
+  if (((q.x + q.y + q.z) & 1) != color) return;
+  const OpV<KT> A{(const KT*)L.op[op], L.ncell};
+  const KT* b = (const KT*)L.b;
+  KT* x = (KT*)L.x;
+  const KT alpha = (KT)cd.alpha;
+  // own slots: mode 1 and 3 (first sweeps of a V-cycle) start from zero,
+  // since this cell has not been written in the current cycle
+  KT xs[3];
+  for (int t = 0; t < 3; ++t) xs[t] = mode == 3 ? (KT)0 : xval<KT>(L, Lp, C, t, mode, alpha);
+  for (int s = 0; s < 3; ++s) {
+    KT D = A.E(C, s), sum = b[(size_t)s * L.ncell + C];
+    for (int t = 0; t < 3; ++t)
+      if (t != s) {
+        const KT g = A.X(C, xidx(s, t));
+        D += g;
+        sum += g * xs[t];
+      }
+    for (int dir = 0; dir < 3; ++dir) {
+      const int xp = q.x + (dir == 0), yp = q.y + (dir == 1), zp = q.z + (dir == 2);
+      if (xp < L.nx && yp < L.ny && zp < L.nz) {
+        const int c2 = lvl_cell(L, xp, yp, zp);
+        for (int t = 0; t < 3; ++t) {
+          const KT g = A.G(C, dir, s, t);
+          if (g == (KT)0) continue;
+          D += g;
+          sum += g * xval<KT>(L, Lp, c2, t, mode == 3 ? 0 : mode, alpha);
+        }
+      }
+      const int xm = q.x - (dir == 0), ym = q.y - (dir == 1), zm = q.z - (dir == 2);
+      if (xm >= 0 && ym >= 0 && zm >= 0) {
+        const int c2 = lvl_cell(L, xm, ym, zm);
+        for (int t = 0; t < 3; ++t) {
+          const KT g = A.G(c2, dir, t, s);
+          if (g == (KT)0) continue;
+          D += g;
+          sum += g * xval<KT>(L, Lp, c2, t, mode == 3 ? 0 : mode, alpha);
+        }
+      }
+    }
+    xs[s] = D > (KT)0 ? sum / D : (KT)0;
+  }
+  for (int s = 0; s < 3; ++s) x[(size_t)s * L.ncell + C] = xs[s];
+}
+
+// Level-l residual restricted to level l+1.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const int2* __restrict__ blk, int l, int op,
+                                                         int need) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!gate(cd, need) || l + 1 >= cd.nlev) return;
+  const MGLevel& L = cd.lv[l];
+  const MGLevel& Lp = cd.lv[l + 1];
+  const int P = bb.y * kBlock + threadIdx.x;
+  if (P >= Lp.ncell) return;
+  const C3 q = c3_of(P, Lp.nx, Lp.ny);
+  const OpV<KT> A{(const KT*)L.op[op], L.ncell};
+  const KT* b = (const KT*)L.b;
+  const KT* x = (const KT*)L.x;
+  const size_t n = L.ncell;
+  KT rs[3] = {0, 0, 0};
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int cx = 2 * q.x + dx, cy = 2 * q.y + dy, cz = 2 * q.z + dz;
+        if (cx >= L.nx || cy >= L.ny || cz >= L.nz) continue;
+        const int c = lvl_cell(L, cx, cy, cz);
+        for (int s = 0; s < 3; ++s) {
+          const KT xsv = x[s * n + c];
+          KT r = b[s * n + c] - A.E(c, s) * xsv;
+          for (int t = 0; t < 3; ++t)
+            if (t != s) r -= A.X(c, xidx(s, t)) * (xsv - x[t * n + c]);
+          for (int dir = 0; dir < 3; ++dir) {
+            const int xp = cx + (dir == 0), yp = cy + (dir == 1), zp = cz + (dir == 2);
+            if (xp < L.nx && yp < L.ny && zp < L.nz) {
+              const int c2 = lvl_cell(L, xp, yp, zp);
+              for (int t = 0; t < 3; ++t) r -= A.G(c, dir, s, t) * (xsv - x[t * n + c2]);
+            }
+            const int xm = cx - (dir == 0), ym = cy - (dir == 1), zm = cz - (dir == 2);
+            if (xm >= 0 && ym >= 0 && zm >= 0) {
+              const int c2 = lvl_cell(L, xm, ym, zm);
+              for (int t = 0; t < 3; ++t) r -= A.G(c2, dir, t, s) * (xsv - x[t * n + c2]);
+            }
+          }
+          rs[s] += r;
+        }
+      }
+  KT* bp = (KT*)Lp.b;
+  for (int s = 0; s < 3; ++s) bp[(size_t)s * Lp.ncell + P] = rs[s];
+}
+
+// Coarsest level: x = M^-1 b (one block per cell, FP64 accumulation).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mg_coarse_apply(CellDev* cells, int ncells, int op, int need) {
+  const int ci = blockIdx.x;
+  if (ci >= ncells) return;
+  const CellDev& cd = cells[ci];
+  if (!gate(cd, need)) return;
+  const MGLevel& L = cd.lv[cd.nlev - 1];
+  const int n = 3 * L.ncell;
+  __shared__ double bs[3 * kCoarseMaxCells];
+  const KT* b = (const KT*)L.b;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const int c = r / 3, s = r % 3;
+    bs[r] = (double)b[(size_t)s * L.ncell + c];
+  }
+  __syncthreads();
+  const double* M = cd.cinv[op];
+  KT* x = (KT*)L.x;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += M[(size_t)r * n + j] * bs[j];
+    const int c = r / 3, s = r % 3;
+    x[(size_t)s * L.ncell + c] = (KT)acc;
+  }
+}
+
+// ----------------------------------------------------- block-triangular glue
+// b0 = v_c - tau * v_phi on pore voxels (row operation removing migration).
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_pc_pre(CellDev* cells, const int2* __restrict__ blk, int src, int need) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!gate(cd, need)) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const KT* v = vsel<KT>(cd, src);
+  const uint32_t mi = cd.meta[i];
+  const int L = lab_of(mi);
+  // undo the row weights of the Krylov system: the multigrid solves the
+  // unweighted scaled operator
+  double wc = 1.0, wp = 0.0;
+  const C3 c = c3_of(i, cd.nx, cd.ny);
+  for (int d = 0; d < 6; ++d) {
+    const int k = fine_nbr(i, c, cd.nx, cd.ny, cd.nz, d);
+    if (k >= 0) weight_add(cd, L, lab_of(cd.meta[k]), wc, wp);
+  }
+  weight_finish(cd, L, c.z, wc, wp);
+  KT r = v[i] / (KT)wc;
+  if (L == PORE) r -= (KT)cd.tau * (v[(size_t)cd.N + i] / (KT)wp);
+  ((KT*)cd.b0)[i] = r;
+}
+
+// b0 = v_phi - (J [z_c; 0])_phi: the potential rows' dependence on the
+// concentration correction (electrolyte dln c/dc term and Butler-Volmer /
+// plating concentration derivatives) moved to the right-hand side.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* __restrict__ blk, int src, int need) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!gate(cd, need)) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const size_t N = cd.N;
+  const KT* v = vsel<KT>(cd, src);
+  const KT* zc = (const KT*)cd.z;
+  const KT* wpo = (const KT*)cd.wpore;
+  const KT* can = (const KT*)cd.coef_an;
+  const KT* cca = (const KT*)cd.coef_ca;
+  const C3 c = c3_of(i, cd.nx, cd.ny);
+  const uint32_t mi = cd.meta[i];
+  const int L = lab_of(mi);
+  const KT vc = zc[i];
+  const KT wi = (L == PORE) ? wpo[i] : (KT)0;
+  const KT Gt = (KT)(cd.Gk * cd.tth);
+  KT yp = (KT)0;
+  double wc = 1.0, wp = 0.0;
+  for (int d = 0; d < 6; ++d) {
+    const int k = fine_nbr(i, c, cd.nx, cd.ny, cd.nz, d);
+    if (k < 0) continue;
+    const uint32_t mk = cd.meta[k];
+    const int Lk = lab_of(mk);
+    weight_add(cd, L, Lk, wc, wp);
+    const KT vck = zc[k];
+    if (L == PORE && Lk == PORE) {
+      yp += Gt * (wpo[k] * vck - wi * vc);   // outward dj from i with v_phi = 0
+    } else if (L == PORE && Lk != PORE) {
+      const uint32_t f = face_rank(mk, d ^ 1);
+      KT q;
+      if (Lk == ANODE) {
+        const KT* co = can + 5 * (size_t)f;
+        q = co[0] * vck + co[1] * vc + co[3] * vc;
+      } else {
+        const KT* co = cca + 3 * (size_t)f;
+        q = co[0] * vck + co[1] * vc;
+      }
+      yp -= q;
+    } else if (L != PORE && Lk == PORE) {
+      const uint32_t f = face_rank(mi, d);
+      KT q;
+      if (L == ANODE) {
+        const KT* co = can + 5 * (size_t)f;
+        q = co[0] * vc + co[1] * vck + co[3] * vck;
+      } else {
+        const KT* co = cca + 3 * (size_t)f;
+        q = co[0] * vc + co[1] * vck;
+      }
+      yp += q;
+    }
+  }
+  weight_finish(cd, L, c.z, wc, wp);
+  ((KT*)cd.b0)[i] = v[N + i] / (KT)wp - yp;
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename KT>
+void launch_mg_setup(const BatchLaunch& b, hipStream_t s) {
+  for (int op = 0; op < 2; ++op) {
+    k_mg_assemble0<KT><<<b.lvl_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl_blk[1], op);
+    for (int l = 1; l + 1 < b.maxlev; ++l)
+      k_mg_assemble<KT><<<b.lvl_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl_blk[l + 1], l, op);
+    k_mg_coarse_build<KT><<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, op);
+  }
+}
+
+template <typename KT>
+static void smooth0(const BatchLaunch& b, int op, int color, int mode, int need, hipStream_t s) {
+  prof_begin(PK_SMOOTH0, s);
+  k_mg0_smooth<KT><<<b.nblk, kBlock, 0, s>>>(b.cells, b.blk, op, color, mode, need);
+  if (prof_on(PK_SMOOTH0)) prof_end(PK_SMOOTH0, s, b.bytes_smooth0);
+}
+
+template <typename KT>
+static void vcycle(const BatchLaunch& b, int op, int nu, int need, hipStream_t s) {
+  const int top = b.maxlev - 1;   // deepest coarsest level over the batch
+  // descend
+  for (int l = 0; l < top; ++l) {
+    for (int it = 0; it < nu; ++it) {
+      if (l == 0) {
+        smooth0<KT>(b, op, 0, it == 0 ? 1 : 0, need, s);
+        smooth0<KT>(b, op, 1, 0, need, s);
+      } else {
+        k_mgl_smooth<KT><<<b.lvl_nblk[l], kBlock, 0, s>>>(b.cells, b.lvl_blk[l], l, op, 0, it == 0 ? 1 : 0, need);
+        k_mgl_smooth<KT><<<b.lvl_nblk[l], kBlock, 0, s>>>(b.cells, b.lvl_blk[l], l, op, 1, it == 0 ? 3 : 0, need);
+      }
+    }
+    if (l == 0)
+      k_mg0_restrict<KT><<<b.lvl_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl_blk[1], op, need);
+    else
+      k_mgl_restrict<KT><<<b.lvl_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl_blk[l + 1], l, op, need);
+  }
+  k_mg_coarse_apply<KT><<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, op, need);
+  // ascend (first post-smoothing half sweep applies the coarse correction)
+  for (int l = top - 1; l >= 0; --l) {
+    for (int it = 0; it < nu; ++it) {
+      if (l == 0) {
+        smooth0<KT>(b, op, 1, it == 0 ? 2 : 0, need, s);
+        smooth0<KT>(b, op, 0, 0, need, s);
+      } else {
+        k_mgl_smooth<KT><<<b.lvl_nblk[l], kBlock, 0, s>>>(b.cells, b.lvl_blk[l], l, op, 1, it == 0 ? 2 : 0, need);
+        k_mgl_smooth<KT><<<b.lvl_nblk[l], kBlock, 0, s>>>(b.cells, b.lvl_blk[l], l, op, 0, 0, need);
+      }
+    }
+  }
+}
+
+template <typename KT>
+void launch_precond(const BatchLaunch& b, int src, int nu, int need, hipStream_t s) {
+  prof_begin(PK_PRECOND, s);
+  k_pc_pre<KT><<<b.nblk, kBlock, 0, s>>>(b.cells, b.blk, src, need);
+  vcycle<KT>(b, 0, nu, need, s);
+  k_pc_mid<KT><<<b.nblk, kBlock, 0, s>>>(b.cells, b.blk, src, need);
+  vcycle<KT>(b, 1, nu, need, s);
+  if (prof_on(PK_PRECOND)) prof_end(PK_PRECOND, s, 0.0);
+}
+
+template void launch_mg_setup<float>(const BatchLaunch&, hipStream_t);
+template void launch_mg_setup<double>(const BatchLaunch&, hipStream_t);
+template void launch_precond<float>(const BatchLaunch&, int, int, int, hipStream_t);
+template void launch_precond<double>(const BatchLaunch&, int, int, int, hipStream_t);
+
+}  // namespace mbx

@@ -1,0 +1,17 @@
+// prof.h — opt-in per-kernel timing with HIP events on the launch stream.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbx {
+
+enum ProfKernel { PK_NONE = 0, PK_RESIDUAL = 1, PK_MATVEC = 2, PK_SMOOTH0 = 3, PK_PRECOND = 4 };
+
+// True when launches of kernel class k are being timed.
+bool prof_on(int k);
+// Brackets one launch: records an event pair on stream s and the launch's
+// algorithmic bytes.
+void prof_begin(int k, hipStream_t s);
+void prof_end(int k, hipStream_t s, double bytes);
+
+}  // namespace mbx

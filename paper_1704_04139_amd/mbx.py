@@ -67,9 +67,13 @@ SIGNATURES = {
     "mbx_cell_inventory": (_i, [_vp, _dp]),
     "mbx_cell_residual": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp]),
     "mbx_cell_jvp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]),
+    "mbx_cell_precond": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]),
+    "mbx_cell_solve": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _d, _vp, ctypes.POINTER(_i)]),
     "mbx_batch_step": (_i, [ctypes.POINTER(_vp), _i, _d, ctypes.POINTER(_i), ctypes.POINTER(StepInfo)]),
     "mbx_cell_footprint": (ctypes.c_int64, [_i, _i, _i, _i, _i, _i]),
     "mbx_last_error": (ctypes.c_char_p, []),
+    "mbx_profile": (_i, [_i]),
+    "mbx_profile_read": (_i, [ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
 }
 
 
@@ -215,6 +219,30 @@ class Cell:
         return y
 
 
+def _probe(fn, cell, c, p, n, c_old, n_old, dt, v):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (c, p, n, c_old, n_old)]
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    y = np.empty(2 * cell.counts.n_vox)
+    _check(fn(cell.handle, *[_ptr(a) for a in arrs], float(dt), _ptr(v), _ptr(y)))
+    return y
+
+
+def precond(cell, c, p, n, c_old, n_old, dt, v):
+    """z = M^-1 v with the solver's preconditioner at the given state."""
+    return _probe(load().mbx_cell_precond, cell, c, p, n, c_old, n_old, dt, v)
+
+
+def solve(cell, c, p, n, c_old, n_old, dt, rhs, rtol):
+    """x with J_hat x = rhs by the solver's GMRES; returns (x, iterations)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (c, p, n, c_old, n_old)]
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+    x = np.empty(2 * cell.counts.n_vox)
+    its = _i()
+    _check(load().mbx_cell_solve(cell.handle, *[_ptr(a) for a in arrs], float(dt), _ptr(rhs), float(rtol),
+                                 _ptr(x), ctypes.byref(its)))
+    return x, its.value
+
+
 def batch_step(cells, dt: float):
     """Step several cells in shared launches; returns (status list, info dicts)."""
     lib = load()
@@ -224,6 +252,24 @@ def batch_step(cells, dt: float):
     infos = (StepInfo * n)()
     _check(lib.mbx_batch_step(hs, n, float(dt), st, infos))
     return list(st), [infos[k].as_dict() for k in range(n)]
+
+
+PROFILE_KERNELS = {"residual": 1, "matvec": 2, "smooth0": 3, "precond": 4}
+
+
+def profile(kernel):
+    """Start timing launches of one kernel class (name or id; None stops)."""
+    k = 0 if kernel is None else PROFILE_KERNELS.get(kernel, kernel)
+    _check(load().mbx_profile(int(k)))
+
+
+def profile_read():
+    """(launches, total ms, total algorithmic bytes) of the timed launches."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(load().mbx_profile_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
 
 
 def footprint(nx, ny, nz, precision="fp64", n_an_faces=0, n_ca_faces=0) -> int:

@@ -311,3 +311,30 @@ def test_batch_equals_alone(mbx):
     for c, ref in zip(cells, alone):
         for x, y in zip(c.get_state(), ref):
             np.testing.assert_allclose(x, y, rtol=1e-12, atol=0)
+
+
+def test_no_read_before_write(mbx, monkeypatch):
+    """Cells whose device memory starts as NaN bytes step to bit-identical
+    results (any read of an unwritten buffer would propagate NaN)."""
+    ws = I.config3(n_cells=3, scale=4)
+    ref_cells = [mbx.Cell(w.labels, w.params, precision="mixed") for w in ws]
+    st, _ = mbx.batch_step(ref_cells, ws[0].dt)
+    assert st == [0, 0, 0]
+    ref = [c.get_state() for c in ref_cells]
+    for c in ref_cells:
+        c.close()
+    monkeypatch.setenv("MBX_POISON", "1")
+    cells = [mbx.Cell(w.labels, w.params, precision="mixed") for w in ws]
+    st, _ = mbx.batch_step(cells, ws[0].dt)
+    assert st == [0, 0, 0]
+    for c, r in zip(cells, ref):
+        for x, y in zip(c.get_state(), r):
+            assert np.array_equal(x, y)
+    w = I.config0()
+    a = mbx.Cell(w.labels, w.params, precision="fp64")
+    a.step(w.dt)
+    monkeypatch.delenv("MBX_POISON")
+    b = mbx.Cell(w.labels, w.params, precision="fp64")
+    b.step(w.dt)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
