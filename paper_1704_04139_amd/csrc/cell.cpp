@@ -76,6 +76,7 @@ struct Layout {
 
 struct LevelDims {
   int n = 0;                       // number of levels incl. the voxel level
+  int lfuse = 1;                   // first level small enough to run inside one workgroup
   int nx[kMaxLevels], ny[kMaxLevels], nz[kMaxLevels], ncell[kMaxLevels];
 };
 
@@ -97,6 +98,8 @@ LevelDims level_dims(int nx, int ny, int nz) {
     d.n++;
     if (d.ncell[l] <= kCoarseMaxCells) break;
   }
+  d.lfuse = d.n - 1;
+  while (d.lfuse > 1 && d.ncell[d.lfuse - 1] <= kFuseMaxCells) --d.lfuse;
   return d;
 }
 
@@ -120,6 +123,8 @@ struct mbx_cell {
   LevelDims ld;
   int2* lvl_blk[kMaxLevels] = {};
   int lvl_nblk[kMaxLevels] = {};
+  int2* lvl8_blk[kMaxLevels] = {};
+  int lvl8_nblk[kMaxLevels] = {};
 };
 
 namespace {
@@ -154,13 +159,14 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   const int nc = ld.ncell[ld.n - 1];
   L.add(8 * (size_t)9 * nc * nc);             // 39 cinv[0]
   L.add(8 * (size_t)9 * nc * nc);             // 40 cinv[1]
-  for (int l = 1; l < ld.n; ++l) {            // 41 + 5(l-1): x, b, op0, op1, blk
+  for (int l = 1; l < ld.n; ++l) {            // 41 + 6(l-1): x, b, op0, op1, blk, blk8
     const size_t n = ld.ncell[l];
     L.add(3 * n * kt);
     L.add(3 * n * kt);
     L.add(kOpStride * n * kt);
     L.add(kOpStride * n * kt);
     L.add(sizeof(int2) * ((n + kBlock - 1) / kBlock));
+    L.add(sizeof(int2) * ((8 * n + kBlock - 1) / kBlock));
   }
   return L;
 }
@@ -248,8 +254,11 @@ struct Batch {
   int m = kRestart;
   int nu = 2;
   int maxlev = 0;
+  int maxfuse = 1;
   int2* lvl_blk[kMaxLevels] = {};
   int lvl_nblk[kMaxLevels] = {};
+  int2* lvl8_blk[kMaxLevels] = {};
+  int lvl8_nblk[kMaxLevels] = {};
   BatchLaunch bl() const {
     BatchLaunch b{};
     for (const mbx_cell* c : cells) {
@@ -264,9 +273,12 @@ struct Batch {
     b.nblk = nblk;
     b.ncell = (int)cells.size();
     b.maxlev = maxlev;
+    b.maxfuse = maxfuse;
     for (int l = 0; l < kMaxLevels; ++l) {
       b.lvl_blk[l] = lvl_blk[l];
       b.lvl_nblk[l] = lvl_nblk[l];
+      b.lvl8_blk[l] = lvl8_blk[l];
+      b.lvl8_nblk[l] = lvl8_nblk[l];
     }
     return b;
   }
@@ -290,8 +302,10 @@ struct Batch {
     hipFree(d_desc);
     hipFree(d_blk);
     hipFree(d_gather);
-    for (int l = 1; l < kMaxLevels; ++l)
-      if (lvl_blk[l]) hipFree(lvl_blk[l]);
+    for (int l = 1; l < kMaxLevels; ++l) {
+      if (lvl_blk[l]) (void)hipFree(lvl_blk[l]);
+      if (lvl8_blk[l]) (void)hipFree(lvl8_blk[l]);
+    }
     hipHostFree(h_desc);
     hipHostFree(h_gather);
     owned = false;
@@ -311,9 +325,12 @@ Batch single(mbx_cell* c) {
   b.mixed = c->mixed;
   b.m = c->m;
   b.maxlev = c->ld.n;
+  b.maxfuse = c->ld.lfuse;
   for (int l = 1; l < c->ld.n; ++l) {
     b.lvl_blk[l] = c->lvl_blk[l];
     b.lvl_nblk[l] = c->lvl_nblk[l];
+    b.lvl8_blk[l] = c->lvl8_blk[l];
+    b.lvl8_nblk[l] = c->lvl8_nblk[l];
   }
   return b;
 }
@@ -341,15 +358,23 @@ int make_batch(mbx_cell* const* cells, int n, Batch& out) {
   for (int c = 0; c < n; ++c)
     for (int k = 0; k < cells[c]->nblk; ++k) tab.push_back(make_int2(c, k));
   b.nblk = (int)tab.size();
-  for (int c = 0; c < n; ++c) b.maxlev = std::max(b.maxlev, cells[c]->ld.n);
+  for (int c = 0; c < n; ++c) {
+    b.maxlev = std::max(b.maxlev, cells[c]->ld.n);
+    b.maxfuse = std::max(b.maxfuse, cells[c]->ld.lfuse);
+  }
   for (int l = 1; l < b.maxlev; ++l) {
-    std::vector<int2> lt;
-    for (int c = 0; c < n; ++c)
-      if (l < cells[c]->ld.n)
-        for (int k = 0; k < cells[c]->lvl_nblk[l]; ++k) lt.push_back(make_int2(c, k));
-    b.lvl_nblk[l] = (int)lt.size();
-    HIPCHK(hipMalloc(&b.lvl_blk[l], sizeof(int2) * std::max<size_t>(lt.size(), 1)));
-    HIPCHK(hipMemcpyAsync(b.lvl_blk[l], lt.data(), sizeof(int2) * lt.size(), hipMemcpyHostToDevice, b.s));
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<int2> lt;
+      for (int c = 0; c < n; ++c)
+        if (l < cells[c]->ld.n) {
+          const int nb = pass == 0 ? cells[c]->lvl_nblk[l] : cells[c]->lvl8_nblk[l];
+          for (int k = 0; k < nb; ++k) lt.push_back(make_int2(c, k));
+        }
+      int2*& dst = pass == 0 ? b.lvl_blk[l] : b.lvl8_blk[l];
+      (pass == 0 ? b.lvl_nblk[l] : b.lvl8_nblk[l]) = (int)lt.size();
+      HIPCHK(hipMalloc(&dst, sizeof(int2) * std::max<size_t>(lt.size(), 1)));
+      HIPCHK(hipMemcpyAsync(dst, lt.data(), sizeof(int2) * lt.size(), hipMemcpyHostToDevice, b.s));
+    }
   }
   HIPCHK(hipMalloc(&b.d_desc, sizeof(CellDev) * n));
   HIPCHK(hipMalloc(&b.d_blk, sizeof(int2) * tab.size()));
@@ -774,6 +799,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.cinv[0] = (double*)(b + L.off[39]);
   h.cinv[1] = (double*)(b + L.off[40]);
   h.nlev = c->ld.n;
+  h.lfuse = c->ld.lfuse;
   h.alpha = g_mg_alpha();
   h.nu = 2;
   h.lv[0].nx = nx;
@@ -781,7 +807,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.lv[0].nz = nz;
   h.lv[0].ncell = N;
   for (int l = 1; l < c->ld.n; ++l) {
-    const int o = 41 + 5 * (l - 1);
+    const int o = 41 + 6 * (l - 1);
     MGLevel& lv = h.lv[l];
     lv.nx = c->ld.nx[l];
     lv.ny = c->ld.ny[l];
@@ -793,6 +819,8 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
     lv.op[1] = b + L.off[o + 3];
     c->lvl_blk[l] = (int2*)(b + L.off[o + 4]);
     c->lvl_nblk[l] = (lv.ncell + kBlock - 1) / kBlock;
+    c->lvl8_blk[l] = (int2*)(b + L.off[o + 5]);
+    c->lvl8_nblk[l] = (8 * lv.ncell + kBlock - 1) / kBlock;
   }
   h.m = c->m;
   h.lam = 1.0;
@@ -813,11 +841,16 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   if (e == hipSuccess) e = hipMemsetAsync(h.ictl, 0, 4 * CTL_NSLOT, s);
   if (e == hipSuccess) e = hipMemsetAsync(h.red, 0, 8 * RED_NSLOT, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->d_blk, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice, s);
-  std::vector<std::vector<int2>> ltabs(c->ld.n);
+  std::vector<std::vector<int2>> ltabs(2 * c->ld.n);
   for (int l = 1; l < c->ld.n && e == hipSuccess; ++l) {
-    ltabs[l].resize(c->lvl_nblk[l]);
-    for (int k = 0; k < c->lvl_nblk[l]; ++k) ltabs[l][k] = make_int2(0, k);
-    e = hipMemcpyAsync(c->lvl_blk[l], ltabs[l].data(), sizeof(int2) * ltabs[l].size(), hipMemcpyHostToDevice, s);
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+      const int nb = pass == 0 ? c->lvl_nblk[l] : c->lvl8_nblk[l];
+      std::vector<int2>& t = ltabs[2 * l + pass];
+      t.resize(nb);
+      for (int k = 0; k < nb; ++k) t[k] = make_int2(0, k);
+      e = hipMemcpyAsync(pass == 0 ? c->lvl_blk[l] : c->lvl8_blk[l], t.data(), sizeof(int2) * t.size(),
+                         hipMemcpyHostToDevice, s);
+    }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup_tmp();

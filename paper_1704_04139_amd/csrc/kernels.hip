@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
     }
   }
   const double vals[4] = {rsq, rmax, msq, dnmax};
-  reduce_cell<4>(cdp, bb.y, vals, 0xAu, cd.red + RED_RSQ);
+  reduce_block<4>(cd, bb.y, vals, 0xAu);
 }
 
 // Right-hand side of the condensed, scaled Newton system:
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __re
     ss = bcr * bcr + bpr * bpr;
   }
   const double vals[1] = {ss};
-  reduce_cell<1>(cdp, bb.y, vals, 0u, cd.red + RED_BSQ);
+  reduce_block<1>(cd, bb.y, vals, 0u);
 }
 
 // ---------------------------------------------------------- preconditioner
@@ -428,54 +428,58 @@ __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* _
 }
 
 // ------------------------------------------------------------------- GMRES
-// Dots of w with basis vectors 0..k into H(:,k) (tgt = 0) or tmp (tgt = 1).
+// Dots of w with basis vectors 0..k: block partials (first pass).
 template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_multidot(CellDev* cells, const int2* __restrict__ blk, int k, int tgt) {
+__global__ void __launch_bounds__(kBlock) k_multidot(CellDev* cells, const int2* __restrict__ blk, int k) {
   const int2 bb = blk[blockIdx.x];
-  CellDev* cdp = cells + bb.x;
-  const CellDev& cd = *cdp;
+  const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE]) return;
-  __shared__ double lds4[4];
-  __shared__ bool flag;
+  __shared__ double lds[4 * kPartStride];
   const int i = bb.y * kBlock + threadIdx.x;
   const size_t N = cd.N;
   double wc = 0.0, wp = 0.0;
-  if (i < cd.N) {
+  const bool in = i < cd.N;
+  if (in) {
     const KT* w = (const KT*)cd.w;
     wc = (double)w[i];
     wp = (double)w[N + i];
   }
   for (int j = 0; j <= k; ++j) {
     double s = 0.0;
-    if (i < cd.N) {
+    if (in) {
       const KT* vj = vec<KT>(cd, j);
       s = (double)vj[i] * wc + (double)vj[N + i] * wp;
     }
-    const double r = block_sum(s, lds4);
-    if (threadIdx.x == 0) part_store(&cd.part[(size_t)bb.y * kPartStride + j], r);
+    wave_to_lds(s, false, lds, kPartStride, j);
   }
-  if (!take_ticket(cdp, &flag)) return;
+  __syncthreads();
+  for (int j = threadIdx.x; j <= k; j += kBlock)
+    cd.part[(size_t)bb.y * kPartStride + j] = combine4(lds, kPartStride, j, false);
+}
+
+// Second pass of k_multidot: H(:,k) (tgt = 0) or tmp (tgt = 1).
+__global__ void __launch_bounds__(kBlock) k_finalize_dots(CellDev* cells, int ncell, int k, int tgt) {
+  const int ci = blockIdx.x;
+  if (ci >= ncell) return;
+  const CellDev& cd = cells[ci];
+  if (!cd.active || cd.ictl[CTL_DONE]) return;
+  __shared__ double lds4[4];
+  __shared__ double res;
   const int m = cd.m;
   double* out = tgt == 0 ? cd.gm + gm_H(m) + (size_t)(m + 1) * k : cd.gm + gm_tmp(m);
   for (int j = 0; j <= k; ++j) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < cd.nblk; b += kBlock) acc += part_load(&cd.part[(size_t)b * kPartStride + j]);
-    acc = block_sum(acc, lds4);
-    if (threadIdx.x == 0) out[j] = acc;
+    const double r = finalize_column(cd, j, false, lds4, &res);
+    if (threadIdx.x == 0) out[j] = r;
   }
-  release_ticket(cdp);
 }
 
-// w -= sum_j h_j V_j with h = H(:,k) (src = 0) or tmp (src = 1; then H(:,k)
-// += tmp); ||w||^2 into H(k+1,k).
+// w -= sum_j h_j V_j with h = H(:,k) (src = 0) or tmp (src = 1); block
+// partials of ||w||^2 (first pass).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_orth(CellDev* cells, const int2* __restrict__ blk, int k, int src) {
   const int2 bb = blk[blockIdx.x];
-  CellDev* cdp = cells + bb.x;
-  const CellDev& cd = *cdp;
+  const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE]) return;
-  __shared__ double lds4[4];
-  __shared__ bool flag;
   const int m = cd.m;
   const double* hc = src == 0 ? cd.gm + gm_H(m) + (size_t)(m + 1) * k : cd.gm + gm_tmp(m);
   const int i = bb.y * kBlock + threadIdx.x;
@@ -494,19 +498,46 @@ __global__ void __launch_bounds__(kBlock) k_orth(CellDev* cells, const int2* __r
     w[N + i] = wp;
     ss = (double)wc * (double)wc + (double)wp * (double)wp;
   }
-  const double r = block_sum(ss, lds4);
-  if (threadIdx.x == 0) part_store(&cd.part[(size_t)bb.y * kPartStride], r);
-  if (!take_ticket(cdp, &flag)) return;
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < cd.nblk; b += kBlock) acc += part_load(&cd.part[(size_t)b * kPartStride]);
-  acc = block_sum(acc, lds4);
+  const double vals[1] = {ss};
+  reduce_block<1>(cd, bb.y, vals, 0u);
+}
+
+// Second pass of k_orth: H(k+1,k) = ||w|| (src = 1 also adds tmp to H(:,k)).
+__global__ void __launch_bounds__(kBlock) k_finalize_norm(CellDev* cells, int ncell, int k, int src) {
+  const int ci = blockIdx.x;
+  if (ci >= ncell) return;
+  const CellDev& cd = cells[ci];
+  if (!cd.active || cd.ictl[CTL_DONE]) return;
+  __shared__ double lds4[4];
+  __shared__ double res;
+  const double acc = finalize_column(cd, 0, false, lds4, &res);
   if (threadIdx.x == 0) {
+    const int m = cd.m;
     double* H = cd.gm + gm_H(m) + (size_t)(m + 1) * k;
-    if (src == 1)
-      for (int j = 0; j <= k; ++j) H[j] += hc[j];
+    if (src == 1) {
+      const double* tmp = cd.gm + gm_tmp(m);
+      for (int j = 0; j <= k; ++j) H[j] += tmp[j];
+    }
     H[k + 1] = sqrt(acc);
   }
-  release_ticket(cdp);
+}
+
+// Second pass of the voxel-block reductions: partial columns 0..K-1 into
+// red[slot..slot+K) (bit j of maxmask: max, else sum).  need: -3 any active
+// cell, otherwise only cells whose GMRES state equals need.
+__global__ void __launch_bounds__(kBlock) k_finalize_red(CellDev* cells, int ncell, int slot, int K, unsigned maxmask,
+                                                         int need) {
+  const int ci = blockIdx.x;
+  if (ci >= ncell) return;
+  const CellDev& cd = cells[ci];
+  if (!cd.active) return;
+  if (need != -3 && cd.ictl[CTL_DONE] != need) return;
+  __shared__ double lds4[4];
+  __shared__ double res;
+  for (int j = 0; j < K; ++j) {
+    const double r = finalize_column(cd, j, (maxmask >> j) & 1u, lds4, &res);
+    if (threadIdx.x == 0) cd.red[slot + j] = r;
+  }
 }
 
 // V_{k+1} = w / H(k+1,k)
@@ -672,7 +703,7 @@ __global__ void __launch_bounds__(kBlock) k_true_residual(CellDev* cells, const 
     ss = (double)rc * (double)rc + (double)rp * (double)rp;
   }
   const double vals[1] = {ss};
-  reduce_cell<1>(cdp, bb.y, vals, 0u, cd.red + RED_BSQ);
+  reduce_block<1>(cd, bb.y, vals, 0u);
 }
 
 // Start a GMRES cycle from the residual in w: V_0 = w/beta (all cells on
@@ -777,7 +808,7 @@ __global__ void __launch_bounds__(kBlock) k_direction(CellDev* cells, const int2
   }
   // scaled max-norm of the full Newton step (step-length limiter)
   const double vals[1] = {dmax};
-  reduce_cell<1>(cdp, bb.y, vals, 0x1u, cd.red + RED_DUMAX);
+  reduce_block<1>(cd, bb.y, vals, 0x1u);
 }
 
 // Trial state u + lam du; counts inadmissible entries (c <= 0, c_s >= c_max,
@@ -813,7 +844,7 @@ __global__ void __launch_bounds__(kBlock) k_trial(CellDev* cells, const int2* __
     }
   }
   const double vals[2] = {bad, dmax};
-  reduce_cell<2>(cdp, bb.y, vals, 0x2u, cd.red + RED_BAD);
+  reduce_block<2>(cd, bb.y, vals, 0x2u);
 }
 
 // State copies: 0 try -> iterate, 1 iterate -> try, 2 iterate -> old (step
@@ -879,7 +910,7 @@ __global__ void __launch_bounds__(kBlock) k_outputs(CellDev* cells, const int2* 
       v[4] = cd.phi[i] - jout * cd.h / (2.0 * cd.sigma[1]);
     }
   }
-  reduce_cell<5>(cdp, bb.y, v, 0u, cd.red + RED_INV0);
+  reduce_block<5>(cd, bb.y, v, 0u);
 }
 
 // Conversions between the raw FP64 scratch pair (dc, dp: 2N contiguous
@@ -929,7 +960,7 @@ __global__ void __launch_bounds__(kBlock) k_norm_w(CellDev* cells, const int2* _
     ss = a * a + b * b;
   }
   const double vals[1] = {ss};
-  reduce_cell<1>(cdp, bb.y, vals, 0u, cd.red + RED_BSQ);
+  reduce_block<1>(cd, bb.y, vals, 0u);
 }
 
 // --------------------------------------------------------------- launchers
@@ -959,10 +990,12 @@ void launch_residual(const BatchLaunch& b, bool lin, hipStream_t s) {
   else
     k_residual<false, KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
   if (prof_on(PK_RESIDUAL)) prof_end(PK_RESIDUAL, s, b.bytes_residual[lin ? 1 : 0]);
+  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_RSQ, 4, 0xAu, -3);
 }
 template <typename KT>
 void launch_rhs(const BatchLaunch& b, hipStream_t s) {
   k_rhs<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_BSQ, 1, 0u, -3);
 }
 template <typename KT>
 void launch_jacobi(const BatchLaunch& b, int src, int dst, int need, hipStream_t s) {
@@ -976,11 +1009,13 @@ void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t
 }
 template <typename KT>
 void launch_multidot(const BatchLaunch& b, int k, int tgt, hipStream_t s) {
-  k_multidot<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, k, tgt);
+  k_multidot<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, k);
+  k_finalize_dots<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, k, tgt);
 }
 template <typename KT>
 void launch_orth(const BatchLaunch& b, int k, int src, hipStream_t s) {
   k_orth<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, k, src);
+  k_finalize_norm<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, k, src);
 }
 template <typename KT>
 void launch_scale_next(const BatchLaunch& b, int k, hipStream_t s) {
@@ -1007,6 +1042,7 @@ void launch_add_z_to_x(const BatchLaunch& b, hipStream_t s) {
 template <typename KT>
 void launch_true_residual(const BatchLaunch& b, hipStream_t s) {
   k_true_residual<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_BSQ, 1, 0u, 2);
 }
 template <typename KT>
 void launch_gm_start(const BatchLaunch& b, int first, hipStream_t s) {
@@ -1025,6 +1061,7 @@ void launch_zero_x(const BatchLaunch& b, hipStream_t s) {
 template <typename KT>
 void launch_norm_w(const BatchLaunch& b, hipStream_t s) {
   k_norm_w<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_BSQ, 1, 0u, -3);
 }
 template <typename KT>
 void launch_convert(const BatchLaunch& b, int sel, int dir, hipStream_t s) {
@@ -1033,13 +1070,18 @@ void launch_convert(const BatchLaunch& b, int sel, int dir, hipStream_t s) {
 template <typename KT>
 void launch_direction(const BatchLaunch& b, hipStream_t s) {
   k_direction<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_DUMAX, 1, 0x1u, -3);
 }
-void launch_trial(const BatchLaunch& b, hipStream_t s) { k_trial<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk); }
+void launch_trial(const BatchLaunch& b, hipStream_t s) {
+  k_trial<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_BAD, 2, 0x2u, -3);
+}
 void launch_copy_state(const BatchLaunch& b, int mode, hipStream_t s) {
   k_copy_state<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, mode);
 }
 void launch_outputs(const BatchLaunch& b, hipStream_t s) {
   k_outputs<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_INV0, 5, 0u, -3);
 }
 
 #define MBX_INST(KT)                                                             \

@@ -30,6 +30,7 @@ enum { PORE = 0, ANODE = 1, CATHODE = 2 };
 // with three slots (pore, anode, cathode aggregates of the finer level).
 constexpr int kMaxLevels = 12;
 constexpr int kCoarseMaxCells = 64;
+constexpr int kFuseMaxCells = 256;    // levels this small run inside one workgroup per cell
 constexpr int kOpStride = 33;   // per coarse cell: E[3], X[3], G[3 dirs][3][3] (SoA)
 struct MGLevel {
   int nx, ny, nz, ncell;
@@ -101,7 +102,8 @@ struct CellDev {
   double i00_pl, n_c, I_app, mu_ref;
   int plating, pad2;
   // multigrid
-  int nlev, pad4;                    // levels incl. the voxel level; coarsest = nlev-1
+  int nlev, lfuse;                   // levels incl. the voxel level; coarsest = nlev-1;
+                                     // levels >= lfuse run in one workgroup (k_mg_coarse_cycle)
   MGLevel lv[kMaxLevels];
   void *b0;                          // KT [N] right-hand side of a level-0 solve
   void *cond_an, *cond_ca;           // KT potential-operator conductance per interface face
@@ -242,26 +244,4 @@ __device__ inline double wave_max(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
   return v;
 }
-// Result valid in thread 0.
-__device__ inline double block_sum(double v, double* lds4) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) lds4[wid] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) r = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
-  return r;
-}
-__device__ inline double block_max(double v, double* lds4) {
-  v = wave_max(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) lds4[wid] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) r = fmax(fmax(lds4[0], lds4[1]), fmax(lds4[2], lds4[3]));
-  return r;
-}
-
 }  // namespace mbx

@@ -18,8 +18,11 @@ struct BatchLaunch {
   int nblk;
   int ncell;
   int maxlev;                            // max multigrid levels over the batch
+  int maxfuse;                           // max first fused level over the batch
   const int2* lvl_blk[kMaxLevels];       // block tables over each level's cells (index >= 1)
   int lvl_nblk[kMaxLevels];
+  const int2* lvl8_blk[kMaxLevels];      // block tables with 8 lanes per level cell (index >= 1)
+  int lvl8_nblk[kMaxLevels];
   // algorithmic bytes per launch (summed over the batch), for timing records
   double bytes_residual[2];              // [0] residual only, [1] with linearisation
   double bytes_matvec;

@@ -109,13 +109,6 @@ __device__ inline int fine_nbr(int i, const C3& c, int nx, int ny, int nz, int d
 
 __device__ inline int lvl_cell(const MGLevel& L, int x, int y, int z) { return x + L.nx * (y + L.ny * z); }
 
-// (A_l x)(c, s) pieces for a coarse cell: D and the off-diagonal sum
-// sum_j g_j x_j (x read from xs, optionally corrected by alpha * xp[parent]).
-template <typename KT>
-struct CoarseRow {
-  KT D, off;
-};
-
 template <typename KT>
 __device__ inline KT xval(const MGLevel& L, const MGLevel* Lp, int c, int t, int mode, KT alpha) {
   if (mode == 1) return (KT)0;
@@ -338,7 +331,23 @@ __global__ void __launch_bounds__(kBlock) k_mg0_smooth(CellDev* cells, const int
   x0[i] = D > (KT)0 ? sum / D : (KT)0;
 }
 
-// Level-0 residual restricted to level 1 (sum per slot over the cell's voxels).
+// Sum over the 8 lanes of an aligned lane group (xor butterfly: every lane
+// ends with the identical value).
+__device__ inline float lane8_sum(float v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  return v;
+}
+__device__ inline double lane8_sum(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  return v;
+}
+
+// Level-0 residual restricted to level 1: 8 lanes per level-1 cell, one per
+// child voxel; the per-slot sums are formed across the lanes.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const int2* __restrict__ blk, int op,
                                                          int need) {
@@ -346,60 +355,55 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
   const CellDev& cd = cells[bb.x];
   if (!gate(cd, need)) return;
   const MGLevel& L1 = cd.lv[1];
-  const int C = bb.y * kBlock + threadIdx.x;
-  if (C >= L1.ncell) return;
-  const C3 q = c3_of(C, L1.nx, L1.ny);
-  const KT* x0 = (const KT*)cd.z + (size_t)op * cd.N;
-  const KT* b0 = (const KT*)cd.b0;
+  const int t = bb.y * kBlock + threadIdx.x;
+  const int C = t >> 3, ch = t & 7;
+  const bool live = C < L1.ncell;   // whole 8-lane groups share C: shuffles stay within live groups
   KT rs[3] = {0, 0, 0};
-  for (int dz = 0; dz < 2; ++dz)
-    for (int dy = 0; dy < 2; ++dy)
-      for (int dx = 0; dx < 2; ++dx) {
-        const int fx = 2 * q.x + dx, fy = 2 * q.y + dy, fz = 2 * q.z + dz;
-        if (fx >= cd.nx || fy >= cd.ny || fz >= cd.nz) continue;
-        const int i = fx + cd.nx * (fy + cd.ny * fz);
-        const uint32_t mi = cd.meta[i];
-        const int L = lab_of(mi);
-        const C3 fc{fx, fy, fz};
-        const KT xi = x0[i];
-        KT r = b0[i] - fine_extra<KT>(cd, op, L, fz) * xi;
-        for (int d = 0; d < 6; ++d) {
-          const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
-          if (k < 0) continue;
-          const uint32_t mk = cd.meta[k];
-          const KT g = fine_cond<KT>(cd, op, L, lab_of(mk), mi, mk, d);
-          if (g == (KT)0) continue;
-          r -= g * (xi - x0[k]);
-        }
-        rs[L] += r;
+  if (live) {
+    const C3 q = c3_of(C, L1.nx, L1.ny);
+    const int fx = 2 * q.x + (ch & 1), fy = 2 * q.y + ((ch >> 1) & 1), fz = 2 * q.z + (ch >> 2);
+    if (fx < cd.nx && fy < cd.ny && fz < cd.nz) {
+      const KT* x0 = (const KT*)cd.z + (size_t)op * cd.N;
+      const KT* b0 = (const KT*)cd.b0;
+      const int i = fx + cd.nx * (fy + cd.ny * fz);
+      const uint32_t mi = cd.meta[i];
+      const int L = lab_of(mi);
+      const C3 fc{fx, fy, fz};
+      const KT xi = x0[i];
+      KT r = b0[i] - fine_extra<KT>(cd, op, L, fz) * xi;
+      for (int d = 0; d < 6; ++d) {
+        const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
+        if (k < 0) continue;
+        const uint32_t mk = cd.meta[k];
+        const KT g = fine_cond<KT>(cd, op, L, lab_of(mk), mi, mk, d);
+        if (g == (KT)0) continue;
+        r -= g * (xi - x0[k]);
       }
-  KT* b1 = (KT*)L1.b;
-  for (int s = 0; s < 3; ++s) b1[(size_t)s * L1.ncell + C] = rs[s];
+      rs[L] = r;
+    }
+  }
+  for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
+  if (live && ch == 0) {
+    KT* b1 = (KT*)L1.b;
+    for (int s = 0; s < 3; ++s) b1[(size_t)s * L1.ncell + C] = rs[s];
+  }
 }
 
-// Coarse-level (l >= 1) red-black Gauss-Seidel half sweep; slots of one
-// cell are relaxed in order.  mode as for k_mg0_smooth (mode 2 reads the
+// Coarse-level (l >= 1) red-black Gauss-Seidel update of cell C; slots of
+// one cell are relaxed in order.  mode as for k_mg0_smooth (mode 2 reads the
 // level l+1 solution for the coarse correction); mode 3 is the first black
 // sweep of a cycle: neighbours (red, just written) are read, the cell's own
 // slots start from zero.
 template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int2* __restrict__ blk, int l, int op,
-                                                       int color, int mode, int need) {
-  const int2 bb = blk[blockIdx.x];
-  const CellDev& cd = cells[bb.x];
-  if (!gate(cd, need) || l >= cd.nlev - 1) return;
+__device__ inline void smooth_cell(const CellDev& cd, int l, int op, int C, int mode) {
   const MGLevel& L = cd.lv[l];
   const MGLevel* Lp = &cd.lv[l + 1];
-  const int C = bb.y * kBlock + threadIdx.x;
-  if (C >= L.ncell) return;
   const C3 q = c3_of(C, L.nx, L.ny);
-  if (((q.x + q.y + q.z) & 1) != color) return;
   const OpV<KT> A{(const KT*)L.op[op], L.ncell};
   const KT* b = (const KT*)L.b;
   KT* x = (KT*)L.x;
   const KT alpha = (KT)cd.alpha;
-  // own slots: mode 1 and 3 (first sweeps of a V-cycle) start from zero,
-  // since this cell has not been written in the current cycle
+  const int nmode = mode == 3 ? 0 : mode;
   KT xs[3];
   for (int t = 0; t < 3; ++t) xs[t] = mode == 3 ? (KT)0 : xval<KT>(L, Lp, C, t, mode, alpha);
   for (int s = 0; s < 3; ++s) {
@@ -418,7 +422,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int
           const KT g = A.G(C, dir, s, t);
           if (g == (KT)0) continue;
           D += g;
-          sum += g * xval<KT>(L, Lp, c2, t, mode == 3 ? 0 : mode, alpha);
+          sum += g * xval<KT>(L, Lp, c2, t, nmode, alpha);
         }
       }
       const int xm = q.x - (dir == 0), ym = q.y - (dir == 1), zm = q.z - (dir == 2);
@@ -428,7 +432,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int
           const KT g = A.G(c2, dir, t, s);
           if (g == (KT)0) continue;
           D += g;
-          sum += g * xval<KT>(L, Lp, c2, t, mode == 3 ? 0 : mode, alpha);
+          sum += g * xval<KT>(L, Lp, c2, t, nmode, alpha);
         }
       }
     }
@@ -437,76 +441,139 @@ __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int
   for (int s = 0; s < 3; ++s) x[(size_t)s * L.ncell + C] = xs[s];
 }
 
-// Level-l residual restricted to level l+1.
+// Residual (per slot) of coarse cell c at level l.
+template <typename KT>
+__device__ inline void residual_cell(const CellDev& cd, int l, int op, int c, KT (&r)[3]) {
+  const MGLevel& L = cd.lv[l];
+  const OpV<KT> A{(const KT*)L.op[op], L.ncell};
+  const KT* b = (const KT*)L.b;
+  const KT* x = (const KT*)L.x;
+  const size_t n = L.ncell;
+  const C3 q = c3_of(c, L.nx, L.ny);
+  for (int s = 0; s < 3; ++s) {
+    const KT xsv = x[s * n + c];
+    KT rr = b[s * n + c] - A.E(c, s) * xsv;
+    for (int t = 0; t < 3; ++t)
+      if (t != s) rr -= A.X(c, xidx(s, t)) * (xsv - x[t * n + c]);
+    for (int dir = 0; dir < 3; ++dir) {
+      const int xp = q.x + (dir == 0), yp = q.y + (dir == 1), zp = q.z + (dir == 2);
+      if (xp < L.nx && yp < L.ny && zp < L.nz) {
+        const int c2 = lvl_cell(L, xp, yp, zp);
+        for (int t = 0; t < 3; ++t) rr -= A.G(c, dir, s, t) * (xsv - x[t * n + c2]);
+      }
+      const int xm = q.x - (dir == 0), ym = q.y - (dir == 1), zm = q.z - (dir == 2);
+      if (xm >= 0 && ym >= 0 && zm >= 0) {
+        const int c2 = lvl_cell(L, xm, ym, zm);
+        for (int t = 0; t < 3; ++t) rr -= A.G(c2, dir, t, s) * (xsv - x[t * n + c2]);
+      }
+    }
+    r[s] = rr;
+  }
+}
+
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int2* __restrict__ blk, int l, int op,
+                                                       int color, int mode, int need) {
+  const int2 bb = blk[blockIdx.x];
+  const CellDev& cd = cells[bb.x];
+  if (!gate(cd, need) || l >= cd.lfuse) return;
+  const MGLevel& L = cd.lv[l];
+  const int C = bb.y * kBlock + threadIdx.x;
+  if (C >= L.ncell) return;
+  const C3 q = c3_of(C, L.nx, L.ny);
+  if (((q.x + q.y + q.z) & 1) != color) return;
+  smooth_cell<KT>(cd, l, op, C, mode);
+}
+
+// Level-l residual restricted to level l+1: 8 lanes per parent, one per child.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const int2* __restrict__ blk, int l, int op,
                                                          int need) {
   const int2 bb = blk[blockIdx.x];
   const CellDev& cd = cells[bb.x];
-  if (!gate(cd, need) || l + 1 >= cd.nlev) return;
+  if (!gate(cd, need) || l >= cd.lfuse) return;
   const MGLevel& L = cd.lv[l];
   const MGLevel& Lp = cd.lv[l + 1];
-  const int P = bb.y * kBlock + threadIdx.x;
-  if (P >= Lp.ncell) return;
-  const C3 q = c3_of(P, Lp.nx, Lp.ny);
-  const OpV<KT> A{(const KT*)L.op[op], L.ncell};
-  const KT* b = (const KT*)L.b;
-  const KT* x = (const KT*)L.x;
-  const size_t n = L.ncell;
+  const int t = bb.y * kBlock + threadIdx.x;
+  const int P = t >> 3, ch = t & 7;
+  const bool live = P < Lp.ncell;
   KT rs[3] = {0, 0, 0};
-  for (int dz = 0; dz < 2; ++dz)
-    for (int dy = 0; dy < 2; ++dy)
-      for (int dx = 0; dx < 2; ++dx) {
-        const int cx = 2 * q.x + dx, cy = 2 * q.y + dy, cz = 2 * q.z + dz;
-        if (cx >= L.nx || cy >= L.ny || cz >= L.nz) continue;
-        const int c = lvl_cell(L, cx, cy, cz);
-        for (int s = 0; s < 3; ++s) {
-          const KT xsv = x[s * n + c];
-          KT r = b[s * n + c] - A.E(c, s) * xsv;
-          for (int t = 0; t < 3; ++t)
-            if (t != s) r -= A.X(c, xidx(s, t)) * (xsv - x[t * n + c]);
-          for (int dir = 0; dir < 3; ++dir) {
-            const int xp = cx + (dir == 0), yp = cy + (dir == 1), zp = cz + (dir == 2);
-            if (xp < L.nx && yp < L.ny && zp < L.nz) {
-              const int c2 = lvl_cell(L, xp, yp, zp);
-              for (int t = 0; t < 3; ++t) r -= A.G(c, dir, s, t) * (xsv - x[t * n + c2]);
-            }
-            const int xm = cx - (dir == 0), ym = cy - (dir == 1), zm = cz - (dir == 2);
-            if (xm >= 0 && ym >= 0 && zm >= 0) {
-              const int c2 = lvl_cell(L, xm, ym, zm);
-              for (int t = 0; t < 3; ++t) r -= A.G(c2, dir, t, s) * (xsv - x[t * n + c2]);
-            }
-          }
-          rs[s] += r;
-        }
-      }
-  KT* bp = (KT*)Lp.b;
-  for (int s = 0; s < 3; ++s) bp[(size_t)s * Lp.ncell + P] = rs[s];
+  if (live) {
+    const C3 q = c3_of(P, Lp.nx, Lp.ny);
+    const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
+    if (cx < L.nx && cy < L.ny && cz < L.nz) residual_cell<KT>(cd, l, op, lvl_cell(L, cx, cy, cz), rs);
+  }
+  for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
+  if (live && ch == 0) {
+    KT* bp = (KT*)Lp.b;
+    for (int s = 0; s < 3; ++s) bp[(size_t)s * Lp.ncell + P] = rs[s];
+  }
 }
 
-// Coarsest level: x = M^-1 b (one block per cell, FP64 accumulation).
+// Levels lfuse..coarsest of one cell in one workgroup (levels small enough
+// that barriers are cheaper than kernel launches): pre-smoothing and
+// restriction down to the coarsest level, dense coarsest solve, coarse
+// correction and post-smoothing back up to lfuse.
 template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_mg_coarse_apply(CellDev* cells, int ncells, int op, int need) {
+__global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int op, int nu, int need) {
   const int ci = blockIdx.x;
   if (ci >= ncells) return;
   const CellDev& cd = cells[ci];
   if (!gate(cd, need)) return;
-  const MGLevel& L = cd.lv[cd.nlev - 1];
-  const int n = 3 * L.ncell;
-  __shared__ double bs[3 * kCoarseMaxCells];
-  const KT* b = (const KT*)L.b;
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
-    const int c = r / 3, s = r % 3;
-    bs[r] = (double)b[(size_t)s * L.ncell + c];
+  const int lc = cd.nlev - 1;
+  for (int l = cd.lfuse; l < lc; ++l) {
+    const MGLevel& L = cd.lv[l];
+    for (int it = 0; it < nu; ++it)
+      for (int color = 0; color < 2; ++color) {
+        const int mode = it == 0 ? (color == 0 ? 1 : 3) : 0;
+        for (int C = threadIdx.x; C < L.ncell; C += blockDim.x) {
+          const C3 q = c3_of(C, L.nx, L.ny);
+          if (((q.x + q.y + q.z) & 1) == color) smooth_cell<KT>(cd, l, op, C, mode);
+        }
+        __syncthreads();
+      }
+    const MGLevel& Lp = cd.lv[l + 1];
+    for (int P = threadIdx.x; P < Lp.ncell; P += blockDim.x) {
+      const C3 q = c3_of(P, Lp.nx, Lp.ny);
+      KT acc[3] = {0, 0, 0};
+      for (int ch = 0; ch < 8; ++ch) {
+        const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
+        if (cx >= L.nx || cy >= L.ny || cz >= L.nz) continue;
+        KT r[3];
+        residual_cell<KT>(cd, l, op, lvl_cell(L, cx, cy, cz), r);
+        for (int s = 0; s < 3; ++s) acc[s] += r[s];
+      }
+      for (int s = 0; s < 3; ++s) ((KT*)Lp.b)[(size_t)s * Lp.ncell + P] = acc[s];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const double* M = cd.cinv[op];
-  KT* x = (KT*)L.x;
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc += M[(size_t)r * n + j] * bs[j];
-    const int c = r / 3, s = r % 3;
-    x[(size_t)s * L.ncell + c] = (KT)acc;
+  {  // coarsest: x = M^-1 b
+    const MGLevel& L = cd.lv[lc];
+    const int n = 3 * L.ncell;
+    __shared__ double bs[3 * kCoarseMaxCells];
+    const KT* b = (const KT*)L.b;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) bs[r] = (double)b[(size_t)(r % 3) * L.ncell + r / 3];
+    __syncthreads();
+    const double* M = cd.cinv[op];
+    KT* x = (KT*)L.x;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc += M[(size_t)r * n + j] * bs[j];
+      x[(size_t)(r % 3) * L.ncell + r / 3] = (KT)acc;
+    }
+    __syncthreads();
+  }
+  for (int l = lc - 1; l >= cd.lfuse; --l) {
+    const MGLevel& L = cd.lv[l];
+    for (int it = 0; it < nu; ++it)
+      for (int color = 1; color >= 0; --color) {
+        const int mode = (it == 0 && color == 1) ? 2 : 0;
+        for (int C = threadIdx.x; C < L.ncell; C += blockDim.x) {
+          const C3 q = c3_of(C, L.nx, L.ny);
+          if (((q.x + q.y + q.z) & 1) == color) smooth_cell<KT>(cd, l, op, C, mode);
+        }
+        __syncthreads();
+      }
   }
 }
 
@@ -617,8 +684,7 @@ static void smooth0(const BatchLaunch& b, int op, int color, int mode, int need,
 
 template <typename KT>
 static void vcycle(const BatchLaunch& b, int op, int nu, int need, hipStream_t s) {
-  const int top = b.maxlev - 1;   // deepest coarsest level over the batch
-  // descend
+  const int top = b.maxfuse;   // levels >= a cell's lfuse run inside k_mg_coarse_cycle
   for (int l = 0; l < top; ++l) {
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
@@ -630,12 +696,11 @@ static void vcycle(const BatchLaunch& b, int op, int nu, int need, hipStream_t s
       }
     }
     if (l == 0)
-      k_mg0_restrict<KT><<<b.lvl_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl_blk[1], op, need);
+      k_mg0_restrict<KT><<<b.lvl8_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl8_blk[1], op, need);
     else
-      k_mgl_restrict<KT><<<b.lvl_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl_blk[l + 1], l, op, need);
+      k_mgl_restrict<KT><<<b.lvl8_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl8_blk[l + 1], l, op, need);
   }
-  k_mg_coarse_apply<KT><<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, op, need);
-  // ascend (first post-smoothing half sweep applies the coarse correction)
+  k_mg_coarse_cycle<KT><<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, op, nu, need);
   for (int l = top - 1; l >= 0; --l) {
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {

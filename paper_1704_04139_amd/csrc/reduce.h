@@ -1,70 +1,57 @@
 // reduce.h — deterministic per-cell reductions across the blocks of a launch.
 //
-// Every block of a cell reduces its values (fixed shuffle tree), stores the
-// block result in the cell's partial buffer and takes a ticket; the block
-// that takes the last ticket sums the partials in block order and writes
-// the result.  The result therefore does not depend on block scheduling, and
-// the same cell gives bit-identical sums alone or inside a batch.
+// Two-pass scheme: every block of a cell reduces its values (wavefront
+// shuffle tree, then the four wavefront results in fixed order) and stores
+// them in the cell's partial buffer; a finalising kernel (one block per
+// cell, launched next on the same stream) sums the partials in block order.
+// The kernel boundary makes the partials visible to the finaliser without
+// any in-kernel fence (on this chip an agent-scope release fence writes back
+// the XCD's L2), and the fixed summation order makes the result independent
+// of block scheduling: the same cell gives bit-identical sums alone or
+// inside a batch.
 #pragma once
 #include "mbx_dev.h"
 
 namespace mbx {
 
-__device__ inline void part_store(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Block-wide reduction of value j (sum, or max when mx): every thread passes
+// its value; the wave result goes to lds[wave * stride + j].  After a
+// __syncthreads the caller combines the four wave slots with combine4.
+__device__ inline void wave_to_lds(double v, bool mx, double* lds, int stride, int j) {
+  v = mx ? wave_max(v) : wave_sum(v);
+  if ((threadIdx.x & 63) == 0) lds[(threadIdx.x >> 6) * stride + j] = v;
 }
-__device__ inline double part_load(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Take the ticket after this block's partials are stored; returns true in
-// every thread of the block that completes the cell.
-__device__ inline bool take_ticket(CellDev* cd, bool* lds_flag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(cd->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    *lds_flag = (t == (unsigned)(cd->nblk - 1));
-  }
-  __syncthreads();
-  const bool last = *lds_flag;
-  if (last) __threadfence();
-  return last;
+__device__ inline double combine4(const double* lds, int stride, int j, bool mx) {
+  const double a = lds[j], b = lds[stride + j], c = lds[2 * stride + j], d = lds[3 * stride + j];
+  return mx ? fmax(fmax(a, b), fmax(c, d)) : (a + b) + (c + d);
 }
 
-__device__ inline void release_ticket(CellDev* cd) {
-  if (threadIdx.x == 0) __hip_atomic_store(cd->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// K values per thread; bit j of maxmask selects max (else sum).  Outputs go
-// to out[j] (written by the completing block).
+// First pass: K values per thread; bit j of maxmask selects max (else sum);
+// the block result goes to the cell's partial row `blk`.
 template <int K>
-__device__ inline void reduce_cell(CellDev* cd, int blk, const double (&v)[K], unsigned maxmask,
-                                   double* out) {
-  __shared__ double lds4[4];
-  __shared__ bool flag;
-  double r[K];
+__device__ inline void reduce_block(const CellDev& cd, int blk, const double (&v)[K], unsigned maxmask) {
+  __shared__ double lds[4 * K];
 #pragma unroll
-  for (int j = 0; j < K; ++j)
-    r[j] = ((maxmask >> j) & 1u) ? block_max(v[j], lds4) : block_sum(v[j], lds4);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) part_store(&cd->part[(size_t)blk * kPartStride + j], r[j]);
+  for (int j = 0; j < K; ++j) wave_to_lds(v[j], (maxmask >> j) & 1u, lds, K, j);
+  __syncthreads();
+  if (threadIdx.x < K)
+    cd.part[(size_t)blk * kPartStride + threadIdx.x] = combine4(lds, K, threadIdx.x, (maxmask >> threadIdx.x) & 1u);
+}
+
+// Second pass (inside a one-block-per-cell kernel): column j of the partial
+// rows summed (or max-reduced) in block order; result valid in all threads.
+__device__ inline double finalize_column(const CellDev& cd, int j, bool mx, double* lds4, double* result) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < cd.nblk; b += kBlock) {
+    const double p = cd.part[(size_t)b * kPartStride + j];
+    acc = mx ? fmax(acc, p) : acc + p;
   }
-  if (!take_ticket(cd, &flag)) return;
-  const int nb = cd->nblk;
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const bool mx = (maxmask >> j) & 1u;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) {
-      const double p = part_load(&cd->part[(size_t)b * kPartStride + j]);
-      acc = mx ? fmax(acc, p) : acc + p;
-    }
-    acc = mx ? block_max(acc, lds4) : block_sum(acc, lds4);
-    if (threadIdx.x == 0) out[j] = acc;
-  }
-  release_ticket(cd);
+  __syncthreads();
+  wave_to_lds(acc, mx, lds4, 1, 0);
+  __syncthreads();
+  if (threadIdx.x == 0) *result = combine4(lds4, 1, 0, mx);
+  __syncthreads();
+  return *result;
 }
 
 }  // namespace mbx
