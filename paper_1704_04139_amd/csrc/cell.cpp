@@ -63,7 +63,7 @@ uint64_t g_next_id = 1;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t off[128];
+  size_t off[160];
   int n = 0;
   size_t total = 0;
   size_t add(size_t bytes) {
@@ -125,9 +125,14 @@ struct mbx_cell {
   int lvl_nblk[kMaxLevels] = {};
   int2* lvl8_blk[kMaxLevels] = {};
   int lvl8_nblk[kMaxLevels] = {};
+  int2* lvlh_blk[kMaxLevels] = {};   // one colour of a red-black sweep (index >= 0)
+  int lvlh_nblk[kMaxLevels] = {};
 };
 
 namespace {
+
+// cells of one colour of a red-black sweep on level l (upper bound)
+size_t half_cells(const LevelDims& ld, int l) { return (size_t)((ld.nx[l] + 1) / 2) * ld.ny[l] * ld.nz[l]; }
 
 size_t kt_size(int precision) { return precision == MBX_MIXED ? sizeof(float) : sizeof(double); }
 
@@ -159,7 +164,7 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   const int nc = ld.ncell[ld.n - 1];
   L.add(8 * (size_t)9 * nc * nc);             // 39 cinv[0]
   L.add(8 * (size_t)9 * nc * nc);             // 40 cinv[1]
-  for (int l = 1; l < ld.n; ++l) {            // 41 + 6(l-1): x, b, op0, op1, blk, blk8
+  for (int l = 1; l < ld.n; ++l) {            // 41 + 7(l-1): x, b, op0, op1, blk, blk8, blkh
     const size_t n = ld.ncell[l];
     L.add(3 * n * kt);
     L.add(3 * n * kt);
@@ -167,7 +172,9 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
     L.add(kOpStride * n * kt);
     L.add(sizeof(int2) * ((n + kBlock - 1) / kBlock));
     L.add(sizeof(int2) * ((8 * n + kBlock - 1) / kBlock));
+    L.add(sizeof(int2) * ((half_cells(ld, l) + kBlock - 1) / kBlock));
   }
+  L.add(sizeof(int2) * ((half_cells(ld, 0) + kBlock - 1) / kBlock));   // 41 + 7(n-1): level-0 blkh
   return L;
 }
 
@@ -259,6 +266,8 @@ struct Batch {
   int lvl_nblk[kMaxLevels] = {};
   int2* lvl8_blk[kMaxLevels] = {};
   int lvl8_nblk[kMaxLevels] = {};
+  int2* lvlh_blk[kMaxLevels] = {};
+  int lvlh_nblk[kMaxLevels] = {};
   BatchLaunch bl() const {
     BatchLaunch b{};
     for (const mbx_cell* c : cells) {
@@ -279,6 +288,8 @@ struct Batch {
       b.lvl_nblk[l] = lvl_nblk[l];
       b.lvl8_blk[l] = lvl8_blk[l];
       b.lvl8_nblk[l] = lvl8_nblk[l];
+      b.lvlh_blk[l] = lvlh_blk[l];
+      b.lvlh_nblk[l] = lvlh_nblk[l];
     }
     return b;
   }
@@ -302,9 +313,10 @@ struct Batch {
     hipFree(d_desc);
     hipFree(d_blk);
     hipFree(d_gather);
-    for (int l = 1; l < kMaxLevels; ++l) {
+    for (int l = 0; l < kMaxLevels; ++l) {
       if (lvl_blk[l]) (void)hipFree(lvl_blk[l]);
       if (lvl8_blk[l]) (void)hipFree(lvl8_blk[l]);
+      if (lvlh_blk[l]) (void)hipFree(lvlh_blk[l]);
     }
     hipHostFree(h_desc);
     hipHostFree(h_gather);
@@ -326,11 +338,13 @@ Batch single(mbx_cell* c) {
   b.m = c->m;
   b.maxlev = c->ld.n;
   b.maxfuse = c->ld.lfuse;
-  for (int l = 1; l < c->ld.n; ++l) {
+  for (int l = 0; l < c->ld.n; ++l) {
     b.lvl_blk[l] = c->lvl_blk[l];
     b.lvl_nblk[l] = c->lvl_nblk[l];
     b.lvl8_blk[l] = c->lvl8_blk[l];
     b.lvl8_nblk[l] = c->lvl8_nblk[l];
+    b.lvlh_blk[l] = c->lvlh_blk[l];
+    b.lvlh_nblk[l] = c->lvlh_nblk[l];
   }
   return b;
 }
@@ -362,16 +376,18 @@ int make_batch(mbx_cell* const* cells, int n, Batch& out) {
     b.maxlev = std::max(b.maxlev, cells[c]->ld.n);
     b.maxfuse = std::max(b.maxfuse, cells[c]->ld.lfuse);
   }
-  for (int l = 1; l < b.maxlev; ++l) {
-    for (int pass = 0; pass < 2; ++pass) {
+  for (int l = 0; l < b.maxlev; ++l) {
+    for (int pass = 0; pass < 3; ++pass) {
+      if (l == 0 && pass < 2) continue;
       std::vector<int2> lt;
       for (int c = 0; c < n; ++c)
         if (l < cells[c]->ld.n) {
-          const int nb = pass == 0 ? cells[c]->lvl_nblk[l] : cells[c]->lvl8_nblk[l];
+          const int nb =
+              pass == 0 ? cells[c]->lvl_nblk[l] : pass == 1 ? cells[c]->lvl8_nblk[l] : cells[c]->lvlh_nblk[l];
           for (int k = 0; k < nb; ++k) lt.push_back(make_int2(c, k));
         }
-      int2*& dst = pass == 0 ? b.lvl_blk[l] : b.lvl8_blk[l];
-      (pass == 0 ? b.lvl_nblk[l] : b.lvl8_nblk[l]) = (int)lt.size();
+      int2*& dst = pass == 0 ? b.lvl_blk[l] : pass == 1 ? b.lvl8_blk[l] : b.lvlh_blk[l];
+      (pass == 0 ? b.lvl_nblk[l] : pass == 1 ? b.lvl8_nblk[l] : b.lvlh_nblk[l]) = (int)lt.size();
       HIPCHK(hipMalloc(&dst, sizeof(int2) * std::max<size_t>(lt.size(), 1)));
       HIPCHK(hipMemcpyAsync(dst, lt.data(), sizeof(int2) * lt.size(), hipMemcpyHostToDevice, b.s));
     }
@@ -807,7 +823,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.lv[0].nz = nz;
   h.lv[0].ncell = N;
   for (int l = 1; l < c->ld.n; ++l) {
-    const int o = 41 + 6 * (l - 1);
+    const int o = 41 + 7 * (l - 1);
     MGLevel& lv = h.lv[l];
     lv.nx = c->ld.nx[l];
     lv.ny = c->ld.ny[l];
@@ -821,7 +837,11 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
     c->lvl_nblk[l] = (lv.ncell + kBlock - 1) / kBlock;
     c->lvl8_blk[l] = (int2*)(b + L.off[o + 5]);
     c->lvl8_nblk[l] = (8 * lv.ncell + kBlock - 1) / kBlock;
+    c->lvlh_blk[l] = (int2*)(b + L.off[o + 6]);
+    c->lvlh_nblk[l] = (int)((half_cells(c->ld, l) + kBlock - 1) / kBlock);
   }
+  c->lvlh_blk[0] = (int2*)(b + L.off[41 + 7 * (c->ld.n - 1)]);
+  c->lvlh_nblk[0] = (int)((half_cells(c->ld, 0) + kBlock - 1) / kBlock);
   h.m = c->m;
   h.lam = 1.0;
   h.rtol = 1e-6;
@@ -841,15 +861,16 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   if (e == hipSuccess) e = hipMemsetAsync(h.ictl, 0, 4 * CTL_NSLOT, s);
   if (e == hipSuccess) e = hipMemsetAsync(h.red, 0, 8 * RED_NSLOT, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->d_blk, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice, s);
-  std::vector<std::vector<int2>> ltabs(2 * c->ld.n);
-  for (int l = 1; l < c->ld.n && e == hipSuccess; ++l) {
-    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
-      const int nb = pass == 0 ? c->lvl_nblk[l] : c->lvl8_nblk[l];
-      std::vector<int2>& t = ltabs[2 * l + pass];
+  std::vector<std::vector<int2>> ltabs(3 * c->ld.n);
+  for (int l = 0; l < c->ld.n && e == hipSuccess; ++l) {
+    for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
+      if (l == 0 && pass < 2) continue;
+      const int nb = pass == 0 ? c->lvl_nblk[l] : pass == 1 ? c->lvl8_nblk[l] : c->lvlh_nblk[l];
+      std::vector<int2>& t = ltabs[3 * l + pass];
       t.resize(nb);
       for (int k = 0; k < nb; ++k) t[k] = make_int2(0, k);
-      e = hipMemcpyAsync(pass == 0 ? c->lvl_blk[l] : c->lvl8_blk[l], t.data(), sizeof(int2) * t.size(),
-                         hipMemcpyHostToDevice, s);
+      e = hipMemcpyAsync(pass == 0 ? c->lvl_blk[l] : pass == 1 ? c->lvl8_blk[l] : c->lvlh_blk[l], t.data(),
+                         sizeof(int2) * t.size(), hipMemcpyHostToDevice, s);
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -160,6 +160,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
     const bool plate = cd.plating != 0;
     double Rc = cd.Vol * (ci - cd.c_old[i]) / dt;
     double Rp = 0.0;
+    const double lci = (L == PORE) ? log(ci) : 0.0;   // ln c of this voxel, shared by its pore faces
     double wc = 1.0, wp = 0.0;   // state-independent diagonal of the scaled rows (merit weights)
     for (int d = 0; d < 6; ++d) {
       const int k = neighbour(cd, i, v.x, v.y, v.z, d);
@@ -180,7 +181,9 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
       const double pa = lo ? pi : pk, pb = lo ? pk : pi;
       weight_add(cd, L, Lk, wc, wp);
       if (L == PORE && Lk == PORE) {
-        const double j = -cd.kappa * (pb - pa) / h + cd.Kd * (log(cb) - log(ca));
+        const double lck = log(ck);
+        const double lca = lo ? lci : lck, lcb = lo ? lck : lci;
+        const double j = -cd.kappa * (pb - pa) / h + cd.Kd * (lcb - lca);
         const double Nf = -cd.De * (cb - ca) / h + cd.tplus / kFaraday * j;
         Rc += sgn * (A * Nf);
         Rp += sgn * (A * j);

@@ -169,7 +169,10 @@ __device__ inline double plated_root(const CellDev& cd, double ce, double ps, do
   double lo = 0.0, hi = n_old + dt * E * invF;
   if (!(hi > 0.0)) return 0.0;
   double n = (guess > lo && guess < hi) ? guess : 0.5 * (lo + hi);
-  for (int it = 0; it < 100; ++it) {
+  // Newton converges quadratically once inside the basin; stop when the
+  // step is below 1e-13 relative (the next step would be at rounding level)
+  // or after a fixed budget (bisection keeps the bracket valid throughout).
+  for (int it = 0; it < 60; ++it) {
     const double n2 = n * n, n4 = n2 * n2, den = nc4 + n4;
     const double f = n4 / den;
     const double g = (n - n_old) / dt + (K * f - E) * invF;
@@ -177,8 +180,9 @@ __device__ inline double plated_root(const CellDev& cd, double ce, double ps, do
     const double dg = 1.0 / dt + K * invF * 4.0 * n2 * n * nc4 / (den * den);
     double nn = n - g / dg;
     if (!(nn > lo && nn < hi)) nn = 0.5 * (lo + hi);
-    if (fabs(nn - n) <= 1e-15 * fmax(nn, cd.n_c * 1e-3) || hi - lo <= 1e-16 * hi) return nn;
+    const double step = fabs(nn - n);
     n = nn;
+    if (step <= 1e-13 * fmax(n, cd.n_c * 1e-6)) break;
   }
   return n;
 }
@@ -203,12 +207,13 @@ __device__ inline Kin interface_kinetics(const CellDev& cd, int ph, double cs, d
   const double sq = sqrt(cs * ce);
   const double pre = 2.0 * cd.i00[s] * sq;
   const double be = cd.beta * eta;
-  k.ii = pre * sinh(be);
+  const double sh = sinh(be);
+  k.ii = pre * sh;
   k.ip = 0.0;
   k.p_ce = k.g_p = k.p_n = 0.0;
   if (lin) {
     const double dU = -cd.U1[s] / (xs * (1.0 - xs)) / cm;
-    k.g = pre * cd.beta * cosh(be);
+    k.g = pre * cd.beta * sqrt(1.0 + sh * sh);   // cosh
     k.d_cs = k.ii / (2.0 * cs) - k.g * dU;
     k.d_ce = k.ii / (2.0 * ce);
   } else {

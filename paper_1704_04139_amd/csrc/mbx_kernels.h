@@ -23,6 +23,8 @@ struct BatchLaunch {
   int lvl_nblk[kMaxLevels];
   const int2* lvl8_blk[kMaxLevels];      // block tables with 8 lanes per level cell (index >= 1)
   int lvl8_nblk[kMaxLevels];
+  const int2* lvlh_blk[kMaxLevels];      // block tables over one colour of a red-black sweep (index >= 0)
+  int lvlh_nblk[kMaxLevels];
   // algorithmic bytes per launch (summed over the batch), for timing records
   double bytes_residual[2];              // [0] residual only, [1] with linearisation
   double bytes_matvec;

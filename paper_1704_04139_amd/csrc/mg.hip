@@ -109,16 +109,179 @@ __device__ inline int fine_nbr(int i, const C3& c, int nx, int ny, int nz, int d
 
 __device__ inline int lvl_cell(const MGLevel& L, int x, int y, int z) { return x + L.nx * (y + L.ny * z); }
 
+// Smoothing modes: which values stand for the cell's own slots and for its
+// neighbours.  "corrected" adds alpha times the parent's level l+1 solution
+// (the coarse-grid correction applied lazily on the first post-sweeps).
+enum { SM_PLAIN = 0, SM_ZERO = 1, SM_CORR = 2, SM_OWNZERO = 3, SM_OWNCORR = 4 };
+__device__ inline bool own_zero(int m) { return m == SM_ZERO || m == SM_OWNZERO; }
+__device__ inline bool own_corr(int m) { return m == SM_CORR || m == SM_OWNCORR; }
+__device__ inline bool nbr_zero(int m) { return m == SM_ZERO; }
+__device__ inline bool nbr_corr(int m) { return m == SM_CORR; }
+
+// Red-black thread mapping: thread t of a level with extents (nx, ny, nz)
+// handles the t-th cell of colour `color` ((x + y + z) & 1 == color) in
+// row-major order; false when t is past the end.
+__device__ inline bool color_cell(int t, int color, int nx, int ny, int nz, C3& q) {
+  const int hx = (nx + 1) >> 1;
+  const int j = t % hx, row = t / hx;
+  q.y = row % ny;
+  q.z = row / ny;
+  q.x = 2 * j + ((color + q.y + q.z) & 1);
+  return q.z < nz && q.x < nx;
+}
+
+// Neighbour cells (+x, -x, +y, -y, +z, -z) of cell c at q; absent neighbours
+// are replaced by c itself and flagged false (their couplings are zeroed, so
+// every load stays in bounds and can be issued without a branch).
+__device__ inline void neighbours6(int c, const C3& q, int nx, int ny, int nz, int (&nb)[6], bool (&ex)[6]) {
+  const int sx = 1, sy = nx, sz = nx * ny;
+  ex[0] = q.x + 1 < nx; ex[1] = q.x > 0;
+  ex[2] = q.y + 1 < ny; ex[3] = q.y > 0;
+  ex[4] = q.z + 1 < nz; ex[5] = q.z > 0;
+  nb[0] = ex[0] ? c + sx : c; nb[1] = ex[1] ? c - sx : c;
+  nb[2] = ex[2] ? c + sy : c; nb[3] = ex[3] ? c - sy : c;
+  nb[4] = ex[4] ? c + sz : c; nb[5] = ex[5] ? c - sz : c;
+}
+
+// Row of the level-0 operator `op` at voxel i: diagonal D (extra term plus
+// all couplings) and S = sum_k g_ik x_k over the neighbours (x_k read from
+// xsrc, plus alpha times the level-1 solution of k's slot when corr).  All
+// loads are issued before any arithmetic depends on them.
 template <typename KT>
-__device__ inline KT xval(const MGLevel& L, const MGLevel* Lp, int c, int t, int mode, KT alpha) {
-  if (mode == 1) return (KT)0;
-  KT v = ((const KT*)L.x)[(size_t)t * L.ncell + c];
-  if (mode == 2) {
-    const C3 q = c3_of(c, L.nx, L.ny);
-    const int pc = lvl_cell(*Lp, q.x >> 1, q.y >> 1, q.z >> 1);
-    v += alpha * ((const KT*)Lp->x)[(size_t)t * Lp->ncell + pc];
+__device__ inline void voxel_row(const CellDev& cd, int op, int i, const C3& c, uint32_t mi, const KT* __restrict__ xsrc,
+                                 bool zero, bool corr, KT& D, KT& S) {
+  int k[6];
+  bool ex[6];
+  neighbours6(i, c, cd.nx, cd.ny, cd.nz, k, ex);
+  const int dmap[6] = {1, 0, 3, 2, 5, 4};   // neighbour slot -> face direction (0:-x 1:+x ...)
+  uint32_t mk[6];
+  KT xk[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) mk[j] = cd.meta[k[j]];
+  if (!zero) {
+    // absent neighbours read voxel i itself, which may not be written yet in
+    // this sweep: select zero (a product with a zero coupling would keep NaN)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const KT v = xsrc[k[j]];
+      xk[j] = ex[j] ? v : (KT)0;
+    }
   }
-  return v;
+  const int L = lab_of(mi);
+  KT g[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int Lk = lab_of(mk[j]);
+    const int d = dmap[j];
+    KT v;
+    if (op == 0) {
+      v = L == Lk ? (KT)(L == PORE ? cd.Dh : cd.Dsh[L == CATHODE]) : (KT)0;
+    } else {
+      const bool iface = (L == PORE) != (Lk == PORE);
+      const bool pore_side = L == PORE;
+      const uint32_t f = iface ? face_rank(pore_side ? mk[j] : mi, pore_side ? (d ^ 1) : d) : 0u;
+      const int Ls = pore_side ? Lk : L;
+      const KT* arr = (const KT*)(Ls == CATHODE ? cd.cond_ca : cd.cond_an);
+      const KT gi = arr[f];
+      v = L == Lk ? (KT)(L == PORE ? cd.Gk : cd.Gs[L == CATHODE]) : (iface ? gi : (KT)0);
+    }
+    g[j] = ex[j] ? v : (KT)0;
+  }
+  if (corr) {
+    const MGLevel& L1 = cd.lv[1];
+    const KT alpha = (KT)cd.alpha;
+    const int px = c.x >> 1, py = c.y >> 1, pz = c.z >> 1;
+    const int pq[6] = {((c.x + 1) >> 1) - px, ((c.x - 1) >> 1) - px, ((c.y + 1) >> 1) - py,
+                       ((c.y - 1) >> 1) - py, ((c.z + 1) >> 1) - pz, ((c.z - 1) >> 1) - pz};
+    const int pc = px + L1.nx * (py + L1.ny * pz);
+    const int pst[6] = {1, 1, L1.nx, L1.nx, L1.nx * L1.ny, L1.nx * L1.ny};
+    const KT* x1 = (const KT*)L1.x;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int pcj = ex[j] ? pc + pq[j] * pst[j] : pc;
+      const KT v = x1[(size_t)lab_of(mk[j]) * L1.ncell + pcj];
+      xk[j] += ex[j] ? alpha * v : (KT)0;
+    }
+  }
+  D = op == 0 ? (KT)1 : ((L == ANODE && c.z == 0) ? (KT)cd.Gcol : (KT)0);
+  S = (KT)0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    D += g[j];
+    if (!zero) S += g[j] * xk[j];
+  }
+}
+
+// Gathered row block of coarse cell C at level l: the 3x3 in-cell couplings,
+// the couplings to the six neighbours and the neighbour values, loaded
+// without branches (absent neighbours read cell C with zero couplings).
+template <typename KT>
+struct CoarseRow {
+  KT E[3], X[3], b[3], xo[3];
+  KT Gp[3][9], Gm[3][9];   // Gp[dir][s*3+t]: own slot s to slot t of the +dir neighbour; Gm from -dir neighbour
+  KT xn[6][3];
+};
+
+template <typename KT>
+__device__ inline void gather_coarse(const CellDev& cd, int l, int op, int C, const C3& q, int mode, CoarseRow<KT>& R) {
+  const MGLevel& L = cd.lv[l];
+  const size_t n = L.ncell;
+  const KT* A = (const KT*)L.op[op];
+  const KT* b = (const KT*)L.b;
+  const KT* x = (const KT*)L.x;
+  int nb[6];
+  bool ex[6];
+  neighbours6(C, q, L.nx, L.ny, L.nz, nb, ex);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    R.E[s] = A[s * n + C];
+    R.X[s] = A[(3 + s) * n + C];
+    R.b[s] = b[s * n + C];
+  }
+#pragma unroll
+  for (int dir = 0; dir < 3; ++dir)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const KT gp = A[(6 + dir * 9 + k) * n + C];
+      const KT gm = A[(6 + dir * 9 + k) * n + nb[2 * dir + 1]];
+      R.Gp[dir][k] = ex[2 * dir] ? gp : (KT)0;
+      R.Gm[dir][k] = ex[2 * dir + 1] ? gm : (KT)0;
+    }
+#pragma unroll
+  for (int t = 0; t < 3; ++t) R.xo[t] = own_zero(mode) ? (KT)0 : x[t * n + C];
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      // absent neighbours read cell C itself (possibly unwritten): select zero
+      const KT v = nbr_zero(mode) ? (KT)0 : x[t * n + nb[j]];
+      R.xn[j][t] = ex[j] ? v : (KT)0;
+    }
+  if (own_corr(mode) || nbr_corr(mode)) {
+    const MGLevel& Lp = cd.lv[l + 1];
+    const size_t np = Lp.ncell;
+    const KT* xp = (const KT*)Lp.x;
+    const KT alpha = (KT)cd.alpha;
+    const int px = q.x >> 1, py = q.y >> 1, pz = q.z >> 1;
+    const int pc = px + Lp.nx * (py + Lp.ny * pz);
+    if (own_corr(mode))
+#pragma unroll
+      for (int t = 0; t < 3; ++t) R.xo[t] += alpha * xp[t * np + pc];
+    if (nbr_corr(mode)) {
+      const int pq[6] = {((q.x + 1) >> 1) - px, ((q.x - 1) >> 1) - px, ((q.y + 1) >> 1) - py,
+                         ((q.y - 1) >> 1) - py, ((q.z + 1) >> 1) - pz, ((q.z - 1) >> 1) - pz};
+      const int pst[6] = {1, 1, Lp.nx, Lp.nx, Lp.nx * Lp.ny, Lp.nx * Lp.ny};
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const int pcj = ex[j] ? pc + pq[j] * pst[j] : pc;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const KT v = xp[t * np + pcj];
+          R.xn[j][t] += ex[j] ? alpha * v : (KT)0;
+        }
+      }
+    }
+  }
 }
 
 }  // namespace
@@ -289,46 +452,25 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int 
 }
 
 // ---------------------------------------------------------------- V-cycle
-// Level-0 red-black Gauss-Seidel half sweep on operator op; the solution
-// lives in the Krylov vector z (concentration part for op 0, potential part
-// for op 1), the right-hand side in b0.  mode 1: x treated as zero (first
-// sweep); mode 2: neighbours corrected by alpha * (level-1 solution).
+// Level-0 red-black Gauss-Seidel half sweep on operator op over the voxels of
+// one colour (threads map to that colour only); the solution lives in the
+// Krylov vector z (concentration part for op 0, potential part for op 1), the
+// right-hand side in b0.  mode SM_ZERO: first sweep (x treated as zero);
+// SM_CORR: neighbours corrected by alpha * (level-1 solution); else plain.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg0_smooth(CellDev* cells, const int2* __restrict__ blk, int op,
                                                        int color, int mode, int need) {
   const int2 bb = blk[blockIdx.x];
   const CellDev& cd = cells[bb.x];
   if (!gate(cd, need)) return;
-  const int i = bb.y * kBlock + threadIdx.x;
-  if (i >= cd.N) return;
-  const C3 c = c3_of(i, cd.nx, cd.ny);
-  if (((c.x + c.y + c.z) & 1) != color) return;
+  C3 c;
+  if (!color_cell(bb.y * kBlock + threadIdx.x, color, cd.nx, cd.ny, cd.nz, c)) return;
+  const int i = c.x + cd.nx * (c.y + cd.ny * c.z);
   KT* x0 = (KT*)cd.z + (size_t)op * cd.N;
-  const KT* b0 = (const KT*)cd.b0;
-  const uint32_t mi = cd.meta[i];
-  const int L = lab_of(mi);
-  KT D = fine_extra<KT>(cd, op, L, c.z);
-  KT sum = b0[i];
-  const MGLevel& L1 = cd.lv[1];
-  const KT alpha = (KT)cd.alpha;
-  for (int d = 0; d < 6; ++d) {
-    const int k = fine_nbr(i, c, cd.nx, cd.ny, cd.nz, d);
-    if (k < 0) continue;
-    const uint32_t mk = cd.meta[k];
-    const int Lk = lab_of(mk);
-    const KT g = fine_cond<KT>(cd, op, L, Lk, mi, mk, d);
-    if (g == (KT)0) continue;
-    D += g;
-    if (mode != 1) {
-      KT xk = x0[k];
-      if (mode == 2) {
-        const C3 ck = c3_of(k, cd.nx, cd.ny);
-        xk += alpha * ((const KT*)L1.x)[(size_t)Lk * L1.ncell + lvl_cell(L1, ck.x >> 1, ck.y >> 1, ck.z >> 1)];
-      }
-      sum += g * xk;
-    }
-  }
-  x0[i] = D > (KT)0 ? sum / D : (KT)0;
+  const KT bi = ((const KT*)cd.b0)[i];
+  KT D, S;
+  voxel_row<KT>(cd, op, i, c, cd.meta[i], x0, mode == SM_ZERO, mode == SM_CORR, D, S);
+  x0[i] = D > (KT)0 ? (bi + S) / D : (KT)0;
 }
 
 // Sum over the 8 lanes of an aligned lane group (xor butterfly: every lane
@@ -361,25 +503,19 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
   KT rs[3] = {0, 0, 0};
   if (live) {
     const C3 q = c3_of(C, L1.nx, L1.ny);
-    const int fx = 2 * q.x + (ch & 1), fy = 2 * q.y + ((ch >> 1) & 1), fz = 2 * q.z + (ch >> 2);
-    if (fx < cd.nx && fy < cd.ny && fz < cd.nz) {
+    const C3 fc{2 * q.x + (ch & 1), 2 * q.y + ((ch >> 1) & 1), 2 * q.z + (ch >> 2)};
+    if (fc.x < cd.nx && fc.y < cd.ny && fc.z < cd.nz) {
       const KT* x0 = (const KT*)cd.z + (size_t)op * cd.N;
-      const KT* b0 = (const KT*)cd.b0;
-      const int i = fx + cd.nx * (fy + cd.ny * fz);
+      const int i = fc.x + cd.nx * (fc.y + cd.ny * fc.z);
       const uint32_t mi = cd.meta[i];
+      const KT xi = x0[i], bi = ((const KT*)cd.b0)[i];
+      KT D, S;
+      voxel_row<KT>(cd, op, i, fc, mi, x0, false, false, D, S);
       const int L = lab_of(mi);
-      const C3 fc{fx, fy, fz};
-      const KT xi = x0[i];
-      KT r = b0[i] - fine_extra<KT>(cd, op, L, fz) * xi;
-      for (int d = 0; d < 6; ++d) {
-        const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
-        if (k < 0) continue;
-        const uint32_t mk = cd.meta[k];
-        const KT g = fine_cond<KT>(cd, op, L, lab_of(mk), mi, mk, d);
-        if (g == (KT)0) continue;
-        r -= g * (xi - x0[k]);
-      }
-      rs[L] = r;
+      const KT r = bi + S - D * xi;
+      rs[0] = L == 0 ? r : (KT)0;
+      rs[1] = L == 1 ? r : (KT)0;
+      rs[2] = L == 2 ? r : (KT)0;
     }
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
@@ -389,84 +525,55 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
   }
 }
 
-// Coarse-level (l >= 1) red-black Gauss-Seidel update of cell C; slots of
-// one cell are relaxed in order.  mode as for k_mg0_smooth (mode 2 reads the
-// level l+1 solution for the coarse correction); mode 3 is the first black
-// sweep of a cycle: neighbours (red, just written) are read, the cell's own
-// slots start from zero.
+// Coarse-level (l >= 1) red-black Gauss-Seidel update of cell C; the slots
+// of one cell are relaxed in order (slot-wise Gauss-Seidel inside the cell).
 template <typename KT>
-__device__ inline void smooth_cell(const CellDev& cd, int l, int op, int C, int mode) {
-  const MGLevel& L = cd.lv[l];
-  const MGLevel* Lp = &cd.lv[l + 1];
-  const C3 q = c3_of(C, L.nx, L.ny);
-  const OpV<KT> A{(const KT*)L.op[op], L.ncell};
-  const KT* b = (const KT*)L.b;
-  KT* x = (KT*)L.x;
-  const KT alpha = (KT)cd.alpha;
-  const int nmode = mode == 3 ? 0 : mode;
-  KT xs[3];
-  for (int t = 0; t < 3; ++t) xs[t] = mode == 3 ? (KT)0 : xval<KT>(L, Lp, C, t, mode, alpha);
+__device__ inline void smooth_cell(const CellDev& cd, int l, int op, int C, const C3& q, int mode) {
+  CoarseRow<KT> R;
+  gather_coarse<KT>(cd, l, op, C, q, mode, R);
+#pragma unroll
   for (int s = 0; s < 3; ++s) {
-    KT D = A.E(C, s), sum = b[(size_t)s * L.ncell + C];
+    KT D = R.E[s], S = R.b[s];
+#pragma unroll
     for (int t = 0; t < 3; ++t)
       if (t != s) {
-        const KT g = A.X(C, xidx(s, t));
+        const KT g = R.X[xidx(s, t)];
         D += g;
-        sum += g * xs[t];
+        S += g * R.xo[t];
       }
-    for (int dir = 0; dir < 3; ++dir) {
-      const int xp = q.x + (dir == 0), yp = q.y + (dir == 1), zp = q.z + (dir == 2);
-      if (xp < L.nx && yp < L.ny && zp < L.nz) {
-        const int c2 = lvl_cell(L, xp, yp, zp);
-        for (int t = 0; t < 3; ++t) {
-          const KT g = A.G(C, dir, s, t);
-          if (g == (KT)0) continue;
-          D += g;
-          sum += g * xval<KT>(L, Lp, c2, t, nmode, alpha);
-        }
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const KT gp = R.Gp[dir][s * 3 + t], gm = R.Gm[dir][t * 3 + s];
+        D += gp + gm;
+        S += gp * R.xn[2 * dir][t] + gm * R.xn[2 * dir + 1][t];
       }
-      const int xm = q.x - (dir == 0), ym = q.y - (dir == 1), zm = q.z - (dir == 2);
-      if (xm >= 0 && ym >= 0 && zm >= 0) {
-        const int c2 = lvl_cell(L, xm, ym, zm);
-        for (int t = 0; t < 3; ++t) {
-          const KT g = A.G(c2, dir, t, s);
-          if (g == (KT)0) continue;
-          D += g;
-          sum += g * xval<KT>(L, Lp, c2, t, nmode, alpha);
-        }
-      }
-    }
-    xs[s] = D > (KT)0 ? sum / D : (KT)0;
+    R.xo[s] = D > (KT)0 ? S / D : (KT)0;
   }
-  for (int s = 0; s < 3; ++s) x[(size_t)s * L.ncell + C] = xs[s];
+  const MGLevel& L = cd.lv[l];
+  KT* x = (KT*)L.x;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) x[(size_t)s * L.ncell + C] = R.xo[s];
 }
 
 // Residual (per slot) of coarse cell c at level l.
 template <typename KT>
-__device__ inline void residual_cell(const CellDev& cd, int l, int op, int c, KT (&r)[3]) {
-  const MGLevel& L = cd.lv[l];
-  const OpV<KT> A{(const KT*)L.op[op], L.ncell};
-  const KT* b = (const KT*)L.b;
-  const KT* x = (const KT*)L.x;
-  const size_t n = L.ncell;
-  const C3 q = c3_of(c, L.nx, L.ny);
+__device__ inline void residual_cell(const CellDev& cd, int l, int op, int c, const C3& q, KT (&r)[3]) {
+  CoarseRow<KT> R;
+  gather_coarse<KT>(cd, l, op, c, q, SM_PLAIN, R);
+#pragma unroll
   for (int s = 0; s < 3; ++s) {
-    const KT xsv = x[s * n + c];
-    KT rr = b[s * n + c] - A.E(c, s) * xsv;
+    const KT xs = R.xo[s];
+    KT rr = R.b[s] - R.E[s] * xs;
+#pragma unroll
     for (int t = 0; t < 3; ++t)
-      if (t != s) rr -= A.X(c, xidx(s, t)) * (xsv - x[t * n + c]);
-    for (int dir = 0; dir < 3; ++dir) {
-      const int xp = q.x + (dir == 0), yp = q.y + (dir == 1), zp = q.z + (dir == 2);
-      if (xp < L.nx && yp < L.ny && zp < L.nz) {
-        const int c2 = lvl_cell(L, xp, yp, zp);
-        for (int t = 0; t < 3; ++t) rr -= A.G(c, dir, s, t) * (xsv - x[t * n + c2]);
-      }
-      const int xm = q.x - (dir == 0), ym = q.y - (dir == 1), zm = q.z - (dir == 2);
-      if (xm >= 0 && ym >= 0 && zm >= 0) {
-        const int c2 = lvl_cell(L, xm, ym, zm);
-        for (int t = 0; t < 3; ++t) rr -= A.G(c2, dir, t, s) * (xsv - x[t * n + c2]);
-      }
-    }
+      if (t != s) rr -= R.X[xidx(s, t)] * (xs - R.xo[t]);
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir)
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        rr -= R.Gp[dir][s * 3 + t] * (xs - R.xn[2 * dir][t]) + R.Gm[dir][t * 3 + s] * (xs - R.xn[2 * dir + 1][t]);
     r[s] = rr;
   }
 }
@@ -478,11 +585,9 @@ __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int
   const CellDev& cd = cells[bb.x];
   if (!gate(cd, need) || l >= cd.lfuse) return;
   const MGLevel& L = cd.lv[l];
-  const int C = bb.y * kBlock + threadIdx.x;
-  if (C >= L.ncell) return;
-  const C3 q = c3_of(C, L.nx, L.ny);
-  if (((q.x + q.y + q.z) & 1) != color) return;
-  smooth_cell<KT>(cd, l, op, C, mode);
+  C3 q;
+  if (!color_cell(bb.y * kBlock + threadIdx.x, color, L.nx, L.ny, L.nz, q)) return;
+  smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode);
 }
 
 // Level-l residual restricted to level l+1: 8 lanes per parent, one per child.
@@ -501,7 +606,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
   if (live) {
     const C3 q = c3_of(P, Lp.nx, Lp.ny);
     const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
-    if (cx < L.nx && cy < L.ny && cz < L.nz) residual_cell<KT>(cd, l, op, lvl_cell(L, cx, cy, cz), rs);
+    if (cx < L.nx && cy < L.ny && cz < L.nz) residual_cell<KT>(cd, l, op, lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
   if (live && ch == 0) {
@@ -525,10 +630,11 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
     const MGLevel& L = cd.lv[l];
     for (int it = 0; it < nu; ++it)
       for (int color = 0; color < 2; ++color) {
-        const int mode = it == 0 ? (color == 0 ? 1 : 3) : 0;
-        for (int C = threadIdx.x; C < L.ncell; C += blockDim.x) {
-          const C3 q = c3_of(C, L.nx, L.ny);
-          if (((q.x + q.y + q.z) & 1) == color) smooth_cell<KT>(cd, l, op, C, mode);
+        const int mode = it == 0 ? (color == 0 ? SM_ZERO : SM_OWNZERO) : SM_PLAIN;
+        const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
+        for (int t = threadIdx.x; t < nh; t += blockDim.x) {
+          C3 q;
+          if (color_cell(t, color, L.nx, L.ny, L.nz, q)) smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode);
         }
         __syncthreads();
       }
@@ -540,7 +646,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
         if (cx >= L.nx || cy >= L.ny || cz >= L.nz) continue;
         KT r[3];
-        residual_cell<KT>(cd, l, op, lvl_cell(L, cx, cy, cz), r);
+        residual_cell<KT>(cd, l, op, lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, r);
         for (int s = 0; s < 3; ++s) acc[s] += r[s];
       }
       for (int s = 0; s < 3; ++s) ((KT*)Lp.b)[(size_t)s * Lp.ncell + P] = acc[s];
@@ -567,10 +673,11 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
     const MGLevel& L = cd.lv[l];
     for (int it = 0; it < nu; ++it)
       for (int color = 1; color >= 0; --color) {
-        const int mode = (it == 0 && color == 1) ? 2 : 0;
-        for (int C = threadIdx.x; C < L.ncell; C += blockDim.x) {
-          const C3 q = c3_of(C, L.nx, L.ny);
-          if (((q.x + q.y + q.z) & 1) == color) smooth_cell<KT>(cd, l, op, C, mode);
+        const int mode = it == 0 ? (color == 1 ? SM_CORR : SM_OWNCORR) : SM_PLAIN;
+        const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
+        for (int t = threadIdx.x; t < nh; t += blockDim.x) {
+          C3 q;
+          if (color_cell(t, color, L.nx, L.ny, L.nz, q)) smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode);
         }
         __syncthreads();
       }
@@ -678,21 +785,29 @@ void launch_mg_setup(const BatchLaunch& b, hipStream_t s) {
 template <typename KT>
 static void smooth0(const BatchLaunch& b, int op, int color, int mode, int need, hipStream_t s) {
   prof_begin(PK_SMOOTH0, s);
-  k_mg0_smooth<KT><<<b.nblk, kBlock, 0, s>>>(b.cells, b.blk, op, color, mode, need);
+  k_mg0_smooth<KT><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, need);
   if (prof_on(PK_SMOOTH0)) prof_end(PK_SMOOTH0, s, b.bytes_smooth0);
 }
 
+template <typename KT>
+static void smoothl(const BatchLaunch& b, int l, int op, int color, int mode, int need, hipStream_t s) {
+  k_mgl_smooth<KT><<<b.lvlh_nblk[l], kBlock, 0, s>>>(b.cells, b.lvlh_blk[l], l, op, color, mode, need);
+}
+
+// One V-cycle on operator op: nu red-black sweeps (red then black) down to
+// the fused levels, then the fused coarse cycle, then nu sweeps (black then
+// red) back up.  The first post-sweep applies the coarse correction lazily.
 template <typename KT>
 static void vcycle(const BatchLaunch& b, int op, int nu, int need, hipStream_t s) {
   const int top = b.maxfuse;   // levels >= a cell's lfuse run inside k_mg_coarse_cycle
   for (int l = 0; l < top; ++l) {
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
-        smooth0<KT>(b, op, 0, it == 0 ? 1 : 0, need, s);
-        smooth0<KT>(b, op, 1, 0, need, s);
+        smooth0<KT>(b, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, need, s);
+        smooth0<KT>(b, op, 1, SM_PLAIN, need, s);
       } else {
-        k_mgl_smooth<KT><<<b.lvl_nblk[l], kBlock, 0, s>>>(b.cells, b.lvl_blk[l], l, op, 0, it == 0 ? 1 : 0, need);
-        k_mgl_smooth<KT><<<b.lvl_nblk[l], kBlock, 0, s>>>(b.cells, b.lvl_blk[l], l, op, 1, it == 0 ? 3 : 0, need);
+        smoothl<KT>(b, l, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, need, s);
+        smoothl<KT>(b, l, op, 1, it == 0 ? SM_OWNZERO : SM_PLAIN, need, s);
       }
     }
     if (l == 0)
@@ -704,11 +819,11 @@ static void vcycle(const BatchLaunch& b, int op, int nu, int need, hipStream_t s
   for (int l = top - 1; l >= 0; --l) {
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
-        smooth0<KT>(b, op, 1, it == 0 ? 2 : 0, need, s);
-        smooth0<KT>(b, op, 0, 0, need, s);
+        smooth0<KT>(b, op, 1, it == 0 ? SM_CORR : SM_PLAIN, need, s);
+        smooth0<KT>(b, op, 0, SM_PLAIN, need, s);
       } else {
-        k_mgl_smooth<KT><<<b.lvl_nblk[l], kBlock, 0, s>>>(b.cells, b.lvl_blk[l], l, op, 1, it == 0 ? 2 : 0, need);
-        k_mgl_smooth<KT><<<b.lvl_nblk[l], kBlock, 0, s>>>(b.cells, b.lvl_blk[l], l, op, 0, 0, need);
+        smoothl<KT>(b, l, op, 1, it == 0 ? SM_CORR : SM_PLAIN, need, s);
+        smoothl<KT>(b, l, op, 0, it == 0 ? SM_OWNCORR : SM_PLAIN, need, s);
       }
     }
   }
