@@ -278,17 +278,19 @@ struct Batch {
       b.bytes_smooth0 += (4.0 + 1.5 * kt) * N + kt * (Fa + Fc);
     }
     b.cells = d_desc;
-    b.blk = d_blk;
+    // a single cell needs no block tables: kernels map block b to {0, b}
+    const bool one = cells.size() == 1;
+    b.blk = one ? nullptr : d_blk;
     b.nblk = nblk;
     b.ncell = (int)cells.size();
     b.maxlev = maxlev;
     b.maxfuse = maxfuse;
     for (int l = 0; l < kMaxLevels; ++l) {
-      b.lvl_blk[l] = lvl_blk[l];
+      b.lvl_blk[l] = one ? nullptr : lvl_blk[l];
       b.lvl_nblk[l] = lvl_nblk[l];
-      b.lvl8_blk[l] = lvl8_blk[l];
+      b.lvl8_blk[l] = one ? nullptr : lvl8_blk[l];
       b.lvl8_nblk[l] = lvl8_nblk[l];
-      b.lvlh_blk[l] = lvlh_blk[l];
+      b.lvlh_blk[l] = one ? nullptr : lvlh_blk[l];
       b.lvlh_nblk[l] = lvlh_nblk[l];
     }
     return b;
@@ -420,10 +422,10 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
     for (; k < m; ++k) {
       launch_precond<KT>(bl, k, B.nu, 0, B.s);
       launch_matvec<KT>(bl, VEC_Z, VEC_W, 0, B.s);
-      launch_multidot<KT>(bl, k, 0, B.s);
-      launch_orth<KT>(bl, k, 0, B.s);
-      launch_multidot<KT>(bl, k, 1, B.s);
-      launch_orth<KT>(bl, k, 1, B.s);
+      // classical Gram-Schmidt with one re-orthogonalisation (CGS2)
+      launch_multidot<KT>(bl, k, 0, B.s);   // H(:,k) = V^T w
+      launch_orth_dots<KT>(bl, k, B.s);     // w -= V H(:,k); tmp = V^T w
+      launch_orth<KT>(bl, k, 1, B.s);       // w -= V tmp; H(:,k) += tmp; H(k+1,k) = |w|
       launch_scale_next<KT>(bl, k, B.s);
       launch_givens(bl, k, B.s);
       if ((k + 1) % check == 0 || k + 1 == m) {
@@ -470,7 +472,6 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
   for (int c = 0; c < nc; ++c) {
     mbx_cell* cl = B.cells[c];
     fill_step_constants(cl->h, dt);
-    cl->h.use_w = 0;
     cl->h.elim_n = 1;
     cl->h.active = 1;
     cl->h.lam = 1.0;
@@ -1002,7 +1003,6 @@ static int load_eval_state(mbx_cell* c, const double* cu, const double* pu, cons
   }
   fill_step_constants(c->h, dt);
   c->h.active = 1;
-  c->h.use_w = 0;    // probes expose the unweighted scaled operator
   c->h.elim_n = 0;   // ... at the caller's plated amounts
   Batch b = single(c);
   return b.upload();

@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(kBlock) k_finish_meta(int N, uint32_t* __restr
 // Zero-current equilibrium (every interface current vanishes; the plated
 // amount makes the plating current zero: f_pre(n) = exp(-F U_an(x0)/RT)).
 __global__ void __launch_bounds__(kBlock) k_init_state(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(kBlock) k_init_state(CellDev* cells, const int
 // coefficient.
 template <bool LIN, typename KT>
 __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   CellDev* cdp = cells + bb.x;
   const CellDev& cd = *cdp;
   if (!cd.active) return;
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
 // also copied to w (the first GMRES residual, x = 0), with ||b||^2.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   CellDev* cdp = cells + bb.x;
   const CellDev& cd = *cdp;
   if (!cd.active) return;
@@ -297,14 +297,6 @@ __global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __re
         }
       }
     }
-    double wc = 1.0, wp = 0.0;
-    for (int d = 0; d < 6; ++d) {
-      const int k = neighbour(cd, i, v.x, v.y, v.z, d);
-      if (k >= 0) weight_add(cd, L, lab_of(cd.meta[k]), wc, wp);
-    }
-    weight_finish(cd, L, v.z, wc, wp);
-    bc *= wc;
-    bp *= wp;
     const size_t N = cd.N;
     KT* b = (KT*)cd.b;
     KT* w = (KT*)cd.w;
@@ -327,7 +319,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __re
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_jacobi(CellDev* cells, const int2* __restrict__ blk, int src, int dst,
                                                    int need) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE] != need) return;
   const int i = bb.y * kBlock + threadIdx.x;
@@ -348,7 +340,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(CellDev* cells, const int2* _
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* __restrict__ blk, int src, int dst,
                                                    int need) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE] != need) return;
   const int i = bb.y * kBlock + threadIdx.x;
@@ -366,7 +358,6 @@ __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* _
   const KT wi = (L == PORE) ? wpo[i] : (KT)0;
   const KT Gk = (KT)cd.Gk, tth = (KT)cd.tth, Dh = (KT)cd.Dh, tau = (KT)cd.tau, Ke = (KT)cd.Ke;
   KT yc = vc, yp = (KT)0;
-  double wc = 1.0, wp = 0.0;
   for (int d = 0; d < 6; ++d) {
     const int k = neighbour(cd, i, c3.x, c3.y, c3.z, d);
     if (k < 0) {
@@ -375,7 +366,6 @@ __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* _
     }
     const uint32_t mk = cd.meta[k];
     const int Lk = lab_of(mk);
-    weight_add(cd, L, Lk, wc, wp);
     const KT vck = v[k], vpk = v[N + k];
     const bool lo = i < k;
     if (L == PORE && Lk == PORE) {
@@ -425,16 +415,15 @@ __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* _
       yp += q + qp;
     }
   }
-  weight_finish(cd, L, c3.z, wc, wp);
-  y[i] = yc * (KT)wc;
-  y[N + i] = yp * (KT)wp;
+  y[i] = yc;
+  y[N + i] = yp;
 }
 
 // ------------------------------------------------------------------- GMRES
 // Dots of w with basis vectors 0..k: block partials (first pass).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_multidot(CellDev* cells, const int2* __restrict__ blk, int k) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE]) return;
   __shared__ double lds[4 * kPartStride];
@@ -457,30 +446,73 @@ __global__ void __launch_bounds__(kBlock) k_multidot(CellDev* cells, const int2*
   }
   __syncthreads();
   for (int j = threadIdx.x; j <= k; j += kBlock)
-    cd.part[(size_t)bb.y * kPartStride + j] = combine4(lds, kPartStride, j, false);
+    cd.part[(size_t)j * cd.nblk + bb.y] = combine4(lds, kPartStride, j, false);
 }
 
-// Second pass of k_multidot: H(:,k) (tgt = 0) or tmp (tgt = 1).
+// Second pass of the dot products: column j = blockIdx.x of cell blockIdx.y
+// into H(j,k) (tgt = 0) or tmp(j) (tgt = 1).
 __global__ void __launch_bounds__(kBlock) k_finalize_dots(CellDev* cells, int ncell, int k, int tgt) {
-  const int ci = blockIdx.x;
-  if (ci >= ncell) return;
+  const int j = blockIdx.x, ci = blockIdx.y;
+  if (ci >= ncell || j > k) return;
   const CellDev& cd = cells[ci];
   if (!cd.active || cd.ictl[CTL_DONE]) return;
   __shared__ double lds4[4];
   __shared__ double res;
   const int m = cd.m;
   double* out = tgt == 0 ? cd.gm + gm_H(m) + (size_t)(m + 1) * k : cd.gm + gm_tmp(m);
-  for (int j = 0; j <= k; ++j) {
-    const double r = finalize_column(cd, j, false, lds4, &res);
-    if (threadIdx.x == 0) out[j] = r;
+  const double r = finalize_column(cd, j, false, lds4, &res);
+  if (threadIdx.x == 0) out[j] = r;
+}
+
+// First Gram-Schmidt pass and the second pass's dot products in one sweep
+// over the basis: w -= sum_j H(j,k) V_j, then block partials of V_j . w for
+// j <= k.  The thread's basis entries stay in registers between the two.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2* __restrict__ blk, int k) {
+  const int2 bb = block_of(blk);
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active || cd.ictl[CTL_DONE]) return;
+  __shared__ double lds[4 * kPartStride];
+  const int m = cd.m;
+  const double* hc = cd.gm + gm_H(m) + (size_t)(m + 1) * k;
+  const int i = bb.y * kBlock + threadIdx.x;
+  const size_t N = cd.N;
+  const bool in = i < cd.N;
+  KT* w = (KT*)cd.w;
+  KT vc[kMaxRestart], vp[kMaxRestart];
+  KT wc = (KT)0, wp = (KT)0;
+  if (in) {
+    wc = w[i];
+    wp = w[N + i];
   }
+#pragma unroll
+  for (int j = 0; j < kMaxRestart; ++j) {
+    if (j <= k) {
+      const KT* vj = vec<KT>(cd, j);
+      vc[j] = in ? vj[i] : (KT)0;
+      vp[j] = in ? vj[N + i] : (KT)0;
+      const KT hj = (KT)hc[j];
+      wc -= hj * vc[j];
+      wp -= hj * vp[j];
+    }
+  }
+  if (in) {
+    w[i] = wc;
+    w[N + i] = wp;
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxRestart; ++j)
+    if (j <= k) wave_to_lds((double)vc[j] * (double)wc + (double)vp[j] * (double)wp, false, lds, kPartStride, j);
+  __syncthreads();
+  for (int j = threadIdx.x; j <= k; j += kBlock)
+    cd.part[(size_t)j * cd.nblk + bb.y] = combine4(lds, kPartStride, j, false);
 }
 
 // w -= sum_j h_j V_j with h = H(:,k) (src = 0) or tmp (src = 1); block
 // partials of ||w||^2 (first pass).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_orth(CellDev* cells, const int2* __restrict__ blk, int k, int src) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE]) return;
   const int m = cd.m;
@@ -546,7 +578,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize_red(CellDev* cells, int nce
 // V_{k+1} = w / H(k+1,k)
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_scale_next(CellDev* cells, const int2* __restrict__ blk, int k) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE]) return;
   const int i = bb.y * kBlock + threadIdx.x;
@@ -622,7 +654,7 @@ __global__ void k_backsolve(CellDev* cells, int ncell) {
 // w = sum_{j<k} y_j V_j (cycle end; runs for converged cells too)
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_combine(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
   {
@@ -650,7 +682,7 @@ __global__ void __launch_bounds__(kBlock) k_combine(CellDev* cells, const int2* 
 // Cycle end: z = M^-1 w (block Jacobi) and x += z, fused.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_update_x_jacobi(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
   {
@@ -671,7 +703,7 @@ __global__ void __launch_bounds__(kBlock) k_update_x_jacobi(CellDev* cells, cons
 // x += z
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_add_z_to_x(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
   {
@@ -690,7 +722,7 @@ __global__ void __launch_bounds__(kBlock) k_add_z_to_x(CellDev* cells, const int
 // Restart: w = b - w (w holds J x) with ||w||^2.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_true_residual(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   CellDev* cdp = cells + bb.x;
   const CellDev& cd = *cdp;
   if (!cd.active || cd.ictl[CTL_DONE] != 2) return;
@@ -713,7 +745,7 @@ __global__ void __launch_bounds__(kBlock) k_true_residual(CellDev* cells, const 
 // the first cycle of a solve, otherwise only cells that must restart).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_gm_start(CellDev* cells, const int2* __restrict__ blk, int first) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
   if (!first && cd.ictl[CTL_DONE] != 2) return;
@@ -774,7 +806,7 @@ __global__ void k_gather_ctl(CellDev* cells, int ncell, double* out) {
 // dn = -R^n/J_nn - (dt/F) (d i_pl, condensed).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_direction(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   CellDev* cdp = cells + bb.x;
   const CellDev& cd = *cdp;
   if (!cd.active) return;
@@ -817,7 +849,7 @@ __global__ void __launch_bounds__(kBlock) k_direction(CellDev* cells, const int2
 // Trial state u + lam du; counts inadmissible entries (c <= 0, c_s >= c_max,
 // n < 0, non-finite) and the scaled max-norm of the step.
 __global__ void __launch_bounds__(kBlock) k_trial(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   CellDev* cdp = cells + bb.x;
   const CellDev& cd = *cdp;
   if (!cd.active) return;
@@ -853,7 +885,7 @@ __global__ void __launch_bounds__(kBlock) k_trial(CellDev* cells, const int2* __
 // State copies: 0 try -> iterate, 1 iterate -> try, 2 iterate -> old (step
 // start), 3 old -> iterate and try (rollback), 4 old -> try (step start).
 __global__ void __launch_bounds__(kBlock) k_copy_state(CellDev* cells, const int2* __restrict__ blk, int mode) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
@@ -891,7 +923,7 @@ __global__ void __launch_bounds__(kBlock) k_copy_state(CellDev* cells, const int
 // state): Li inventories per phase and the plated layer, and the sum over
 // cathode collector faces of the extrapolated collector potential.
 __global__ void __launch_bounds__(kBlock) k_outputs(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   CellDev* cdp = cells + bb.x;
   const CellDev& cd = *cdp;
   if (!cd.active) return;
@@ -920,7 +952,7 @@ __global__ void __launch_bounds__(kBlock) k_outputs(CellDev* cells, const int2* 
 // doubles) and a Krylov vector: dir 0 doubles -> KT vector, 1 KT -> doubles.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_convert(CellDev* cells, const int2* __restrict__ blk, int sel, int dir) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
@@ -938,7 +970,7 @@ __global__ void __launch_bounds__(kBlock) k_convert(CellDev* cells, const int2* 
 // x = 0 (start of a solve from a given right-hand side)
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_zero_x(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
@@ -951,7 +983,7 @@ __global__ void __launch_bounds__(kBlock) k_zero_x(CellDev* cells, const int2* _
 // ||w||^2 into RED_BSQ
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_norm_w(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   CellDev* cdp = cells + bb.x;
   const CellDev& cd = *cdp;
   if (!cd.active) return;
@@ -1013,7 +1045,12 @@ void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t
 template <typename KT>
 void launch_multidot(const BatchLaunch& b, int k, int tgt, hipStream_t s) {
   k_multidot<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, k);
-  k_finalize_dots<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, k, tgt);
+  k_finalize_dots<<<dim3(k + 1, b.ncell), kBlock, 0, s>>>(b.cells, b.ncell, k, tgt);
+}
+template <typename KT>
+void launch_orth_dots(const BatchLaunch& b, int k, hipStream_t s) {
+  k_orth_dots<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, k);
+  k_finalize_dots<<<dim3(k + 1, b.ncell), kBlock, 0, s>>>(b.cells, b.ncell, k, 1);
 }
 template <typename KT>
 void launch_orth(const BatchLaunch& b, int k, int src, hipStream_t s) {
@@ -1097,6 +1134,7 @@ void launch_outputs(const BatchLaunch& b, hipStream_t s) {
   template void launch_norm_w<KT>(const BatchLaunch&, hipStream_t);                  \
   template void launch_multidot<KT>(const BatchLaunch&, int, int, hipStream_t);  \
   template void launch_orth<KT>(const BatchLaunch&, int, int, hipStream_t);      \
+  template void launch_orth_dots<KT>(const BatchLaunch&, int, hipStream_t);     \
   template void launch_scale_next<KT>(const BatchLaunch&, int, hipStream_t);     \
   template void launch_combine<KT>(const BatchLaunch&, hipStream_t);             \
   template void launch_update_x_jacobi<KT>(const BatchLaunch&, hipStream_t);     \

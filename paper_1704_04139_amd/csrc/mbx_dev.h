@@ -39,6 +39,13 @@ struct MGLevel {
   void* op[2];   // KT [kOpStride*ncell] for the concentration (0) and potential (1) operators
 };
 
+// Block -> {cell, block within the cell}: from the batch's block table, or
+// {0, blockIdx.x} for a single-cell launch (no table: one dependent load less
+// at the start of every kernel).
+__device__ inline int2 block_of(const int2* __restrict__ blk) {
+  return blk ? blk[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+}
+
 __host__ __device__ inline int lab_of(uint32_t m) { return int(m & 3u); }
 __host__ __device__ inline uint32_t mask_of(uint32_t m) { return (m >> 2) & 63u; }
 __host__ __device__ inline uint32_t base_of(uint32_t m) { return m >> 8; }
@@ -71,7 +78,6 @@ struct CellDev {
   int nx, ny, nz, N;
   int F_an, F_ca, n_top, nblk;
   int active;         // 0: every kernel skips this cell
-  int use_w;          // 1: Krylov system rows weighted by 1/(transport diagonal)
   int elim_n;         // 1: residual kernels solve each face's plating balance for n
   int pad0;
   const uint32_t* meta;
@@ -137,19 +143,14 @@ __device__ inline int neighbour(const CellDev& cd, int i, int x, int y, int z, i
   }
 }
 
-// Row weights of the Newton system: the reciprocal of the state-independent
-// part of each scaled row's diagonal (mass + same-phase transport +
-// collector), so that every weighted row measures the error of its own
-// unknown.  A row with no transport coupling keeps weight 1.
+// State-independent part of a scaled row's diagonal (mass + same-phase
+// transport; the collector term is added by the caller): the merit norm
+// divides each residual row by it, so that every weighted row measures the
+// error of its own unknown.
 __device__ inline void weight_add(const CellDev& cd, int L, int Lk, double& wc, double& wp) {
   if (L != Lk) return;
   wc += (L == PORE) ? cd.Dh : cd.Dsh[L - 1];
   wp += (L == PORE) ? cd.Gk : cd.Gs[L - 1];
-}
-__device__ inline void weight_finish(const CellDev& cd, int L, int z, double& wc, double& wp) {
-  if (L == ANODE && z == 0) wp += cd.Gcol;
-  wc = cd.use_w ? 1.0 / wc : 1.0;
-  wp = cd.use_w ? 1.0 / fmax(wp, 1.0) : 1.0;
 }
 
 // Plated amount that zeroes the face's plating balance (Sec. 2.3, eq. 2.8):

@@ -48,6 +48,9 @@ template <typename KT> void launch_zero_x(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_norm_w(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_multidot(const BatchLaunch& b, int k, int tgt, hipStream_t s);
 template <typename KT> void launch_orth(const BatchLaunch& b, int k, int src, hipStream_t s);
+// first Gram-Schmidt pass (coefficients H(:,k)) fused with the dot products of
+// the second pass (into tmp)
+template <typename KT> void launch_orth_dots(const BatchLaunch& b, int k, hipStream_t s);
 template <typename KT> void launch_scale_next(const BatchLaunch& b, int k, hipStream_t s);
 void launch_givens(const BatchLaunch& b, int k, hipStream_t s);
 void launch_backsolve(const BatchLaunch& b, hipStream_t s);

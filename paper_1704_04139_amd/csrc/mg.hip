@@ -47,6 +47,15 @@ __device__ inline bool gate(const CellDev& cd, int need) {
   if (need == -1) return st == 1 || st == 2;
   return st == need;
 }
+// The GMRES-state part of the gate alone.  Hot kernels test cd.active first,
+// issue their loads, and test this only before their stores, so the flag load
+// overlaps the data loads instead of preceding them.
+__device__ inline bool gate_state(const CellDev& cd, int need) {
+  if (need == -2) return true;
+  const int st = cd.ictl[CTL_DONE];
+  if (need == -1) return st == 1 || st == 2;
+  return st == need;
+}
 
 template <typename KT>
 __device__ inline KT* vsel(const CellDev& cd, int sel) {
@@ -291,7 +300,7 @@ __device__ inline void gather_coarse(const CellDev& cd, int l, int op, int C, co
 // the cell between different slots -> X; faces to the +dir neighbour cell -> G.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg_assemble0(CellDev* cells, const int2* __restrict__ blk, int op) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.nlev < 2) return;
   const MGLevel& L1 = cd.lv[1];
@@ -337,7 +346,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_assemble0(CellDev* cells, const i
 // transfer; same-slot couplings inside an aggregate cancel).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg_assemble(CellDev* cells, const int2* __restrict__ blk, int l, int op) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || l + 1 >= cd.nlev) return;
   const MGLevel& Lc = cd.lv[l];
@@ -460,9 +469,9 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int 
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg0_smooth(CellDev* cells, const int2* __restrict__ blk, int op,
                                                        int color, int mode, int need) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!gate(cd, need)) return;
+  if (!cd.active) return;
   C3 c;
   if (!color_cell(bb.y * kBlock + threadIdx.x, color, cd.nx, cd.ny, cd.nz, c)) return;
   const int i = c.x + cd.nx * (c.y + cd.ny * c.z);
@@ -470,6 +479,7 @@ __global__ void __launch_bounds__(kBlock) k_mg0_smooth(CellDev* cells, const int
   const KT bi = ((const KT*)cd.b0)[i];
   KT D, S;
   voxel_row<KT>(cd, op, i, c, cd.meta[i], x0, mode == SM_ZERO, mode == SM_CORR, D, S);
+  if (!gate_state(cd, need)) return;
   x0[i] = D > (KT)0 ? (bi + S) / D : (KT)0;
 }
 
@@ -493,9 +503,9 @@ __device__ inline double lane8_sum(double v) {
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const int2* __restrict__ blk, int op,
                                                          int need) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!gate(cd, need)) return;
+  if (!cd.active) return;
   const MGLevel& L1 = cd.lv[1];
   const int t = bb.y * kBlock + threadIdx.x;
   const int C = t >> 3, ch = t & 7;
@@ -519,6 +529,7 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
     }
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
+  if (!gate_state(cd, need)) return;   // uniform over the block (one cell)
   if (live && ch == 0) {
     KT* b1 = (KT*)L1.b;
     for (int s = 0; s < 3; ++s) b1[(size_t)s * L1.ncell + C] = rs[s];
@@ -528,7 +539,7 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
 // Coarse-level (l >= 1) red-black Gauss-Seidel update of cell C; the slots
 // of one cell are relaxed in order (slot-wise Gauss-Seidel inside the cell).
 template <typename KT>
-__device__ inline void smooth_cell(const CellDev& cd, int l, int op, int C, const C3& q, int mode) {
+__device__ inline void smooth_cell(const CellDev& cd, int l, int op, int C, const C3& q, int mode, int need) {
   CoarseRow<KT> R;
   gather_coarse<KT>(cd, l, op, C, q, mode, R);
 #pragma unroll
@@ -551,6 +562,7 @@ __device__ inline void smooth_cell(const CellDev& cd, int l, int op, int C, cons
       }
     R.xo[s] = D > (KT)0 ? S / D : (KT)0;
   }
+  if (!gate_state(cd, need)) return;
   const MGLevel& L = cd.lv[l];
   KT* x = (KT*)L.x;
 #pragma unroll
@@ -581,22 +593,22 @@ __device__ inline void residual_cell(const CellDev& cd, int l, int op, int c, co
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int2* __restrict__ blk, int l, int op,
                                                        int color, int mode, int need) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!gate(cd, need) || l >= cd.lfuse) return;
+  if (!cd.active || l >= cd.lfuse) return;
   const MGLevel& L = cd.lv[l];
   C3 q;
   if (!color_cell(bb.y * kBlock + threadIdx.x, color, L.nx, L.ny, L.nz, q)) return;
-  smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode);
+  smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode, need);
 }
 
 // Level-l residual restricted to level l+1: 8 lanes per parent, one per child.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const int2* __restrict__ blk, int l, int op,
                                                          int need) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!gate(cd, need) || l >= cd.lfuse) return;
+  if (!cd.active || l >= cd.lfuse) return;
   const MGLevel& L = cd.lv[l];
   const MGLevel& Lp = cd.lv[l + 1];
   const int t = bb.y * kBlock + threadIdx.x;
@@ -609,6 +621,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
     if (cx < L.nx && cy < L.ny && cz < L.nz) residual_cell<KT>(cd, l, op, lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
+  if (!gate_state(cd, need)) return;   // uniform over the block (one cell)
   if (live && ch == 0) {
     KT* bp = (KT*)Lp.b;
     for (int s = 0; s < 3; ++s) bp[(size_t)s * Lp.ncell + P] = rs[s];
@@ -634,7 +647,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
-          if (color_cell(t, color, L.nx, L.ny, L.nz, q)) smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode);
+          if (color_cell(t, color, L.nx, L.ny, L.nz, q)) smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode, -2);
         }
         __syncthreads();
       }
@@ -677,7 +690,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
-          if (color_cell(t, color, L.nx, L.ny, L.nz, q)) smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode);
+          if (color_cell(t, color, L.nx, L.ny, L.nz, q)) smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode, -2);
         }
         __syncthreads();
       }
@@ -688,25 +701,16 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
 // b0 = v_c - tau * v_phi on pore voxels (row operation removing migration).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_pc_pre(CellDev* cells, const int2* __restrict__ blk, int src, int need) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!gate(cd, need)) return;
+  if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
   const KT* v = vsel<KT>(cd, src);
   const uint32_t mi = cd.meta[i];
-  const int L = lab_of(mi);
-  // undo the row weights of the Krylov system: the multigrid solves the
-  // unweighted scaled operator
-  double wc = 1.0, wp = 0.0;
-  const C3 c = c3_of(i, cd.nx, cd.ny);
-  for (int d = 0; d < 6; ++d) {
-    const int k = fine_nbr(i, c, cd.nx, cd.ny, cd.nz, d);
-    if (k >= 0) weight_add(cd, L, lab_of(cd.meta[k]), wc, wp);
-  }
-  weight_finish(cd, L, c.z, wc, wp);
-  KT r = v[i] / (KT)wc;
-  if (L == PORE) r -= (KT)cd.tau * (v[(size_t)cd.N + i] / (KT)wp);
+  const KT vc = v[i], vp = v[(size_t)cd.N + i];
+  const KT r = lab_of(mi) == PORE ? vc - (KT)cd.tau * vp : vc;
+  if (!gate_state(cd, need)) return;
   ((KT*)cd.b0)[i] = r;
 }
 
@@ -715,9 +719,9 @@ __global__ void __launch_bounds__(kBlock) k_pc_pre(CellDev* cells, const int2* _
 // plating concentration derivatives) moved to the right-hand side.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* __restrict__ blk, int src, int need) {
-  const int2 bb = blk[blockIdx.x];
+  const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!gate(cd, need)) return;
+  if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
   const size_t N = cd.N;
@@ -727,48 +731,44 @@ __global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* _
   const KT* can = (const KT*)cd.coef_an;
   const KT* cca = (const KT*)cd.coef_ca;
   const C3 c = c3_of(i, cd.nx, cd.ny);
+  int k[6];
+  bool ex[6];
+  neighbours6(i, c, cd.nx, cd.ny, cd.nz, k, ex);
+  const int dmap[6] = {1, 0, 3, 2, 5, 4};   // neighbour slot -> face direction
   const uint32_t mi = cd.meta[i];
+  const KT vc = zc[i], wiv = wpo[i], vpi = v[N + i];
+  uint32_t mk[6];
+  KT vk[6], wk[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    mk[j] = cd.meta[k[j]];
+    vk[j] = zc[k[j]];
+    wk[j] = wpo[k[j]];
+  }
   const int L = lab_of(mi);
-  const KT vc = zc[i];
-  const KT wi = (L == PORE) ? wpo[i] : (KT)0;
+  const KT wi = L == PORE ? wiv : (KT)0;
   const KT Gt = (KT)(cd.Gk * cd.tth);
   KT yp = (KT)0;
-  double wc = 1.0, wp = 0.0;
-  for (int d = 0; d < 6; ++d) {
-    const int k = fine_nbr(i, c, cd.nx, cd.ny, cd.nz, d);
-    if (k < 0) continue;
-    const uint32_t mk = cd.meta[k];
-    const int Lk = lab_of(mk);
-    weight_add(cd, L, Lk, wc, wp);
-    const KT vck = zc[k];
-    if (L == PORE && Lk == PORE) {
-      yp += Gt * (wpo[k] * vck - wi * vc);   // outward dj from i with v_phi = 0
-    } else if (L == PORE && Lk != PORE) {
-      const uint32_t f = face_rank(mk, d ^ 1);
-      KT q;
-      if (Lk == ANODE) {
-        const KT* co = can + 5 * (size_t)f;
-        q = co[0] * vck + co[1] * vc + co[3] * vc;
-      } else {
-        const KT* co = cca + 3 * (size_t)f;
-        q = co[0] * vck + co[1] * vc;
-      }
-      yp -= q;
-    } else if (L != PORE && Lk == PORE) {
-      const uint32_t f = face_rank(mi, d);
-      KT q;
-      if (L == ANODE) {
-        const KT* co = can + 5 * (size_t)f;
-        q = co[0] * vc + co[1] * vck + co[3] * vck;
-      } else {
-        const KT* co = cca + 3 * (size_t)f;
-        q = co[0] * vc + co[1] * vck;
-      }
-      yp += q;
-    }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int Lk = lab_of(mk[j]);
+    const int d = dmap[j];
+    const bool pp = L == PORE && Lk == PORE;
+    const bool iface = (L == PORE) != (Lk == PORE);
+    const bool pore_side = L == PORE;
+    const uint32_t f = iface ? face_rank(pore_side ? mk[j] : mi, pore_side ? (d ^ 1) : d) : 0u;
+    const bool an = (pore_side ? Lk : L) == ANODE;
+    const KT* co = an ? can + 5 * (size_t)f : cca + 3 * (size_t)f;
+    const KT c0 = co[0], c1 = co[1], c3 = co[an ? 3 : 1];
+    const KT vs = pore_side ? vk[j] : vc, vpo = pore_side ? vc : vk[j];
+    // interface flux derivative w.r.t. the concentrations (potential part zero)
+    const KT q = c0 * vs + c1 * vpo + (an ? c3 * vpo : (KT)0);
+    const KT t = pp ? Gt * (wk[j] * vk[j] - wi * vc)      // outward dj from i
+                    : (iface ? (pore_side ? -q : q) : (KT)0);
+    yp += ex[j] ? t : (KT)0;
   }
-  weight_finish(cd, L, c.z, wc, wp);
-  ((KT*)cd.b0)[i] = v[N + i] / (KT)wp - yp;
+  if (!gate_state(cd, need)) return;
+  ((KT*)cd.b0)[i] = vpi - yp;
 }
 
 // ---------------------------------------------------------------- launchers

@@ -2,8 +2,10 @@
 //
 // Two-pass scheme: every block of a cell reduces its values (wavefront
 // shuffle tree, then the four wavefront results in fixed order) and stores
-// them in the cell's partial buffer; a finalising kernel (one block per
-// cell, launched next on the same stream) sums the partials in block order.
+// them in the cell's partial buffer (column-major: value j of block b at
+// j * nblk + b, so the finaliser's reads are coalesced); a finalising kernel
+// (one block per cell and column, launched next on the same stream) sums the
+// partials in block order.
 // The kernel boundary makes the partials visible to the finaliser without
 // any in-kernel fence (on this chip an agent-scope release fence writes back
 // the XCD's L2), and the fixed summation order makes the result independent
@@ -35,7 +37,7 @@ __device__ inline void reduce_block(const CellDev& cd, int blk, const double (&v
   for (int j = 0; j < K; ++j) wave_to_lds(v[j], (maxmask >> j) & 1u, lds, K, j);
   __syncthreads();
   if (threadIdx.x < K)
-    cd.part[(size_t)blk * kPartStride + threadIdx.x] = combine4(lds, K, threadIdx.x, (maxmask >> threadIdx.x) & 1u);
+    cd.part[(size_t)threadIdx.x * cd.nblk + blk] = combine4(lds, K, threadIdx.x, (maxmask >> threadIdx.x) & 1u);
 }
 
 // Second pass (inside a one-block-per-cell kernel): column j of the partial
@@ -43,7 +45,7 @@ __device__ inline void reduce_block(const CellDev& cd, int blk, const double (&v
 __device__ inline double finalize_column(const CellDev& cd, int j, bool mx, double* lds4, double* result) {
   double acc = 0.0;
   for (int b = threadIdx.x; b < cd.nblk; b += kBlock) {
-    const double p = cd.part[(size_t)b * kPartStride + j];
+    const double p = cd.part[(size_t)j * cd.nblk + b];
     acc = mx ? fmax(acc, p) : acc + p;
   }
   __syncthreads();
