@@ -208,6 +208,79 @@ int mbx_cell_solve(mbx_cell *c, const double *c_u, const double *phi_u, const do
 int mbx_batch_step(mbx_cell *const *cells, int n, double dt, int *status_out,
                    mbx_step_info *infos);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous-batching step server for many independent parameter queries
+ * (the many-query setting of Sec. 1 and Sec. 2.5, here answered by the full
+ * order model).  A request is a voxel image, a parameter set and a number
+ * of implicit Euler steps of the server's dt.  One worker thread owns all
+ * device work: it admits queued requests first-come first-served while their
+ * device footprint (mbx_cell_footprint) fits the budget next to the running
+ * cells, creates their cells (state resident in device memory), advances all
+ * running cells by one step per mbx_batch_step, and retires a request after
+ * its last step (or its first failed step), releasing its memory.  New
+ * requests join at the next step.  A request's results do not depend on
+ * which other requests share its batches (deterministic per-cell
+ * reductions).  submit / poll / result / drain / stats are thread-safe and
+ * do not touch the device. */
+typedef struct mbx_server mbx_server;
+
+enum { MBX_REQ_DONE = 0, MBX_REQ_QUEUED = 1, MBX_REQ_RUNNING = 2 };
+
+typedef struct {
+  int status;            /* MBX_REQ_*, or the negative MBX_E* code the request failed with */
+  int steps_done;        /* completed steps */
+  double V;              /* cell voltage after the last completed step, V */
+  double t_submit;       /* server clock (s, mbx_server_clock) at submission */
+  double t_admit;        /* ... when its cell was created (0 while queued) */
+  double t_done;         /* ... when it finished or failed (0 before) */
+  int64_t newton_iters;  /* totals over its steps */
+  int64_t krylov_iters;
+  int64_t n_vox;         /* voxels (after admission) */
+} mbx_request_info;
+
+typedef struct {
+  int64_t steps_run;     /* cell-steps completed */
+  int64_t batches;       /* batched steps launched */
+  double busy_s;         /* wall time spent inside batched steps, s */
+  int64_t bytes_in_use;  /* footprint of the admitted requests, bytes */
+  int running, queued;
+} mbx_server_info;
+
+/* Create a server: budget_bytes of device memory for cells, precision mode
+ * (MBX_FP64 / MBX_MIXED) and step dt (s) shared by all requests, keep_state
+ * = 1 to keep each finished request's final state on the host for
+ * mbx_server_result, stream as for mbx_cell_create (device work runs on the
+ * device current at this call).  Starts the worker thread.
+ * Errors: MBX_EINVAL, MBX_EHIP. */
+int mbx_server_create(int64_t budget_bytes, int precision, double dt, int keep_state, void *stream,
+                      mbx_server **out);
+
+/* Queue a request (labels and parameters as mbx_cell_create; copied) for
+ * n_steps steps; *id receives its handle.  p->precision must equal the
+ * server's.  MBX_EBUDGET if the request alone exceeds the budget. */
+int mbx_server_submit(mbx_server *s, const uint8_t *labels, int nx, int ny, int nz, const mbx_params *p,
+                      int n_steps, int64_t *id);
+
+/* Snapshot of a request's progress. MBX_EINVAL for an unknown id. */
+int mbx_server_poll(mbx_server *s, int64_t id, mbx_request_info *info);
+
+/* Final state of a finished request (keep_state servers): layouts as
+ * mbx_cell_get_state, host pointers, any may be null.  MBX_ESTATE if the
+ * request is not MBX_REQ_DONE or the server does not keep states. */
+int mbx_server_result(mbx_server *s, int64_t id, double *cfield, double *phi, double *n_pl);
+
+/* Block until no request is queued or running, at most timeout_s seconds
+ * (MBX_ESTATE on time-out). */
+int mbx_server_drain(mbx_server *s, double timeout_s);
+
+/* Seconds since the server was created (the clock of mbx_request_info). */
+double mbx_server_clock(const mbx_server *s);
+
+int mbx_server_stats(mbx_server *s, mbx_server_info *out);
+
+/* Stop the worker (after the step in flight) and release every cell. */
+void mbx_server_destroy(mbx_server *s);
+
 /* Kernel timing for measurement: after mbx_profile(k), every launch of
  * kernel class k (1 FP64 residual + linearisation, 2 matrix-free J*v,
  * 3 level-0 multigrid smoothing half-sweep, 4 whole preconditioner

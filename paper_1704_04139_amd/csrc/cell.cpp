@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -931,6 +932,10 @@ int mbx_batch_step(mbx_cell* const* cells, int n, double dt, int* status_out, mb
     for (int j = 0; j < i; ++j)
       if (cells[j] == cells[i]) return fail(MBX_EINVAL, "cell %d appears twice", i);
   }
+  // the batch-table cache is shared: batched steps from different threads
+  // (a server's worker and a caller) run one at a time
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
   Batch b;
   if (int e = make_batch(cells, n, b)) return e;
   return run_step(b, dt, status_out, infos);

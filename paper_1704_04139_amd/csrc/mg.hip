@@ -19,6 +19,8 @@
 // conductances) exactly representable on every level.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "mbx_dev.h"
 #include "mbx_kernels.h"
 #include "prof.h"
@@ -797,10 +799,27 @@ static void smoothl(const BatchLaunch& b, int l, int op, int color, int mode, in
 // One V-cycle on operator op: nu red-black sweeps (red then black) down to
 // the fused levels, then the fused coarse cycle, then nu sweeps (black then
 // red) back up.  The first post-sweep applies the coarse correction lazily.
+// Sweep counts: nu on the voxel level, nu_c on the launched coarse levels,
+// nu_f inside the fused coarse cycle (MBX_MG_NU0 / MBX_MG_NUC / MBX_MG_NUF
+// override the defaults 2 / 2 / 2).
+static int env_int(const char* name, int def, int lo, int hi) {
+  const char* v = std::getenv(name);
+  if (!v) return def;
+  const int x = std::atoi(v);
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+static int sweeps(int which) {
+  static const int n[3] = {env_int("MBX_MG_NU0", 2, 1, 8), env_int("MBX_MG_NUC", 2, 1, 8),
+                           env_int("MBX_MG_NUF", 2, 1, 8)};
+  return n[which];
+}
+
 template <typename KT>
-static void vcycle(const BatchLaunch& b, int op, int nu, int need, hipStream_t s) {
+static void vcycle(const BatchLaunch& b, int op, int nu_unused, int need, hipStream_t s) {
+  (void)nu_unused;
   const int top = b.maxfuse;   // levels >= a cell's lfuse run inside k_mg_coarse_cycle
   for (int l = 0; l < top; ++l) {
+    const int nu = sweeps(l == 0 ? 0 : 1);
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
         smooth0<KT>(b, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, need, s);
@@ -815,8 +834,9 @@ static void vcycle(const BatchLaunch& b, int op, int nu, int need, hipStream_t s
     else
       k_mgl_restrict<KT><<<b.lvl8_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl8_blk[l + 1], l, op, need);
   }
-  k_mg_coarse_cycle<KT><<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, op, nu, need);
+  k_mg_coarse_cycle<KT><<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, op, sweeps(2), need);
   for (int l = top - 1; l >= 0; --l) {
+    const int nu = sweeps(l == 0 ? 0 : 1);
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
         smooth0<KT>(b, op, 1, it == 0 ? SM_CORR : SM_PLAIN, need, s);

@@ -44,6 +44,26 @@ class StepInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", _i), ("steps_done", _i), ("V", _d), ("t_submit", _d), ("t_admit", _d),
+                ("t_done", _d), ("newton_iters", ctypes.c_int64), ("krylov_iters", ctypes.c_int64),
+                ("n_vox", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("steps_run", ctypes.c_int64), ("batches", ctypes.c_int64), ("busy_s", _d),
+                ("bytes_in_use", ctypes.c_int64), ("running", _i), ("queued", _i)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+MBX_REQ_DONE, MBX_REQ_QUEUED, MBX_REQ_RUNNING = 0, 1, 2
+
+
 class MbxError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
@@ -74,6 +94,14 @@ SIGNATURES = {
     "mbx_last_error": (ctypes.c_char_p, []),
     "mbx_profile": (_i, [_i]),
     "mbx_profile_read": (_i, [ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
+    "mbx_server_create": (_i, [ctypes.c_int64, _i, _d, _i, _vp, ctypes.POINTER(_vp)]),
+    "mbx_server_submit": (_i, [_vp, _vp, _i, _i, _i, ctypes.POINTER(Params), _i, ctypes.POINTER(ctypes.c_int64)]),
+    "mbx_server_poll": (_i, [_vp, ctypes.c_int64, ctypes.POINTER(RequestInfo)]),
+    "mbx_server_result": (_i, [_vp, ctypes.c_int64, _vp, _vp, _vp]),
+    "mbx_server_drain": (_i, [_vp, _d]),
+    "mbx_server_clock": (_d, [_vp]),
+    "mbx_server_stats": (_i, [_vp, ctypes.POINTER(ServerInfo)]),
+    "mbx_server_destroy": (None, [_vp]),
 }
 
 
@@ -275,3 +303,79 @@ def profile_read():
 def footprint(nx, ny, nz, precision="fp64", n_an_faces=0, n_ca_faces=0) -> int:
     return int(load().mbx_cell_footprint(nx, ny, nz, MBX_MIXED if precision == "mixed" else MBX_FP64,
                                          n_an_faces, n_ca_faces))
+
+
+class Server:
+    """Continuous-batching step server (worker thread in the library)."""
+
+    def __init__(self, budget_bytes: int, precision: str, dt: float, keep_state: bool = False, stream=None):
+        lib = load()
+        h = _vp()
+        prec = MBX_MIXED if precision == "mixed" else MBX_FP64
+        _check(lib.mbx_server_create(int(budget_bytes), prec, float(dt), int(keep_state),
+                                     _vp(stream) if stream else None, ctypes.byref(h)))
+        self._h = h
+        self.precision = precision
+        self._sizes = {}
+
+    def submit(self, labels: np.ndarray, params, n_steps: int, **knobs) -> int:
+        lab = np.ascontiguousarray(labels, dtype=np.uint8)
+        nz, ny, nx = lab.shape
+        p = params if isinstance(params, Params) else make_params(params, self.precision, **knobs)
+        rid = ctypes.c_int64()
+        _check(load().mbx_server_submit(self._h, _ptr(lab), nx, ny, nz, ctypes.byref(p), int(n_steps),
+                                        ctypes.byref(rid)))
+        self._sizes[rid.value] = lab
+        return rid.value
+
+    def poll(self, rid: int) -> dict:
+        info = RequestInfo()
+        _check(load().mbx_server_poll(self._h, int(rid), ctypes.byref(info)))
+        return info.as_dict()
+
+    def result(self, rid: int):
+        """Final (c, phi, n) of a finished request (keep_state servers)."""
+        lab = self._sizes[rid]
+        N = lab.size
+        n_an = int(_count_anode_faces(lab))
+        c, phi, n = np.empty(N), np.empty(N), np.empty(n_an)
+        _check(load().mbx_server_result(self._h, int(rid), _ptr(c), _ptr(phi), _ptr(n) if n_an else None))
+        return c, phi, n
+
+    def drain(self, timeout_s: float = 600.0):
+        _check(load().mbx_server_drain(self._h, float(timeout_s)))
+
+    def clock(self) -> float:
+        return load().mbx_server_clock(self._h)
+
+    def stats(self) -> dict:
+        info = ServerInfo()
+        _check(load().mbx_server_stats(self._h, ctypes.byref(info)))
+        return info.as_dict()
+
+    def close(self):
+        if self._h:
+            load().mbx_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _count_anode_faces(lab: np.ndarray) -> int:
+    """Anode/pore faces of a label image (layout (nz, ny, nx)): the length of
+    the plated-amount array."""
+    an = lab == 1
+    pore = lab == 0
+    n = 0
+    for ax in range(3):
+        a0 = [slice(None)] * 3
+        a1 = [slice(None)] * 3
+        a0[ax] = slice(0, -1)
+        a1[ax] = slice(1, None)
+        n += int(np.count_nonzero(an[tuple(a0)] & pore[tuple(a1)]))
+        n += int(np.count_nonzero(pore[tuple(a0)] & an[tuple(a1)]))
+    return n

@@ -1,0 +1,104 @@
+"""Continuous-batching server: results equal solo runs, admission honours the
+memory budget, request bookkeeping is consistent.
+
+Served parameter queries are the many-query use of the model (Sec. 1,
+Sec. 2.5).  Every request's final state must equal the same cell stepped
+alone to 1e-12 relative (per-cell deterministic reductions), whichever
+requests shared its batches.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1704_04139_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mbx(lib):
+    from paper_1704_04139_amd import mbx as m
+    return m
+
+
+def solo(mbx, w, precision, n_steps):
+    c = mbx.Cell(w.labels, w.params, precision=precision)
+    for _ in range(n_steps):
+        c.step(w.dt)
+    st = c.get_state()
+    V = c.voltage()
+    c.close()
+    return st, V
+
+
+def footprint(mbx, w, precision):
+    lab = np.ascontiguousarray(w.labels, dtype=np.uint8)
+    nz, ny, nx = lab.shape
+    fa = mbx._count_anode_faces(lab)
+    solid_ca = lab == 2
+    pore = lab == 0
+    fc = 0
+    for ax in range(3):
+        a0 = [slice(None)] * 3
+        a1 = [slice(None)] * 3
+        a0[ax] = slice(0, -1)
+        a1[ax] = slice(1, None)
+        fc += int(np.count_nonzero(solid_ca[tuple(a0)] & pore[tuple(a1)]))
+        fc += int(np.count_nonzero(pore[tuple(a0)] & solid_ca[tuple(a1)]))
+    return mbx.load().mbx_cell_footprint(nx, ny, nz, mbx.MBX_MIXED if precision == "mixed" else mbx.MBX_FP64,
+                                         fa, fc)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_equals_solo(mbx, precision):
+    ws = I.config4_requests(4, scale=4)
+    steps = [3, 2, 4, 3]
+    say("serve", precision, [w.labels.shape for w in ws])
+    srv = mbx.Server(budget_bytes=64 << 30, precision=precision, dt=ws[0].dt, keep_state=True)
+    ids = []
+    for k, (w, n) in enumerate(zip(ws, steps)):
+        ids.append(srv.submit(w.labels, w.params, n))
+    srv.drain(300.0)
+    infos = [srv.poll(i) for i in ids]
+    results = [srv.result(i) for i in ids]
+    stats = srv.stats()
+    srv.close()
+    say("stats", stats)
+    assert stats["steps_run"] == sum(steps)
+    assert stats["running"] == 0 and stats["queued"] == 0 and stats["bytes_in_use"] == 0
+    for w, n, info, res in zip(ws, steps, infos, results):
+        assert info["status"] == mbx.MBX_REQ_DONE
+        assert info["steps_done"] == n
+        assert 0.0 <= info["t_submit"] <= info["t_admit"] <= info["t_done"]
+        ref, V = solo(mbx, w, precision, n)
+        assert abs(info["V"] - V) <= 1e-12 * abs(V)
+        for x, y in zip(res, ref):
+            np.testing.assert_allclose(x, y, rtol=1e-12, atol=0)
+
+
+def test_budget_admission(mbx):
+    """With room for one request at a time, requests run strictly one after
+    another in submission order; a request larger than the budget is refused."""
+    w0 = I.config4_requests(1, scale=4)[0]
+    ws = [w0, w0, w0]
+    fp = footprint(mbx, w0, "mixed")
+    say("footprint", fp)
+    budget = 2 * fp - 1          # one fits, two do not
+    srv = mbx.Server(budget_bytes=budget, precision="mixed", dt=ws[0].dt)
+    ids = [srv.submit(w.labels, w.params, 2) for w in ws]
+    srv.drain(300.0)
+    infos = [srv.poll(i) for i in ids]
+    big = I.config4_requests(1, base_seed=2101, scale=1)[0]
+    with pytest.raises(mbx.MbxError) as e:
+        srv.submit(big.labels, big.params, 1)
+    assert e.value.code == mbx.MBX_EBUDGET
+    srv.close()
+    for a, b in zip(infos, infos[1:]):
+        assert b["t_admit"] >= a["t_done"]
+    assert all(i["status"] == mbx.MBX_REQ_DONE and i["steps_done"] == 2 for i in infos)
