@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the full-order implicit cell step on one MI355X.
 
-A step is one implicit Euler step (eq. 2.13) of the 64 x 64 x 160 full cell
-(anode 64 / separator 32 / cathode 64 layers, overlapping-sphere electrodes
-with radius 3-6 voxels and porosity drawn in [0.30, 0.40], 2C charge, dt = 5 s,
-plating on): FP64 residual, Newton, multigrid-preconditioned GMRES, line
-search, outputs.  The metric is DOF x steps / s with DOF = 2 x voxels.
-Inputs are resident in HBM before the timed region; timing brackets exactly
---steps steps with a device synchronisation on both sides.
+Default mode (one JSON line): a step is one implicit Euler step (eq. 2.13)
+of the 64 x 64 x 160 full cell (anode 64 / separator 32 / cathode 64
+layers, overlapping-sphere electrodes with radius 3-6 voxels and porosity
+drawn in [0.30, 0.40], 2C charge, dt = 5 s, plating on): FP64 residual,
+Newton, multigrid-preconditioned GMRES, step limiter, outputs.  The metric is
+DOF x steps / s with DOF = 2 x voxels.  Inputs are resident in HBM before
+the timed region; timing brackets exactly --steps steps with a device
+synchronisation on both sides.  Extra objects: `fp64` (the plain FP64 path
+on the same workload), `batched` (32 cells of 32x32x80 .. 96x96x240 with
+sampled C-rate, temperature and plating rate, stepped together),
+`roofline` (the dominant kernel's algorithmic bytes per launch over its
+event-timed average launch duration), `cpu_baseline` (the CPU oracle on a
+bounded down-scaled sample of the same workload).
 
-Prints one JSON line.  Extra objects: `fp64` (the plain FP64 path on the same
-workload), `roofline` (the dominant kernel's algorithmic bytes per launch over
-its event-timed average launch duration), `cpu_baseline` (the CPU oracle on
-a bounded down-scaled sample of the same workload).
+--mode serve (one JSON line): parameter queries of 48x48x120 .. 128x128x320
+cells, 12 steps of 5 s each, arriving as a Poisson stream at a continuous-
+batching server; reports completed requests/s and p50/p99 latency from
+arrival to result, mixed and FP64.
 """
 import argparse
 import json
@@ -20,6 +26,8 @@ import os
 import subprocess
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -101,6 +109,79 @@ def cpu_baseline():
             "host_cpu": cpu, "host_nproc": os.cpu_count()}
 
 
+def run_batched(n_cells, steps, precision, stream):
+    """32-cell batch (sampled queries), all cells advanced by shared launches."""
+    import torch
+    from paper_1704_04139_amd import inputs as I
+    from paper_1704_04139_amd import mbx
+    ws = I.config3(n_cells=n_cells)
+    cells = [mbx.Cell(w.labels, w.params, precision=precision, stream=stream) for w in ws]
+    dof = sum(2 * c.counts.n_vox for c in cells)
+    print(f"[bench] batched: {n_cells} cells created, {dof} DOF", file=sys.stderr, flush=True)
+    st, _ = mbx.batch_step(cells, ws[0].dt)          # warm-up step (also builds the batch tables)
+    torch.cuda.synchronize()
+    print("[bench] batched: warm-up step done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    kry = newt = 0
+    for k in range(steps):
+        st, infos = mbx.batch_step(cells, ws[0].dt)
+        kry += sum(i["krylov_iters"] for i in infos)
+        newt += sum(i["newton_iters"] for i in infos)
+        print(f"[bench] batched: step {k + 1}/{steps} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for c in cells:
+        c.close()
+    return {"value": dof * steps / wall, "unit": "DOF*steps/s", "cells": n_cells, "dof": dof, "steps": steps,
+            "ms_per_step": 1e3 * wall / steps, "failed": int(sum(1 for x in st if x != 0)),
+            "newton_per_cell_step": newt / (steps * n_cells), "krylov_per_cell_step": kry / (steps * n_cells),
+            "precision": precision}
+
+
+def run_serving(precision, rate_offered, n_req, n_cap, stream, budget_gb):
+    """Poisson arrivals at a continuous-batching server; capacity first, then
+    a run at 70% utilisation if the offered rate exceeds the capacity."""
+    from paper_1704_04139_amd import inputs as I
+    from paper_1704_04139_amd import mbx
+    steps = 12
+    reqs = I.config4_requests(n_req + n_cap)
+    dofsteps = [2 * w.labels.size * steps for w in reqs]
+    # capacity: a closed burst of n_cap requests
+    srv = mbx.Server(int(budget_gb * 2**30), precision, dt=5.0, stream=stream)
+    t0 = srv.clock()
+    ids = [srv.submit(w.labels, w.params, steps) for w in reqs[:n_cap]]
+    srv.drain(1200.0)
+    t1 = max(srv.poll(i)["t_done"] for i in ids)
+    srv.close()
+    cap = sum(dofsteps[:n_cap]) / (t1 - t0)
+    mean_req = float(np.mean(dofsteps[n_cap:]))
+    rho_offered = rate_offered * mean_req / cap
+    rate = rate_offered if rho_offered < 1.0 else 0.7 * cap / mean_req
+    arrivals = I.poisson_arrivals(rate, n_req)
+    srv = mbx.Server(int(budget_gb * 2**30), precision, dt=5.0, stream=stream)
+    base = srv.clock()
+    ids = []
+    for a, w in zip(arrivals, reqs[n_cap:]):
+        while srv.clock() - base < a:
+            time.sleep(min(0.005, max(0.0, a - (srv.clock() - base))))
+        ids.append(srv.submit(w.labels, w.params, steps))
+        print(f"[serve] {precision} request {len(ids)}/{n_req} at {srv.clock() - base:.2f} s", file=sys.stderr,
+              flush=True)
+    srv.drain(3600.0)
+    infos = [srv.poll(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+    span = max(i["t_done"] for i in infos) - base
+    ok = [i for i in infos if i["status"] == mbx.MBX_REQ_DONE]
+    return {"precision": precision, "capacity_dofsteps_per_s": cap, "offered_rate_hz": rate_offered,
+            "rho_offered": rho_offered, "rate_hz": rate, "rho": rate * mean_req / cap, "requests": n_req,
+            "completed": len(ok), "completed_per_s": len(ok) / span, "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()), "max_s": float(lat.max()),
+            "busy_frac": st["busy_s"] / span, "batches": st["batches"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +189,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["mixed", "fp64", "both"], default="both")
+    ap.add_argument("--mode", choices=["step", "serve"], default="step")
+    ap.add_argument("--batch-cells", type=int, default=32)
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed batched steps (0: skip the batched run)")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="offered arrival rate, requests/s")
+    ap.add_argument("--budget-gb", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); independent cells shard across GPUs "
@@ -119,6 +206,18 @@ def main():
     mbx.load()
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
+    if args.mode == "serve":
+        out = {"metric": "served requests/s", "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+               "data": "synthetic", "config": {"workload": "parameter queries 48x48x120 .. 128x128x320, 12 x 5 s, "
+                                                           "Poisson arrivals, continuous batching"}}
+        for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
+            out[prec] = run_serving(prec, args.serve_rate, args.serve_requests, 6, stream, args.budget_gb)
+            print(f"[bench] serve {prec}: {json.dumps(out[prec])}", file=sys.stderr, flush=True)
+        main_prec = "mixed" if "mixed" in out else "fp64"
+        out["value"] = out[main_prec]["completed_per_s"]
+        out["p50_s"], out["p99_s"] = out[main_prec]["p50_s"], out[main_prec]["p99_s"]
+        print(json.dumps(out), flush=True)
+        return
     w = I.config1()
     print(f"[bench] workload {w.name}, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
     res = {}
@@ -158,6 +257,9 @@ def main():
         f = res["fp64"]
         line["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "newton_per_step": f["newton_per_step"],
                         "krylov_per_step": f["krylov_per_step"]}
+    if args.batch_steps > 0:
+        print(f"[bench] batched: {args.batch_cells} cells, {args.batch_steps} timed steps", file=sys.stderr, flush=True)
+        line["batched"] = run_batched(args.batch_cells, args.batch_steps, main_prec, stream)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, 1 thread)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()

@@ -44,7 +44,15 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(MBX_EHIP, "%s: %s", #expr, hipGetErrorString(e_));   \
   } while (0)
 
-constexpr int kRestart = 30;
+constexpr int kRestart = 40;          // GMRES restart length (MBX_GMRES_M overrides, at most kMaxRestart)
+int restart_len() {
+  static int m = -1;
+  if (m < 0) {
+    const char* v = std::getenv("MBX_GMRES_M");
+    m = v ? std::max(4, std::min(kMaxRestart, std::atoi(v))) : kRestart;
+  }
+  return m;
+}
 constexpr double kStepLimit = 4.0;   // largest scaled Newton update taken in one iteration
 
 bool g_verbose() {
@@ -146,9 +154,10 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   L.add(5 * kt * std::max(F_an, 1));          // 17 coef_an
   L.add(3 * kt * std::max(F_ca, 1));          // 18 coef_ca
   L.add(kt * (size_t)N);                      // 19 wpore
-  L.add(4 * kt * (size_t)N);                  // 20 dinv
+  L.add(0);                                   // 20 (unused)
   L.add((size_t)(m + 1) * 2 * N * kt);        // 21 Vb
-  for (int k = 0; k < 4; ++k) L.add(2 * (size_t)N * kt);  // 22..25 w z b x
+  for (int k = 0; k < 3; ++k) L.add(2 * (size_t)N * kt);  // 22..24 w z b
+  L.add(2 * (size_t)N * 8);                   // 25 x (FP64)
   L.add((size_t)nblk * kPartStride * 8);      // 26 part
   L.add(64);                                  // 27 ticket
   L.add(8 * RED_NSLOT);                       // 28 red
@@ -299,7 +308,42 @@ struct Batch {
   int upload() {
     for (size_t c = 0; c < cells.size(); ++c) h_desc[c] = cells[c]->h;
     HIPCHK(hipMemcpyAsync(d_desc, h_desc, sizeof(CellDev) * cells.size(), hipMemcpyHostToDevice, s));
+    std::vector<char> on(cells.size());
+    for (size_t c = 0; c < cells.size(); ++c) on[c] = cells[c]->h.active != 0;
+    if (int e = set_active(on)) return e;
     // the pinned staging buffer is rewritten by the next upload
+    HIPCHK(hipStreamSynchronize(s));
+    return MBX_OK;
+  }
+  // Host copies of the full block tables of a multi-cell batch.  Launches
+  // cover only the cells marked on: the device tables are rewritten with the
+  // blocks of those cells whenever the set changes, so cells that have
+  // finished cost no dispatched workgroups.  (An empty set keeps the tables.)
+  std::vector<int2> full_blk, full_lvl[3][kMaxLevels], cur_tab[1 + 3 * kMaxLevels];
+  std::vector<char> cur_on;
+  int set_active(const std::vector<char>& on) {
+    if (cells.size() < 2 || on == cur_on) return MBX_OK;
+    bool any = false;
+    for (char o : on) any = any || o;
+    if (!any) return MBX_OK;
+    cur_on = on;
+    auto filt = [&](const std::vector<int2>& full, std::vector<int2>& out, int2* dev, int& count) -> int {
+      out.clear();
+      for (const int2& e : full)
+        if (on[e.x]) out.push_back(e);
+      count = (int)out.size();
+      if (count) HIPCHK(hipMemcpyAsync(dev, out.data(), sizeof(int2) * out.size(), hipMemcpyHostToDevice, s));
+      return MBX_OK;
+    };
+    int e = filt(full_blk, cur_tab[0], d_blk, nblk);
+    for (int l = 0; l < maxlev && e == MBX_OK; ++l) {
+      if (lvl_blk[l]) e = filt(full_lvl[0][l], cur_tab[1 + l], lvl_blk[l], lvl_nblk[l]);
+      if (lvl8_blk[l] && e == MBX_OK) e = filt(full_lvl[1][l], cur_tab[1 + kMaxLevels + l], lvl8_blk[l], lvl8_nblk[l]);
+      if (lvlh_blk[l] && e == MBX_OK)
+        e = filt(full_lvl[2][l], cur_tab[1 + 2 * kMaxLevels + l], lvlh_blk[l], lvlh_nblk[l]);
+    }
+    if (e != MBX_OK) return e;
+    // the host vectors are the copy sources
     HIPCHK(hipStreamSynchronize(s));
     return MBX_OK;
   }
@@ -358,11 +402,13 @@ struct BatchCache {
   Batch b;
 } g_batch_cache;
 
-int make_batch(mbx_cell* const* cells, int n, Batch& out) {
+// The batch lives in the cache (its device block tables carry state: the
+// active-cell compaction), so callers work on the cached object itself.
+int make_batch(mbx_cell* const* cells, int n, Batch*& out) {
   std::vector<uint64_t> ids(n);
   for (int i = 0; i < n; ++i) ids[i] = cells[i]->id;
   if (g_batch_cache.b.owned && g_batch_cache.ids == ids) {
-    out = g_batch_cache.b;
+    out = &g_batch_cache.b;
     return MBX_OK;
   }
   g_batch_cache.b.release();
@@ -391,6 +437,7 @@ int make_batch(mbx_cell* const* cells, int n, Batch& out) {
         }
       int2*& dst = pass == 0 ? b.lvl_blk[l] : pass == 1 ? b.lvl8_blk[l] : b.lvlh_blk[l];
       (pass == 0 ? b.lvl_nblk[l] : pass == 1 ? b.lvl8_nblk[l] : b.lvlh_nblk[l]) = (int)lt.size();
+      b.full_lvl[pass][l] = lt;
       HIPCHK(hipMalloc(&dst, sizeof(int2) * std::max<size_t>(lt.size(), 1)));
       HIPCHK(hipMemcpyAsync(dst, lt.data(), sizeof(int2) * lt.size(), hipMemcpyHostToDevice, b.s));
     }
@@ -402,57 +449,70 @@ int make_batch(mbx_cell* const* cells, int n, Batch& out) {
   HIPCHK(hipHostMalloc(&b.h_gather, sizeof(double) * kGather * n, hipHostMallocDefault));
   HIPCHK(hipMemcpyAsync(b.d_blk, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice, b.s));
   HIPCHK(hipStreamSynchronize(b.s));
+  b.full_blk = tab;
+  b.cur_on.assign(n, 1);
   b.owned = true;
   g_batch_cache.ids = ids;
   g_batch_cache.b = b;
-  out = b;
+  out = &g_batch_cache.b;
   return MBX_OK;
 }
 
 // ------------------------------------------------------------------ GMRES
 template <typename KT>
 int gmres(Batch& B, int max_iters, int* iters_out) {
-  const BatchLaunch bl = B.bl();
   const int m = B.m;
   const int check = 4;
   int total = 0;
-  launch_gm_start<KT>(bl, 1, B.s);
-  launch_gm_flags(bl, 1, B.s);
+  launch_gm_start<KT>(B.bl(), 1, B.s);
+  launch_gm_flags(B.bl(), 1, B.s);
   while (total < max_iters) {
     int k = 0;
     for (; k < m; ++k) {
-      launch_precond<KT>(bl, k, B.nu, 0, B.s);
-      launch_matvec<KT>(bl, VEC_Z, VEC_W, 0, B.s);
+      launch_precond<KT>(B.bl(), k, B.nu, 0, B.s);
+      launch_matvec<KT>(B.bl(), VEC_Z, VEC_W, 0, B.s);
       // classical Gram-Schmidt with one re-orthogonalisation (CGS2)
-      launch_multidot<KT>(bl, k, 0, B.s);   // H(:,k) = V^T w
-      launch_orth_dots<KT>(bl, k, B.s);     // w -= V H(:,k); tmp = V^T w
-      launch_orth<KT>(bl, k, 1, B.s);       // w -= V tmp; H(:,k) += tmp; H(k+1,k) = |w|
-      launch_scale_next<KT>(bl, k, B.s);
-      launch_givens(bl, k, B.s);
+      launch_multidot<KT>(B.bl(), k, 0, B.s);   // H(:,k) = V^T w
+      launch_orth_dots<KT>(B.bl(), k, B.s);     // w -= V H(:,k); tmp = V^T w
+      launch_orth<KT>(B.bl(), k, 1, B.s);       // w -= V tmp; H(:,k) += tmp; H(k+1,k) = |w|
+      launch_scale_next<KT>(B.bl(), k, B.s);
+      launch_givens(B.bl(), k, B.s);
       if ((k + 1) % check == 0 || k + 1 == m) {
         if (int e = B.gather()) return e;
         bool running = false;
-        for (size_t c = 0; c < B.cells.size(); ++c)
-          if (B.cells[c]->h.active && B.ctl(c, CTL_DONE) == 0) running = true;
+        std::vector<char> on(B.cells.size());
+        for (size_t c = 0; c < B.cells.size(); ++c) {
+          on[c] = B.cells[c]->h.active && B.ctl(c, CTL_DONE) == 0;
+          running = running || on[c];
+        }
         if (!running) {
           ++k;
           break;
         }
+        if (int e = B.set_active(on)) return e;   // launch only the cells still iterating
       }
     }
     total += k;
-    launch_backsolve(bl, B.s);
-    launch_combine<KT>(bl, B.s);
-    launch_precond<KT>(bl, VEC_W, B.nu, -1, B.s);
-    launch_add_z_to_x<KT>(bl, B.s);
-    launch_matvec<KT>(bl, VEC_X, VEC_W, 2, B.s);
-    launch_true_residual<KT>(bl, B.s);
-    launch_gm_start<KT>(bl, 0, B.s);
-    launch_gm_flags(bl, 0, B.s);
+    {
+      std::vector<char> on(B.cells.size());
+      for (size_t c = 0; c < B.cells.size(); ++c) on[c] = B.cells[c]->h.active != 0;
+      if (int e = B.set_active(on)) return e;   // cycle end: every active cell
+    }
+    launch_backsolve(B.bl(), B.s);
+    launch_combine<KT>(B.bl(), B.s);
+    launch_precond<KT>(B.bl(), VEC_W, B.nu, -1, B.s);
+    launch_add_z_to_x<KT>(B.bl(), B.s);
+    launch_true_residual<KT>(B.bl(), B.s);   // w = b - J x for the cells that restart
+    launch_gm_start<KT>(B.bl(), 0, B.s);
+    launch_gm_flags(B.bl(), 0, B.s);
     if (int e = B.gather()) return e;
     bool all = true;
-    for (size_t c = 0; c < B.cells.size(); ++c)
+    for (size_t c = 0; c < B.cells.size(); ++c) {
       if (B.cells[c]->h.active && B.ctl(c, CTL_DONE) != 3) all = false;
+      if (g_verbose() && B.cells[c]->h.active)
+        fprintf(stderr, "[mbx] cell %zu gmres cycle end: iters %d state %d |r| %.3e tol %.3e beta0 %.3e\n", c,
+                total, B.ctl(c, CTL_DONE), std::sqrt(B.red(c, RED_BSQ)), B.red(c, RED_TOL), B.red(c, RED_BETA0));
+    }
     if (all) break;
   }
   if (iters_out) *iters_out = total;
@@ -460,13 +520,19 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
 }
 
 // ------------------------------------------------------------------ Newton
+constexpr double kEtaMax = 0.1;        // loosest GMRES relative tolerance of a Newton correction (FP64)
+constexpr double kEtaMaxMixed = 1e-4;  // ... in the mixed mode
+constexpr double kEwGamma = 0.9;
 template <typename KT>
 int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
   const int nc = (int)B.cells.size();
-  const BatchLaunch bl = B.bl();
   auto t0 = std::chrono::steady_clock::now();
   std::vector<int> st(nc, 1);   // 1 running, 0 converged, < 0 failed
-  std::vector<double> rn(nc), rmax(nc), res0(nc), eta(nc, 1e-4), du(nc, 0.0), lam(nc, 1.0), mr(nc), dnm(nc, 0.0);
+  // the mixed mode accepts limited steps without a residual test, so its
+  // corrections are solved tighter
+  const double eta_max = B.mixed ? kEtaMaxMixed : kEtaMax;
+  std::vector<double> rn(nc), rmax(nc), res0(nc), eta(nc, eta_max), du(nc, 0.0), lam(nc, 1.0), mr(nc), dnm(nc, 0.0),
+      qconv(nc, 1.0);
   // FP32 Krylov cannot resolve relative residuals much below 1e-6
   const double eta_floor = B.cells[0]->p.krylov_rtol;
   std::vector<int> nit(nc, 0), kit(nc, 0);
@@ -479,9 +545,9 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
     cl->h.m = B.m;
   }
   if (int e = B.upload()) return e;
-  launch_copy_state(bl, 2, B.s);   // u^n <- state
-  launch_copy_state(bl, 1, B.s);   // trial <- state
-  launch_residual<KT>(bl, true, B.s);
+  launch_copy_state(B.bl(), 2, B.s);   // u^n <- state
+  launch_copy_state(B.bl(), 1, B.s);   // trial <- state
+  launch_residual<KT>(B.bl(), true, B.s);
   if (int e = B.gather()) return e;
   for (int c = 0; c < nc; ++c) {
     rn[c] = std::sqrt(B.red(c, RED_RSQ));
@@ -501,14 +567,14 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
     }
     if (!any) break;
     if (int e = B.upload()) return e;
-    launch_mg_setup<KT>(bl, B.s);
-    launch_rhs<KT>(bl, B.s);
+    launch_mg_setup<KT>(B.bl(), B.s);
+    launch_rhs<KT>(B.bl(), B.s);
     int kits = 0;
     if (int e = gmres<KT>(B, B.cells[0]->p.krylov_max, &kits)) return e;
     if (int e = B.gather()) return e;
     for (int c = 0; c < nc; ++c)
       if (st[c] == 1) kit[c] += B.ctl(c, CTL_ITERS);
-    launch_direction<KT>(bl, B.s);
+    launch_direction<KT>(B.bl(), B.s);
     if (int e = B.gather()) return e;
     // step-length limiter: no scaled update larger than kStepLimit (potentials
     // in RT/F, concentrations relative to c0 / c_max), then halving until the
@@ -534,7 +600,7 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
       }
       if (!anys) break;
       if (int e = B.upload()) return e;
-      launch_trial(bl, B.s);
+      launch_trial(B.bl(), B.s);
       if (int e = B.gather()) return e;
       std::vector<double> dmax(nc, 0.0);
       for (int c = 0; c < nc; ++c) {
@@ -546,7 +612,7 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
         }
       }
       if (int e = B.upload()) return e;
-      launch_residual<KT>(bl, true, B.s);
+      launch_residual<KT>(B.bl(), true, B.s);
       if (int e = B.gather()) return e;
       for (int c = 0; c < nc; ++c) {
         if (!searching[c] || !B.cells[c]->h.active) continue;
@@ -571,8 +637,14 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
           mr[c] = m1;
           rmax[c] = B.red(c, RED_RMAX);
           const double ratio = rprev > 0.0 ? r1 / rprev : 0.0;
+          qconv[c] = ratio;
           (void)mprev;
-          eta[c] = std::max(eta_floor, std::min(1e-4, 0.5 * ratio * ratio));
+          // forcing term (Eisenstat-Walker, choice 2, gamma 0.9, alpha 2):
+          // loose while Newton is far from the root, tight once it converges
+          double e = kEwGamma * ratio * ratio;
+          const double prev = kEwGamma * eta[c] * eta[c];
+          if (prev > 0.1) e = std::max(e, prev);
+          eta[c] = std::max(eta_floor, std::min(eta_max, e));
         } else {
           lam[c] *= 0.5;
         }
@@ -589,14 +661,19 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
       nit[c] = it;
     }
     if (int e = B.upload()) return e;
-    launch_copy_state(bl, 0, B.s);   // accept: state <- trial
+    launch_copy_state(B.bl(), 0, B.s);   // accept: state <- trial
     for (int c = 0; c < nc; ++c) {
       if (st[c] != 1) continue;
       const mbx_params& p = B.cells[c]->p;
       if (g_verbose())
         fprintf(stderr, "[mbx] cell %d newton %d: lam %.3g |r|2 %.3e |r|inf %.3e merit %.3e du %.3e dn %.3e eta %.1e gmres %d (beta0 %.3e)\n",
                 c, it, lam[c], rn[c], rmax[c], mr[c], du[c], dnm[c], eta[c], B.ctl(c, CTL_ITERS), B.red(c, RED_BETA0));
-      if (lam[c] == 1.0 && du[c] <= p.newton_tol && dnm[c] <= p.newton_tol && rmax[c] <= p.res_tol) st[c] = 0;
+      // error left after this update: the update itself, or (contraction
+      // q = residual ratio of this iteration) the estimate |du| q / (1 - q)
+      const double dmx = std::max(du[c], dnm[c]);
+      const double q = qconv[c];
+      const double err = (q < 0.5) ? dmx * q / (1.0 - q) : dmx;
+      if (lam[c] == 1.0 && rmax[c] <= p.res_tol && (dmx <= p.newton_tol || err <= p.newton_tol)) st[c] = 0;
     }
   }
   // roll back failures, outputs for the converged cells
@@ -605,10 +682,10 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
     B.cells[c]->h.active = st[c] < 0;
   }
   if (int e = B.upload()) return e;
-  launch_copy_state(bl, 3, B.s);
+  launch_copy_state(B.bl(), 3, B.s);
   for (int c = 0; c < nc; ++c) B.cells[c]->h.active = 1;
   if (int e = B.upload()) return e;
-  launch_outputs(bl, B.s);
+  launch_outputs(B.bl(), B.s);
   if (int e = B.gather()) return e;
   const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int c = 0; c < nc; ++c) {
@@ -662,7 +739,8 @@ int64_t mbx_cell_footprint(int nx, int ny, int nz, int precision, int n_an_faces
   const int64_t N = (int64_t)nx * ny * nz;
   if (N <= 0 || N > (1 << 28)) return -1;
   const int nblk = (int)((N + kBlock - 1) / kBlock);
-  Layout L = make_layout((int)N, n_an_faces, n_ca_faces, nblk, kRestart, kt_size(precision), level_dims(nx, ny, nz));
+  Layout L = make_layout((int)N, n_an_faces, n_ca_faces, nblk, restart_len(), kt_size(precision),
+                         level_dims(nx, ny, nz));
   return (int64_t)L.total;
 }
 
@@ -749,7 +827,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   c->F_ca = F_ca;
   c->n_top = hflags[2];
   c->nblk = (N + kBlock - 1) / kBlock;
-  c->m = kRestart;
+  c->m = restart_len();
   c->mixed = p.precision == MBX_MIXED;
   c->s = s;
   const size_t kt = kt_size(p.precision);
@@ -795,12 +873,11 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.coef_an = b + L.off[17];
   h.coef_ca = b + L.off[18];
   h.wpore = b + L.off[19];
-  h.dinv = b + L.off[20];
   h.Vb = b + L.off[21];
   h.w = b + L.off[22];
   h.z = b + L.off[23];
   h.b = b + L.off[24];
-  h.x = b + L.off[25];
+  h.x = (double*)(b + L.off[25]);
   h.part = (double*)(b + L.off[26]);
   h.ticket = (unsigned*)(b + L.off[27]);
   h.red = (double*)(b + L.off[28]);
@@ -936,9 +1013,9 @@ int mbx_batch_step(mbx_cell* const* cells, int n, double dt, int* status_out, mb
   // (a server's worker and a caller) run one at a time
   static std::mutex mu;
   std::lock_guard<std::mutex> lk(mu);
-  Batch b;
+  Batch* b = nullptr;
   if (int e = make_batch(cells, n, b)) return e;
-  return run_step(b, dt, status_out, infos);
+  return run_step(*b, dt, status_out, infos);
 }
 
 int mbx_cell_set_current(mbx_cell* c, double I_app) {

@@ -8,24 +8,13 @@
 
 #include "mbx_dev.h"
 #include "mbx_kernels.h"
+#include "jv.h"
 #include "reduce.h"
 #include "prof.h"
 
 #include <hipcub/hipcub.hpp>
 
 namespace mbx {
-
-struct VoxCoord {
-  int x, y, z;
-};
-__device__ inline VoxCoord coord_of(const CellDev& cd, int i) {
-  VoxCoord v;
-  v.x = i % cd.nx;
-  const int t = i / cd.nx;
-  v.y = t % cd.ny;
-  v.z = t / cd.ny;
-  return v;
-}
 
 template <typename KT>
 __device__ inline KT* vec(const CellDev& cd, int sel) {
@@ -34,7 +23,6 @@ __device__ inline KT* vec(const CellDev& cd, int sel) {
     case VEC_Z: return (KT*)cd.z;
     case VEC_W: return (KT*)cd.w;
     case VEC_B: return (KT*)cd.b;
-    case VEC_X: return (KT*)cd.x;
     default: return (KT*)cd.Vb + (size_t)sel * n2;
   }
 }
@@ -300,13 +288,13 @@ __global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __re
     const size_t N = cd.N;
     KT* b = (KT*)cd.b;
     KT* w = (KT*)cd.w;
-    KT* x = (KT*)cd.x;
+    double* x = cd.x;
     b[i] = (KT)bc;
     b[N + i] = (KT)bp;
     w[i] = (KT)bc;
     w[N + i] = (KT)bp;
-    x[i] = (KT)0;
-    x[N + i] = (KT)0;
+    x[i] = 0.0;
+    x[N + i] = 0.0;
     const double bcr = (double)(KT)bc, bpr = (double)(KT)bp;
     ss = bcr * bcr + bpr * bpr;
   }
@@ -314,109 +302,21 @@ __global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __re
   reduce_block<1>(cd, bb.y, vals, 0u);
 }
 
-// ---------------------------------------------------------- preconditioner
-// Block Jacobi: z = D^-1 v with the inverse 2x2 (c, phi) voxel blocks.
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_jacobi(CellDev* cells, const int2* __restrict__ blk, int src, int dst,
-                                                   int need) {
-  const int2 bb = block_of(blk);
-  const CellDev& cd = cells[bb.x];
-  if (!cd.active || cd.ictl[CTL_DONE] != need) return;
-  const int i = bb.y * kBlock + threadIdx.x;
-  if (i >= cd.N) return;
-  const size_t N = cd.N;
-  const KT* v = vec<KT>(cd, src);
-  KT* z = vec<KT>(cd, dst);
-  const KT* di = (const KT*)cd.dinv + 4 * (size_t)i;
-  const KT vc = v[i], vp = v[N + i];
-  z[i] = di[0] * vc + di[1] * vp;
-  z[N + i] = di[2] * vc + di[3] * vp;
-}
-
 // ----------------------------------------------------------------- J * v
-// Matrix-free product with the scaled, condensed Jacobian of the residual:
-// same stencil as k_residual, linear in v, coefficients from the last
-// linearisation.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* __restrict__ blk, int src, int dst,
                                                    int need) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!cd.active || cd.ictl[CTL_DONE] != need) return;
+  if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
-  const size_t N = cd.N;
-  const KT* v = vec<KT>(cd, src);
+  KT yc, yp;
+  jv_row<KT, KT, KT>(cd, i, vec<KT>(cd, src), yc, yp);
+  if (cd.ictl[CTL_DONE] != need) return;
   KT* y = vec<KT>(cd, dst);
-  const KT* wpo = (const KT*)cd.wpore;
-  const KT* can = (const KT*)cd.coef_an;
-  const KT* cca = (const KT*)cd.coef_ca;
-  const VoxCoord c3 = coord_of(cd, i);
-  const uint32_t mi = cd.meta[i];
-  const int L = lab_of(mi);
-  const KT vc = v[i], vp = v[N + i];
-  const KT wi = (L == PORE) ? wpo[i] : (KT)0;
-  const KT Gk = (KT)cd.Gk, tth = (KT)cd.tth, Dh = (KT)cd.Dh, tau = (KT)cd.tau, Ke = (KT)cd.Ke;
-  KT yc = vc, yp = (KT)0;
-  for (int d = 0; d < 6; ++d) {
-    const int k = neighbour(cd, i, c3.x, c3.y, c3.z, d);
-    if (k < 0) {
-      if (d == 4 && L == ANODE) yp += (KT)cd.Gcol * vp;
-      continue;
-    }
-    const uint32_t mk = cd.meta[k];
-    const int Lk = lab_of(mk);
-    const KT vck = v[k], vpk = v[N + k];
-    const bool lo = i < k;
-    if (L == PORE && Lk == PORE) {
-      const KT wk = wpo[k];
-      const KT vca = lo ? vc : vck, vcb = lo ? vck : vc;
-      const KT vpa = lo ? vp : vpk, vpb = lo ? vpk : vp;
-      const KT wa = lo ? wi : wk, wb = lo ? wk : wi;
-      const KT dj = Gk * (-(vpb - vpa) + tth * (wb * vcb - wa * vca));
-      const KT dN = -Dh * (vcb - vca) + tau * dj;
-      if (lo) {
-        yc += dN;
-        yp += dj;
-      } else {
-        yc -= dN;
-        yp -= dj;
-      }
-    } else if (L == Lk) {
-      const int s = L - 1;
-      // -D (v_k - v_i) seen from voxel i, in either orientation
-      yc += (KT)cd.Dsh[s] * (vc - vck);
-      yp += (KT)cd.Gs[s] * (vp - vpk);
-    } else if (L == PORE) {
-      const uint32_t f = face_rank(mk, d ^ 1);
-      KT q, qp = (KT)0;
-      if (Lk == ANODE) {
-        const KT* co = can + 5 * (size_t)f;
-        q = co[0] * vck + co[1] * vc + co[2] * (vpk - vp);
-        qp = co[3] * vc + co[4] * (vpk - vp);
-      } else {
-        const KT* co = cca + 3 * (size_t)f;
-        q = co[0] * vck + co[1] * vc + co[2] * (vpk - vp);
-      }
-      yc -= Ke * (q + qp);
-      yp -= q + qp;
-    } else {
-      const uint32_t f = face_rank(mi, d);
-      KT q, qp = (KT)0;
-      if (L == ANODE) {
-        const KT* co = can + 5 * (size_t)f;
-        q = co[0] * vc + co[1] * vck + co[2] * (vp - vpk);
-        qp = co[3] * vck + co[4] * (vp - vpk);
-      } else {
-        const KT* co = cca + 3 * (size_t)f;
-        q = co[0] * vc + co[1] * vck + co[2] * (vp - vpk);
-      }
-      yc += (KT)cd.Ks[L - 1] * q;
-      yp += q + qp;
-    }
-  }
   y[i] = yc;
-  y[N + i] = yp;
+  y[(size_t)cd.N + i] = yp;
 }
 
 // ------------------------------------------------------------------- GMRES
@@ -679,26 +579,6 @@ __global__ void __launch_bounds__(kBlock) k_combine(CellDev* cells, const int2* 
   w[N + i] = ap;
 }
 
-// Cycle end: z = M^-1 w (block Jacobi) and x += z, fused.
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_update_x_jacobi(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = block_of(blk);
-  const CellDev& cd = cells[bb.x];
-  if (!cd.active) return;
-  {
-    const int st = cd.ictl[CTL_DONE];
-    if (st != 1 && st != 2) return;
-  }
-  const int i = bb.y * kBlock + threadIdx.x;
-  if (i >= cd.N) return;
-  const size_t N = cd.N;
-  const KT* w = (const KT*)cd.w;
-  KT* x = (KT*)cd.x;
-  const KT* di = (const KT*)cd.dinv + 4 * (size_t)i;
-  const KT vc = w[i], vp = w[N + i];
-  x[i] += di[0] * vc + di[1] * vp;
-  x[N + i] += di[2] * vc + di[3] * vp;
-}
 
 // x += z
 template <typename KT>
@@ -714,25 +594,30 @@ __global__ void __launch_bounds__(kBlock) k_add_z_to_x(CellDev* cells, const int
   if (i >= cd.N) return;
   const size_t N = cd.N;
   const KT* z = (const KT*)cd.z;
-  KT* x = (KT*)cd.x;
-  x[i] += z[i];
-  x[N + i] += z[N + i];
+  double* x = cd.x;
+  x[i] += (double)z[i];
+  x[N + i] += (double)z[N + i];
 }
 
-// Restart: w = b - w (w holds J x) with ||w||^2.
+// Restart: w = b - J x with ||w||^2.  The iterate x is kept in FP64 and the
+// product is accumulated in FP64 in both precision modes: in the mixed mode
+// the rows with large conductance would otherwise turn the FP32 rounding of
+// a large common potential shift into a residual floor far above the
+// tolerance (restarted GMRES then acts as iterative refinement).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_true_residual(CellDev* cells, const int2* __restrict__ blk) {
   const int2 bb = block_of(blk);
-  CellDev* cdp = cells + bb.x;
-  const CellDev& cd = *cdp;
+  const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE] != 2) return;
   const int i = bb.y * kBlock + threadIdx.x;
   double ss = 0.0;
   if (i < cd.N) {
     const size_t N = cd.N;
+    double yc, yp;
+    jv_row<KT, double, double>(cd, i, (const double*)cd.x, yc, yp);
     const KT* b = (const KT*)cd.b;
     KT* w = (KT*)cd.w;
-    const KT rc = b[i] - w[i], rp = b[N + i] - w[N + i];
+    const KT rc = (KT)((double)b[i] - yc), rp = (KT)((double)b[N + i] - yp);
     w[i] = rc;
     w[N + i] = rp;
     ss = (double)rc * (double)rc + (double)rp * (double)rp;
@@ -814,10 +699,10 @@ __global__ void __launch_bounds__(kBlock) k_direction(CellDev* cells, const int2
   double dmax = 0.0;
   if (i < cd.N) {
   const size_t N = cd.N;
-  const KT* x = (const KT*)cd.x;
+  const double* x = cd.x;
   const uint32_t mi = cd.meta[i];
   const int L = lab_of(mi);
-  const double xc = (double)x[i], xp = (double)x[N + i];
+  const double xc = x[i], xp = x[N + i];
   cd.dc[i] = cref_of(cd, L) * xc;
   cd.dp[i] = cd.VT * xp;
   dmax = fmax(fabs(xc), fabs(xp));
@@ -957,6 +842,16 @@ __global__ void __launch_bounds__(kBlock) k_convert(CellDev* cells, const int2* 
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
   const size_t N = cd.N;
+  if (sel == VEC_X) {   // the iterate is FP64 in both modes
+    if (dir == 0) {
+      cd.x[i] = cd.dc[i];
+      cd.x[N + i] = cd.dp[i];
+    } else {
+      cd.dc[i] = cd.x[i];
+      cd.dp[i] = cd.x[N + i];
+    }
+    return;
+  }
   KT* v = vec<KT>(cd, sel);
   if (dir == 0) {
     v[i] = (KT)cd.dc[i];
@@ -975,9 +870,9 @@ __global__ void __launch_bounds__(kBlock) k_zero_x(CellDev* cells, const int2* _
   if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
-  KT* x = (KT*)cd.x;
-  x[i] = (KT)0;
-  x[(size_t)cd.N + i] = (KT)0;
+  double* x = cd.x;
+  x[i] = 0.0;
+  x[(size_t)cd.N + i] = 0.0;
 }
 
 // ||w||^2 into RED_BSQ
@@ -1033,10 +928,6 @@ void launch_rhs(const BatchLaunch& b, hipStream_t s) {
   k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_BSQ, 1, 0u, -3);
 }
 template <typename KT>
-void launch_jacobi(const BatchLaunch& b, int src, int dst, int need, hipStream_t s) {
-  k_jacobi<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need);
-}
-template <typename KT>
 void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t s) {
   prof_begin(PK_MATVEC, s);
   k_matvec<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need);
@@ -1070,10 +961,6 @@ void launch_backsolve(const BatchLaunch& b, hipStream_t s) {
 template <typename KT>
 void launch_combine(const BatchLaunch& b, hipStream_t s) {
   k_combine<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
-}
-template <typename KT>
-void launch_update_x_jacobi(const BatchLaunch& b, hipStream_t s) {
-  k_update_x_jacobi<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
 }
 template <typename KT>
 void launch_add_z_to_x(const BatchLaunch& b, hipStream_t s) {
@@ -1127,7 +1014,6 @@ void launch_outputs(const BatchLaunch& b, hipStream_t s) {
 #define MBX_INST(KT)                                                             \
   template void launch_residual<KT>(const BatchLaunch&, bool, hipStream_t);      \
   template void launch_rhs<KT>(const BatchLaunch&, hipStream_t);                 \
-  template void launch_jacobi<KT>(const BatchLaunch&, int, int, int, hipStream_t);  \
   template void launch_matvec<KT>(const BatchLaunch&, int, int, int, hipStream_t);  \
   template void launch_convert<KT>(const BatchLaunch&, int, int, hipStream_t);      \
   template void launch_zero_x<KT>(const BatchLaunch&, hipStream_t);                  \
@@ -1137,7 +1023,6 @@ void launch_outputs(const BatchLaunch& b, hipStream_t s) {
   template void launch_orth_dots<KT>(const BatchLaunch&, int, hipStream_t);     \
   template void launch_scale_next<KT>(const BatchLaunch&, int, hipStream_t);     \
   template void launch_combine<KT>(const BatchLaunch&, hipStream_t);             \
-  template void launch_update_x_jacobi<KT>(const BatchLaunch&, hipStream_t);     \
   template void launch_add_z_to_x<KT>(const BatchLaunch&, hipStream_t);          \
   template void launch_true_residual<KT>(const BatchLaunch&, hipStream_t);       \
   template void launch_gm_start<KT>(const BatchLaunch&, int, hipStream_t);       \

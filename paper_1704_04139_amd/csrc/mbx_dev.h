@@ -89,9 +89,9 @@ struct CellDev {
   double *rn_jnn, *sq;               // per anode face: R^n/J_nn, condensation term
   void *coef_an, *coef_ca;           // KT: 5 per anode face, 3 per cathode face
   void *wpore;                       // KT: c0/c on pore voxels
-  void *dinv;                        // KT: 4 per voxel (row-major inverse 2x2 block)
   void *Vb;                          // KT: (m+1) Krylov basis vectors of 2N
-  void *w, *z, *b, *x;               // KT: 2N each
+  void *w, *z, *b;                   // KT: 2N each (Krylov work vector, preconditioned vector, rhs)
+  double *x;                         // 2N: GMRES iterate, FP64 in both modes
   double *part;                      // nblk * kPartStride partial sums
   unsigned *ticket;                  // one reduction ticket
   double *red;                       // RED_NSLOT outputs (device-written)
@@ -132,6 +132,18 @@ __host__ __device__ inline int gm_tmp(int m) { return (m + 1) * m + (m + 1) + 3 
 __host__ __device__ inline int gm_size(int m) { return (m + 1) * m + 2 * (m + 1) + 3 * m; }
 
 // Neighbour of voxel (x,y,z) in direction d, or -1 outside the box.
+struct VoxCoord {
+  int x, y, z;
+};
+__device__ inline VoxCoord coord_of(const CellDev& cd, int i) {
+  VoxCoord v;
+  v.x = i % cd.nx;
+  const int t = i / cd.nx;
+  v.y = t % cd.ny;
+  v.z = t / cd.ny;
+  return v;
+}
+
 __device__ inline int neighbour(const CellDev& cd, int i, int x, int y, int z, int d) {
   switch (d) {
     case 0: return x > 0 ? i - 1 : -1;

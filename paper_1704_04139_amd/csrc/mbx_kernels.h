@@ -41,7 +41,6 @@ hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* ou
 
 template <typename KT> void launch_residual(const BatchLaunch& b, bool lin, hipStream_t s);
 template <typename KT> void launch_rhs(const BatchLaunch& b, hipStream_t s);
-template <typename KT> void launch_jacobi(const BatchLaunch& b, int src, int dst, int need, hipStream_t s);
 template <typename KT> void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t s);
 template <typename KT> void launch_convert(const BatchLaunch& b, int sel, int dir, hipStream_t s);
 template <typename KT> void launch_zero_x(const BatchLaunch& b, hipStream_t s);
@@ -55,7 +54,6 @@ template <typename KT> void launch_scale_next(const BatchLaunch& b, int k, hipSt
 void launch_givens(const BatchLaunch& b, int k, hipStream_t s);
 void launch_backsolve(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_combine(const BatchLaunch& b, hipStream_t s);
-template <typename KT> void launch_update_x_jacobi(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_add_z_to_x(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_true_residual(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_gm_start(const BatchLaunch& b, int first, hipStream_t s);

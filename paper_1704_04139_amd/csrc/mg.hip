@@ -66,7 +66,6 @@ __device__ inline KT* vsel(const CellDev& cd, int sel) {
     case VEC_Z: return (KT*)cd.z;
     case VEC_W: return (KT*)cd.w;
     case VEC_B: return (KT*)cd.b;
-    case VEC_X: return (KT*)cd.x;
     default: return (KT*)cd.Vb + (size_t)sel * n2;
   }
 }
