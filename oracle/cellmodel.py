@@ -18,7 +18,7 @@ What it computes (arXiv 1704.04139, MULTIBAT):
     Euler in time, one concentration and one potential unknown per voxel.
   * Sec. 2.5 (output functionals): cell voltage and mean solid concentration.
 
-Readings where the paper is silent (each listed in the design doc): full cell with
+Readings where the paper is silent: full cell with
 the cathode following the same intercalation law; constant coefficients;
 the 1/c term discretised as RT (ln c_k - ln c_i)/h with thermodynamic factor
 theta; BV evaluated from the two adjacent cell values; per-face plated amount

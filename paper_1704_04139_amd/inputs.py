@@ -12,7 +12,7 @@ fully connected by construction (Sec. 2.1, connectivity graph of the
 tessellation), so solid voxels that are not face-connected to their own
 current collector plane are returned to the pore phase, and pore voxels that
 are not face-connected to the separator (closed porosity) are filled with the
-surrounding electrode's solid.  Both rules are stated in the design doc.
+surrounding electrode's solid.
 
 Random numbers come from a counter-based generator, SplitMix64 (Steele,
 Lea and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014):
