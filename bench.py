@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="offered arrival rate, requests/s")
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first (calibrates profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); independent cells shard across GPUs "
@@ -206,6 +208,14 @@ def main():
     mbx.load()
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * 2**20 // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {args.copy_probe_mib} MiB device-to-device", file=sys.stderr, flush=True)
+        del a, b
     if args.mode == "serve":
         out = {"metric": "served requests/s", "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
                "data": "synthetic", "config": {"workload": "parameter queries 48x48x120 .. 128x128x320, 12 x 5 s, "

@@ -91,7 +91,15 @@ struct LevelDims {
 
 // Ceil-halving hierarchy down to at most kCoarseMaxCells coarse cells (at
 // least one coarse level).
-LevelDims level_dims(int nx, int ny, int nz) {
+// LDS elements (KT) the fused coarse cycle stages for levels lf..n-1: x and b
+// of every level, the operator of every level but the coarsest.
+size_t fused_elems(const LevelDims& d, int lf) {
+  size_t e = 0;
+  for (int l = lf; l < d.n; ++l) e += (size_t)d.ncell[l] * (6 + (l + 1 < d.n ? kOpStride : 0));
+  return e;
+}
+
+LevelDims level_dims(int nx, int ny, int nz, size_t kt) {
   LevelDims d;
   d.nx[0] = nx;
   d.ny[0] = ny;
@@ -108,7 +116,9 @@ LevelDims level_dims(int nx, int ny, int nz) {
     if (d.ncell[l] <= kCoarseMaxCells) break;
   }
   d.lfuse = d.n - 1;
-  while (d.lfuse > 1 && d.ncell[d.lfuse - 1] <= kFuseMaxCells) --d.lfuse;
+  while (d.lfuse > 1 && d.ncell[d.lfuse - 1] <= kFuseMaxCells &&
+         fused_elems(d, d.lfuse - 1) * kt <= kFusedLdsBytes)
+    --d.lfuse;
   return d;
 }
 
@@ -295,6 +305,8 @@ struct Batch {
     b.ncell = (int)cells.size();
     b.maxlev = maxlev;
     b.maxfuse = maxfuse;
+    b.fused_lds = 0;
+    for (const mbx_cell* c : cells) b.fused_lds = std::max(b.fused_lds, fused_elems(c->ld, c->ld.lfuse));
     for (int l = 0; l < kMaxLevels; ++l) {
       b.lvl_blk[l] = one ? nullptr : lvl_blk[l];
       b.lvl_nblk[l] = lvl_nblk[l];
@@ -740,7 +752,7 @@ int64_t mbx_cell_footprint(int nx, int ny, int nz, int precision, int n_an_faces
   if (N <= 0 || N > (1 << 28)) return -1;
   const int nblk = (int)((N + kBlock - 1) / kBlock);
   Layout L = make_layout((int)N, n_an_faces, n_ca_faces, nblk, restart_len(), kt_size(precision),
-                         level_dims(nx, ny, nz));
+                         level_dims(nx, ny, nz, kt_size(precision)));
   return (int64_t)L.total;
 }
 
@@ -831,7 +843,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   c->mixed = p.precision == MBX_MIXED;
   c->s = s;
   const size_t kt = kt_size(p.precision);
-  c->ld = level_dims(nx, ny, nz);
+  c->ld = level_dims(nx, ny, nz, kt_size(p.precision));
   if (c->ld.ncell[c->ld.n - 1] > kCoarseMaxCells) {
     cleanup_tmp();
     delete c;

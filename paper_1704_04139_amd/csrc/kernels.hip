@@ -385,20 +385,36 @@ __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2
     wc = w[i];
     wp = w[N + i];
   }
+  // chunks of 8 basis vectors: one uniform branch per chunk, the chunk's 16
+  // loads issued together (indices past k are clamped to k and not used)
+  const KT* V = (const KT*)cd.Vb;
+  const size_t n2 = 2 * N;
+  const size_t ii = in ? (size_t)i : 0;
 #pragma unroll
-  for (int j = 0; j < kMaxRestart; ++j) {
-    if (j <= k) {
-      const KT* vj = vec<KT>(cd, j);
-      vc[j] = in ? vj[i] : (KT)0;
-      vp[j] = in ? vj[N + i] : (KT)0;
-      const KT hj = (KT)hc[j];
-      wc -= hj * vc[j];
-      wp -= hj * vp[j];
+  for (int c = 0; c < kMaxRestart; c += 8) {
+    if (c <= k) {
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const int j = c + jj < k ? c + jj : k;
+        vc[c + jj] = V[(size_t)j * n2 + ii];
+        vp[c + jj] = V[(size_t)j * n2 + N + ii];
+      }
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj)
+        if (c + jj <= k) {
+          const KT hj = (KT)hc[c + jj];
+          wc -= hj * vc[c + jj];
+          wp -= hj * vp[c + jj];
+        }
     }
   }
   if (in) {
     w[i] = wc;
     w[N + i] = wp;
+  }
+  if (!in) {
+    wc = (KT)0;
+    wp = (KT)0;
   }
 #pragma unroll
   for (int j = 0; j < kMaxRestart; ++j)

@@ -22,6 +22,7 @@ constexpr double kGasR = 8.314462618;      // J/(mol K)
 constexpr int kBlock = 256;                // threads per voxel block (4 wavefronts)
 constexpr int kMaxRestart = 40;            // GMRES restart length bound
 constexpr int kPartStride = kMaxRestart + 2;
+static_assert(kMaxRestart % 8 == 0, "basis loads are issued in chunks of 8");
 
 enum { PORE = 0, ANODE = 1, CATHODE = 2 };
 
@@ -31,6 +32,7 @@ enum { PORE = 0, ANODE = 1, CATHODE = 2 };
 constexpr int kMaxLevels = 12;
 constexpr int kCoarseMaxCells = 64;
 constexpr int kFuseMaxCells = 256;    // levels this small run inside one workgroup per cell
+constexpr size_t kFusedLdsBytes = 60 * 1024;   // LDS the fused levels may stage
 constexpr int kOpStride = 33;   // per coarse cell: E[3], X[3], G[3 dirs][3][3] (SoA)
 struct MGLevel {
   int nx, ny, nz, ncell;

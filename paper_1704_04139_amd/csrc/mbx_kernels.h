@@ -19,6 +19,7 @@ struct BatchLaunch {
   int ncell;
   int maxlev;                            // max multigrid levels over the batch
   int maxfuse;                           // max first fused level over the batch
+  size_t fused_lds;                      // LDS elements (KT) of the fused coarse cycle, max over the batch
   const int2* lvl_blk[kMaxLevels];       // block tables over each level's cells (index >= 1)
   int lvl_nblk[kMaxLevels];
   const int2* lvl8_blk[kMaxLevels];      // block tables with 8 lanes per level cell (index >= 1)

@@ -232,9 +232,12 @@ struct CoarseRow {
   KT xn[6][3];
 };
 
+// L: the level, Lp: the next coarser level (read in the corrected modes),
+// alpha: the coarse-correction factor.  The level descriptors may point into
+// device memory or into LDS.
 template <typename KT>
-__device__ inline void gather_coarse(const CellDev& cd, int l, int op, int C, const C3& q, int mode, CoarseRow<KT>& R) {
-  const MGLevel& L = cd.lv[l];
+__device__ inline void gather_coarse(const MGLevel& L, const MGLevel& Lp, KT alpha, int op, int C, const C3& q,
+                                     int mode, CoarseRow<KT>& R) {
   const size_t n = L.ncell;
   const KT* A = (const KT*)L.op[op];
   const KT* b = (const KT*)L.b;
@@ -268,10 +271,8 @@ __device__ inline void gather_coarse(const CellDev& cd, int l, int op, int C, co
       R.xn[j][t] = ex[j] ? v : (KT)0;
     }
   if (own_corr(mode) || nbr_corr(mode)) {
-    const MGLevel& Lp = cd.lv[l + 1];
     const size_t np = Lp.ncell;
     const KT* xp = (const KT*)Lp.x;
-    const KT alpha = (KT)cd.alpha;
     const int px = q.x >> 1, py = q.y >> 1, pz = q.z >> 1;
     const int pc = px + Lp.nx * (py + Lp.ny * pz);
     if (own_corr(mode))
@@ -540,9 +541,10 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
 // Coarse-level (l >= 1) red-black Gauss-Seidel update of cell C; the slots
 // of one cell are relaxed in order (slot-wise Gauss-Seidel inside the cell).
 template <typename KT>
-__device__ inline void smooth_cell(const CellDev& cd, int l, int op, int C, const C3& q, int mode, int need) {
+__device__ inline void smooth_cell(const CellDev& cd, const MGLevel& L, const MGLevel& Lp, KT alpha, int op, int C,
+                                   const C3& q, int mode, int need) {
   CoarseRow<KT> R;
-  gather_coarse<KT>(cd, l, op, C, q, mode, R);
+  gather_coarse<KT>(L, Lp, alpha, op, C, q, mode, R);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     KT D = R.E[s], S = R.b[s];
@@ -564,7 +566,6 @@ __device__ inline void smooth_cell(const CellDev& cd, int l, int op, int C, cons
     R.xo[s] = D > (KT)0 ? S / D : (KT)0;
   }
   if (!gate_state(cd, need)) return;
-  const MGLevel& L = cd.lv[l];
   KT* x = (KT*)L.x;
 #pragma unroll
   for (int s = 0; s < 3; ++s) x[(size_t)s * L.ncell + C] = R.xo[s];
@@ -572,9 +573,9 @@ __device__ inline void smooth_cell(const CellDev& cd, int l, int op, int C, cons
 
 // Residual (per slot) of coarse cell c at level l.
 template <typename KT>
-__device__ inline void residual_cell(const CellDev& cd, int l, int op, int c, const C3& q, KT (&r)[3]) {
+__device__ inline void residual_cell(const MGLevel& L, int op, int c, const C3& q, KT (&r)[3]) {
   CoarseRow<KT> R;
-  gather_coarse<KT>(cd, l, op, c, q, SM_PLAIN, R);
+  gather_coarse<KT>(L, L, (KT)0, op, c, q, SM_PLAIN, R);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const KT xs = R.xo[s];
@@ -600,7 +601,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int
   const MGLevel& L = cd.lv[l];
   C3 q;
   if (!color_cell(bb.y * kBlock + threadIdx.x, color, L.nx, L.ny, L.nz, q)) return;
-  smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode, need);
+  smooth_cell<KT>(cd, L, cd.lv[l + 1], (KT)cd.alpha, op, lvl_cell(L, q.x, q.y, q.z), q, mode, need);
 }
 
 // Level-l residual restricted to level l+1: 8 lanes per parent, one per child.
@@ -619,7 +620,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
   if (live) {
     const C3 q = c3_of(P, Lp.nx, Lp.ny);
     const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
-    if (cx < L.nx && cy < L.ny && cz < L.nz) residual_cell<KT>(cd, l, op, lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
+    if (cx < L.nx && cy < L.ny && cz < L.nz) residual_cell<KT>(L, op, lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
   if (!gate_state(cd, need)) return;   // uniform over the block (one cell)
@@ -632,27 +633,67 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
 // Levels lfuse..coarsest of one cell in one workgroup (levels small enough
 // that barriers are cheaper than kernel launches): pre-smoothing and
 // restriction down to the coarsest level, dense coarsest solve, coarse
-// correction and post-smoothing back up to lfuse.
+// correction and post-smoothing back up to lfuse.  The operators and vectors
+// of these levels are staged in LDS first (the dynamic shared-memory size is
+// fused_lds_bytes); the coarsest inverse stays in device memory (symmetric:
+// read column-wise, coalesced).  Only the level-lfuse solution is written
+// back: the launched level above reads it for its coarse correction.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int op, int nu, int need) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ MGLevel S[kMaxLevels];
   const int ci = blockIdx.x;
   if (ci >= ncells) return;
   const CellDev& cd = cells[ci];
   if (!gate(cd, need)) return;
-  const int lc = cd.nlev - 1;
-  for (int l = cd.lfuse; l < lc; ++l) {
-    const MGLevel& L = cd.lv[l];
+  const int lf = cd.lfuse, lc = cd.nlev - 1;
+  const KT alpha = (KT)cd.alpha;
+  // stage: operator op of every fused level, the restricted right-hand side of level lf
+  if (threadIdx.x == 0) {
+    KT* p = (KT*)smem;
+    for (int l = lf; l <= lc; ++l) {
+      const MGLevel& G = cd.lv[l];
+      MGLevel& L = S[l];
+      L = G;
+      const size_t n = G.ncell;
+      L.x = p;
+      p += 3 * n;
+      L.b = p;
+      p += 3 * n;
+      if (l < lc) {
+        L.op[op] = p;
+        p += (size_t)kOpStride * n;
+      }
+    }
+  }
+  __syncthreads();
+  for (int l = lf; l < lc; ++l) {
+    const size_t n = (size_t)kOpStride * S[l].ncell;
+    const KT* src = (const KT*)cd.lv[l].op[op];
+    KT* dst = (KT*)S[l].op[op];
+    for (size_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+  }
+  {
+    const size_t n = 3 * (size_t)S[lf].ncell;
+    const KT* src = (const KT*)cd.lv[lf].b;
+    KT* dst = (KT*)S[lf].b;
+    for (size_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+  }
+  __syncthreads();
+  for (int l = lf; l < lc; ++l) {
+    const MGLevel& L = S[l];
+    const MGLevel& Lp = S[l + 1];
+    const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
     for (int it = 0; it < nu; ++it)
       for (int color = 0; color < 2; ++color) {
         const int mode = it == 0 ? (color == 0 ? SM_ZERO : SM_OWNZERO) : SM_PLAIN;
-        const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
-          if (color_cell(t, color, L.nx, L.ny, L.nz, q)) smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode, -2);
+          if (color_cell(t, color, L.nx, L.ny, L.nz, q))
+            smooth_cell<KT>(cd, L, Lp, alpha, op, lvl_cell(L, q.x, q.y, q.z), q, mode, -2);
         }
         __syncthreads();
       }
-    const MGLevel& Lp = cd.lv[l + 1];
     for (int P = threadIdx.x; P < Lp.ncell; P += blockDim.x) {
       const C3 q = c3_of(P, Lp.nx, Lp.ny);
       KT acc[3] = {0, 0, 0};
@@ -660,41 +701,46 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
         if (cx >= L.nx || cy >= L.ny || cz >= L.nz) continue;
         KT r[3];
-        residual_cell<KT>(cd, l, op, lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, r);
+        residual_cell<KT>(L, op, lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, r);
         for (int s = 0; s < 3; ++s) acc[s] += r[s];
       }
       for (int s = 0; s < 3; ++s) ((KT*)Lp.b)[(size_t)s * Lp.ncell + P] = acc[s];
     }
     __syncthreads();
   }
-  {  // coarsest: x = M^-1 b
-    const MGLevel& L = cd.lv[lc];
+  {  // coarsest: x = M^-1 b (M symmetric: row r read as column r, coalesced)
+    const MGLevel& L = S[lc];
     const int n = 3 * L.ncell;
-    __shared__ double bs[3 * kCoarseMaxCells];
     const KT* b = (const KT*)L.b;
-    for (int r = threadIdx.x; r < n; r += blockDim.x) bs[r] = (double)b[(size_t)(r % 3) * L.ncell + r / 3];
-    __syncthreads();
     const double* M = cd.cinv[op];
     KT* x = (KT*)L.x;
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
       double acc = 0.0;
-      for (int j = 0; j < n; ++j) acc += M[(size_t)r * n + j] * bs[j];
+      for (int j = 0; j < n; ++j) acc += M[(size_t)j * n + r] * (double)b[(size_t)(j % 3) * L.ncell + j / 3];
       x[(size_t)(r % 3) * L.ncell + r / 3] = (KT)acc;
     }
     __syncthreads();
   }
-  for (int l = lc - 1; l >= cd.lfuse; --l) {
-    const MGLevel& L = cd.lv[l];
+  for (int l = lc - 1; l >= lf; --l) {
+    const MGLevel& L = S[l];
+    const MGLevel& Lp = S[l + 1];
+    const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
     for (int it = 0; it < nu; ++it)
       for (int color = 1; color >= 0; --color) {
         const int mode = it == 0 ? (color == 1 ? SM_CORR : SM_OWNCORR) : SM_PLAIN;
-        const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
-          if (color_cell(t, color, L.nx, L.ny, L.nz, q)) smooth_cell<KT>(cd, l, op, lvl_cell(L, q.x, q.y, q.z), q, mode, -2);
+          if (color_cell(t, color, L.nx, L.ny, L.nz, q))
+            smooth_cell<KT>(cd, L, Lp, alpha, op, lvl_cell(L, q.x, q.y, q.z), q, mode, -2);
         }
         __syncthreads();
       }
+  }
+  {
+    const size_t n = 3 * (size_t)S[lf].ncell;
+    const KT* src = (const KT*)S[lf].x;
+    KT* dst = (KT*)cd.lv[lf].x;
+    for (size_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
   }
 }
 
@@ -833,7 +879,7 @@ static void vcycle(const BatchLaunch& b, int op, int nu_unused, int need, hipStr
     else
       k_mgl_restrict<KT><<<b.lvl8_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl8_blk[l + 1], l, op, need);
   }
-  k_mg_coarse_cycle<KT><<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, op, sweeps(2), need);
+  k_mg_coarse_cycle<KT><<<b.ncell, kBlock, b.fused_lds * sizeof(KT), s>>>(b.cells, b.ncell, op, sweeps(2), need);
   for (int l = top - 1; l >= 0; --l) {
     const int nu = sweeps(l == 0 ? 0 : 1);
     for (int it = 0; it < nu; ++it) {
