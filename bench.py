@@ -139,6 +139,22 @@ def run_batched(n_cells, steps, precision, stream):
             "precision": precision}
 
 
+def _drain(srv, what, limit_s=3600.0):
+    """Wait for the server to go idle, printing progress every 30 s."""
+    from paper_1704_04139_amd import mbx
+    t0 = time.perf_counter()
+    while True:
+        try:
+            srv.drain(30.0)
+            return
+        except mbx.MbxError as e:
+            if e.code != mbx.MBX_ESTATE or time.perf_counter() - t0 > limit_s:
+                raise
+        st = srv.stats()
+        print(f"[serve] {what}: {st['running']} running, {st['queued']} queued, {st['steps_run']} cell-steps done",
+              file=sys.stderr, flush=True)
+
+
 def run_serving(precision, rate_offered, n_req, n_cap, stream, budget_gb):
     """Poisson arrivals at a continuous-batching server; capacity first, then
     a run at 70% utilisation if the offered rate exceeds the capacity."""
@@ -151,7 +167,7 @@ def run_serving(precision, rate_offered, n_req, n_cap, stream, budget_gb):
     srv = mbx.Server(int(budget_gb * 2**30), precision, dt=5.0, stream=stream)
     t0 = srv.clock()
     ids = [srv.submit(w.labels, w.params, steps) for w in reqs[:n_cap]]
-    srv.drain(1200.0)
+    _drain(srv, f"{precision} capacity burst")
     t1 = max(srv.poll(i)["t_done"] for i in ids)
     srv.close()
     cap = sum(dofsteps[:n_cap]) / (t1 - t0)
@@ -168,7 +184,7 @@ def run_serving(precision, rate_offered, n_req, n_cap, stream, budget_gb):
         ids.append(srv.submit(w.labels, w.params, steps))
         print(f"[serve] {precision} request {len(ids)}/{n_req} at {srv.clock() - base:.2f} s", file=sys.stderr,
               flush=True)
-    srv.drain(3600.0)
+    _drain(srv, f"{precision} Poisson run")
     infos = [srv.poll(i) for i in ids]
     st = srv.stats()
     srv.close()
@@ -193,6 +209,8 @@ def main():
     ap.add_argument("--batch-cells", type=int, default=32)
     ap.add_argument("--batch-steps", type=int, default=2, help="timed batched steps (0: skip the batched run)")
     ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-capacity-requests", type=int, default=6,
+                    help="requests of the closed burst that measures the server's capacity")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="offered arrival rate, requests/s")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -221,7 +239,8 @@ def main():
                "data": "synthetic", "config": {"workload": "parameter queries 48x48x120 .. 128x128x320, 12 x 5 s, "
                                                            "Poisson arrivals, continuous batching"}}
         for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
-            out[prec] = run_serving(prec, args.serve_rate, args.serve_requests, 6, stream, args.budget_gb)
+            out[prec] = run_serving(prec, args.serve_rate, args.serve_requests, args.serve_capacity_requests, stream,
+                                    args.budget_gb)
             print(f"[bench] serve {prec}: {json.dumps(out[prec])}", file=sys.stderr, flush=True)
         main_prec = "mixed" if "mixed" in out else "fp64"
         out["value"] = out[main_prec]["completed_per_s"]

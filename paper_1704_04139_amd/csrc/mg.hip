@@ -225,6 +225,20 @@ __device__ inline void voxel_row(const CellDev& cd, int op, int i, const C3& c, 
 // Gathered row block of coarse cell C at level l: the 3x3 in-cell couplings,
 // the couplings to the six neighbours and the neighbour values, loaded
 // without branches (absent neighbours read cell C with zero couplings).
+// A coarse level as the smoother sees it: extents, the vectors and the
+// operator being solved (typed pointers, in device memory or in LDS).
+template <typename KT>
+struct LV {
+  int nx, ny, nz, ncell;
+  KT* x;
+  KT* b;
+  const KT* A;
+};
+template <typename KT>
+__device__ inline LV<KT> view(const MGLevel& L, int op) {
+  return LV<KT>{L.nx, L.ny, L.nz, L.ncell, (KT*)L.x, (KT*)L.b, (const KT*)L.op[op]};
+}
+
 template <typename KT>
 struct CoarseRow {
   KT E[3], X[3], b[3], xo[3];
@@ -236,12 +250,12 @@ struct CoarseRow {
 // alpha: the coarse-correction factor.  The level descriptors may point into
 // device memory or into LDS.
 template <typename KT>
-__device__ inline void gather_coarse(const MGLevel& L, const MGLevel& Lp, KT alpha, int op, int C, const C3& q,
-                                     int mode, CoarseRow<KT>& R) {
+__device__ inline void gather_coarse(const LV<KT>& L, const LV<KT>& Lp, KT alpha, int C, const C3& q, int mode,
+                                     CoarseRow<KT>& R) {
   const size_t n = L.ncell;
-  const KT* A = (const KT*)L.op[op];
-  const KT* b = (const KT*)L.b;
-  const KT* x = (const KT*)L.x;
+  const KT* A = L.A;
+  const KT* b = L.b;
+  const KT* x = L.x;
   int nb[6];
   bool ex[6];
   neighbours6(C, q, L.nx, L.ny, L.nz, nb, ex);
@@ -272,7 +286,7 @@ __device__ inline void gather_coarse(const MGLevel& L, const MGLevel& Lp, KT alp
     }
   if (own_corr(mode) || nbr_corr(mode)) {
     const size_t np = Lp.ncell;
-    const KT* xp = (const KT*)Lp.x;
+    const KT* xp = Lp.x;
     const int px = q.x >> 1, py = q.y >> 1, pz = q.z >> 1;
     const int pc = px + Lp.nx * (py + Lp.ny * pz);
     if (own_corr(mode))
@@ -541,10 +555,10 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
 // Coarse-level (l >= 1) red-black Gauss-Seidel update of cell C; the slots
 // of one cell are relaxed in order (slot-wise Gauss-Seidel inside the cell).
 template <typename KT>
-__device__ inline void smooth_cell(const CellDev& cd, const MGLevel& L, const MGLevel& Lp, KT alpha, int op, int C,
-                                   const C3& q, int mode, int need) {
+__device__ inline void smooth_cell(const CellDev& cd, const LV<KT>& L, const LV<KT>& Lp, KT alpha, int C, const C3& q,
+                                   int mode, int need) {
   CoarseRow<KT> R;
-  gather_coarse<KT>(L, Lp, alpha, op, C, q, mode, R);
+  gather_coarse<KT>(L, Lp, alpha, C, q, mode, R);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     KT D = R.E[s], S = R.b[s];
@@ -566,16 +580,16 @@ __device__ inline void smooth_cell(const CellDev& cd, const MGLevel& L, const MG
     R.xo[s] = D > (KT)0 ? S / D : (KT)0;
   }
   if (!gate_state(cd, need)) return;
-  KT* x = (KT*)L.x;
+  KT* x = L.x;
 #pragma unroll
   for (int s = 0; s < 3; ++s) x[(size_t)s * L.ncell + C] = R.xo[s];
 }
 
 // Residual (per slot) of coarse cell c at level l.
 template <typename KT>
-__device__ inline void residual_cell(const MGLevel& L, int op, int c, const C3& q, KT (&r)[3]) {
+__device__ inline void residual_cell(const LV<KT>& L, int c, const C3& q, KT (&r)[3]) {
   CoarseRow<KT> R;
-  gather_coarse<KT>(L, L, (KT)0, op, c, q, SM_PLAIN, R);
+  gather_coarse<KT>(L, L, (KT)0, c, q, SM_PLAIN, R);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const KT xs = R.xo[s];
@@ -601,7 +615,8 @@ __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int
   const MGLevel& L = cd.lv[l];
   C3 q;
   if (!color_cell(bb.y * kBlock + threadIdx.x, color, L.nx, L.ny, L.nz, q)) return;
-  smooth_cell<KT>(cd, L, cd.lv[l + 1], (KT)cd.alpha, op, lvl_cell(L, q.x, q.y, q.z), q, mode, need);
+  smooth_cell<KT>(cd, view<KT>(L, op), view<KT>(cd.lv[l + 1], op), (KT)cd.alpha, lvl_cell(L, q.x, q.y, q.z), q,
+                  mode, need);
 }
 
 // Level-l residual restricted to level l+1: 8 lanes per parent, one per child.
@@ -620,7 +635,8 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
   if (live) {
     const C3 q = c3_of(P, Lp.nx, Lp.ny);
     const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
-    if (cx < L.nx && cy < L.ny && cz < L.nz) residual_cell<KT>(L, op, lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
+    if (cx < L.nx && cy < L.ny && cz < L.nz)
+      residual_cell<KT>(view<KT>(L, op), lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
   if (!gate_state(cd, need)) return;   // uniform over the block (one cell)
@@ -641,48 +657,43 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int op, int nu, int need) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ MGLevel S[kMaxLevels];
   const int ci = blockIdx.x;
   if (ci >= ncells) return;
   const CellDev& cd = cells[ci];
   if (!gate(cd, need)) return;
   const int lf = cd.lfuse, lc = cd.nlev - 1;
   const KT alpha = (KT)cd.alpha;
-  // stage: operator op of every fused level, the restricted right-hand side of level lf
-  if (threadIdx.x == 0) {
-    KT* p = (KT*)smem;
-    for (int l = lf; l <= lc; ++l) {
-      const MGLevel& G = cd.lv[l];
-      MGLevel& L = S[l];
-      L = G;
-      const size_t n = G.ncell;
-      L.x = p;
-      p += 3 * n;
-      L.b = p;
-      p += 3 * n;
-      if (l < lc) {
-        L.op[op] = p;
-        p += (size_t)kOpStride * n;
-      }
-    }
-  }
-  __syncthreads();
+  KT* const base = (KT*)smem;
+  // LDS element offsets of level l's x, b and operator: levels lf..lc in order
+  auto offset = [&](int l) {
+    size_t o = 0;
+    for (int k = lf; k < l; ++k) o += (size_t)cd.lv[k].ncell * (6 + (k < lc ? kOpStride : 0));
+    return o;
+  };
+  // level l with its arrays in LDS (built where used, so that the compiler
+  // sees LDS pointers and emits LDS instructions)
+  auto lds_level = [&](int l) {
+    const MGLevel& G = cd.lv[l];
+    const size_t o = offset(l), n = G.ncell;
+    return LV<KT>{G.nx, G.ny, G.nz, G.ncell, base + o, base + o + 3 * n, base + o + 6 * n};
+  };
+  // stage: operator op of every fused level but the coarsest, right-hand side of level lf
   for (int l = lf; l < lc; ++l) {
-    const size_t n = (size_t)kOpStride * S[l].ncell;
+    const size_t n = (size_t)kOpStride * cd.lv[l].ncell;
     const KT* src = (const KT*)cd.lv[l].op[op];
-    KT* dst = (KT*)S[l].op[op];
+    KT* dst = base + offset(l) + 6 * (size_t)cd.lv[l].ncell;
     for (size_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
   }
   {
-    const size_t n = 3 * (size_t)S[lf].ncell;
+    const size_t n = 3 * (size_t)cd.lv[lf].ncell;
     const KT* src = (const KT*)cd.lv[lf].b;
-    KT* dst = (KT*)S[lf].b;
+    KT* dst = base + offset(lf) + n;
     for (size_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
   }
   __syncthreads();
   for (int l = lf; l < lc; ++l) {
-    const MGLevel& L = S[l];
-    const MGLevel& Lp = S[l + 1];
+    const LV<KT> L = lds_level(l);
+    const LV<KT> Lp = lds_level(l + 1);
     const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
     for (int it = 0; it < nu; ++it)
       for (int color = 0; color < 2; ++color) {
@@ -690,7 +701,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
           if (color_cell(t, color, L.nx, L.ny, L.nz, q))
-            smooth_cell<KT>(cd, L, Lp, alpha, op, lvl_cell(L, q.x, q.y, q.z), q, mode, -2);
+            smooth_cell<KT>(cd, L, Lp, alpha, q.x + L.nx * (q.y + L.ny * q.z), q, mode, -2);
         }
         __syncthreads();
       }
@@ -701,19 +712,19 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
         if (cx >= L.nx || cy >= L.ny || cz >= L.nz) continue;
         KT r[3];
-        residual_cell<KT>(L, op, lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, r);
+        residual_cell<KT>(L, cx + L.nx * (cy + L.ny * cz), C3{cx, cy, cz}, r);
         for (int s = 0; s < 3; ++s) acc[s] += r[s];
       }
-      for (int s = 0; s < 3; ++s) ((KT*)Lp.b)[(size_t)s * Lp.ncell + P] = acc[s];
+      for (int s = 0; s < 3; ++s) Lp.b[(size_t)s * Lp.ncell + P] = acc[s];
     }
     __syncthreads();
   }
   {  // coarsest: x = M^-1 b (M symmetric: row r read as column r, coalesced)
-    const MGLevel& L = S[lc];
+    const LV<KT> L = lds_level(lc);
     const int n = 3 * L.ncell;
-    const KT* b = (const KT*)L.b;
+    const KT* b = L.b;
     const double* M = cd.cinv[op];
-    KT* x = (KT*)L.x;
+    KT* x = L.x;
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
       double acc = 0.0;
       for (int j = 0; j < n; ++j) acc += M[(size_t)j * n + r] * (double)b[(size_t)(j % 3) * L.ncell + j / 3];
@@ -722,8 +733,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
     __syncthreads();
   }
   for (int l = lc - 1; l >= lf; --l) {
-    const MGLevel& L = S[l];
-    const MGLevel& Lp = S[l + 1];
+    const LV<KT> L = lds_level(l);
+    const LV<KT> Lp = lds_level(l + 1);
     const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
     for (int it = 0; it < nu; ++it)
       for (int color = 1; color >= 0; --color) {
@@ -731,14 +742,14 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
           if (color_cell(t, color, L.nx, L.ny, L.nz, q))
-            smooth_cell<KT>(cd, L, Lp, alpha, op, lvl_cell(L, q.x, q.y, q.z), q, mode, -2);
+            smooth_cell<KT>(cd, L, Lp, alpha, q.x + L.nx * (q.y + L.ny * q.z), q, mode, -2);
         }
         __syncthreads();
       }
   }
   {
-    const size_t n = 3 * (size_t)S[lf].ncell;
-    const KT* src = (const KT*)S[lf].x;
+    const size_t n = 3 * (size_t)cd.lv[lf].ncell;
+    const KT* src = base + offset(lf);
     KT* dst = (KT*)cd.lv[lf].x;
     for (size_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
   }
