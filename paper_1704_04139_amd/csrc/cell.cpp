@@ -279,7 +279,6 @@ struct Batch {
   bool owned = false;
   bool mixed = false;
   int m = kRestart;
-  int nu = 2;
   int maxlev = 0;
   int maxfuse = 1;
   int2* lvl_blk[kMaxLevels] = {};
@@ -306,7 +305,11 @@ struct Batch {
     b.maxlev = maxlev;
     b.maxfuse = maxfuse;
     b.fused_lds = 0;
-    for (const mbx_cell* c : cells) b.fused_lds = std::max(b.fused_lds, fused_elems(c->ld, c->ld.lfuse));
+    b.max_nu = 1;
+    for (const mbx_cell* c : cells) {
+      b.fused_lds = std::max(b.fused_lds, fused_elems(c->ld, c->ld.lfuse));
+      b.max_nu = std::max(b.max_nu, c->h.nu);
+    }
     for (int l = 0; l < kMaxLevels; ++l) {
       b.lvl_blk[l] = one ? nullptr : lvl_blk[l];
       b.lvl_nblk[l] = lvl_nblk[l];
@@ -481,7 +484,7 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
   while (total < max_iters) {
     int k = 0;
     for (; k < m; ++k) {
-      launch_precond<KT>(B.bl(), k, B.nu, 0, B.s);
+      launch_precond<KT>(B.bl(), k, 0, B.s);
       launch_matvec<KT>(B.bl(), VEC_Z, VEC_W, 0, B.s);
       // classical Gram-Schmidt with one re-orthogonalisation (CGS2)
       launch_multidot<KT>(B.bl(), k, 0, B.s);   // H(:,k) = V^T w
@@ -512,7 +515,7 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
     }
     launch_backsolve(B.bl(), B.s);
     launch_combine<KT>(B.bl(), B.s);
-    launch_precond<KT>(B.bl(), VEC_W, B.nu, -1, B.s);
+    launch_precond<KT>(B.bl(), VEC_W, -1, B.s);
     launch_add_z_to_x<KT>(B.bl(), B.s);
     launch_true_residual<KT>(B.bl(), B.s);   // w = b - J x for the cells that restart
     launch_gm_start<KT>(B.bl(), 0, B.s);
@@ -532,6 +535,9 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
 }
 
 // ------------------------------------------------------------------ Newton
+constexpr int kSweepsMin = 2;         // smoothing sweeps per side a cell starts with
+constexpr int kSweepsMax = 6;
+constexpr int kSlowSolve = 60;        // Krylov iterations of one correction that call for more smoothing
 constexpr double kEtaMax = 0.1;        // loosest GMRES relative tolerance of a Newton correction (FP64)
 constexpr double kEtaMaxMixed = 1e-4;  // ... in the mixed mode
 constexpr double kEwGamma = 0.9;
@@ -584,8 +590,20 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
     int kits = 0;
     if (int e = gmres<KT>(B, B.cells[0]->p.krylov_max, &kits)) return e;
     if (int e = B.gather()) return e;
-    for (int c = 0; c < nc; ++c)
-      if (st[c] == 1) kit[c] += B.ctl(c, CTL_ITERS);
+    for (int c = 0; c < nc; ++c) {
+      if (st[c] != 1) continue;
+      const int its = B.ctl(c, CTL_ITERS);
+      kit[c] += its;
+      // sweep autotuning: a cell whose corrections need many Krylov
+      // iterations gets more smoothing from its next solve on (kept for
+      // later steps; more sweeps cost less than the iterations they save)
+      CellDev& h = B.cells[c]->h;
+      if (its > kSlowSolve && h.nu < kSweepsMax) {
+        h.nu = std::min(kSweepsMax, h.nu + 2);
+        h.nu_f = h.nu;
+        if (g_verbose()) fprintf(stderr, "[mbx] cell %d: %d Krylov iterations, smoothing sweeps -> %d\n", c, its, h.nu);
+      }
+    }
     launch_direction<KT>(B.bl(), B.s);
     if (int e = B.gather()) return e;
     // step-length limiter: no scaled update larger than kStepLimit (potentials
@@ -908,7 +926,8 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.nlev = c->ld.n;
   h.lfuse = c->ld.lfuse;
   h.alpha = g_mg_alpha();
-  h.nu = 2;
+  h.nu = kSweepsMin;
+  h.nu_f = kSweepsMin;
   h.lv[0].nx = nx;
   h.lv[0].ny = ny;
   h.lv[0].nz = nz;
@@ -1153,11 +1172,11 @@ int mbx_cell_precond(mbx_cell* c, const double* cu, const double* pu, const doub
   HIPCHK(hipMemcpyAsync(c->h.dc, v, N16, hipMemcpyHostToDevice, c->s));
   if (c->mixed) {
     launch_convert<float>(b.bl(), VEC_W, 0, c->s);
-    launch_precond<float>(b.bl(), VEC_W, b.nu, -2, c->s);
+    launch_precond<float>(b.bl(), VEC_W, -2, c->s);
     launch_convert<float>(b.bl(), VEC_Z, 1, c->s);
   } else {
     launch_convert<double>(b.bl(), VEC_W, 0, c->s);
-    launch_precond<double>(b.bl(), VEC_W, b.nu, -2, c->s);
+    launch_precond<double>(b.bl(), VEC_W, -2, c->s);
     launch_convert<double>(b.bl(), VEC_Z, 1, c->s);
   }
   HIPCHK(hipMemcpyAsync(z, c->h.dc, N16, hipMemcpyDeviceToHost, c->s));

@@ -117,7 +117,7 @@ struct CellDev {
   void *cond_an, *cond_ca;           // KT potential-operator conductance per interface face
   double *cinv[2];                   // coarsest-level dense inverses (FP64), (3*ncell)^2 each
   double alpha;                      // coarse-correction scale
-  int nu, pad5;                      // smoothing sweeps (red+black pairs) per side
+  int nu, nu_f;                      // smoothing sweeps (red+black pairs) per side: launched levels / fused levels
   // scaled-operator constants
   double Kd;                         // kappa (1-t+) theta RT/(F h)
   double Gk, tth, Dh, tau, Ke, Gcol;

@@ -20,6 +20,7 @@ struct BatchLaunch {
   int maxlev;                            // max multigrid levels over the batch
   int maxfuse;                           // max first fused level over the batch
   size_t fused_lds;                      // LDS elements (KT) of the fused coarse cycle, max over the batch
+  int max_nu;                            // most smoothing sweeps any cell of the batch asks for
   const int2* lvl_blk[kMaxLevels];       // block tables over each level's cells (index >= 1)
   int lvl_nblk[kMaxLevels];
   const int2* lvl8_blk[kMaxLevels];      // block tables with 8 lanes per level cell (index >= 1)
@@ -68,6 +69,6 @@ void launch_outputs(const BatchLaunch& b, hipStream_t s);
 // multigrid preconditioner (mg.hip)
 template <typename KT> void launch_mg_setup(const BatchLaunch& b, hipStream_t s);
 // z = M^-1 v_src; need: GMRES state gate (>= 0 equal, -1 cycle end, -2 always)
-template <typename KT> void launch_precond(const BatchLaunch& b, int src, int nu, int need, hipStream_t s);
+template <typename KT> void launch_precond(const BatchLaunch& b, int src, int need, hipStream_t s);
 
 }  // namespace mbx

@@ -19,7 +19,6 @@
 // conductances) exactly representable on every level.
 #include <hip/hip_runtime.h>
 
-#include <cstdlib>
 
 #include "mbx_dev.h"
 #include "mbx_kernels.h"
@@ -484,10 +483,10 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int 
 // SM_CORR: neighbours corrected by alpha * (level-1 solution); else plain.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg0_smooth(CellDev* cells, const int2* __restrict__ blk, int op,
-                                                       int color, int mode, int need) {
+                                                       int color, int mode, int it, int need) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!cd.active) return;
+  if (!cd.active || it >= cd.nu) return;   // cells that asked for fewer sweeps skip this one
   C3 c;
   if (!color_cell(bb.y * kBlock + threadIdx.x, color, cd.nx, cd.ny, cd.nz, c)) return;
   const int i = c.x + cd.nx * (c.y + cd.ny * c.z);
@@ -608,10 +607,10 @@ __device__ inline void residual_cell(const LV<KT>& L, int c, const C3& q, KT (&r
 
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int2* __restrict__ blk, int l, int op,
-                                                       int color, int mode, int need) {
+                                                       int color, int mode, int it, int need) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!cd.active || l >= cd.lfuse) return;
+  if (!cd.active || l >= cd.lfuse || it >= cd.nu) return;
   const MGLevel& L = cd.lv[l];
   C3 q;
   if (!color_cell(bb.y * kBlock + threadIdx.x, color, L.nx, L.ny, L.nz, q)) return;
@@ -655,13 +654,14 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
 // read column-wise, coalesced).  Only the level-lfuse solution is written
 // back: the launched level above reads it for its coarse correction.
 template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int op, int nu, int need) {
+__global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int op, int need) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ci = blockIdx.x;
   if (ci >= ncells) return;
   const CellDev& cd = cells[ci];
   if (!gate(cd, need)) return;
   const int lf = cd.lfuse, lc = cd.nlev - 1;
+  const int nu = cd.nu_f;
   const KT alpha = (KT)cd.alpha;
   KT* const base = (KT*)smem;
   // LDS element offsets of level l's x, b and operator: levels lf..lc in order
@@ -841,48 +841,37 @@ void launch_mg_setup(const BatchLaunch& b, hipStream_t s) {
 }
 
 template <typename KT>
-static void smooth0(const BatchLaunch& b, int op, int color, int mode, int need, hipStream_t s) {
+static void smooth0(const BatchLaunch& b, int op, int color, int mode, int it, int need, hipStream_t s) {
   prof_begin(PK_SMOOTH0, s);
-  k_mg0_smooth<KT><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, need);
+  k_mg0_smooth<KT><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, it, need);
   if (prof_on(PK_SMOOTH0)) prof_end(PK_SMOOTH0, s, b.bytes_smooth0);
 }
 
 template <typename KT>
-static void smoothl(const BatchLaunch& b, int l, int op, int color, int mode, int need, hipStream_t s) {
-  k_mgl_smooth<KT><<<b.lvlh_nblk[l], kBlock, 0, s>>>(b.cells, b.lvlh_blk[l], l, op, color, mode, need);
+static void smoothl(const BatchLaunch& b, int l, int op, int color, int mode, int it, int need, hipStream_t s) {
+  k_mgl_smooth<KT><<<b.lvlh_nblk[l], kBlock, 0, s>>>(b.cells, b.lvlh_blk[l], l, op, color, mode, it, need);
 }
 
 // One V-cycle on operator op: nu red-black sweeps (red then black) down to
 // the fused levels, then the fused coarse cycle, then nu sweeps (black then
 // red) back up.  The first post-sweep applies the coarse correction lazily.
-// Sweep counts: nu on the voxel level, nu_c on the launched coarse levels,
-// nu_f inside the fused coarse cycle (MBX_MG_NU0 / MBX_MG_NUC / MBX_MG_NUF
-// override the defaults 2 / 2 / 2).
-static int env_int(const char* name, int def, int lo, int hi) {
-  const char* v = std::getenv(name);
-  if (!v) return def;
-  const int x = std::atoi(v);
-  return x < lo ? lo : (x > hi ? hi : x);
-}
-static int sweeps(int which) {
-  static const int n[3] = {env_int("MBX_MG_NU0", 2, 1, 8), env_int("MBX_MG_NUC", 2, 1, 8),
-                           env_int("MBX_MG_NUF", 2, 1, 8)};
-  return n[which];
-}
-
+// One V-cycle on operator op: red-black sweeps (red then black) down to the
+// fused levels, the fused coarse cycle, then sweeps (black then red) back up.
+// The first post-sweep applies the coarse correction lazily.  Each cell runs
+// its own number of sweeps (CellDev::nu, nu_f); the launches cover the most
+// any cell of the batch asks for and the others skip the surplus.
 template <typename KT>
-static void vcycle(const BatchLaunch& b, int op, int nu_unused, int need, hipStream_t s) {
-  (void)nu_unused;
+static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
   const int top = b.maxfuse;   // levels >= a cell's lfuse run inside k_mg_coarse_cycle
+  const int nu = b.max_nu;
   for (int l = 0; l < top; ++l) {
-    const int nu = sweeps(l == 0 ? 0 : 1);
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
-        smooth0<KT>(b, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, need, s);
-        smooth0<KT>(b, op, 1, SM_PLAIN, need, s);
+        smooth0<KT>(b, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, it, need, s);
+        smooth0<KT>(b, op, 1, SM_PLAIN, it, need, s);
       } else {
-        smoothl<KT>(b, l, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, need, s);
-        smoothl<KT>(b, l, op, 1, it == 0 ? SM_OWNZERO : SM_PLAIN, need, s);
+        smoothl<KT>(b, l, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, it, need, s);
+        smoothl<KT>(b, l, op, 1, it == 0 ? SM_OWNZERO : SM_PLAIN, it, need, s);
       }
     }
     if (l == 0)
@@ -890,34 +879,33 @@ static void vcycle(const BatchLaunch& b, int op, int nu_unused, int need, hipStr
     else
       k_mgl_restrict<KT><<<b.lvl8_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl8_blk[l + 1], l, op, need);
   }
-  k_mg_coarse_cycle<KT><<<b.ncell, kBlock, b.fused_lds * sizeof(KT), s>>>(b.cells, b.ncell, op, sweeps(2), need);
+  k_mg_coarse_cycle<KT><<<b.ncell, kBlock, b.fused_lds * sizeof(KT), s>>>(b.cells, b.ncell, op, need);
   for (int l = top - 1; l >= 0; --l) {
-    const int nu = sweeps(l == 0 ? 0 : 1);
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
-        smooth0<KT>(b, op, 1, it == 0 ? SM_CORR : SM_PLAIN, need, s);
-        smooth0<KT>(b, op, 0, SM_PLAIN, need, s);
+        smooth0<KT>(b, op, 1, it == 0 ? SM_CORR : SM_PLAIN, it, need, s);
+        smooth0<KT>(b, op, 0, SM_PLAIN, it, need, s);
       } else {
-        smoothl<KT>(b, l, op, 1, it == 0 ? SM_CORR : SM_PLAIN, need, s);
-        smoothl<KT>(b, l, op, 0, it == 0 ? SM_OWNCORR : SM_PLAIN, need, s);
+        smoothl<KT>(b, l, op, 1, it == 0 ? SM_CORR : SM_PLAIN, it, need, s);
+        smoothl<KT>(b, l, op, 0, it == 0 ? SM_OWNCORR : SM_PLAIN, it, need, s);
       }
     }
   }
 }
 
 template <typename KT>
-void launch_precond(const BatchLaunch& b, int src, int nu, int need, hipStream_t s) {
+void launch_precond(const BatchLaunch& b, int src, int need, hipStream_t s) {
   prof_begin(PK_PRECOND, s);
   k_pc_pre<KT><<<b.nblk, kBlock, 0, s>>>(b.cells, b.blk, src, need);
-  vcycle<KT>(b, 0, nu, need, s);
+  vcycle<KT>(b, 0, need, s);
   k_pc_mid<KT><<<b.nblk, kBlock, 0, s>>>(b.cells, b.blk, src, need);
-  vcycle<KT>(b, 1, nu, need, s);
+  vcycle<KT>(b, 1, need, s);
   if (prof_on(PK_PRECOND)) prof_end(PK_PRECOND, s, 0.0);
 }
 
 template void launch_mg_setup<float>(const BatchLaunch&, hipStream_t);
 template void launch_mg_setup<double>(const BatchLaunch&, hipStream_t);
-template void launch_precond<float>(const BatchLaunch&, int, int, int, hipStream_t);
-template void launch_precond<double>(const BatchLaunch&, int, int, int, hipStream_t);
+template void launch_precond<float>(const BatchLaunch&, int, int, hipStream_t);
+template void launch_precond<double>(const BatchLaunch&, int, int, hipStream_t);
 
 }  // namespace mbx
