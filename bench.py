@@ -208,8 +208,8 @@ def main():
     ap.add_argument("--mode", choices=["step", "serve"], default="step")
     ap.add_argument("--batch-cells", type=int, default=32)
     ap.add_argument("--batch-steps", type=int, default=2, help="timed batched steps (0: skip the batched run)")
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-capacity-requests", type=int, default=6,
+    ap.add_argument("--serve-requests", type=int, default=12)
+    ap.add_argument("--serve-capacity-requests", type=int, default=8,
                     help="requests of the closed burst that measures the server's capacity")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="offered arrival rate, requests/s")
     ap.add_argument("--budget-gb", type=float, default=200.0)
