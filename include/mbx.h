@@ -86,7 +86,8 @@ typedef struct {
   double res_tol;        /* scaled residual tolerance (default 1e-6 if <= 0) */
   double krylov_rtol;    /* floor of the GMRES relative tolerance (forcing term) (default 1e-6 if <= 0) */
   int newton_max;        /* Newton iteration cap (default 30 if <= 0) */
-  int krylov_max;        /* GMRES iteration cap per Newton iteration (default 2000 if <= 0) */
+  int krylov_max;        /* GMRES iteration cap per Newton iteration (default 600 if <= 0); at the cap the
+                            correction is taken as it stands (inexact Newton) */
 } mbx_params;
 
 typedef struct {

@@ -760,7 +760,7 @@ int mbx_params_default(mbx_params* p) {
   p->res_tol = 1e-6;
   p->krylov_rtol = 1e-6;
   p->newton_max = 30;
-  p->krylov_max = 2000;
+  p->krylov_max = 600;
   p->thermo = 1.0;
   return MBX_OK;
 }
@@ -787,7 +787,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   if (p.res_tol <= 0) p.res_tol = 1e-6;
   if (p.krylov_rtol <= 0) p.krylov_rtol = 1e-6;
   if (p.newton_max <= 0) p.newton_max = 30;
-  if (p.krylov_max <= 0) p.krylov_max = 2000;
+  if (p.krylov_max <= 0) p.krylov_max = 600;
   const int N = (int)N64;
   hipStream_t s = (hipStream_t)stream;
 
