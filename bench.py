@@ -208,8 +208,8 @@ def main():
     ap.add_argument("--mode", choices=["step", "serve"], default="step")
     ap.add_argument("--batch-cells", type=int, default=32)
     ap.add_argument("--batch-steps", type=int, default=2, help="timed batched steps (0: skip the batched run)")
-    ap.add_argument("--serve-requests", type=int, default=12)
-    ap.add_argument("--serve-capacity-requests", type=int, default=8,
+    ap.add_argument("--serve-requests", type=int, default=10)
+    ap.add_argument("--serve-capacity-requests", type=int, default=6,
                     help="requests of the closed burst that measures the server's capacity")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="offered arrival rate, requests/s")
     ap.add_argument("--budget-gb", type=float, default=200.0)
@@ -238,11 +238,11 @@ def main():
         out = {"metric": "served requests/s", "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
                "data": "synthetic", "config": {"workload": "parameter queries 48x48x120 .. 128x128x320, 12 x 5 s, "
                                                            "Poisson arrivals, continuous batching"}}
-        for prec in (["mixed", "fp64"] if args.precision == "both" else [args.precision]):
+        for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
             out[prec] = run_serving(prec, args.serve_rate, args.serve_requests, args.serve_capacity_requests, stream,
                                     args.budget_gb)
             print(f"[bench] serve {prec}: {json.dumps(out[prec])}", file=sys.stderr, flush=True)
-        main_prec = "mixed" if "mixed" in out else "fp64"
+        main_prec = "fp64" if "fp64" in out else "mixed"
         out["value"] = out[main_prec]["completed_per_s"]
         out["p50_s"], out["p99_s"] = out[main_prec]["p50_s"], out[main_prec]["p99_s"]
         print(json.dumps(out), flush=True)
