@@ -98,6 +98,7 @@ typedef struct {
   double du_final;       /* scaled max-norm of the last Newton update */
   double V;              /* cell voltage after the step, V */
   double wall_s;         /* wall time of the step, s */
+  int substeps;          /* implicit Euler steps the step took: 1, or 2 after a retried failure */
 } mbx_step_info;
 
 typedef struct mbx_cell mbx_cell;
@@ -124,9 +125,12 @@ int mbx_cell_create(const uint8_t *labels, int nx, int ny, int nz,
 void mbx_cell_destroy(mbx_cell *c);
 
 /* Advance one implicit Euler step of size dt (s), eq. 2.13: solve
- * F(u^{n+1}; u^n) = 0 by Newton + preconditioned GMRES.  Transactional: on
- * any error (MBX_ENEWTON, MBX_ENAN, MBX_EHIP) the state stays at u^n.
- * info may be null.  Blocks until the step is complete. */
+ * F(u^{n+1}; u^n) = 0 by Newton + preconditioned GMRES.  If Newton fails
+ * (no convergence within newton_max iterations, or no 10% decrease of the
+ * residual over 4 iterations after the 8th), the step is retried once as two
+ * steps of dt/2 (the same scheme on a finer time grid; info->substeps).
+ * Transactional: on any error (MBX_ENEWTON, MBX_ENAN, MBX_EHIP) the state
+ * stays at u^n.  info may be null.  Blocks until the step is complete. */
 int mbx_cell_step(mbx_cell *c, double dt, mbx_step_info *info);
 
 /* Change the applied current (A) for the following steps (parameter mu of

@@ -538,6 +538,9 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
 constexpr int kSweepsMin = 2;         // smoothing sweeps per side a cell starts with
 constexpr int kSweepsMax = 6;
 constexpr int kSlowSolve = 60;        // Krylov iterations of one correction that call for more smoothing
+constexpr int kStallMinIter = 8;      // Newton iterations before stagnation is tested
+constexpr size_t kStallWindow = 4;
+constexpr int kMaxHalvings = 1;       // a failed step is retried once, as two half steps
 constexpr double kEtaMax = 0.1;        // loosest GMRES relative tolerance of a Newton correction (FP64)
 constexpr double kEtaMaxMixed = 1e-4;  // ... in the mixed mode
 constexpr double kEwGamma = 0.9;
@@ -554,6 +557,7 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
   // FP32 Krylov cannot resolve relative residuals much below 1e-6
   const double eta_floor = B.cells[0]->p.krylov_rtol;
   std::vector<int> nit(nc, 0), kit(nc, 0);
+  std::vector<std::vector<double>> rhist(nc);   // accepted residual 2-norms
   for (int c = 0; c < nc; ++c) {
     mbx_cell* cl = B.cells[c];
     fill_step_constants(cl->h, dt);
@@ -703,7 +707,18 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
       const double dmx = std::max(du[c], dnm[c]);
       const double q = qconv[c];
       const double err = (q < 0.5) ? dmx * q / (1.0 - q) : dmx;
-      if (lam[c] == 1.0 && rmax[c] <= p.res_tol && (dmx <= p.newton_tol || err <= p.newton_tol)) st[c] = 0;
+      if (lam[c] == 1.0 && rmax[c] <= p.res_tol && (dmx <= p.newton_tol || err <= p.newton_tol)) {
+        st[c] = 0;
+        continue;
+      }
+      // stagnation: no 10% decrease of the residual 2-norm over the last
+      // kStallWindow iterations; give up early (the caller may split the step)
+      rhist[c].push_back(rn[c]);
+      const size_t h = rhist[c].size();
+      if (it >= kStallMinIter && h > kStallWindow && rn[c] > 0.9 * rhist[c][h - 1 - kStallWindow]) {
+        if (g_verbose()) fprintf(stderr, "[mbx] cell %d newton %d: stagnated\n", c, it);
+        st[c] = MBX_ENEWTON;
+      }
     }
   }
   // roll back failures, outputs for the converged cells
@@ -736,6 +751,101 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
 
 int run_step(Batch& B, double dt, int* status, mbx_step_info* infos) {
   return B.mixed ? newton<float>(B, dt, status, infos) : newton<double>(B, dt, status, infos);
+}
+
+int make_batch(mbx_cell* const* cells, int n, Batch*& out);
+
+// One step of dt for the given cells (one launch sequence for all of them).
+// Cells whose Newton iteration fails are rolled back to u^n and retried as
+// two steps of dt/2, recursively up to kMaxHalvings times: the same implicit
+// Euler scheme on a finer time grid.  A cell that still fails is restored to
+// u^n (transactional).  infos accumulate iterations over the sub-steps.
+int step_recover(std::vector<mbx_cell*> cells, double dt, int* status, mbx_step_info* infos, int depth) {
+  const int n = (int)cells.size();
+  Batch one;
+  Batch* B = nullptr;
+  if (n == 1) {
+    one = single(cells[0]);
+    B = &one;
+  } else if (int e = make_batch(cells.data(), n, B)) {
+    return e;
+  }
+  std::vector<mbx_step_info> inf(n);
+  if (int e = run_step(*B, dt, status, inf.data())) return e;
+  for (int i = 0; i < n; ++i) {
+    inf[i].substeps = 1;
+    if (depth == 0) {
+      infos[i] = inf[i];
+    } else {
+      infos[i].newton_iters += inf[i].newton_iters;
+      infos[i].krylov_iters += inf[i].krylov_iters;
+    }
+  }
+  std::vector<int> fail_idx;
+  for (int i = 0; i < n; ++i)
+    if (status[i] == MBX_ENEWTON || status[i] == MBX_ENAN) fail_idx.push_back(i);
+  if (fail_idx.empty() || depth >= kMaxHalvings) return MBX_OK;
+  // retry the failed cells as two half steps, from a host copy of u^n
+  std::vector<mbx_cell*> sub;
+  std::vector<std::vector<double>> save(fail_idx.size() * 3);
+  for (size_t k = 0; k < fail_idx.size(); ++k) {
+    mbx_cell* c = cells[fail_idx[k]];
+    sub.push_back(c);
+    save[3 * k].resize(c->N);
+    save[3 * k + 1].resize(c->N);
+    save[3 * k + 2].resize(std::max(c->F_an, 1));
+    if (int e = mbx_cell_get_state(c, save[3 * k].data(), save[3 * k + 1].data(), save[3 * k + 2].data(), 0)) return e;
+  }
+  if (g_verbose()) fprintf(stderr, "[mbx] %zu cell(s) failed at dt %g: retrying as two steps of %g\n", sub.size(), dt, dt / 2);
+  const int m = (int)sub.size();
+  std::vector<int> sst(m, 0), ok(m, 1);
+  std::vector<mbx_step_info> sinf(m);
+  for (int half = 0; half < 2; ++half) {
+    std::vector<mbx_cell*> run;
+    std::vector<int> map;
+    for (int k = 0; k < m; ++k)
+      if (ok[k]) {
+        run.push_back(sub[k]);
+        map.push_back(k);
+      }
+    if (run.empty()) break;
+    std::vector<int> rst(run.size(), 0);
+    std::vector<mbx_step_info> rinf(run.size());
+    if (int e = step_recover(run, dt / 2, rst.data(), rinf.data(), depth + 1)) return e;
+    for (size_t j = 0; j < run.size(); ++j) {
+      const int k = map[j];
+      sinf[k].newton_iters += rinf[j].newton_iters;
+      sinf[k].krylov_iters += rinf[j].krylov_iters;
+      sinf[k].substeps += rinf[j].substeps;
+      sinf[k].res0 = half == 0 ? rinf[j].res0 : sinf[k].res0;
+      sinf[k].res_final = rinf[j].res_final;
+      sinf[k].du_final = rinf[j].du_final;
+      sinf[k].V = rinf[j].V;
+      if (rst[j] != MBX_OK) {
+        ok[k] = 0;
+        sst[k] = rst[j];
+      }
+    }
+  }
+  for (int k = 0; k < m; ++k) {
+    const int i = fail_idx[k];
+    mbx_step_info& o = infos[i];
+    o.newton_iters += sinf[k].newton_iters;
+    o.krylov_iters += sinf[k].krylov_iters;
+    if (ok[k]) {
+      status[i] = MBX_OK;
+      o.substeps = sinf[k].substeps;
+      o.res_final = sinf[k].res_final;
+      o.du_final = sinf[k].du_final;
+      o.V = sinf[k].V;
+    } else {
+      status[i] = sst[k];
+      mbx_cell* c = sub[k];
+      if (int e = mbx_cell_set_state(c, save[3 * k].data(), save[3 * k + 1].data(), save[3 * k + 2].data(), 0))
+        return e;
+    }
+  }
+  return MBX_OK;
 }
 
 int sync_outputs(mbx_cell* c) {
@@ -1022,9 +1132,11 @@ void mbx_cell_destroy(mbx_cell* c) {
 int mbx_cell_step(mbx_cell* c, double dt, mbx_step_info* info) {
   if (!c) return fail(MBX_EINVAL, "null cell");
   if (!(std::isfinite(dt) && dt > 0.0)) return fail(MBX_EINVAL, "dt must be finite and > 0");
-  Batch b = single(c);
   int st = 0;
-  if (int e = run_step(b, dt, &st, info)) return e;
+  mbx_step_info tmp{};
+  const auto t0 = std::chrono::steady_clock::now();
+  if (int e = step_recover({c}, dt, &st, info ? info : &tmp, 0)) return e;
+  if (info) info->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (st == MBX_ENEWTON) return fail(MBX_ENEWTON, "Newton did not converge; state left at u^n");
   if (st == MBX_ENAN) return fail(MBX_ENAN, "non-finite residual; state left at u^n");
   return st;
@@ -1044,9 +1156,8 @@ int mbx_batch_step(mbx_cell* const* cells, int n, double dt, int* status_out, mb
   // (a server's worker and a caller) run one at a time
   static std::mutex mu;
   std::lock_guard<std::mutex> lk(mu);
-  Batch* b = nullptr;
-  if (int e = make_batch(cells, n, b)) return e;
-  return run_step(*b, dt, status_out, infos);
+  std::vector<mbx_step_info> tmp(infos ? 0 : n);
+  return step_recover(std::vector<mbx_cell*>(cells, cells + n), dt, status_out, infos ? infos : tmp.data(), 0);
 }
 
 int mbx_cell_set_current(mbx_cell* c, double I_app) {

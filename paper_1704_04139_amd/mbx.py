@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("newton_iters", _i), ("krylov_iters", _i), ("res0", _d), ("res_final", _d),
-                ("du_final", _d), ("V", _d), ("wall_s", _d)]
+                ("du_final", _d), ("V", _d), ("wall_s", _d), ("substeps", _i)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
