@@ -36,6 +36,28 @@ HBM_PEAK_GBS = 8000.0
 PROFILED_KERNEL = "smooth0"     # the kernel class with the largest share of GPU time
 
 
+def measured_traffic(precision):
+    """HBM bytes per launch of the profiled kernel from the committed counter
+    summary (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    the summary is for another precision or the kernel source has changed."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "mg0_smooth_traffic.txt")
+    try:
+        kv = {}
+        for ln in open(path):
+            if ":" in ln:
+                k, v = ln.split(":", 1)
+                kv[k.strip()] = v.split()[0] if v.split() else ""
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_1704_04139_amd/csrc/mg.hip", "paper_1704_04139_amd/csrc/mbx_dev.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if kv.get("precision") != precision or kv.get("source_sha256") != h.hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def run_gpu(w, precision, steps, warmup, stream):
     import torch
     from paper_1704_04139_amd import mbx
@@ -279,7 +301,8 @@ def main():
         "newton_per_step": r["newton_per_step"],
         "krylov_per_step": r["krylov_per_step"],
         "roofline": {"bound": "hbm", "kernel": PROFILED_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": measured_traffic(main_prec),
                      "launches": k["launches"], "avg_us": 1e3 * k["ms"] / max(k["launches"], 1),
                      "bytes_per_launch": k["bytes"] / max(k["launches"], 1)},
     }

@@ -292,10 +292,12 @@ void mbx_server_destroy(mbx_server *s);
  * application; 0 stops timing) is bracketed by a pair of HIP events recorded
  * on the stream it runs on, together with the launch's algorithmic bytes
  * (every array element the operation must read or write, counted once).
- * mbx_profile clears earlier records.  mbx_profile_read waits for the
- * recorded events and returns the number of timed launches, their summed
- * duration (ms) and summed algorithmic bytes.  Timing adds two event
- * records per launch; it is not meant to be left on in production. */
+ * Class 3 brackets each group of back-to-back half sweeps of one V-cycle side
+ * with one event pair.  mbx_profile clears earlier records.
+ * mbx_profile_read waits for the recorded events and returns the number of
+ * timed launches, their summed duration (ms) and summed algorithmic bytes.
+ * Timing adds event records to the stream; it is not meant to be left on in
+ * production. */
 int mbx_profile(int kernel);
 int mbx_profile_read(int64_t *launches, double *total_ms, double *total_bytes);
 

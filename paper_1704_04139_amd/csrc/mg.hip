@@ -842,9 +842,7 @@ void launch_mg_setup(const BatchLaunch& b, hipStream_t s) {
 
 template <typename KT>
 static void smooth0(const BatchLaunch& b, int op, int color, int mode, int it, int need, hipStream_t s) {
-  prof_begin(PK_SMOOTH0, s);
   k_mg0_smooth<KT><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, it, need);
-  if (prof_on(PK_SMOOTH0)) prof_end(PK_SMOOTH0, s, b.bytes_smooth0);
 }
 
 template <typename KT>
@@ -865,6 +863,7 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
   const int top = b.maxfuse;   // levels >= a cell's lfuse run inside k_mg_coarse_cycle
   const int nu = b.max_nu;
   for (int l = 0; l < top; ++l) {
+    if (l == 0) prof_begin(PK_SMOOTH0, s);   // the 2 nu level-0 half sweeps run back to back
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
         smooth0<KT>(b, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, it, need, s);
@@ -874,6 +873,7 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
         smoothl<KT>(b, l, op, 1, it == 0 ? SM_OWNZERO : SM_PLAIN, it, need, s);
       }
     }
+    if (l == 0 && prof_on(PK_SMOOTH0)) prof_end_n(PK_SMOOTH0, s, 2.0 * nu * b.bytes_smooth0, 2 * nu);
     if (l == 0)
       k_mg0_restrict<KT><<<b.lvl8_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl8_blk[1], op, need);
     else
@@ -881,6 +881,7 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
   }
   k_mg_coarse_cycle<KT><<<b.ncell, kBlock, b.fused_lds * sizeof(KT), s>>>(b.cells, b.ncell, op, need);
   for (int l = top - 1; l >= 0; --l) {
+    if (l == 0) prof_begin(PK_SMOOTH0, s);
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
         smooth0<KT>(b, op, 1, it == 0 ? SM_CORR : SM_PLAIN, it, need, s);
@@ -890,6 +891,7 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
         smoothl<KT>(b, l, op, 0, it == 0 ? SM_OWNCORR : SM_PLAIN, it, need, s);
       }
     }
+    if (l == 0 && prof_on(PK_SMOOTH0)) prof_end_n(PK_SMOOTH0, s, 2.0 * nu * b.bytes_smooth0, 2 * nu);
   }
 }
 

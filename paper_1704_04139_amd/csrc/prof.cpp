@@ -12,6 +12,7 @@ namespace {
 struct Rec {
   hipEvent_t a, b;
   double bytes;
+  int launches;
 };
 
 std::mutex g_mu;
@@ -42,16 +43,18 @@ void prof_begin(int k, hipStream_t s) {
   if (g_open) (void)hipEventRecord(g_open, s);
 }
 
-void prof_end(int k, hipStream_t s, double bytes) {
+void prof_end_n(int k, hipStream_t s, double bytes, int launches) {
   if (!prof_on(k)) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_open) return;
   hipEvent_t e = take_event();
   if (!e) return;
   (void)hipEventRecord(e, s);
-  g_recs.push_back(Rec{g_open, e, bytes});
+  g_recs.push_back(Rec{g_open, e, bytes, launches});
   g_open = nullptr;
 }
+
+void prof_end(int k, hipStream_t s, double bytes) { prof_end_n(k, s, bytes, 1); }
 
 }  // namespace mbx
 
@@ -72,14 +75,16 @@ int mbx_profile(int kernel) {
 int mbx_profile_read(int64_t* launches, double* total_ms, double* total_bytes) {
   std::lock_guard<std::mutex> lk(mbx::g_mu);
   double ms = 0.0, by = 0.0;
+  int64_t n = 0;
   for (auto& r : mbx::g_recs) {
     if (hipEventSynchronize(r.b) != hipSuccess) return MBX_EHIP;
     float t = 0.0f;
     if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return MBX_EHIP;
     ms += t;
     by += r.bytes;
+    n += r.launches;
   }
-  if (launches) *launches = (int64_t)mbx::g_recs.size();
+  if (launches) *launches = n;
   if (total_ms) *total_ms = ms;
   if (total_bytes) *total_bytes = by;
   return MBX_OK;

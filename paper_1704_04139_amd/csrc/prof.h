@@ -13,5 +13,9 @@ bool prof_on(int k);
 // algorithmic bytes.
 void prof_begin(int k, hipStream_t s);
 void prof_end(int k, hipStream_t s, double bytes);
+// Closes a bracket around `launches` back-to-back launches of class k
+// (their summed algorithmic bytes): the per-launch average then carries one
+// event pair's overhead divided among them.
+void prof_end_n(int k, hipStream_t s, double bytes, int launches);
 
 }  // namespace mbx
