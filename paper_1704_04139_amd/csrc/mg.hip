@@ -232,11 +232,17 @@ struct LV {
   KT* x;
   KT* b;
   const KT* A;
+  int op;   // 0: concentration operator (same-slot couplings only), 1: potential operator
 };
 template <typename KT>
 __device__ inline LV<KT> view(const MGLevel& L, int op) {
-  return LV<KT>{L.nx, L.ny, L.nz, L.ncell, (KT*)L.x, (KT*)L.b, (const KT*)L.op[op]};
+  return LV<KT>{L.nx, L.ny, L.nz, L.ncell, (KT*)L.x, (KT*)L.b, (const KT*)L.op[op], op};
 }
+
+// Couplings that are zero by construction and never loaded: the
+// concentration operator couples only equal slots (no cross-phase transport);
+// anode and cathode never share a face, so slots 1 and 2 are never coupled.
+__host__ __device__ constexpr bool cross_zero(int s, int t) { return (s == 1 && t == 2) || (s == 2 && t == 1); }
 
 template <typename KT>
 struct CoarseRow {
@@ -258,18 +264,23 @@ __device__ inline void gather_coarse(const LV<KT>& L, const LV<KT>& Lp, KT alpha
   int nb[6];
   bool ex[6];
   neighbours6(C, q, L.nx, L.ny, L.nz, nb, ex);
+  const bool cross = L.op != 0;
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     R.E[s] = A[s * n + C];
-    R.X[s] = A[(3 + s) * n + C];
+    R.X[s] = (cross && s != 2) ? A[(3 + s) * n + C] : (KT)0;   // X pairs (0,1) (0,2) (1,2)
     R.b[s] = b[s * n + C];
   }
 #pragma unroll
   for (int dir = 0; dir < 3; ++dir)
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const KT gp = A[(6 + dir * 9 + k) * n + C];
-      const KT gm = A[(6 + dir * 9 + k) * n + nb[2 * dir + 1]];
+      const int s = k / 3, t = k % 3;
+      KT gp = (KT)0, gm = (KT)0;
+      if (s == t || (cross && !cross_zero(s, t))) {
+        gp = A[(6 + dir * 9 + k) * n + C];
+        gm = A[(6 + dir * 9 + k) * n + nb[2 * dir + 1]];
+      }
       R.Gp[dir][k] = ex[2 * dir] ? gp : (KT)0;
       R.Gm[dir][k] = ex[2 * dir + 1] ? gm : (KT)0;
     }
@@ -405,18 +416,12 @@ __global__ void __launch_bounds__(kBlock) k_mg_assemble(CellDev* cells, const in
 
 // Dense inverse of the coarsest operator (one block per cell, FP64,
 // Gauss-Jordan without pivoting: the operator is symmetric positive
-// definite; empty slots get an identity row).
+// definite; empty slots get an identity row).  Matrices of up to
+// kCoarseLdsDim rows are assembled and inverted in LDS and then written out.
+constexpr int kCoarseLdsDim = 88;   // 88^2 doubles = 61,952 B of LDS
+
 template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int ncells, int op) {
-  const int ci = blockIdx.x;
-  if (ci >= ncells) return;
-  const CellDev& cd = cells[ci];
-  if (!cd.active) return;
-  const int lc = cd.nlev - 1;
-  const MGLevel& L = cd.lv[lc];
-  const OpV<KT> A{(const KT*)L.op[op], L.ncell};
-  const int n = 3 * L.ncell;
-  double* M = cd.cinv[op];
+__device__ inline void coarse_assemble(const MGLevel& L, const OpV<KT>& A, double* M, int n) {
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = 0.0;
   __syncthreads();
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
@@ -452,26 +457,48 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int 
     M[(size_t)r * n + r] = D > 0.0 ? D : 1.0;
   }
   __syncthreads();
-  // in-place Gauss-Jordan inversion
-  __shared__ double piv;
+}
+
+// In-place Gauss-Jordan inversion of the n x n matrix M (all threads).
+__device__ inline void gauss_jordan(double* M, int n, double* piv) {
   for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) piv = M[(size_t)k * n + k];
+    if (threadIdx.x == 0) *piv = M[(size_t)k * n + k];
     __syncthreads();
-    const double inv = 1.0 / piv;
+    const double inv = 1.0 / *piv;
     for (int j = threadIdx.x; j < n; j += blockDim.x) M[(size_t)k * n + j] = (j == k ? inv : M[(size_t)k * n + j] * inv);
     __syncthreads();
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
       const int i = e / n, j = e % n;
-      if (i == k) continue;
-      const double f = M[(size_t)i * n + k];
-      if (j == k)
-        continue;
-      M[(size_t)i * n + j] -= f * M[(size_t)k * n + j];
+      if (i == k || j == k) continue;   // row k and column k are read only in this pass
+      M[(size_t)i * n + j] -= M[(size_t)i * n + k] * M[(size_t)k * n + j];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x)
       if (i != k) M[(size_t)i * n + k] = -M[(size_t)i * n + k] * M[(size_t)k * n + k];
     __syncthreads();
+  }
+}
+
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int ncells, int op) {
+  __shared__ double Ms[kCoarseLdsDim * kCoarseLdsDim];
+  __shared__ double piv;
+  const int ci = blockIdx.x;
+  if (ci >= ncells) return;
+  const CellDev& cd = cells[ci];
+  if (!cd.active) return;
+  const int lc = cd.nlev - 1;
+  const MGLevel& L = cd.lv[lc];
+  const OpV<KT> A{(const KT*)L.op[op], L.ncell};
+  const int n = 3 * L.ncell;
+  double* M = cd.cinv[op];
+  if (n <= kCoarseLdsDim) {
+    coarse_assemble<KT>(L, A, Ms, n);
+    gauss_jordan(Ms, n, &piv);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = Ms[e];
+  } else {
+    coarse_assemble<KT>(L, A, M, n);
+    gauss_jordan(M, n, &piv);
   }
 }
 
@@ -675,7 +702,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
   auto lds_level = [&](int l) {
     const MGLevel& G = cd.lv[l];
     const size_t o = offset(l), n = G.ncell;
-    return LV<KT>{G.nx, G.ny, G.nz, G.ncell, base + o, base + o + 3 * n, base + o + 6 * n};
+    return LV<KT>{G.nx, G.ny, G.nz, G.ncell, base + o, base + o + 3 * n, base + o + 6 * n, op};
   };
   // stage: operator op of every fused level but the coarsest, right-hand side of level lf
   for (int l = lf; l < lc; ++l) {
