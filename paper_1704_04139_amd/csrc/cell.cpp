@@ -66,6 +66,12 @@ double g_mg_alpha() {
   const char* e = std::getenv("MBX_MG_ALPHA");
   return e ? std::atof(e) : 1.8;
 }
+// smoothing sweeps a new cell starts with (MBX_MG_NU overrides the default 2)
+int g_sweeps_min() {
+  const char* e = std::getenv("MBX_MG_NU");
+  const int v = e ? std::atoi(e) : 2;
+  return v < 1 ? 1 : (v > 6 ? 6 : v);
+}
 constexpr int kGather = RED_NSLOT + CTL_NSLOT;
 uint64_t g_next_id = 1;
 
@@ -535,8 +541,7 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
 }
 
 // ------------------------------------------------------------------ Newton
-constexpr int kSweepsMin = 2;         // smoothing sweeps per side a cell starts with
-constexpr int kSweepsMax = 6;
+constexpr int kSweepsMax = 6;         // most smoothing sweeps per side the autotuning gives a cell
 constexpr int kSlowSolve = 60;        // Krylov iterations of one correction that call for more smoothing
 constexpr int kStallMinIter = 8;      // Newton iterations before stagnation is tested
 constexpr size_t kStallWindow = 4;
@@ -1036,8 +1041,8 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.nlev = c->ld.n;
   h.lfuse = c->ld.lfuse;
   h.alpha = g_mg_alpha();
-  h.nu = kSweepsMin;
-  h.nu_f = kSweepsMin;
+  h.nu = g_sweeps_min();
+  h.nu_f = h.nu;
   h.lv[0].nx = nx;
   h.lv[0].ny = ny;
   h.lv[0].nz = nz;

@@ -105,6 +105,31 @@ __device__ inline KT fine_extra(const CellDev& cd, int op, int L, int z) {
   return (L == ANODE && z == 0) ? (KT)cd.Gcol : (KT)0;
 }
 
+// Interface part of the concentration operator's diagonal at voxel i, face
+// (neighbour label Lk, direction d from i): the own-concentration derivative
+// of the Butler-Volmer / plating molar flux through that face, in the rows of
+// the preconditioned system (solid rows as they are, pore rows after the
+// migration row operation, which scales them by -(1 - t+)).  Negative values
+// are dropped so the block stays positive definite.  Near a depleted particle
+// surface the open-circuit-potential slope makes this term dominate the row.
+template <typename KT>
+__device__ inline KT c_iface_term(const CellDev& cd, int L, int Lk, uint32_t mi, uint32_t mk, int d) {
+  const bool iface = (L == PORE) != (Lk == PORE);
+  if (!iface) return (KT)0;
+  const bool pore_side = L == PORE;
+  const uint32_t f = face_rank(pore_side ? mk : mi, pore_side ? (d ^ 1) : d);
+  const bool an = (pore_side ? Lk : L) == ANODE;
+  const KT* co = an ? (const KT*)cd.coef_an + 5 * (size_t)f : (const KT*)cd.coef_ca + 3 * (size_t)f;
+  KT v;
+  if (pore_side) {
+    const KT d_ce = co[1] + (an ? co[3] : (KT)0);
+    v = (KT)(cd.tau - cd.Ke) * d_ce;
+  } else {
+    v = (KT)cd.Ks[L == CATHODE] * co[0];
+  }
+  return v > (KT)0 ? v : (KT)0;
+}
+
 __device__ inline int fine_nbr(int i, const C3& c, int nx, int ny, int nz, int d) {
   switch (d) {
     case 0: return c.x > 0 ? i - 1 : -1;
@@ -178,6 +203,7 @@ __device__ inline void voxel_row(const CellDev& cd, int op, int i, const C3& c, 
   }
   const int L = lab_of(mi);
   KT g[6];
+  KT dint = (KT)0;   // interface part of the concentration diagonal
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     const int Lk = lab_of(mk[j]);
@@ -185,6 +211,8 @@ __device__ inline void voxel_row(const CellDev& cd, int op, int i, const C3& c, 
     KT v;
     if (op == 0) {
       v = L == Lk ? (KT)(L == PORE ? cd.Dh : cd.Dsh[L == CATHODE]) : (KT)0;
+      const KT t = c_iface_term<KT>(cd, L, Lk, mi, mk[j], d);
+      dint += ex[j] ? t : (KT)0;
     } else {
       const bool iface = (L == PORE) != (Lk == PORE);
       const bool pore_side = L == PORE;
@@ -212,7 +240,7 @@ __device__ inline void voxel_row(const CellDev& cd, int op, int i, const C3& c, 
       xk[j] += ex[j] ? alpha * v : (KT)0;
     }
   }
-  D = op == 0 ? (KT)1 : ((L == ANODE && c.z == 0) ? (KT)cd.Gcol : (KT)0);
+  D = op == 0 ? (KT)1 + dint : ((L == ANODE && c.z == 0) ? (KT)cd.Gcol : (KT)0);
   S = (KT)0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
@@ -345,6 +373,14 @@ __global__ void __launch_bounds__(kBlock) k_mg_assemble0(CellDev* cells, const i
         const int Li = lab_of(mi);
         const C3 fc{fx, fy, fz};
         E[Li] += fine_extra<KT>(cd, op, Li, fz);
+        if (op == 0)   // interface part of the concentration diagonal, all six faces
+          for (int d = 0; d < 6; ++d) {
+            const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
+            if (k >= 0) {
+              const uint32_t mk = cd.meta[k];
+              E[Li] += c_iface_term<KT>(cd, Li, lab_of(mk), mi, mk, d);
+            }
+          }
         for (int d = 1; d < 6; d += 2) {   // + directions only: each face counted once
           const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
           if (k < 0) continue;
