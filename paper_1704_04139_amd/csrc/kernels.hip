@@ -760,13 +760,19 @@ __global__ void __launch_bounds__(kBlock) k_trial(CellDev* cells, const int2* __
     const uint32_t mi = cd.meta[i];
     const int L = lab_of(mi);
     const double lam = cd.lam;
-    const double c = cd.c[i] + lam * cd.dc[i];
+    const double c0 = cd.c[i];
+    const double cref = cref_of(cd, L);
+    // fraction to the boundary, per voxel: a concentration moves at most 90%
+    // of the way to 0 (or, in a solid, to c_max) in one iteration, so that a
+    // few voxels near depletion do not shrink the whole step
+    double c = c0 + lam * cd.dc[i];
+    c = fmax(c, kToBoundary * c0);
+    if (L != PORE) c = fmin(c, cref - kToBoundary * (cref - c0));
     const double p = cd.phi[i] + lam * cd.dp[i];
     cd.c_try[i] = c;
     cd.phi_try[i] = p;
-    const double cref = cref_of(cd, L);
     if (!(c > 0.0) || !isfinite(p) || (L != PORE && !(c < cref))) bad += 1.0;
-    dmax = fmax(fabs(lam * cd.dc[i]) / cref, fabs(lam * cd.dp[i]) / cd.VT);
+    dmax = fmax(fabs(c - c0) / cref, fabs(lam * cd.dp[i]) / cd.VT);
     if (!isfinite(dmax)) bad += 1.0;
     if (L == ANODE && !cd.elim_n) {
       const uint32_t cnt = __popc(mask_of(mi));

@@ -33,6 +33,7 @@ constexpr int kMaxLevels = 12;
 constexpr int kCoarseMaxCells = 64;
 constexpr int kFuseMaxCells = 256;    // levels this small run inside one workgroup per cell
 constexpr size_t kFusedLdsBytes = 60 * 1024;   // LDS the fused levels may stage
+constexpr double kToBoundary = 0.1;   // a Newton update leaves at least this fraction of the distance to a bound
 constexpr int kOpStride = 33;   // per coarse cell: E[3], X[3], G[3 dirs][3][3] (SoA)
 struct MGLevel {
   int nx, ny, nz, ncell;
