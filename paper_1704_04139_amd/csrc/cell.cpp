@@ -170,7 +170,7 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   L.add(5 * kt * std::max(F_an, 1));          // 17 coef_an
   L.add(3 * kt * std::max(F_ca, 1));          // 18 coef_ca
   L.add(kt * (size_t)N);                      // 19 wpore
-  L.add(0);                                   // 20 (unused)
+  L.add(kt * (size_t)N);                      // 20 dint
   L.add((size_t)(m + 1) * 2 * N * kt);        // 21 Vb
   for (int k = 0; k < 3; ++k) L.add(2 * (size_t)N * kt);  // 22..24 w z b
   L.add(2 * (size_t)N * 8);                   // 25 x (FP64)
@@ -300,7 +300,10 @@ struct Batch {
       b.bytes_residual[0] += 44.0 * N + 24.0 * Fa;
       b.bytes_residual[1] += 44.0 * N + 24.0 * Fa + kt * N + (6.0 * kt + 16.0) * Fa + 4.0 * kt * Fc;
       b.bytes_matvec += (4.0 + 5.0 * kt) * N + 5.0 * kt * Fa + 3.0 * kt * Fc;
-      b.bytes_smooth0 += (4.0 + 1.5 * kt) * N + kt * (Fa + Fc);
+      // one half sweep: meta of all voxels, x of the other colour, b of its own,
+      // the new x; averaged over the two operators: interface conductances
+      // (potential operator) and the per-voxel interface diagonal (concentration)
+      b.bytes_smooth0 += (4.0 + 1.5 * kt) * N + 0.5 * kt * (Fa + Fc) + 0.25 * kt * N;
     }
     b.cells = d_desc;
     // a single cell needs no block tables: kernels map block b to {0, b}
@@ -1018,6 +1021,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.coef_an = b + L.off[17];
   h.coef_ca = b + L.off[18];
   h.wpore = b + L.off[19];
+  h.dint = b + L.off[20];
   h.Vb = b + L.off[21];
   h.w = b + L.off[22];
   h.z = b + L.off[23];

@@ -95,6 +95,7 @@ struct CellDev {
   void *Vb;                          // KT: (m+1) Krylov basis vectors of 2N
   void *w, *z, *b;                   // KT: 2N each (Krylov work vector, preconditioned vector, rhs)
   double *x;                         // 2N: GMRES iterate, FP64 in both modes
+  void *dint;                        // KT: N, interface part of the concentration preconditioner's diagonal
   double *part;                      // nblk * kPartStride partial sums
   unsigned *ticket;                  // one reduction ticket
   double *red;                       // RED_NSLOT outputs (device-written)

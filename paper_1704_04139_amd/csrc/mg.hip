@@ -203,7 +203,8 @@ __device__ inline void voxel_row(const CellDev& cd, int op, int i, const C3& c, 
   }
   const int L = lab_of(mi);
   KT g[6];
-  KT dint = (KT)0;   // interface part of the concentration diagonal
+  // interface part of the concentration diagonal (per voxel, from the setup)
+  const KT dint = op == 0 ? ((const KT*)cd.dint)[i] : (KT)0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     const int Lk = lab_of(mk[j]);
@@ -211,8 +212,6 @@ __device__ inline void voxel_row(const CellDev& cd, int op, int i, const C3& c, 
     KT v;
     if (op == 0) {
       v = L == Lk ? (KT)(L == PORE ? cd.Dh : cd.Dsh[L == CATHODE]) : (KT)0;
-      const KT t = c_iface_term<KT>(cd, L, Lk, mi, mk[j], d);
-      dint += ex[j] ? t : (KT)0;
     } else {
       const bool iface = (L == PORE) != (Lk == PORE);
       const bool pore_side = L == PORE;
@@ -373,14 +372,18 @@ __global__ void __launch_bounds__(kBlock) k_mg_assemble0(CellDev* cells, const i
         const int Li = lab_of(mi);
         const C3 fc{fx, fy, fz};
         E[Li] += fine_extra<KT>(cd, op, Li, fz);
-        if (op == 0)   // interface part of the concentration diagonal, all six faces
+        if (op == 0) {   // interface part of the concentration diagonal, all six faces
+          KT di = (KT)0;
           for (int d = 0; d < 6; ++d) {
             const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
             if (k >= 0) {
               const uint32_t mk = cd.meta[k];
-              E[Li] += c_iface_term<KT>(cd, Li, lab_of(mk), mi, mk, d);
+              di += c_iface_term<KT>(cd, Li, lab_of(mk), mi, mk, d);
             }
           }
+          E[Li] += di;
+          ((KT*)cd.dint)[i] = di;   // for the level-0 smoother and restriction
+        }
         for (int d = 1; d < 6; d += 2) {   // + directions only: each face counted once
           const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
           if (k < 0) continue;
