@@ -211,13 +211,14 @@ def run_serving(precision, rate_offered, n_req, n_cap, stream, budget_gb):
     st = srv.stats()
     srv.close()
     lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+    status = [int(i["status"]) for i in infos]
     span = max(i["t_done"] for i in infos) - base
     ok = [i for i in infos if i["status"] == mbx.MBX_REQ_DONE]
     return {"precision": precision, "capacity_dofsteps_per_s": cap, "offered_rate_hz": rate_offered,
             "rho_offered": rho_offered, "rate_hz": rate, "rho": rate * mean_req / cap, "requests": n_req,
             "completed": len(ok), "completed_per_s": len(ok) / span, "p50_s": float(np.percentile(lat, 50)),
             "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()), "max_s": float(lat.max()),
-            "busy_frac": st["busy_s"] / span, "batches": st["batches"]}
+            "busy_frac": st["busy_s"] / span, "batches": st["batches"], "status": status}
 
 
 def main():

@@ -81,6 +81,7 @@ struct mbx_server {
   std::condition_variable idle_cv;   // drain waiters
   std::deque<Request*> queue;
   std::vector<Request*> running;     // touched by the worker only (read under mu by stats)
+  int admitting = 0;                 // taken off the queue, cell not created yet (under mu)
   std::unordered_map<int64_t, std::unique_ptr<Request>> all;
   int64_t next_id = 1;
   bool stop = false;
@@ -121,7 +122,7 @@ void mbx_server::loop() {
     std::vector<Request*> admit;
     {
       std::unique_lock<std::mutex> lk(mu);
-      if (running.empty() && queue.empty()) idle_cv.notify_all();
+      if (running.empty() && queue.empty() && admitting == 0) idle_cv.notify_all();
       cv.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
       if (stop) break;
       // first-come first-served: the head waits until it fits
@@ -131,6 +132,7 @@ void mbx_server::loop() {
         used += r->footprint;
         admit.push_back(r);
       }
+      admitting += (int)admit.size();
     }
     for (Request* r : admit) {
       const int rc = mbx_cell_create(r->labels.data(), r->nx, r->ny, r->nz, &r->p, stream, &r->cell);
@@ -138,6 +140,8 @@ void mbx_server::loop() {
         r->err = mbx_last_error();
         r->cell = nullptr;
         retire(r, rc);
+        std::lock_guard<std::mutex> lk(mu);
+        --admitting;
         continue;
       }
       std::vector<uint8_t>().swap(r->labels);   // the cell holds its own copy
@@ -148,6 +152,7 @@ void mbx_server::loop() {
       r->info.t_admit = now();
       r->info.n_vox = N;
       running.push_back(r);
+      --admitting;
     }
     if (running.empty()) continue;
     const int n = (int)running.size();
@@ -270,7 +275,7 @@ int mbx_server_drain(mbx_server* s, double timeout_s) {
   if (!s) return MBX_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
   const bool ok = s->idle_cv.wait_for(lk, std::chrono::duration<double>(timeout_s),
-                                      [&] { return s->queue.empty() && s->running.empty(); });
+                                      [&] { return s->queue.empty() && s->running.empty() && s->admitting == 0; });
   return ok ? MBX_OK : MBX_ESTATE;
 }
 
