@@ -175,7 +175,7 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   for (int k = 0; k < 3; ++k) L.add(2 * (size_t)N * kt);  // 22..24 w z b
   L.add(2 * (size_t)N * 8);                   // 25 x (FP64)
   L.add((size_t)nblk * kPartStride * 8);      // 26 part
-  L.add(64);                                  // 27 ticket
+  L.add(0);                                   // 27 (unused)
   L.add(8 * RED_NSLOT);                       // 28 red
   L.add(4 * CTL_NSLOT);                       // 29 ictl
   L.add(8 * (size_t)gm_size(m));              // 30 gm
@@ -1028,7 +1028,6 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.b = b + L.off[24];
   h.x = (double*)(b + L.off[25]);
   h.part = (double*)(b + L.off[26]);
-  h.ticket = (unsigned*)(b + L.off[27]);
   h.red = (double*)(b + L.off[28]);
   h.ictl = (int*)(b + L.off[29]);
   h.gm = (double*)(b + L.off[30]);
@@ -1085,7 +1084,6 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   if (e == hipSuccess) {
     launch_finish_meta(N, (uint32_t*)h.meta, (const int*)(tmp + o_oa), (const int*)(tmp + o_oc), c->faces_an,
                        c->faces_ca, s);
-    e = hipMemsetAsync(h.ticket, 0, 64, s);
   }
   if (e == hipSuccess) e = hipMemsetAsync(h.ictl, 0, 4 * CTL_NSLOT, s);
   if (e == hipSuccess) e = hipMemsetAsync(h.red, 0, 8 * RED_NSLOT, s);

@@ -56,8 +56,8 @@ __device__ inline uint32_t face_rank(uint32_t m, int d) {
   return base_of(m) + (uint32_t)__popc(mask_of(m) & ((1u << d) - 1u));
 }
 
-// Slots of the per-cell reduction output array `red`.  A kernel performs at
-// most one reduce_cell call (the partial buffer and ticket are per cell).
+// Slots of the per-cell reduction output array `red` (written by the
+// finalising kernels of the two-pass reductions).
 enum {
   RED_RSQ = 0,     // sum of squared scaled residual
   RED_RMAX = 1,    // max |scaled residual|
@@ -97,7 +97,6 @@ struct CellDev {
   double *x;                         // 2N: GMRES iterate, FP64 in both modes
   void *dint;                        // KT: N, interface part of the concentration preconditioner's diagonal
   double *part;                      // nblk * kPartStride partial sums
-  unsigned *ticket;                  // one reduction ticket
   double *red;                       // RED_NSLOT outputs (device-written)
   int *ictl;                         // CTL_NSLOT flags (device-written)
   double *gm;                        // GMRES small arrays (see gm_* offsets)

@@ -50,3 +50,36 @@ def test_missing_library_fails_loudly(tmp_path):
             mbx.load(str(tmp_path / "nope.so"))
         finally:
             mbx._lib = saved
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes structures have the sizes and field offsets the C compiler
+    gives the header's structs (a drift here would corrupt every call)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mbx_params": mbx.Params, "mbx_step_info": mbx.StepInfo,
+               "mbx_request_info": mbx.RequestInfo, "mbx_server_info": mbx.ServerInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mbx.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            a, b, v = ln.split()
+            got[(a, b)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
