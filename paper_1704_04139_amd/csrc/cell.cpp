@@ -425,6 +425,10 @@ struct BatchCache {
   std::vector<uint64_t> ids;
   Batch b;
 } g_batch_cache;
+// guards g_batch_cache: batched steps from different threads (a server's
+// worker and a caller) run one at a time, and destroying a cell that the
+// cached batch holds waits for them
+std::mutex g_batch_mu;
 
 // The batch lives in the cache (its device block tables carry state: the
 // active-cell compaction), so callers work on the cached object itself.
@@ -1124,6 +1128,7 @@ void mbx_cell_destroy(mbx_cell* c) {
   if (!c) return;
   if (c->s) hipStreamSynchronize(c->s);
   else hipDeviceSynchronize();
+  std::lock_guard<std::mutex> lk(g_batch_mu);
   for (size_t k = 0; k < g_batch_cache.ids.size(); ++k)
     if (g_batch_cache.ids[k] == c->id) {
       g_batch_cache.b.release();
@@ -1159,10 +1164,7 @@ int mbx_batch_step(mbx_cell* const* cells, int n, double dt, int* status_out, mb
     for (int j = 0; j < i; ++j)
       if (cells[j] == cells[i]) return fail(MBX_EINVAL, "cell %d appears twice", i);
   }
-  // the batch-table cache is shared: batched steps from different threads
-  // (a server's worker and a caller) run one at a time
-  static std::mutex mu;
-  std::lock_guard<std::mutex> lk(mu);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
   std::vector<mbx_step_info> tmp(infos ? 0 : n);
   return step_recover(std::vector<mbx_cell*>(cells, cells + n), dt, status_out, infos ? infos : tmp.data(), 0);
 }
