@@ -101,14 +101,24 @@ def _fill_slab(lab: np.ndarray, z0: int, z1: int, phase: int, porosity: float,
 
 
 def _clean_connectivity(lab: np.ndarray, z_an: int, z_sep: int) -> None:
-    """Solid not face-connected to its collector -> pore; pore not connected to the
-    separator -> solid of the electrode it sits in."""
+    """Solid clusters that do not span their electrode -> pore; pore not connected
+    to the separator -> solid of the electrode it sits in.
+
+    A cluster spans its electrode when it is face-connected both to its collector
+    plane and to the electrode's face on the separator.  Every other cluster is
+    removed, as well as the isolated ones: a cluster that touches only the
+    cathode collector would take its share of the applied current, which is spread
+    evenly over the solid voxels of that plane, with no path to the rest of the
+    electrode.  It would then use up its lithium within seconds, after which an
+    implicit Euler step has no admissible solution.
+    """
     nz = lab.shape[0]
-    for phase, plane in ((ANODE, 0), (CATHODE, nz - 1)):
+    for phase, plane, sep_face in ((ANODE, 0, z_an - 1), (CATHODE, nz - 1, z_sep)):
         comp, n = _face_components(lab == phase)
         if n == 0:
             continue
-        keep = np.unique(comp[plane][comp[plane] > 0])
+        keep = np.intersect1d(np.unique(comp[plane][comp[plane] > 0]),
+                              np.unique(comp[sep_face][comp[sep_face] > 0]))
         drop = (comp > 0) & ~np.isin(comp, keep)
         lab[drop] = PORE
     comp, n = _face_components(lab == PORE)

@@ -27,10 +27,12 @@ def test_sphere_cell_rules():
     assert np.all(lab[:a] != I.CATHODE) and np.all(lab[a + s:] != I.ANODE)
     assert np.any(lab[0] == I.ANODE) and np.any(lab[-1] == I.CATHODE)
     st = ndi.generate_binary_structure(3, 1)
-    for ph, plane in ((I.ANODE, 0), (I.CATHODE, nz - 1)):
+    for ph, plane, sep_face in ((I.ANODE, 0, a - 1), (I.CATHODE, nz - 1, a + s)):
         comp, n = ndi.label(lab == ph, structure=st)
         on_plane = set(np.unique(comp[plane])) - {0}
+        on_sep = set(np.unique(comp[sep_face])) - {0}
         assert set(range(1, n + 1)) == on_plane            # every solid cluster reaches its collector
+        assert set(range(1, n + 1)) == on_sep              # ... and the separator
     comp, n = ndi.label(lab == I.PORE, structure=st)
     assert n == 1                                          # no closed pores
     por = np.mean(lab[:a] == I.PORE)
@@ -65,3 +67,37 @@ def test_sampled_queries_ranges():
     t = I.poisson_arrivals(20.0, 2000)
     assert np.all(np.diff(t) > 0)
     assert abs(len(t) / t[-1] - 20.0) < 2.0
+
+
+def _spanning(lab):
+    """Every solid cluster of each electrode touches both its collector plane and
+    its face on the separator."""
+    nz = lab.shape[0]
+    a = int(np.nonzero((lab == I.ANODE).any(axis=(1, 2)))[0].max()) + 1
+    c = int(np.nonzero((lab == I.CATHODE).any(axis=(1, 2)))[0].min())
+    st = ndi.generate_binary_structure(3, 1)
+    for ph, plane, sep_face in ((I.ANODE, 0, a - 1), (I.CATHODE, nz - 1, c)):
+        comp, n = ndi.label(lab == ph, structure=st)
+        ids = set(range(1, n + 1))
+        if ids != set(np.unique(comp[plane])) - {0} or ids != set(np.unique(comp[sep_face])) - {0}:
+            return False
+    return True
+
+
+def test_served_queries_have_spanning_clusters():
+    """The raw draws of seed 2004 at quarter scale and seed 2013 at full scale
+    hold cathode clusters that touch the collector plane but not the
+    separator; the generator removes them.  A cluster left on the cathode
+    collector would carry its share of the applied current alone and run out
+    of lithium within a few 5 s steps."""
+    for w in I.config4_requests(4, scale=4):
+        assert _spanning(w.labels), w.name
+    w = I.config4_requests(13)[12]
+    assert _spanning(w.labels), w.name
+    # the largest cathode cluster carries the collector: no collector voxel
+    # feeds a cluster holding fewer than 20 voxels per collector voxel
+    comp, n = ndi.label(w.labels == I.CATHODE, structure=ndi.generate_binary_structure(3, 1))
+    top = comp[-1][comp[-1] > 0]
+    ids, m = np.unique(top, return_counts=True)
+    k = ndi.sum(np.ones_like(comp), comp, ids)
+    assert np.min(k / m) > 20.0
