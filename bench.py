@@ -190,9 +190,12 @@ def run_serving(precision, rate_offered, n_req, n_cap, stream, budget_gb):
     t0 = srv.clock()
     ids = [srv.submit(w.labels, w.params, steps) for w in reqs[:n_cap]]
     _drain(srv, f"{precision} capacity burst")
-    t1 = max(srv.poll(i)["t_done"] for i in ids)
+    cinfos = [srv.poll(i) for i in ids]
+    cap_errors = {k: srv.error(i) for k, (i, inf) in enumerate(zip(ids, cinfos)) if inf["status"] < 0}
+    t1 = max(inf["t_done"] for inf in cinfos)
     srv.close()
-    cap = sum(dofsteps[:n_cap]) / (t1 - t0)
+    # DOF x steps actually completed (a failed request stops early)
+    cap = sum(2 * w.labels.size * inf["steps_done"] for w, inf in zip(reqs[:n_cap], cinfos)) / (t1 - t0)
     mean_req = float(np.mean(dofsteps[n_cap:]))
     rho_offered = rate_offered * mean_req / cap
     rate = rate_offered if rho_offered < 1.0 else 0.7 * cap / mean_req
@@ -208,17 +211,21 @@ def run_serving(precision, rate_offered, n_req, n_cap, stream, budget_gb):
               flush=True)
     _drain(srv, f"{precision} Poisson run")
     infos = [srv.poll(i) for i in ids]
+    errors = {k: srv.error(i) for k, (i, inf) in enumerate(zip(ids, infos)) if inf["status"] < 0}
     st = srv.stats()
     srv.close()
-    lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
     status = [int(i["status"]) for i in infos]
     span = max(i["t_done"] for i in infos) - base
     ok = [i for i in infos if i["status"] == mbx.MBX_REQ_DONE]
+    # latency percentiles over the requests that completed all their steps (a
+    # failed request retires early and would pull them down)
+    lat = np.array([i["t_done"] - i["t_submit"] for i in ok]) if ok else np.array([np.nan])
     return {"precision": precision, "capacity_dofsteps_per_s": cap, "offered_rate_hz": rate_offered,
             "rho_offered": rho_offered, "rate_hz": rate, "rho": rate * mean_req / cap, "requests": n_req,
             "completed": len(ok), "completed_per_s": len(ok) / span, "p50_s": float(np.percentile(lat, 50)),
             "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()), "max_s": float(lat.max()),
-            "busy_frac": st["busy_s"] / span, "batches": st["batches"], "status": status}
+            "busy_frac": st["busy_s"] / span, "batches": st["batches"], "status": status, "errors": errors,
+            "capacity_errors": cap_errors}
 
 
 def main():

@@ -274,6 +274,13 @@ int mbx_server_poll(mbx_server *s, int64_t id, mbx_request_info *info);
  * request is not MBX_REQ_DONE or the server does not keep states. */
 int mbx_server_result(mbx_server *s, int64_t id, double *cfield, double *phi, double *n_pl);
 
+/* Message of a request that ended with an error (status < 0), as
+ * mbx_last_error gave it when the request failed: copied, NUL-terminated and
+ * truncated, into buf of len bytes (host memory owned by the caller).  An
+ * empty string for a request without an error.  MBX_EINVAL for an unknown id
+ * or a null buf / len < 1. */
+int mbx_server_error(mbx_server *s, int64_t id, char *buf, int len);
+
 /* Block until no request is queued or running, at most timeout_s seconds
  * (MBX_ESTATE on time-out). */
 int mbx_server_drain(mbx_server *s, double timeout_s);

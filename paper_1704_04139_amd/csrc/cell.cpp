@@ -373,6 +373,9 @@ struct Batch {
   }
   int gather() {
     launch_gather_ctl(bl(), d_gather, s);
+    // a rejected launch leaves its error for the next query on this thread
+    // (a library such as rocPRIM would report it as its own): surface it here
+    HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h_gather, d_gather, sizeof(double) * kGather * cells.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return MBX_OK;
@@ -381,16 +384,16 @@ struct Batch {
   int ctl(int c, int slot) const { return (int)h_gather[(size_t)c * kGather + RED_NSLOT + slot]; }
   void release() {
     if (!owned) return;
-    hipFree(d_desc);
-    hipFree(d_blk);
-    hipFree(d_gather);
+    (void)hipFree(d_desc);
+    (void)hipFree(d_blk);
+    (void)hipFree(d_gather);
     for (int l = 0; l < kMaxLevels; ++l) {
       if (lvl_blk[l]) (void)hipFree(lvl_blk[l]);
       if (lvl8_blk[l]) (void)hipFree(lvl8_blk[l]);
       if (lvlh_blk[l]) (void)hipFree(lvlh_blk[l]);
     }
-    hipHostFree(h_desc);
-    hipHostFree(h_gather);
+    (void)hipHostFree(h_desc);
+    (void)hipHostFree(h_gather);
     owned = false;
   }
 };
@@ -923,7 +926,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
                o_fl = T.add(64), o_scan = T.add(scan_bytes);
   char* tmp = nullptr;
   if (hipMalloc(&tmp, T.total) != hipSuccess) return fail(MBX_ENOMEM, "device allocation of %zu bytes failed", T.total);
-  auto cleanup_tmp = [&]() { hipFree(tmp); };
+  auto cleanup_tmp = [&]() { (void)hipFree(tmp); };
   int* flags = (int*)(tmp + o_fl);
   int hflags[4] = {0, 0, 0, 0};
   int tail[4] = {0, 0, 0, 0};
@@ -999,7 +1002,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
     // debugging aid: NaN bytes everywhere, so a read before the first write shows up
     if (hipMemsetAsync(c->dmem, 0xff, L.total, s) != hipSuccess) {
       cleanup_tmp();
-      hipFree(c->dmem);
+      (void)hipFree(c->dmem);
       delete c;
       return fail(MBX_EHIP, "poison fill failed");
     }
@@ -1126,8 +1129,8 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
 
 void mbx_cell_destroy(mbx_cell* c) {
   if (!c) return;
-  if (c->s) hipStreamSynchronize(c->s);
-  else hipDeviceSynchronize();
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  else (void)hipDeviceSynchronize();
   std::lock_guard<std::mutex> lk(g_batch_mu);
   for (size_t k = 0; k < g_batch_cache.ids.size(); ++k)
     if (g_batch_cache.ids[k] == c->id) {
@@ -1135,9 +1138,9 @@ void mbx_cell_destroy(mbx_cell* c) {
       g_batch_cache.ids.clear();
       break;
     }
-  hipFree(c->dmem);
-  hipHostFree(c->h_gather);
-  hipHostFree(c->h_desc_pinned);
+  (void)hipFree(c->dmem);
+  (void)hipHostFree(c->h_gather);
+  (void)hipHostFree(c->h_desc_pinned);
   delete c;
 }
 

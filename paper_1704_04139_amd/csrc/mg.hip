@@ -896,29 +896,32 @@ __global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* _
 }
 
 // ---------------------------------------------------------------- launchers
+// A level's block table is empty when no cell that is still iterating has
+// that level (the batch mixes grid sizes): such launches are skipped, since a
+// launch of zero workgroups is a configuration error.
 template <typename KT>
 void launch_mg_setup(const BatchLaunch& b, hipStream_t s) {
   for (int op = 0; op < 2; ++op) {
-    k_mg_assemble0<KT><<<b.lvl_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl_blk[1], op);
+    if (b.lvl_nblk[1] > 0) k_mg_assemble0<KT><<<b.lvl_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl_blk[1], op);
     for (int l = 1; l + 1 < b.maxlev; ++l)
-      k_mg_assemble<KT><<<b.lvl_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl_blk[l + 1], l, op);
+      if (b.lvl_nblk[l + 1] > 0)
+        k_mg_assemble<KT><<<b.lvl_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl_blk[l + 1], l, op);
     k_mg_coarse_build<KT><<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, op);
   }
 }
 
 template <typename KT>
 static void smooth0(const BatchLaunch& b, int op, int color, int mode, int it, int need, hipStream_t s) {
+  if (b.lvlh_nblk[0] <= 0) return;
   k_mg0_smooth<KT><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, it, need);
 }
 
 template <typename KT>
 static void smoothl(const BatchLaunch& b, int l, int op, int color, int mode, int it, int need, hipStream_t s) {
+  if (b.lvlh_nblk[l] <= 0) return;
   k_mgl_smooth<KT><<<b.lvlh_nblk[l], kBlock, 0, s>>>(b.cells, b.lvlh_blk[l], l, op, color, mode, it, need);
 }
 
-// One V-cycle on operator op: nu red-black sweeps (red then black) down to
-// the fused levels, then the fused coarse cycle, then nu sweeps (black then
-// red) back up.  The first post-sweep applies the coarse correction lazily.
 // One V-cycle on operator op: red-black sweeps (red then black) down to the
 // fused levels, the fused coarse cycle, then sweeps (black then red) back up.
 // The first post-sweep applies the coarse correction lazily.  Each cell runs
@@ -940,6 +943,7 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
       }
     }
     if (l == 0 && prof_on(PK_SMOOTH0)) prof_end_n(PK_SMOOTH0, s, 2.0 * nu * b.bytes_smooth0, 2 * nu);
+    if (b.lvl8_nblk[l + 1] <= 0) continue;
     if (l == 0)
       k_mg0_restrict<KT><<<b.lvl8_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl8_blk[1], op, need);
     else

@@ -249,6 +249,19 @@ int mbx_server_submit(mbx_server* s, const uint8_t* labels, int nx, int ny, int 
   return MBX_OK;
 }
 
+int mbx_server_error(mbx_server* s, int64_t id, char* buf, int len) {
+  if (!s || !buf || len < 1) return MBX_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return MBX_EINVAL;
+  const Request& r = *it->second;
+  const std::string& e = r.info.status < 0 ? r.err : std::string();
+  const size_t n = std::min(e.size(), (size_t)len - 1);
+  memcpy(buf, e.data(), n);
+  buf[n] = '\0';
+  return MBX_OK;
+}
+
 int mbx_server_poll(mbx_server* s, int64_t id, mbx_request_info* info) {
   if (!s || !info) return MBX_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);

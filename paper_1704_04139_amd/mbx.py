@@ -98,6 +98,7 @@ SIGNATURES = {
     "mbx_server_submit": (_i, [_vp, _vp, _i, _i, _i, ctypes.POINTER(Params), _i, ctypes.POINTER(ctypes.c_int64)]),
     "mbx_server_poll": (_i, [_vp, ctypes.c_int64, ctypes.POINTER(RequestInfo)]),
     "mbx_server_result": (_i, [_vp, ctypes.c_int64, _vp, _vp, _vp]),
+    "mbx_server_error": (_i, [_vp, ctypes.c_int64, ctypes.c_char_p, _i]),
     "mbx_server_drain": (_i, [_vp, _d]),
     "mbx_server_clock": (_d, [_vp]),
     "mbx_server_stats": (_i, [_vp, ctypes.POINTER(ServerInfo)]),
@@ -332,6 +333,12 @@ class Server:
         info = RequestInfo()
         _check(load().mbx_server_poll(self._h, int(rid), ctypes.byref(info)))
         return info.as_dict()
+
+    def error(self, rid: int) -> str:
+        """Error message of a request that failed ('' otherwise)."""
+        buf = ctypes.create_string_buffer(512)
+        _check(load().mbx_server_error(self._h, int(rid), buf, len(buf)))
+        return buf.value.decode(errors="replace")
 
     def result(self, rid: int):
         """Final (c, phi, n) of a finished request (keep_state servers)."""

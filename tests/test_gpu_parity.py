@@ -313,6 +313,37 @@ def test_batch_equals_alone(mbx):
             np.testing.assert_allclose(x, y, rtol=1e-12, atol=0)
 
 
+def test_batch_with_idle_larger_cell(mbx):
+    """A cell at rest (no current) converges in its first Newton iteration and
+    leaves the active set, while the charging cell beside it has fewer
+    multigrid levels: the block tables of the levels only the idle cell has
+    become empty.  The batched steps succeed, leave no launch error behind
+    (creating another cell runs a library scan, which would report one), and
+    match the charging cell stepped alone."""
+    big = I.sphere_cell(32, 32, 80, 11, 2.0, 3.5, 0.35, 0.33)
+    small = I.sphere_cell(8, 8, 20, 12, 2.0, 3.0, 0.35, 0.35)
+    rest = I.CellParams(I_app=0.0)
+    prm = I.CellParams()
+    prm.I_app = 2.0 * I.one_c_current(small, prm)
+    say("idle larger cell in a batch", big.shape, small.shape)
+    alone = mbx.Cell(small, prm)
+    for _ in range(2):
+        alone.step(5.0)
+    ref = alone.get_state()
+    alone.close()
+    cells = [mbx.Cell(big, rest), mbx.Cell(small, prm)]
+    for _ in range(2):
+        st, infos = mbx.batch_step(cells, 5.0)
+        assert st == [0, 0]
+        assert infos[0]["newton_iters"] < infos[1]["newton_iters"]
+    extra = mbx.Cell(small, prm)
+    extra.close()
+    for x, y in zip(cells[1].get_state(), ref):
+        np.testing.assert_allclose(x, y, rtol=1e-12, atol=0)
+    for c in cells:
+        c.close()
+
+
 def test_no_read_before_write(mbx, monkeypatch):
     """Cells whose device memory starts as NaN bytes step to bit-identical
     results (any read of an unwritten buffer would propagate NaN)."""

@@ -67,11 +67,13 @@ def test_served_equals_solo(mbx, precision):
     srv.drain(300.0)
     infos = [srv.poll(i) for i in ids]
     results = [srv.result(i) for i in ids]
+    errors = [srv.error(i) for i in ids]
     stats = srv.stats()
     srv.close()
     say("stats", stats)
     assert stats["steps_run"] == sum(steps)
     assert stats["running"] == 0 and stats["queued"] == 0 and stats["bytes_in_use"] == 0
+    assert all(srv_err == "" for srv_err in errors)
     for w, n, info, res in zip(ws, steps, infos, results):
         assert info["status"] == mbx.MBX_REQ_DONE
         assert info["steps_done"] == n
@@ -98,6 +100,13 @@ def test_budget_admission(mbx):
     with pytest.raises(mbx.MbxError) as e:
         srv.submit(big.labels, big.params, 1)
     assert e.value.code == mbx.MBX_EBUDGET
+    # a request whose labels the library rejects fails at admission with a message
+    bad = w0.labels.copy()
+    bad[-1][bad[-1] == I.CATHODE] = I.PORE
+    rid = srv.submit(bad, w0.params, 1)
+    srv.drain(60.0)
+    assert srv.poll(rid)["status"] == mbx.MBX_ELABEL
+    assert "plane" in srv.error(rid)
     srv.close()
     for a, b in zip(infos, infos[1:]):
         assert b["t_admit"] >= a["t_done"]
