@@ -2,3 +2,4 @@
 only: imported by tests, the smoke check and the benchmark's CPU baseline)."""
 from .cellmodel import (FARADAY, GAS_R, Geometry, Model, NewtonFailure,  # noqa: F401
                         newton_step, simulate, ocp, f_pre)
+from .pod import gram, pod  # noqa: F401,E402
