@@ -13,7 +13,10 @@ on the same workload), `batched` (32 cells of 32x32x80 .. 96x96x240 with
 sampled C-rate, temperature and plating rate, stepped together),
 `roofline` (the dominant kernel's algorithmic bytes per launch over its
 event-timed average launch duration), `cpu_baseline` (the CPU oracle on a
-bounded down-scaled sample of the same workload).
+bounded down-scaled sample of the same workload), `pod` (the POD of Sec.
+2.5 by the method of snapshots, on 96 captured states and Newton stages per
+field of the same cell, with the Gram kernel's FP64 matrix-core roofline
+and the oracle POD timed on one core).
 
 --mode serve (one JSON line): parameter queries of 48x48x120 .. 128x128x320
 cells, 12 steps of 5 s each, arriving as a Poisson stream at a continuous-
@@ -131,6 +134,68 @@ def cpu_baseline():
             "host_cpu": cpu, "host_nproc": os.cpu_count()}
 
 
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+
+
+def run_pod(w, n_snap, reps, stream, with_oracle):
+    """POD by the method of snapshots (Sec. 2.5) of the concentration and the
+    potential snapshot sets of the benchmark cell: its states and Newton
+    stages, captured on the device while it steps (untimed), then reps timed
+    POD calls per field at rtol 1e-7 (the tolerance of Sec. 3.2)."""
+    import torch
+    from paper_1704_04139_amd import mbx
+    cell = mbx.Cell(w.labels, w.params, precision="fp64", stream=stream)
+    N = cell.counts.n_vox
+    dc = torch.empty((n_snap, N), dtype=torch.float64, device="cuda")
+    dp = torch.empty((n_snap, N), dtype=torch.float64, device="cuda")
+    cell.capture(dc.data_ptr(), dp.data_ptr(), N, n_snap)
+    steps = 0
+    while cell.captured()[0] < n_snap and steps < 200:
+        cell.step(w.dt)
+        steps += 1
+    m = cell.captured()[0]
+    cell.close()
+    torch.cuda.synchronize()
+    print(f"[bench] pod: {m} snapshots per field captured over {steps} steps", file=sys.stderr, flush=True)
+    du = torch.empty((m, N), dtype=torch.float64, device="cuda")
+    ks = {}
+    for name, buf in (("c", dc), ("phi", dp)):          # warm-up
+        _, ks[name] = mbx.pod(buf.data_ptr(), N, m, N, du.data_ptr(), N, m, 1e-7, stream=stream)
+    torch.cuda.synchronize()
+    mbx.profile("gram")
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for buf in (dc, dp):
+            mbx.pod(buf.data_ptr(), N, m, N, du.data_ptr(), N, m, 1e-7, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, ms, nbytes = mbx.profile_read()
+    mbx.profile(None)
+    flops = float(N) * m * (m + 1)                  # the m(m+1)/2 distinct entries, 2 flops per row each
+    avg_s = ms * 1e-3 / max(launches, 1)
+    out = {"snapshots": m, "rows": N, "fields": ["c", "phi"], "steps_captured": steps, "rtol": 1e-7,
+           "k": ks, "ms_per_pod": 1e3 * (t1 - t0) / (2 * reps),
+           "gram": {"bound": "mfma", "kernel": "gram", "achieved": flops / avg_s / 1e12 if launches else None,
+                    "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": flops / avg_s / 1e12 / FP64_MFMA_PEAK_TFLOPS if launches else None,
+                    "launches": launches, "avg_us": 1e6 * avg_s, "flops_per_launch": flops,
+                    "bytes_per_launch": nbytes / max(launches, 1),
+                    "hbm_gbs": nbytes / max(launches, 1) / avg_s / 1e9 if launches else None}}
+    if with_oracle:
+        import oracle
+        from threadpoolctl import threadpool_limits
+        S = dc[:m].cpu().numpy().T.copy()
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            oracle.pod(S, rtol=1e-7)
+            t1 = time.perf_counter()
+        out["cpu_oracle"] = {"ms_per_pod": 1e3 * (t1 - t0), "cores": 1, "kind": "oracle",
+                             "sample": f"the same {N} x {m} concentration snapshots, NumPy/LAPACK, 1 thread"}
+    del dc, dp, du
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batched(n_cells, steps, precision, stream):
     """32-cell batch (sampled queries), all cells advanced by shared launches."""
     import torch
@@ -243,6 +308,8 @@ def main():
                     help="requests of the closed burst that measures the server's capacity")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="offered arrival rate, requests/s")
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--pod-snapshots", type=int, default=96,
+                    help="snapshots per field for the POD measurement (0: skip it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (calibrates profiler byte counters)")
     args = ap.parse_args()
@@ -320,6 +387,10 @@ def main():
             f = res[other]
             line[other] = {"value": f["value"], "ms_per_step": f["ms_per_step"],
                            "newton_per_step": f["newton_per_step"], "krylov_per_step": f["krylov_per_step"]}
+    if args.pod_snapshots > 0:
+        line["pod"] = run_pod(w, args.pod_snapshots, 3, stream, not args.no_cpu_baseline)
+        print(f"[bench] pod: {line['pod']['ms_per_pod']:.2f} ms per field, Gram "
+              f"{line['pod']['gram']['avg_us']:.1f} us", file=sys.stderr, flush=True)
     if args.batch_steps > 0:
         print(f"[bench] batched: {args.batch_cells} cells, {args.batch_steps} timed steps", file=sys.stderr, flush=True)
         line["batched"] = run_batched(args.batch_cells, args.batch_steps, main_prec, stream)

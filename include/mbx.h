@@ -154,6 +154,23 @@ int mbx_cell_get_state(const mbx_cell *c, double *cfield, double *phi, double *n
 int mbx_cell_set_state(mbx_cell *c, const double *cfield, const double *phi,
                        const double *n_pl, int device_ptrs);
 
+/* Snapshot capture for the POD of Sec. 2.5, whose snapshot sets hold the
+ * solution of every time step and the intermediate Newton stages.  From this
+ * call on, the cell appends its state as one column of c_snap and one of
+ * phi_snap (device addresses, column-major, leading dimension ld >= N, room
+ * for capacity columns; either may be null to skip that field): first the
+ * current state, then the iterate after every accepted Newton update (the
+ * last one of a step is the step's solution).  The columns of a step that
+ * fails are dropped again (the state is restored to u^n).  Once capacity
+ * columns are taken, further ones are counted as dropped and not written.
+ * The copies run on the cell's stream, ordered with its steps.  The caller
+ * owns the buffers and keeps them alive while capture is on; capacity = 0
+ * (or both pointers null) turns capture off.  Errors: MBX_EINVAL. */
+int mbx_cell_capture(mbx_cell *c, double *c_snap, double *phi_snap, int64_t ld, int capacity);
+
+/* Columns written since mbx_cell_capture, and columns that found no room. */
+int mbx_cell_captured(const mbx_cell *c, int *count, int *dropped);
+
 /* Cell voltage (Sec. 2.5 output functional s_cp): mean over the cathode
  * collector faces of the solid potential extrapolated across half a voxel
  * with the applied flux; the anode collector is the 0 V reference. */
@@ -296,7 +313,7 @@ void mbx_server_destroy(mbx_server *s);
 /* Kernel timing for measurement: after mbx_profile(k), every launch of
  * kernel class k (1 FP64 residual + linearisation, 2 matrix-free J*v,
  * 3 level-0 multigrid smoothing half-sweep, 4 whole preconditioner
- * application; 0 stops timing) is bracketed by a pair of HIP events recorded
+ * application, 5 Gram-matrix kernel of mbx_pod; 0 stops timing) is bracketed by a pair of HIP events recorded
  * on the stream it runs on, together with the launch's algorithmic bytes
  * (every array element the operation must read or write, counted once).
  * Class 3 brackets each group of back-to-back half sweeps of one V-cycle side
@@ -307,6 +324,36 @@ void mbx_server_destroy(mbx_server *s);
  * production. */
 int mbx_profile(int kernel);
 int mbx_profile_read(int64_t *launches, double *total_ms, double *total_bytes);
+
+/* Most snapshots one POD takes (the host eigen-decomposition is O(m^3)). */
+#define MBX_POD_MAX_SNAPSHOTS 512
+
+/* POD of a snapshot set by the method of snapshots (Sec. 2.5; Sirovich's
+ * method, which the paper cites): K = S^T W S, K = V diag(lam) V^T with lam
+ * descending, sigma_i = sqrt(max(lam_i, 0)), modes u_i = S v_i / sigma_i.
+ * S: n x m snapshots, device, column-major, leading dimension lds >= n,
+ * 1 <= m <= MBX_POD_MAX_SNAPSHOTS.  w: n positive weights of the inner product
+ * (device; null: Euclidean).  A mode is kept while sigma_i > rtol sigma_1
+ * (Sec. 3.2 uses rtol = 1e-7), at most k_max of them.  Each mode's sign
+ * makes the largest-magnitude entry of v_i positive (the first on ties).
+ * Outputs: modes (device, n x k_max column-major, leading dimension
+ * ldm >= n; columns k.. are not written), sigma (host, all m singular
+ * values, descending), *k_out = number of kept modes.  K is formed on the
+ * GPU's FP64 matrix cores; its eigen-decomposition runs on the host (cyclic
+ * Jacobi).  Singular values below about 1e-8 sigma_1 carry the rounding of
+ * K (the method squares the condition number).  Allocates a device
+ * workspace of about 8 (2048 x 4096 + m^2 + 32 m ceil(k/32)) bytes for the
+ * call and synchronises the stream.  Errors: MBX_EINVAL, MBX_ENOMEM,
+ * MBX_ENAN (non-finite Gram matrix), MBX_EHIP. */
+int mbx_pod(const double *S, int64_t n, int m, int64_t lds, const double *w, double rtol, int k_max,
+            double *modes, int64_t ldm, double *sigma, int *k_out, void *stream);
+
+/* The eigen-decomposition step of mbx_pod on its own (host memory): A is a
+ * symmetric m x m matrix (column-major; exactly symmetric, else
+ * MBX_EINVAL), lam receives the m eigenvalues in descending order and V
+ * (m x m, column-major) the eigenvectors, signed as in mbx_pod.  Cyclic
+ * Jacobi rotations.  Errors: MBX_EINVAL, MBX_ENAN. */
+int mbx_sym_eig(int m, const double *A, double *lam, double *V);
 
 /* Device bytes a cell of this size would allocate (for admission control). */
 int64_t mbx_cell_footprint(int nx, int ny, int nz, int precision, int n_an_faces, int n_ca_faces);

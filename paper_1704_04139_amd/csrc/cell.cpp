@@ -130,6 +130,10 @@ LevelDims level_dims(int nx, int ny, int nz, size_t kt) {
 
 }  // namespace
 
+namespace mbx {
+int report_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace mbx
+
 struct mbx_cell {
   uint64_t id;
   mbx_params p;
@@ -152,9 +156,30 @@ struct mbx_cell {
   int lvl8_nblk[kMaxLevels] = {};
   int2* lvlh_blk[kMaxLevels] = {};   // one colour of a red-black sweep (index >= 0)
   int lvlh_nblk[kMaxLevels] = {};
+  // snapshot capture (caller-owned device columns)
+  double* cap_c = nullptr;
+  double* cap_phi = nullptr;
+  int64_t cap_ld = 0;
+  int cap_capacity = 0, cap_count = 0, cap_dropped = 0;
 };
 
 namespace {
+
+// Appends the cell's current iterate to its snapshot columns (capture on).
+int capture_column(mbx_cell* c, hipStream_t s) {
+  if (c->cap_capacity <= 0) return MBX_OK;
+  if (c->cap_count >= c->cap_capacity) {
+    ++c->cap_dropped;
+    return MBX_OK;
+  }
+  const size_t off = (size_t)c->cap_count * (size_t)c->cap_ld;
+  if (c->cap_c)
+    HIPCHK(hipMemcpyAsync(c->cap_c + off, c->h.c, 8 * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  if (c->cap_phi)
+    HIPCHK(hipMemcpyAsync(c->cap_phi + off, c->h.phi, 8 * (size_t)c->N, hipMemcpyDeviceToDevice, s));
+  ++c->cap_count;
+  return MBX_OK;
+}
 
 // cells of one colour of a red-black sweep on level l (upper bound)
 size_t half_cells(const LevelDims& ld, int l) { return (size_t)((ld.nx[l] + 1) / 2) * ld.ny[l] * ld.nz[l]; }
@@ -573,6 +598,12 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
   const double eta_floor = B.cells[0]->p.krylov_rtol;
   std::vector<int> nit(nc, 0), kit(nc, 0);
   std::vector<std::vector<double>> rhist(nc);   // accepted residual 2-norms
+  // snapshot columns at the step start: a failed step drops its own again
+  std::vector<int> cap0(nc), capd0(nc);
+  for (int c = 0; c < nc; ++c) {
+    cap0[c] = B.cells[c]->cap_count;
+    capd0[c] = B.cells[c]->cap_dropped;
+  }
   for (int c = 0; c < nc; ++c) {
     mbx_cell* cl = B.cells[c];
     fill_step_constants(cl->h, dt);
@@ -711,6 +742,9 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
     }
     if (int e = B.upload()) return e;
     launch_copy_state(B.bl(), 0, B.s);   // accept: state <- trial
+    for (int c = 0; c < nc; ++c)         // Newton stage snapshots
+      if (B.cells[c]->h.active)
+        if (int e = capture_column(B.cells[c], B.s)) return e;
     for (int c = 0; c < nc; ++c) {
       if (st[c] != 1) continue;
       const mbx_params& p = B.cells[c]->p;
@@ -740,6 +774,10 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
   for (int c = 0; c < nc; ++c) {
     if (st[c] == 1) st[c] = MBX_ENEWTON;
     B.cells[c]->h.active = st[c] < 0;
+    if (st[c] < 0) {
+      B.cells[c]->cap_count = cap0[c];
+      B.cells[c]->cap_dropped = capd0[c];
+    }
   }
   if (int e = B.upload()) return e;
   launch_copy_state(B.bl(), 3, B.s);
@@ -1170,6 +1208,30 @@ int mbx_batch_step(mbx_cell* const* cells, int n, double dt, int* status_out, mb
   std::lock_guard<std::mutex> lk(g_batch_mu);
   std::vector<mbx_step_info> tmp(infos ? 0 : n);
   return step_recover(std::vector<mbx_cell*>(cells, cells + n), dt, status_out, infos ? infos : tmp.data(), 0);
+}
+
+int mbx_cell_capture(mbx_cell* c, double* c_snap, double* phi_snap, int64_t ld, int capacity) {
+  if (!c) return fail(MBX_EINVAL, "null cell");
+  if (capacity < 0) return fail(MBX_EINVAL, "capacity must be >= 0");
+  if (capacity == 0 || (!c_snap && !phi_snap)) {
+    c->cap_c = c->cap_phi = nullptr;
+    c->cap_capacity = c->cap_count = c->cap_dropped = 0;
+    return MBX_OK;
+  }
+  if (ld < c->N) return fail(MBX_EINVAL, "ld must be >= the number of voxels");
+  c->cap_c = c_snap;
+  c->cap_phi = phi_snap;
+  c->cap_ld = ld;
+  c->cap_capacity = capacity;
+  c->cap_count = c->cap_dropped = 0;
+  return capture_column(c, c->s);
+}
+
+int mbx_cell_captured(const mbx_cell* c, int* count, int* dropped) {
+  if (!c) return fail(MBX_EINVAL, "null cell");
+  if (count) *count = c->cap_count;
+  if (dropped) *dropped = c->cap_dropped;
+  return MBX_OK;
 }
 
 int mbx_cell_set_current(mbx_cell* c, double I_app) {

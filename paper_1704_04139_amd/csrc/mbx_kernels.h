@@ -71,4 +71,20 @@ template <typename KT> void launch_mg_setup(const BatchLaunch& b, hipStream_t s)
 // z = M^-1 v_src; need: GMRES state gate (>= 0 equal, -1 cycle end, -2 always)
 template <typename KT> void launch_precond(const BatchLaunch& b, int src, int need, hipStream_t s);
 
+// POD by the method of snapshots (pod.hip).  Snapshots S: n x m column-major.
+int gram_tile();               // edge of the Gram tiles (pairs index tiles of this size)
+int gram_rows_step();          // rows per split are a multiple of this
+int modes_cols_per_thread();   // kpad is a multiple of this
+// partial Gram tiles part[(y npairs + p) tile^2] of W S[:, ti] ^T S[:, tj] over row slice y
+void launch_gram(const double* S, int64_t n, int m, int64_t lds, const double* w, int64_t rows_per_split, int nsplit,
+                 const int2* pairs, int npairs, double* part, hipStream_t s);
+// K (m x m, symmetric) = sum of the slices, in slice order
+void launch_gram_reduce(const double* part, int nsplit, const int2* pairs, int npairs, int m, double* K, hipStream_t s);
+// U[:, q] = S C[:, q] for q < k (C row-major m x kpad)
+void launch_modes(const double* S, int64_t n, int m, int64_t lds, const double* C, int kpad, int k, double* U,
+                  int64_t ldu, hipStream_t s);
+
+// Sets the calling thread's mbx_last_error message and returns code.
+int report_error(int code, const char* msg);
+
 }  // namespace mbx

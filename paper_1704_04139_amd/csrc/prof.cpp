@@ -62,7 +62,7 @@ extern "C" {
 
 int mbx_profile(int kernel) {
   std::lock_guard<std::mutex> lk(mbx::g_mu);
-  if (kernel < mbx::PK_NONE || kernel > mbx::PK_PRECOND) return MBX_EINVAL;
+  if (kernel < mbx::PK_NONE || kernel > mbx::PK_GRAM) return MBX_EINVAL;
   mbx::g_kernel = kernel;
   for (auto& r : mbx::g_recs) {
     mbx::g_pool.push_back(r.a);

@@ -5,7 +5,7 @@
 
 namespace mbx {
 
-enum ProfKernel { PK_NONE = 0, PK_RESIDUAL = 1, PK_MATVEC = 2, PK_SMOOTH0 = 3, PK_PRECOND = 4 };
+enum ProfKernel { PK_NONE = 0, PK_RESIDUAL = 1, PK_MATVEC = 2, PK_SMOOTH0 = 3, PK_PRECOND = 4, PK_GRAM = 5 };
 
 // True when launches of kernel class k are being timed.
 bool prof_on(int k);

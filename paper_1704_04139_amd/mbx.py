@@ -91,6 +91,11 @@ SIGNATURES = {
     "mbx_cell_solve": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _d, _vp, ctypes.POINTER(_i)]),
     "mbx_batch_step": (_i, [ctypes.POINTER(_vp), _i, _d, ctypes.POINTER(_i), ctypes.POINTER(StepInfo)]),
     "mbx_cell_footprint": (ctypes.c_int64, [_i, _i, _i, _i, _i, _i]),
+    "mbx_cell_capture": (_i, [_vp, _vp, _vp, ctypes.c_int64, _i]),
+    "mbx_cell_captured": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "mbx_pod": (_i, [_vp, ctypes.c_int64, _i, ctypes.c_int64, _vp, _d, _i, _vp, ctypes.c_int64, _dp,
+                     ctypes.POINTER(_i), _vp]),
+    "mbx_sym_eig": (_i, [_i, _dp, _dp, _dp]),
     "mbx_last_error": (ctypes.c_char_p, []),
     "mbx_profile": (_i, [_i]),
     "mbx_profile_read": (_i, [ctypes.POINTER(ctypes.c_int64), _dp, _dp]),
@@ -113,6 +118,15 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library {path} is missing: run python -m paper_1704_04139_amd.build")
+    # The library and PyTorch exchange device pointers and streams, so the
+    # process must hold one HIP runtime.  PyTorch's wheel carries its own
+    # libamdhip64 with the SONAME the library needs: importing torch first
+    # binds the library to that copy.  Loaded the other way round, torch would
+    # map a second runtime, and whichever initialises the GPU second fails.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -218,6 +232,17 @@ class Cell:
     def get_state_device(self, c_ptr: int, p_ptr: int, n_ptr: int):
         _check(load().mbx_cell_get_state(self._h, _vp(c_ptr), _vp(p_ptr), _vp(n_ptr), 1))
 
+    def capture(self, c_ptr: int, p_ptr: int, ld: int, capacity: int):
+        """Snapshot capture into caller-owned device columns (0 pointers skip a field)."""
+        _check(load().mbx_cell_capture(self._h, _vp(c_ptr) if c_ptr else None, _vp(p_ptr) if p_ptr else None,
+                                       int(ld), int(capacity)))
+
+    def captured(self):
+        """(columns written, columns dropped for lack of room)."""
+        a, b = _i(), _i()
+        _check(load().mbx_cell_captured(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def set_state(self, c, p, n):
         c, p, n = (np.ascontiguousarray(a, dtype=np.float64) for a in (c, p, n))
         _check(load().mbx_cell_set_state(self._h, _ptr(c), _ptr(p), _ptr(n), 0))
@@ -283,7 +308,29 @@ def batch_step(cells, dt: float):
     return list(st), [infos[k].as_dict() for k in range(n)]
 
 
-PROFILE_KERNELS = {"residual": 1, "matvec": 2, "smooth0": 3, "precond": 4}
+def pod(S_ptr: int, n: int, m: int, lds: int, modes_ptr: int, ldm: int, k_max: int, rtol: float = 1e-7,
+        w_ptr: int = 0, stream=None):
+    """POD of the n x m device snapshots at S_ptr into the device modes at
+    modes_ptr (column-major); returns (sigma: all m singular values, k)."""
+    sigma = np.empty(m)
+    k = _i()
+    _check(load().mbx_pod(_vp(S_ptr), int(n), int(m), int(lds), _vp(w_ptr) if w_ptr else None, float(rtol),
+                          int(k_max), _vp(modes_ptr), int(ldm), sigma.ctypes.data_as(_dp), ctypes.byref(k),
+                          _vp(stream) if stream else None))
+    return sigma, k.value
+
+
+def sym_eig(A: np.ndarray):
+    """Eigenvalues (descending) and eigenvectors of a symmetric matrix (host)."""
+    A = np.asfortranarray(A, dtype=np.float64)
+    m = A.shape[0]
+    lam = np.empty(m)
+    V = np.empty((m, m), order="F")
+    _check(load().mbx_sym_eig(m, A.ctypes.data_as(_dp), lam.ctypes.data_as(_dp), V.ctypes.data_as(_dp)))
+    return lam, V
+
+
+PROFILE_KERNELS = {"residual": 1, "matvec": 2, "smooth0": 3, "precond": 4, "gram": 5}
 
 
 def profile(kernel):

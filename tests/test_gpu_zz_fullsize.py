@@ -81,3 +81,44 @@ def test_fullsize_step_solves_the_oracle_equations(mbx, full, precision):
         assert (inv1["anode"] - inv0["anode"]) + (inv1["plated"] - inv0["plated"]) == pytest.approx(q, rel=1e-6)
         assert inv1["cathode"] - inv0["cathode"] == pytest.approx(-q, rel=1e-6)
     cell.close()
+
+
+def test_fullsize_pod_matches_oracle(mbx, full):
+    """POD (Sec. 2.5) of the 64x64x160 cell's snapshot sets at the size the
+    benchmark times: 96 captured states and Newton stages per field,
+    655,360 rows.  Singular values within the Gram-rounding bar of
+    tests/test_gpu_pod.py, the same kept count at rtol 1e-4, and the modes."""
+    import torch
+    import oracle
+    w, model = full
+    cell = mbx.Cell(w.labels, w.params)
+    N = cell.counts.n_vox
+    m = 96
+    dc = torch.empty((m, N), dtype=torch.float64, device="cuda")
+    dp = torch.empty((m, N), dtype=torch.float64, device="cuda")
+    cell.capture(dc.data_ptr(), dp.data_ptr(), N, m)
+    steps = 0
+    while cell.captured()[0] < m and steps < 200:
+        cell.step(w.dt)
+        steps += 1
+    assert cell.captured()[0] == m
+    cell.close()
+    say("captured", m, "columns over", steps, "steps")
+    u = 2.0 ** -53
+    du = torch.empty((m, N), dtype=torch.float64, device="cuda")
+    for name, buf in (("c", dc), ("phi", dp)):
+        sigma, k = mbx.pod(buf.data_ptr(), N, m, N, du.data_ptr(), N, m, 1e-4)
+        torch.cuda.synchronize()
+        S = buf.cpu().numpy().T.copy()
+        ref_modes, ref_sigma, _ = oracle.pod(S, rtol=1e-4)
+        lam_g, lam_o = sigma ** 2, ref_sigma ** 2
+        dl = 10.0 * (N * u * float(np.sum(S * S)) + 2 * m * u * lam_o[0])
+        say(name, "k", k, "max |dlam|", np.max(np.abs(lam_g - lam_o)), "bar", dl)
+        assert np.max(np.abs(lam_g - lam_o)) <= dl
+        assert k == ref_modes.shape[1]
+        modes = du[:k].cpu().numpy().T
+        for i in range(min(k, 8)):
+            gap = np.min(np.abs(np.delete(lam_o, i) - lam_o[i]))
+            bar = 10.0 * dl / gap * (ref_sigma[0] / ref_sigma[i]) + 1e-11
+            d = min(np.linalg.norm(modes[:, i] - s * ref_modes[:, i]) for s in (1.0, -1.0))
+            assert d <= bar, (name, i, d, bar)
