@@ -342,7 +342,7 @@ int mbx_profile_read(int64_t *launches, double *total_ms, double *total_bytes);
  * GPU's FP64 matrix cores; its eigen-decomposition runs on the host (cyclic
  * Jacobi).  Singular values below about 1e-8 sigma_1 carry the rounding of
  * K (the method squares the condition number).  Allocates a device
- * workspace of about 8 (2048 x 4096 + m^2 + 32 m ceil(k/32)) bytes for the
+ * workspace of about 8 (2048 x 1024 + m^2 + 32 m ceil(k/32)) bytes for the
  * call and synchronises the stream.  Errors: MBX_EINVAL, MBX_ENOMEM,
  * MBX_ENAN (non-finite Gram matrix), MBX_EHIP. */
 int mbx_pod(const double *S, int64_t n, int m, int64_t lds, const double *w, double rtol, int k_max,
