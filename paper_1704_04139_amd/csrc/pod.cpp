@@ -92,9 +92,14 @@ bool jacobi_eig(int m, std::vector<double>& A, std::vector<double>& lam, std::ve
   return true;
 }
 
+// Workspace of one mbx_pod call.  On every exit, including an error after
+// work was enqueued, the stream is drained before the buffers are freed.
 struct DevBufs {
+  hipStream_t s;
   void* p[4] = {nullptr, nullptr, nullptr, nullptr};
+  explicit DevBufs(hipStream_t st) : s(st) {}
   ~DevBufs() {
+    (void)hipStreamSynchronize(s);
     for (void* x : p)
       if (x) (void)hipFree(x);
   }
@@ -141,7 +146,7 @@ int mbx_pod(const double* S, int64_t n, int m, int64_t lds, const double* w, dou
   int64_t R = (n + want - 1) / want;
   R = (R + step - 1) / step * step;
   const int nsplit = (int)((n + R - 1) / R);
-  DevBufs d;
+  DevBufs d(s);
   const size_t part_elems = (size_t)nsplit * np * tile * tile;
   hipError_t e = hipMalloc(&d.p[0], sizeof(int2) * np);
   if (e == hipSuccess) e = hipMalloc(&d.p[1], sizeof(double) * part_elems);
