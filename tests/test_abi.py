@@ -83,3 +83,20 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_binding_shares_one_hip_runtime_with_torch():
+    """Loading the library through the binding leaves one HIP runtime in the
+    process, also when torch is used afterwards (PyTorch's wheel carries its
+    own libamdhip64 under the same SONAME; two copies in one process made
+    the library's allocations fail once torch had set up the GPU)."""
+    import subprocess
+    import sys
+    code = ("from paper_1704_04139_amd import mbx\n"
+            "mbx.load()\n"
+            "import torch\n"
+            "maps = [l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l and 'r-xp' in l]\n"
+            "print(len(set(maps)))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert r.returncode == 0, r.stderr[-500:]
+    assert r.stdout.strip().splitlines()[-1] == "1"
