@@ -39,12 +39,13 @@ HBM_PEAK_GBS = 8000.0
 PROFILED_KERNEL = "smooth0"     # the kernel class with the largest share of GPU time
 
 
-def measured_traffic(precision):
-    """HBM bytes per launch of the profiled kernel from the committed counter
-    summary (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
-    the summary is for another precision or the kernel source has changed."""
+def committed_traffic(summary, sources, precision):
+    """HBM bytes per launch of a profiled kernel from a committed counter
+    summary under profiles/ (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated), or None when the summary is for another precision or
+    the kernel's source files have changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "mg0_smooth_traffic.txt")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         kv = {}
         for ln in open(path):
@@ -54,11 +55,17 @@ def measured_traffic(precision):
     except OSError:
         return None
     h = hashlib.sha256()
-    for f in ("paper_1704_04139_amd/csrc/mg.hip", "paper_1704_04139_amd/csrc/mbx_dev.h"):
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if kv.get("precision") != precision or kv.get("source_sha256") != h.hexdigest():
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def measured_traffic(precision):
+    """Traffic of the level-0 smoother (the roofline kernel of the step)."""
+    return committed_traffic("mg0_smooth_traffic.txt",
+                             ("paper_1704_04139_amd/csrc/mg.hip", "paper_1704_04139_amd/csrc/mbx_dev.h"), precision)
 
 
 def run_gpu(w, precision, steps, warmup, stream):
@@ -178,6 +185,7 @@ def run_pod(w, n_snap, reps, stream, with_oracle):
            "gram": {"bound": "mfma", "kernel": "gram", "achieved": flops / avg_s / 1e12 if launches else None,
                     "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": flops / avg_s / 1e12 / FP64_MFMA_PEAK_TFLOPS if launches else None,
+                    "traffic": committed_traffic("gram_traffic.txt", ("paper_1704_04139_amd/csrc/pod.hip",), "fp64"),
                     "launches": launches, "avg_us": 1e6 * avg_s, "flops_per_launch": flops,
                     "bytes_per_launch": nbytes / max(launches, 1),
                     "hbm_gbs": nbytes / max(launches, 1) / avg_s / 1e9 if launches else None}}

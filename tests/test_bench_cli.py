@@ -20,3 +20,21 @@ def test_traffic_figure_only_for_its_precision_and_source():
     t = bench.measured_traffic("fp64")
     assert t is None or t > 0          # None once the kernel source has changed since the counters
     assert bench.measured_traffic("mixed") is None
+
+
+def test_gram_traffic_figure_matches_its_source(tmp_path, monkeypatch):
+    """The Gram kernel's committed counter summary is used only for the
+    source it was taken on: a copy of the tree with an edited pod.hip gets
+    None."""
+    import shutil
+    import bench
+    t = bench.committed_traffic("gram_traffic.txt", ("paper_1704_04139_amd/csrc/pod.hip",), "fp64")
+    assert t is None or t > 5.0e8      # at least the snapshot bytes read once
+    root = tmp_path / "tree"
+    (root / "profiles").mkdir(parents=True)
+    (root / "paper_1704_04139_amd" / "csrc").mkdir(parents=True)
+    shutil.copy(os.path.join(ROOT, "profiles", "gram_traffic.txt"), root / "profiles")
+    src = open(os.path.join(ROOT, "paper_1704_04139_amd", "csrc", "pod.hip")).read()
+    (root / "paper_1704_04139_amd" / "csrc" / "pod.hip").write_text(src + "\n// edited\n")
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    assert bench.committed_traffic("gram_traffic.txt", ("paper_1704_04139_amd/csrc/pod.hip",), "fp64") is None
