@@ -15,16 +15,21 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=o
          "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd.insert(1, "-xhip")
-        _run(cmd, verbose)
+        cmds.append(cmd)
         objs.append(obj)
+    # the sources compile independently; at most `jobs` compilers at a time
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
