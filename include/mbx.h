@@ -348,6 +348,21 @@ int mbx_profile_read(int64_t *launches, double *total_ms, double *total_bytes);
 int mbx_pod(const double *S, int64_t n, int m, int64_t lds, const double *w, double rtol, int k_max,
             double *modes, int64_t ldm, double *sigma, int *k_out, void *stream);
 
+/* mbx_pod without any device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, results, errors and numerics are those of
+ * mbx_pod (the same kernels, bit-identical results).  The workspace is a
+ * static device array of 21 MiB that each device the library runs on holds
+ * until the process ends; it covers every m <= MBX_POD_MAX_SNAPSHOTS (a
+ * request that would need more fails with MBX_EINVAL and a message).  Its
+ * device address is looked up once per device, on the first call with that
+ * device current.  Every call on one device shares that device's array:
+ * calls that overlap on one device (several threads or streams) race and
+ * must be serialised by the caller.  Synchronises the stream.  Host work
+ * arrays of O(m^2) doubles still come from the host heap. */
+int mbx_pod_noalloc(const double *S, int64_t n, int m, int64_t lds, const double *w, double rtol, int k_max,
+                    double *modes, int64_t ldm, double *sigma, int *k_out, void *stream);
+
 /* The eigen-decomposition step of mbx_pod on its own (host memory): A is a
  * symmetric m x m matrix (column-major; exactly symmetric, else
  * MBX_EINVAL), lam receives the m eigenvalues in descending order and V

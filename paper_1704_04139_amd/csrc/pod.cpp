@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mbx.h"
@@ -14,7 +16,38 @@
 
 using namespace mbx;
 
+// Workspace of mbx_pod_noalloc, one copy per device, held until the process
+// ends.  It covers the largest POD any call may ask for (m = 512 snapshots:
+// 16 MiB of partial Gram tiles, 2 MiB each for K and for the eigenvector
+// coefficients, and the tile pairs).  Host code never passes the array's name
+// to a kernel or a copy: each device's address comes from hipGetSymbolAddress.
+constexpr size_t kPodScratchBytes = size_t(21) << 20;
+static __device__ __align__(256) char scratch[kPodScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of the scratch array, looked
+// up once per device with that device current.
+int scratch_address(char** out) {
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev); e != hipSuccess)
+    return report_error(MBX_EHIP, hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return report_error(MBX_EINVAL, "mbx_pod_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return report_error(MBX_EHIP, "mbx_pod_noalloc: hipGetSymbolAddress of the scratch array failed");
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MBX_OK;
+}
 
 // Eigen-decomposition of a symmetric m x m matrix by cyclic Jacobi rotations
 // (Jacobi 1846; the rotation that zeroes a_pq is chosen with |angle| <= pi/4,
@@ -105,6 +138,101 @@ struct DevBufs {
   }
 };
 
+// Device workspace of one POD call: the tile pairs, the partial Gram tiles of
+// every row slice, K and the scaled eigenvector matrix C.  part_bytes and the
+// other sizes follow from (n, m, k); the offsets are 256-byte aligned.
+struct PodPlan {
+  std::vector<int2> pairs;
+  int np = 0, nsplit = 0, tile = 0;
+  int64_t R = 0;
+  size_t off_pairs = 0, off_part = 0, off_K = 0, off_C = 0, total = 0;
+};
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+PodPlan pod_plan(int64_t n, int m, int k_cap) {
+  PodPlan P;
+  P.tile = gram_tile();
+  const int nt = (m + P.tile - 1) / P.tile;
+  for (int ti = 0; ti < nt; ++ti)
+    for (int tj = ti; tj < nt; ++tj) P.pairs.push_back(make_int2(ti, tj));
+  P.np = (int)P.pairs.size();
+  // row slices: about 2048 workgroups in all, each slice a multiple of the
+  // staging step
+  const int step = gram_rows_step();
+  const int64_t want = std::max<int64_t>(1, 2048 / P.np);
+  int64_t R = (n + want - 1) / want;
+  P.R = (R + step - 1) / step * step;
+  P.nsplit = (int)((n + P.R - 1) / P.R);
+  const int q = modes_cols_per_thread();
+  const int kpad = (k_cap + q - 1) / q * q;
+  P.off_pairs = 0;
+  P.off_part = up256(sizeof(int2) * P.np);
+  P.off_K = P.off_part + up256(sizeof(double) * (size_t)P.nsplit * P.np * P.tile * P.tile);
+  P.off_C = P.off_K + up256(sizeof(double) * (size_t)m * m);
+  P.total = P.off_C + up256(sizeof(double) * (size_t)m * kpad);
+  return P;
+}
+
+// The POD on a workspace ws of at least pod_plan(n, m, min(k_max, m)).total
+// bytes (device memory).  Synchronises the stream before it returns, on
+// every path that enqueued work.
+int pod_run(const double* S, int64_t n, int m, int64_t lds, const double* w, double rtol, int k_max,
+            double* modes, int64_t ldm, double* sigma, int* k_out, hipStream_t s, const PodPlan& P, char* ws) {
+  struct Drain {
+    hipStream_t s;
+    ~Drain() { (void)hipStreamSynchronize(s); }
+  } drain{s};
+  int2* d_pairs = (int2*)(ws + P.off_pairs);
+  double* d_part = (double*)(ws + P.off_part);
+  double* d_K = (double*)(ws + P.off_K);
+  double* d_C = (double*)(ws + P.off_C);
+  std::vector<double> K((size_t)m * m);
+  if (hipMemcpyAsync(d_pairs, P.pairs.data(), sizeof(int2) * P.np, hipMemcpyHostToDevice, s) != hipSuccess)
+    return report_error(MBX_EHIP, "mbx_pod: copy of the tile pairs failed");
+  prof_begin(PK_GRAM, s);
+  launch_gram(S, n, m, lds, w, P.R, P.nsplit, d_pairs, P.np, d_part, s);
+  // algorithmic bytes: every snapshot entry (and weight) read once
+  prof_end(PK_GRAM, s, 8.0 * (double)n * m + (w ? 8.0 * (double)n : 0.0));
+  launch_gram_reduce(d_part, P.nsplit, d_pairs, P.np, m, d_K, s);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(K.data(), d_K, sizeof(double) * K.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return report_error(MBX_EHIP, hipGetErrorString(e));
+  std::vector<double> lam, V;
+  if (!jacobi_eig(m, K, lam, V)) return report_error(MBX_ENAN, "mbx_pod: non-finite Gram matrix");
+  for (int i = 0; i < m; ++i) sigma[i] = std::sqrt(std::max(lam[i], 0.0));
+  int k = 0;
+  while (k < std::min(k_max, m) && sigma[k] > rtol * sigma[0] && sigma[k] > 0.0) ++k;
+  if (k == 0) return MBX_OK;
+  const int q = modes_cols_per_thread();
+  const int kpad = (k + q - 1) / q * q;
+  std::vector<double> C((size_t)m * kpad, 0.0);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < k; ++i) C[(size_t)j * kpad + i] = V[(size_t)i * m + j] / sigma[i];
+  e = hipMemcpyAsync(d_C, C.data(), sizeof(double) * C.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    launch_modes(S, n, m, lds, d_C, kpad, k, modes, ldm, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return report_error(MBX_EHIP, hipGetErrorString(e));
+  *k_out = k;
+  return MBX_OK;
+}
+
+int pod_check(const double* S, int64_t n, int m, int64_t lds, double rtol, int k_max, double* modes, int64_t ldm,
+              double* sigma, int* k_out) {
+  if (!S || !modes || !sigma || !k_out) return report_error(MBX_EINVAL, "mbx_pod: null pointer");
+  if (n < 1 || m < 1 || m > MBX_POD_MAX_SNAPSHOTS || lds < n || ldm < n || k_max < 1 || !(rtol >= 0.0) ||
+      !std::isfinite(rtol))
+    return report_error(MBX_EINVAL,
+                        "mbx_pod: need n >= 1, 1 <= m <= MBX_POD_MAX_SNAPSHOTS, lds >= n, ldm >= n, k_max >= 1, "
+                        "finite rtol >= 0");
+  *k_out = 0;
+  return MBX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -125,71 +253,27 @@ int mbx_sym_eig(int m, const double* A, double* lam, double* V) {
 
 int mbx_pod(const double* S, int64_t n, int m, int64_t lds, const double* w, double rtol, int k_max, double* modes,
             int64_t ldm, double* sigma, int* k_out, void* stream) {
-  if (!S || !modes || !sigma || !k_out) return report_error(MBX_EINVAL, "mbx_pod: null pointer");
-  if (n < 1 || m < 1 || m > MBX_POD_MAX_SNAPSHOTS || lds < n || ldm < n || k_max < 1 || !(rtol >= 0.0) ||
-      !std::isfinite(rtol))
-    return report_error(MBX_EINVAL,
-                        "mbx_pod: need n >= 1, 1 <= m <= MBX_POD_MAX_SNAPSHOTS, lds >= n, ldm >= n, k_max >= 1, "
-                        "finite rtol >= 0");
-  *k_out = 0;
+  if (int e = pod_check(S, n, m, lds, rtol, k_max, modes, ldm, sigma, k_out)) return e;
   hipStream_t s = (hipStream_t)stream;
-  const int tile = gram_tile();
-  const int nt = (m + tile - 1) / tile;
-  std::vector<int2> pairs;
-  for (int ti = 0; ti < nt; ++ti)
-    for (int tj = ti; tj < nt; ++tj) pairs.push_back(make_int2(ti, tj));
-  const int np = (int)pairs.size();
-  // row slices: about 2048 workgroups in all, each slice a multiple of the
-  // staging step
-  const int step = gram_rows_step();
-  const int64_t want = std::max<int64_t>(1, 2048 / np);
-  int64_t R = (n + want - 1) / want;
-  R = (R + step - 1) / step * step;
-  const int nsplit = (int)((n + R - 1) / R);
+  const PodPlan P = pod_plan(n, m, std::min(k_max, m));
   DevBufs d(s);
-  const size_t part_elems = (size_t)nsplit * np * tile * tile;
-  hipError_t e = hipMalloc(&d.p[0], sizeof(int2) * np);
-  if (e == hipSuccess) e = hipMalloc(&d.p[1], sizeof(double) * part_elems);
-  if (e == hipSuccess) e = hipMalloc(&d.p[2], sizeof(double) * (size_t)m * m);
-  if (e != hipSuccess) return report_error(MBX_ENOMEM, hipGetErrorString(e));
-  int2* d_pairs = (int2*)d.p[0];
-  double* d_part = (double*)d.p[1];
-  double* d_K = (double*)d.p[2];
-  std::vector<double> K((size_t)m * m);
-  if (hipMemcpyAsync(d_pairs, pairs.data(), sizeof(int2) * np, hipMemcpyHostToDevice, s) != hipSuccess)
-    return report_error(MBX_EHIP, "mbx_pod: copy of the tile pairs failed");
-  prof_begin(PK_GRAM, s);
-  launch_gram(S, n, m, lds, w, R, nsplit, d_pairs, np, d_part, s);
-  // algorithmic bytes: every snapshot entry (and weight) read once
-  prof_end(PK_GRAM, s, 8.0 * (double)n * m + (w ? 8.0 * (double)n : 0.0));
-  launch_gram_reduce(d_part, nsplit, d_pairs, np, m, d_K, s);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(K.data(), d_K, sizeof(double) * K.size(), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return report_error(MBX_EHIP, hipGetErrorString(e));
-  std::vector<double> lam, V;
-  if (!jacobi_eig(m, K, lam, V)) return report_error(MBX_ENAN, "mbx_pod: non-finite Gram matrix");
-  for (int i = 0; i < m; ++i) sigma[i] = std::sqrt(std::max(lam[i], 0.0));
-  int k = 0;
-  while (k < std::min(k_max, m) && sigma[k] > rtol * sigma[0] && sigma[k] > 0.0) ++k;
-  if (k == 0) return MBX_OK;
-  const int q = modes_cols_per_thread();
-  const int kpad = (k + q - 1) / q * q;
-  std::vector<double> C((size_t)m * kpad, 0.0);
-  for (int j = 0; j < m; ++j)
-    for (int i = 0; i < k; ++i) C[(size_t)j * kpad + i] = V[(size_t)i * m + j] / sigma[i];
-  e = hipMalloc(&d.p[3], sizeof(double) * C.size());
-  if (e != hipSuccess) return report_error(MBX_ENOMEM, hipGetErrorString(e));
-  double* d_C = (double*)d.p[3];
-  e = hipMemcpyAsync(d_C, C.data(), sizeof(double) * C.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) {
-    launch_modes(S, n, m, lds, d_C, kpad, k, modes, ldm, s);
-    e = hipGetLastError();
+  if (hipError_t e = hipMalloc(&d.p[0], P.total); e != hipSuccess) return report_error(MBX_ENOMEM, hipGetErrorString(e));
+  return pod_run(S, n, m, lds, w, rtol, k_max, modes, ldm, sigma, k_out, s, P, (char*)d.p[0]);
+}
+
+int mbx_pod_noalloc(const double* S, int64_t n, int m, int64_t lds, const double* w, double rtol, int k_max,
+                    double* modes, int64_t ldm, double* sigma, int* k_out, void* stream) {
+  if (int e = pod_check(S, n, m, lds, rtol, k_max, modes, ldm, sigma, k_out)) return e;
+  const PodPlan P = pod_plan(n, m, std::min(k_max, m));
+  if (P.total > kPodScratchBytes) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "mbx_pod_noalloc: the POD needs %zu workspace bytes, more than the %zu of the scratch array",
+             P.total, kPodScratchBytes);
+    return report_error(MBX_EINVAL, msg);
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return report_error(MBX_EHIP, hipGetErrorString(e));
-  *k_out = k;
-  return MBX_OK;
+  char* ws = nullptr;
+  if (int e = scratch_address(&ws)) return e;
+  return pod_run(S, n, m, lds, w, rtol, k_max, modes, ldm, sigma, k_out, (hipStream_t)stream, P, ws);
 }
 
 }  // extern "C"

@@ -95,6 +95,8 @@ SIGNATURES = {
     "mbx_cell_captured": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "mbx_pod": (_i, [_vp, ctypes.c_int64, _i, ctypes.c_int64, _vp, _d, _i, _vp, ctypes.c_int64, _dp,
                      ctypes.POINTER(_i), _vp]),
+    "mbx_pod_noalloc": (_i, [_vp, ctypes.c_int64, _i, ctypes.c_int64, _vp, _d, _i, _vp, ctypes.c_int64, _dp,
+                             ctypes.POINTER(_i), _vp]),
     "mbx_sym_eig": (_i, [_i, _dp, _dp, _dp]),
     "mbx_last_error": (ctypes.c_char_p, []),
     "mbx_profile": (_i, [_i]),
@@ -309,12 +311,14 @@ def batch_step(cells, dt: float):
 
 
 def pod(S_ptr: int, n: int, m: int, lds: int, modes_ptr: int, ldm: int, k_max: int, rtol: float = 1e-7,
-        w_ptr: int = 0, stream=None):
+        w_ptr: int = 0, stream=None, noalloc: bool = False):
     """POD of the n x m device snapshots at S_ptr into the device modes at
-    modes_ptr (column-major); returns (sigma: all m singular values, k)."""
+    modes_ptr (column-major); returns (sigma: all m singular values, k).
+    noalloc=True calls mbx_pod_noalloc (static device workspace)."""
     sigma = np.empty(m)
     k = _i()
-    _check(load().mbx_pod(_vp(S_ptr), int(n), int(m), int(lds), _vp(w_ptr) if w_ptr else None, float(rtol),
+    fn = load().mbx_pod_noalloc if noalloc else load().mbx_pod
+    _check(fn(_vp(S_ptr), int(n), int(m), int(lds), _vp(w_ptr) if w_ptr else None, float(rtol),
                           int(k_max), _vp(modes_ptr), int(ldm), sigma.ctypes.data_as(_dp), ctypes.byref(k),
                           _vp(stream) if stream else None))
     return sigma, k.value
