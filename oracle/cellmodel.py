@@ -425,9 +425,20 @@ def newton_step(model: Model, u_old, dt, u_guess=None, tol_du=1e-10, tol_res=1e-
     raise NewtonFailure(f"no convergence in {max_iter} iterations: {hist[-3:]}")
 
 
-def simulate(labels, prm: dict, dt: float, steps: int, u0=None, **kw):
-    """Run `steps` implicit Euler steps from the equilibrium (or u0).
-    Returns the model and the list of states [u^0, ..., u^steps]."""
+def cutoff_reached(V: float, V_cut, I_app: float) -> bool:
+    """Voltage cutoff of a constant-current run: a charge (I_app >= 0) stops
+    once the cell voltage is at or above V_cut, a discharge once it is at or
+    below it.  No interpolation inside a step: the step that crosses is the
+    last one."""
+    if V_cut is None or V_cut <= 0:
+        return False
+    return V >= V_cut if I_app >= 0 else V <= V_cut
+
+
+def simulate(labels, prm: dict, dt: float, steps: int, u0=None, V_cut=None, **kw):
+    """Run up to `steps` implicit Euler steps from the equilibrium (or u0),
+    stopping after the first step whose cell voltage reaches V_cut (if given).
+    Returns the model, the list of states [u^0, ..., u^k] and per-step infos."""
     model = Model(Geometry(labels), prm)
     u = model.initial_state() if u0 is None else np.array(u0, dtype=float)
     states = [u]
@@ -436,4 +447,6 @@ def simulate(labels, prm: dict, dt: float, steps: int, u0=None, **kw):
         u, info = newton_step(model, u, dt, **kw)
         states.append(u)
         infos.append(info)
+        if cutoff_reached(model.voltage(u), V_cut, prm["I_app"]):
+            break
     return model, states, infos

@@ -387,3 +387,78 @@ def test_geometry_validation():
     lab[0] = I.PORE                         # no anode solid on the collector plane
     with pytest.raises(ValueError):
         Geometry(lab)
+
+
+# ---------------------------------------------------------------------------
+# C-11 open-circuit potentials: values the reading states and identities of the
+# form U(x) = a0 + a1 ln((1-x)/x).  A swapped log argument, a dropped a0 or a
+# sign error in docp fails one of these.
+# ---------------------------------------------------------------------------
+def test_ocp_stated_values():
+    p = I.CellParams()
+    # the reading states U_an(0.05) = 0.208 V and an initial OCV of about 3.57 V
+    assert ocp(p.U_an, 0.05) == pytest.approx(0.2083, abs=5e-4)
+    ocv = ocp(p.U_ca, 0.95) - ocp(p.U_an, 0.05)
+    assert ocv == pytest.approx(3.565, abs=5e-3)
+    # an electrode near full lithiation sits below its half-SOC value, near
+    # empty above it: U decreases with the stoichiometry
+    x = np.linspace(0.01, 0.99, 99)
+    assert np.all(np.diff(ocp(p.U_an, x)) < 0) and np.all(np.diff(ocp(p.U_ca, x)) < 0)
+
+
+def test_ocp_identities_and_slope():
+    a = (0.37, 0.021)
+    assert ocp(a, 0.5) == a[0]                                       # ln 1 = 0
+    e = np.e
+    assert ocp(a, 1.0 / (1.0 + e)) == pytest.approx(a[0] + a[1], rel=1e-15, abs=1e-15)   # (1-x)/x = e
+    x = np.array([0.02, 0.2, 0.5, 0.7, 0.97])
+    np.testing.assert_allclose(ocp(a, x) + ocp(a, 1.0 - x), 2 * a[0], rtol=1e-14)          # odd about x = 1/2
+    # derivative against the complex-step derivative of U (exact to rounding)
+    hcs = 1e-30
+    d_cs = np.imag(ocp(a, x + 1j * hcs)) / hcs
+    np.testing.assert_allclose(oracle.cellmodel.docp(a, x), d_cs, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.5 output functional s_ac (mean Li concentration of each electrode's
+# active material): the initial stoichiometries at equilibrium, and without
+# plating a drift of exactly I dt / (F V_solid) per step in each electrode
+# (charge conservation across the interfaces, eq. 2.4).
+# ---------------------------------------------------------------------------
+def test_mean_solid_closed_forms():
+    w = I.config0()
+    prm = params(I_app=w.params.I_app, plating=0)
+    model = Model(Geometry(w.labels), prm)
+    u0 = model.initial_state()
+    s0 = model.mean_solid(u0)
+    assert s0["anode"] == pytest.approx(prm["x0"] * prm["cmax_an"], rel=1e-15)
+    assert s0["cathode"] == pytest.approx(prm["y0"] * prm["cmax_ca"], rel=1e-15)
+    dt = 10.0
+    u = u0
+    n_an = np.count_nonzero(w.labels == I.ANODE)
+    n_ca = np.count_nonzero(w.labels == I.CATHODE)
+    vol = prm["h"] ** 3
+    for k in range(1, 3):
+        u, _ = newton_step(model, u, dt, tol_du=1e-12)
+        s = model.mean_solid(u)
+        rise = k * prm["I_app"] * dt / (FARADAY * vol)
+        assert s["anode"] == pytest.approx(s0["anode"] + rise / n_an, rel=1e-9)
+        assert s["cathode"] == pytest.approx(s0["cathode"] - rise / n_ca, rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# C-15 voltage cutoff: a run stops after the first step at or above V_cut.
+# ---------------------------------------------------------------------------
+def test_cutoff_stops_after_the_first_crossing():
+    lab = column(3, 2, 3)
+    prm = params(I_app=5.0 * (0.44e-6) ** 2)          # 5 A/m^2 through the 1 x 1 column
+    model, states, _ = oracle.simulate(lab, prm, 20.0, 8)
+    V = np.array([model.voltage(u) for u in states])
+    assert np.all(np.diff(V[1:]) > 0)
+    V_cut = 0.5 * (V[4] + V[5])                      # crossed during step 5
+    _, cut_states, _ = oracle.simulate(lab, prm, 20.0, 8, V_cut=V_cut)
+    assert len(cut_states) - 1 == 5
+    np.testing.assert_array_equal(cut_states[-1], states[5])
+    assert not oracle.cutoff_reached(V[4], V_cut, prm["I_app"]) and oracle.cutoff_reached(V[5], V_cut, prm["I_app"])
+    assert oracle.cutoff_reached(3.0, 3.1, -1.0) and not oracle.cutoff_reached(3.2, 3.1, -1.0)   # discharge
+    assert not oracle.cutoff_reached(9.0, None, 1.0) and not oracle.cutoff_reached(9.0, 0.0, 1.0)
