@@ -82,12 +82,15 @@ typedef struct {
   double n_c;            /* f_pre constant, mol/m^2 */
   int plating;           /* 0: no plating reaction, 1: plating/stripping on */
   int precision;         /* MBX_FP64 or MBX_MIXED */
-  double newton_tol;     /* scaled update tolerance (default 1e-9 if <= 0) */
+  double newton_tol;     /* scaled update tolerance (if <= 0: 1e-9 for MBX_FP64, 1e-8 for MBX_MIXED) */
   double res_tol;        /* scaled residual tolerance (default 1e-6 if <= 0) */
   double krylov_rtol;    /* floor of the GMRES relative tolerance (forcing term) (default 1e-6 if <= 0) */
   int newton_max;        /* Newton iteration cap (default 30 if <= 0) */
   int krylov_max;        /* GMRES iteration cap per Newton iteration (default 600 if <= 0); at the cap the
                             correction is taken as it stands (inexact Newton) */
+  double V_cut;          /* cell-voltage cutoff, V (0: none).  A run (mbx_cell_run, a served request) stops
+                            after the first step whose voltage reaches it: V >= V_cut while charging
+                            (I_app > 0), V <= V_cut while discharging; no interpolation within the step */
 } mbx_params;
 
 typedef struct {
@@ -103,8 +106,8 @@ typedef struct {
 
 typedef struct mbx_cell mbx_cell;
 
-/* Fill *p with the library's defaults for the numerical knobs and zeros for
- * the physical fields.  Returns MBX_EINVAL on a null pointer. */
+/* Fill *p with the library's defaults for the numerical knobs (newton_tol = 0:
+ * the precision mode's default) and zeros for the physical fields.  Returns MBX_EINVAL on a null pointer. */
 int mbx_params_default(mbx_params *p);
 
 /* Create a cell from voxel labels (Sec. 2.4: the voxel image defines the
@@ -175,6 +178,24 @@ int mbx_cell_captured(const mbx_cell *c, int *count, int *dropped);
  * collector faces of the solid potential extrapolated across half a voxel
  * with the applied flux; the anode collector is the 0 V reference. */
 int mbx_cell_voltage(const mbx_cell *c, double *V);
+
+/* Mean lithium concentration of each electrode's active material, mol/m^3:
+ * out[0] anode, out[1] cathode (Sec. 2.5 output functional s_ac, the average
+ * Li concentration in the electrode, a linear functional of the state). */
+int mbx_cell_mean_solid(const mbx_cell *c, double out[2]);
+
+/* Step loop with the voltage cutoff (Sec. 2.5 output s_cp as the stopping
+ * criterion of a charge): advances up to max_steps implicit Euler steps of dt
+ * (each as mbx_cell_step) and stops after the first step whose cell voltage
+ * reaches p->V_cut (see mbx_params; V_cut = 0 runs all max_steps).
+ *   V_out     : host, max_steps doubles or null; receives V after each step taken
+ *   steps_out : steps completed (required)
+ *   cutoff_out: 1 if the cutoff stopped the run, else 0 (may be null)
+ *   retried   : steps that were retried as two half steps (may be null)
+ * Returns MBX_OK, or the code of the first failed step (the state then stays
+ * at the start of that step, *steps_out counts the steps before it). */
+int mbx_cell_run(mbx_cell *c, double dt, int max_steps, double *V_out, int *steps_out, int *cutoff_out,
+                 int *retried);
 
 /* Lithium inventories (mol) in electrolyte, anode solid, cathode solid and
  * the plated layer (Sec. 2.4 conservative scheme: at convergence the total
@@ -258,6 +279,11 @@ typedef struct {
   int64_t newton_iters;  /* totals over its steps */
   int64_t krylov_iters;
   int64_t n_vox;         /* voxels (after admission) */
+  int64_t n_an_faces;    /* anode interface faces = length of the plated-amount array (after admission) */
+  int cutoff;            /* 1 if a step brought the voltage to the request's cutoff (p->V_cut); the
+                            request stopped after that step */
+  int retried;           /* steps that were retried as two half steps (dt/2 each) */
+  double s_ac[2];        /* mean anode / cathode solid concentration after the last step, mol/m^3 */
 } mbx_request_info;
 
 typedef struct {
@@ -278,7 +304,7 @@ int mbx_server_create(int64_t budget_bytes, int precision, double dt, int keep_s
                       mbx_server **out);
 
 /* Queue a request (labels and parameters as mbx_cell_create; copied) for
- * n_steps steps; *id receives its handle.  p->precision must equal the
+ * n_steps steps, fewer if p->V_cut stops it first; *id receives its handle.  p->precision must equal the
  * server's.  MBX_EBUDGET if the request alone exceeds the budget. */
 int mbx_server_submit(mbx_server *s, const uint8_t *labels, int nx, int ny, int nz, const mbx_params *p,
                       int n_steps, int64_t *id);

@@ -2,7 +2,8 @@
 //
 // One implicit Euler step (eq. 2.13) is a damped Newton iteration on the FP64
 // residual; each Newton correction solves the condensed, scaled Jacobian
-// system with restarted GMRES (right preconditioned, classical Gram-Schmidt
+// system with restarted flexible GMRES (right preconditioned, the
+// preconditioned basis kept as the product saw it; classical Gram-Schmidt
 // with one re-orthogonalisation).  Every kernel launch covers all cells of a
 // batch; the host only reads a few per-cell scalars at sync points.
 #include <hip/hip_runtime.h>
@@ -138,6 +139,7 @@ struct mbx_cell {
   uint64_t id;
   mbx_params p;
   int nx, ny, nz, N, F_an, F_ca, n_top, nblk, m;
+  int64_t n_an_vox = 0, n_ca_vox = 0;   // solid voxels per electrode (the s_ac denominators)
   bool mixed;
   hipStream_t s;
   char* dmem = nullptr;
@@ -226,10 +228,25 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
     L.add(sizeof(int2) * ((half_cells(ld, l) + kBlock - 1) / kBlock));
   }
   L.add(sizeof(int2) * ((half_cells(ld, 0) + kBlock - 1) / kBlock));   // 41 + 7(n-1): level-0 blkh
+  L.add(16 * (size_t)std::max(F_an + F_ca, 1));                        // 42 + 7(n-1): face results
+  L.add((size_t)m * 2 * N * kt);                                       // 43 + 7(n-1): flexible-GMRES basis Z
   return L;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+namespace mbx {
+// Voltage cutoff (V_cut > 0): reached when a charge (I_app >= 0) brings the
+// cell voltage up to V_cut, or a discharge brings it down to V_cut.
+bool cutoff_reached(const mbx_params& p, double V) {
+  if (!(p.V_cut > 0.0)) return false;
+  return p.I_app >= 0.0 ? V >= p.V_cut : V <= p.V_cut;
+}
+}  // namespace mbx
+
+namespace {
 
 int check_params(const mbx_params* p) {
   if (!p) return fail(MBX_EINVAL, "null parameter struct");
@@ -247,6 +264,7 @@ int check_params(const mbx_params* p) {
   if (!(std::isfinite(p->i00_pl) && p->i00_pl >= 0.0)) return fail(MBX_EINVAL, "i00_pl must be finite and >= 0");
   if (p->precision != MBX_FP64 && p->precision != MBX_MIXED) return fail(MBX_EINVAL, "unknown precision mode");
   if (p->plating != 0 && p->plating != 1) return fail(MBX_EINVAL, "plating must be 0 or 1");
+  if (!(std::isfinite(p->V_cut) && p->V_cut >= 0.0)) return fail(MBX_EINVAL, "V_cut must be finite and >= 0");
   return MBX_OK;
 }
 
@@ -322,8 +340,11 @@ struct Batch {
     BatchLaunch b{};
     for (const mbx_cell* c : cells) {
       const double N = c->N, Fa = c->F_an, Fc = c->F_ca, kt = c->mixed ? 4.0 : 8.0;
-      b.bytes_residual[0] += 44.0 * N + 24.0 * Fa;
-      b.bytes_residual[1] += 44.0 * N + 24.0 * Fa + kt * N + (6.0 * kt + 16.0) * Fa + 4.0 * kt * Fc;
+      // state, old state, labels and rows of every voxel; the face lists; the
+      // plated amounts (old, guess, new) and rows; with the linearisation the
+      // face records, conductances and the pore 1/c weights
+      b.bytes_residual[0] += 44.0 * N + 4.0 * (Fa + Fc) + 32.0 * Fa;
+      b.bytes_residual[1] += 44.0 * N + 4.0 * (Fa + Fc) + 32.0 * Fa + kt * N + (6.0 * kt + 16.0) * Fa + 4.0 * kt * Fc;
       b.bytes_matvec += (4.0 + 5.0 * kt) * N + 5.0 * kt * Fa + 3.0 * kt * Fc;
       // one half sweep: meta of all voxels, x of the other colour, b of its own,
       // the new x; averaged over the two operators: interface conductances
@@ -336,6 +357,7 @@ struct Batch {
     b.blk = one ? nullptr : d_blk;
     b.nblk = nblk;
     b.ncell = (int)cells.size();
+    b.faces_single = one ? cells[0]->F_an + cells[0]->F_ca : 0;
     b.maxlev = maxlev;
     b.maxfuse = maxfuse;
     b.fused_lds = 0;
@@ -521,12 +543,13 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
   const int check = 4;
   int total = 0;
   launch_gm_start<KT>(B.bl(), 1, B.s);
-  launch_gm_flags(B.bl(), 1, B.s);
+  const int refine = sizeof(KT) < sizeof(double);
+  launch_gm_flags(B.bl(), 1, refine, B.s);
   while (total < max_iters) {
     int k = 0;
     for (; k < m; ++k) {
       launch_precond<KT>(B.bl(), k, 0, B.s);
-      launch_matvec<KT>(B.bl(), VEC_Z, VEC_W, 0, B.s);
+      launch_matvec<KT>(B.bl(), VEC_Z, VEC_W, 0, k, B.s);
       // classical Gram-Schmidt with one re-orthogonalisation (CGS2)
       launch_multidot<KT>(B.bl(), k, 0, B.s);   // H(:,k) = V^T w
       launch_orth_dots<KT>(B.bl(), k, B.s);     // w -= V H(:,k); tmp = V^T w
@@ -555,12 +578,10 @@ int gmres(Batch& B, int max_iters, int* iters_out) {
       if (int e = B.set_active(on)) return e;   // cycle end: every active cell
     }
     launch_backsolve(B.bl(), B.s);
-    launch_combine<KT>(B.bl(), B.s);
-    launch_precond<KT>(B.bl(), VEC_W, -1, B.s);
-    launch_add_z_to_x<KT>(B.bl(), B.s);
+    launch_update_x<KT>(B.bl(), B.s);          // flexible GMRES: x += Z y
     launch_true_residual<KT>(B.bl(), B.s);   // w = b - J x for the cells that restart
     launch_gm_start<KT>(B.bl(), 0, B.s);
-    launch_gm_flags(B.bl(), 0, B.s);
+    launch_gm_flags(B.bl(), 0, refine, B.s);
     if (int e = B.gather()) return e;
     bool all = true;
     for (size_t c = 0; c < B.cells.size(); ++c) {
@@ -581,17 +602,16 @@ constexpr int kSlowSolve = 60;        // Krylov iterations of one correction tha
 constexpr int kStallMinIter = 8;      // Newton iterations before stagnation is tested
 constexpr size_t kStallWindow = 4;
 constexpr int kMaxHalvings = 1;       // a failed step is retried once, as two half steps
-constexpr double kEtaMax = 0.1;        // loosest GMRES relative tolerance of a Newton correction (FP64)
-constexpr double kEtaMaxMixed = 1e-4;  // ... in the mixed mode
+constexpr double kEtaMax = 0.1;        // loosest GMRES relative tolerance of a Newton correction
 constexpr double kEwGamma = 0.9;
 template <typename KT>
 int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
   const int nc = (int)B.cells.size();
   auto t0 = std::chrono::steady_clock::now();
   std::vector<int> st(nc, 1);   // 1 running, 0 converged, < 0 failed
-  // the mixed mode accepts limited steps without a residual test, so its
-  // corrections are solved tighter
-  const double eta_max = B.mixed ? kEtaMaxMixed : kEtaMax;
+  // both modes meet the forcing term with the true (FP64-accumulated)
+  // residual: the mixed mode refines its FP32 corrections inside GMRES
+  const double eta_max = kEtaMax;
   std::vector<double> rn(nc), rmax(nc), res0(nc), eta(nc, eta_max), du(nc, 0.0), lam(nc, 1.0), mr(nc), dnm(nc, 0.0),
       qconv(nc, 1.0);
   // FP32 Krylov cannot resolve relative residuals much below 1e-6
@@ -696,17 +716,13 @@ int newton(Batch& B, double dt, int* status, mbx_step_info* infos) {
       if (int e = B.gather()) return e;
       for (int c = 0; c < nc; ++c) {
         if (!searching[c] || !B.cells[c]->h.active) continue;
-        // FP64: the scaled residual 2-norm must not grow.  Mixed: an FP32
-        // correction carries rounding noise of ~1e-7 |x| into every entry,
-        // which rows with large conductance (anode potential) turn into
-        // residual growth unrelated to progress; the limited full step is
-        // taken and the FP64 residual of the next Newton iteration refines it.
+        // the scaled FP64 residual 2-norm must not grow (both modes: the mixed
+        // mode's corrections meet their tolerance with the true residual)
         const double r1 = std::sqrt(B.red(c, RED_RSQ));
         const double m1 = std::sqrt(B.red(c, RED_MSQ));
         // once the iterate meets the residual tolerance the remaining
         // differences are rounding noise: take the full step
-        const bool ok = std::isfinite(r1) &&
-                        (B.mixed || r1 <= rn[c] || rmax[c] <= B.cells[c]->p.res_tol || hlv == 20);
+        const bool ok = std::isfinite(r1) && (r1 <= rn[c] || rmax[c] <= B.cells[c]->p.res_tol || hlv == 20);
         if (ok) {
           searching[c] = 0;
           du[c] = dmax[c] / lam[c];
@@ -838,12 +854,16 @@ int step_recover(std::vector<mbx_cell*> cells, double dt, int* status, mbx_step_
   for (int i = 0; i < n; ++i)
     if (status[i] == MBX_ENEWTON || status[i] == MBX_ENAN) fail_idx.push_back(i);
   if (fail_idx.empty() || depth >= kMaxHalvings) return MBX_OK;
-  // retry the failed cells as two half steps, from a host copy of u^n
+  // retry the failed cells as two half steps, from a host copy of u^n (and
+  // of the snapshot count: a retry that fails drops its columns again)
   std::vector<mbx_cell*> sub;
   std::vector<std::vector<double>> save(fail_idx.size() * 3);
+  std::vector<int> cap_save(fail_idx.size()), capd_save(fail_idx.size());
   for (size_t k = 0; k < fail_idx.size(); ++k) {
     mbx_cell* c = cells[fail_idx[k]];
     sub.push_back(c);
+    cap_save[k] = c->cap_count;
+    capd_save[k] = c->cap_dropped;
     save[3 * k].resize(c->N);
     save[3 * k + 1].resize(c->N);
     save[3 * k + 2].resize(std::max(c->F_an, 1));
@@ -896,6 +916,8 @@ int step_recover(std::vector<mbx_cell*> cells, double dt, int* status, mbx_step_
       mbx_cell* c = sub[k];
       if (int e = mbx_cell_set_state(c, save[3 * k].data(), save[3 * k + 1].data(), save[3 * k + 2].data(), 0))
         return e;
+      c->cap_count = cap_save[k];
+      c->cap_dropped = capd_save[k];
     }
   }
   return MBX_OK;
@@ -919,7 +941,7 @@ const char* mbx_last_error(void) { return g_err.c_str(); }
 int mbx_params_default(mbx_params* p) {
   if (!p) return fail(MBX_EINVAL, "null parameter struct");
   std::memset(p, 0, sizeof *p);
-  p->newton_tol = 1e-9;
+  p->newton_tol = 0.0;   // the precision mode's default
   p->res_tol = 1e-6;
   p->krylov_rtol = 1e-6;
   p->newton_max = 30;
@@ -946,7 +968,8 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   if (N64 > (1 << 28)) return fail(MBX_EINVAL, "grid too large (more than 2^28 voxels)");
   if (int e = check_params(pin)) return e;
   mbx_params p = *pin;
-  if (p.newton_tol <= 0) p.newton_tol = 1e-9;
+  // scaled-update tolerance: 100x below each mode's state-error target (FP64 1e-8, mixed 1e-6)
+  if (p.newton_tol <= 0) p.newton_tol = p.precision == MBX_MIXED ? 1e-8 : 1e-9;
   if (p.res_tol <= 0) p.res_tol = 1e-6;
   if (p.krylov_rtol <= 0) p.krylov_rtol = 1e-6;
   if (p.newton_max <= 0) p.newton_max = 30;
@@ -1019,6 +1042,10 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   c->F_an = F_an;
   c->F_ca = F_ca;
   c->n_top = hflags[2];
+  for (int i = 0; i < N; ++i) {
+    c->n_an_vox += labels[i] == ANODE;
+    c->n_ca_vox += labels[i] == CATHODE;
+  }
   c->nblk = (N + kBlock - 1) / kBlock;
   c->m = restart_len();
   c->mixed = p.precision == MBX_MIXED;
@@ -1114,6 +1141,10 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
     c->lvlh_nblk[l] = (int)((half_cells(c->ld, l) + kBlock - 1) / kBlock);
   }
   c->lvlh_blk[0] = (int2*)(b + L.off[41 + 7 * (c->ld.n - 1)]);
+  h.fres = (double*)(b + L.off[42 + 7 * (c->ld.n - 1)]);
+  h.Zb = b + L.off[43 + 7 * (c->ld.n - 1)];
+  h.faces_an = c->faces_an;
+  h.faces_ca = c->faces_ca;
   c->lvlh_nblk[0] = (int)((half_cells(c->ld, 0) + kBlock - 1) / kBlock);
   h.m = c->m;
   h.lam = 1.0;
@@ -1287,6 +1318,36 @@ int mbx_cell_inventory(const mbx_cell* cc, double out[4]) {
   return MBX_OK;
 }
 
+int mbx_cell_mean_solid(const mbx_cell* cc, double out[2]) {
+  if (!cc || !out) return fail(MBX_EINVAL, "null argument");
+  mbx_cell* c = const_cast<mbx_cell*>(cc);
+  if (int e = sync_outputs(c)) return e;
+  out[0] = c->h_gather[RED_INV0 + 1] / (c->h.Vol * (double)c->n_an_vox);
+  out[1] = c->h_gather[RED_INV0 + 2] / (c->h.Vol * (double)c->n_ca_vox);
+  return MBX_OK;
+}
+
+int mbx_cell_run(mbx_cell* c, double dt, int max_steps, double* V_out, int* steps_out, int* cutoff_out,
+                 int* retried) {
+  if (!c || !steps_out) return fail(MBX_EINVAL, "null cell or steps_out");
+  if (max_steps < 0) return fail(MBX_EINVAL, "max_steps must be >= 0");
+  *steps_out = 0;
+  if (cutoff_out) *cutoff_out = 0;
+  if (retried) *retried = 0;
+  for (int k = 0; k < max_steps; ++k) {
+    mbx_step_info info{};
+    if (int e = mbx_cell_step(c, dt, &info)) return e;
+    *steps_out = k + 1;
+    if (V_out) V_out[k] = info.V;
+    if (retried && info.substeps > 1) ++*retried;
+    if (cutoff_reached(c->p, info.V)) {
+      if (cutoff_out) *cutoff_out = 1;
+      break;
+    }
+  }
+  return MBX_OK;
+}
+
 static int load_eval_state(mbx_cell* c, const double* cu, const double* pu, const double* nu, const double* cold,
                            const double* nold, double dt) {
   if (!cu || !pu || !cold || (c->F_an && (!nu || !nold))) return fail(MBX_EINVAL, "null argument");
@@ -1332,11 +1393,11 @@ int mbx_cell_jvp(mbx_cell* c, const double* cu, const double* pu, const double* 
   HIPCHK(hipMemcpyAsync(c->h.dc, v, N16, hipMemcpyHostToDevice, c->s));
   if (c->mixed) {
     launch_convert<float>(b.bl(), VEC_Z, 0, c->s);
-    launch_matvec<float>(b.bl(), VEC_Z, VEC_W, 0, c->s);
+    launch_matvec<float>(b.bl(), VEC_Z, VEC_W, 0, -1, c->s);
     launch_convert<float>(b.bl(), VEC_W, 1, c->s);
   } else {
     launch_convert<double>(b.bl(), VEC_Z, 0, c->s);
-    launch_matvec<double>(b.bl(), VEC_Z, VEC_W, 0, c->s);
+    launch_matvec<double>(b.bl(), VEC_Z, VEC_W, 0, -1, c->s);
     launch_convert<double>(b.bl(), VEC_W, 1, c->s);
   }
   HIPCHK(hipMemcpyAsync(y, c->h.dc, N16, hipMemcpyDeviceToHost, c->s));

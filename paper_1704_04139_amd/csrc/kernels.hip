@@ -14,6 +14,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 namespace mbx {
 
 template <typename KT>
@@ -119,18 +121,94 @@ __global__ void __launch_bounds__(kBlock) k_init_state(CellDev* cells, const int
 
 // --------------------------------------------------------------- residual
 // FP64 residual of the implicit Euler system (eq. 2.13) at the trial state,
-// with every face flux evaluated from the two adjacent voxels in the same
-// order on both sides (so the scatter conserves Li to rounding):
+// in two passes.
+//
+// Interface pass (k_iface): one thread per solid/pore face of the compacted
+// per-phase face lists (anode faces, then cathode faces, each in canonical
+// order).  It evaluates the face's Butler-Volmer intercalation (eq. 2.5) and,
+// on anode faces, plating/stripping (eq. 2.8) with the plated amount
+// eliminated by its own balance (plated_root) -- once per face -- and stores
+// the intercalation and the total current of the face, the plated-amount row
+// R^n, and with LIN the scaled face coefficients of the linearisation
+// (plating condensed onto the voxel unknowns) and the potential-operator
+// conductance of the face.
+//
+// Voxel pass (k_residual): one thread per voxel; every same-phase face flux
+// is evaluated from the two adjacent voxels in the same orientation on both
+// sides, every interface face's current is read from the face pass, so the
+// scatter conserves Li to rounding:
 //   pore/pore   j = -kappa dphi/h + kappa (1-t+) theta RT/F dln c/h,
 //               N = -De dc/h + t+/F j                     (eqs. 2.3-2.4, 2.6)
 //   solid/solid N = -Ds dc/h, j = -sigma dphi/h            (eqs. 2.1-2.2)
-//   solid/pore  Butler-Volmer intercalation (2.5) and, on anode faces,
-//               plating/stripping (2.8) as the numerical flux (eq. 2.4)
+//   solid/pore  the face current as the numerical flux (eq. 2.4)
 //   collectors  anode at phi = 0 across h/2; cathode galvanostatic.
-// With LIN it also writes the linearisation used by the Krylov solve: the
-// scaled face coefficients (plating condensed onto the voxel unknowns), the
-// potential-operator conductance of each interface face and the pore 1/c
-// coefficient.
+// With LIN it also writes the pore 1/c coefficient.
+__device__ inline int face_neighbour(const CellDev& cd, int s, int d) {
+  switch (d) {
+    case 0: return s - 1;
+    case 1: return s + 1;
+    case 2: return s - cd.nx;
+    case 3: return s + cd.nx;
+    case 4: return s - cd.nx * cd.ny;
+    default: return s + cd.nx * cd.ny;
+  }
+}
+
+// grid_stride: blocks per cell of the launch (the launch covers the cell's
+// faces in strides of grid_stride * kBlock); 0 = the cell's voxel block count.
+template <bool LIN, typename KT>
+__global__ void __launch_bounds__(kBlock) k_iface(CellDev* cells, const int2* __restrict__ blk, int grid_stride) {
+  const int2 bb = block_of(blk);
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  const int Fa = cd.F_an, F = cd.F_an + cd.F_ca;
+  const int stride = (grid_stride > 0 ? grid_stride : cd.nblk) * kBlock;
+  const bool plate = cd.plating != 0;
+  const double A = cd.A, dt = cd.dt, mu = cd.mu_ref;
+  for (int g = bb.y * kBlock + (int)threadIdx.x; g < F; g += stride) {
+    const bool an = g < Fa;
+    const int f = an ? g : g - Fa;
+    const int e = an ? cd.faces_an[f] : cd.faces_ca[f];
+    const int sv = e >> 3, d = e & 7;
+    const int pv = face_neighbour(cd, sv, d);
+    const double cs = cd.c_try[sv], ce = cd.c_try[pv], ps = cd.phi_try[sv], pe = cd.phi_try[pv];
+    double nf = 0.0;
+    if (an) {
+      nf = cd.n_try[f];
+      if (cd.elim_n) {
+        nf = plate ? plated_root(cd, ce, ps, pe, cd.n_old[f], cd.n[f]) : cd.n_old[f];
+        cd.n_try[f] = nf;
+      }
+    }
+    const Kin q = interface_kinetics(cd, an ? ANODE : CATHODE, cs, ce, ps, pe, nf, an && plate, LIN);
+    cd.fres[g] = q.ii;
+    cd.fres[(size_t)F + g] = q.ii + q.ip;
+    if (an) {
+      const double Rn = A * (nf - cd.n_old[f]) / dt + A * q.ip / kFaraday;
+      cd.Rn[f] = Rn;
+      if (LIN) {
+        const double jnn = A / dt + A * q.p_n / kFaraday;
+        const double kap = (A / dt) / jnn;
+        KT* co = (KT*)cd.coef_an + 5 * (size_t)f;
+        co[0] = (KT)(q.d_cs * cd.cmax[0] / mu);
+        co[1] = (KT)(q.d_ce * cd.c0 / mu);
+        co[2] = (KT)(q.g * cd.VT / mu);
+        co[3] = (KT)(kap * q.p_ce * cd.c0 / mu);
+        co[4] = (KT)(kap * q.g_p * cd.VT / mu);
+        cd.rn_jnn[f] = Rn / jnn;
+        cd.sq[f] = q.p_n * Rn / (jnn * mu);
+        ((KT*)cd.cond_an)[f] = (KT)((q.g + kap * q.g_p) * cd.VT / mu);
+      }
+    } else if (LIN) {
+      KT* co = (KT*)cd.coef_ca + 3 * (size_t)f;
+      co[0] = (KT)(q.d_cs * cd.cmax[1] / mu);
+      co[1] = (KT)(q.d_ce * cd.c0 / mu);
+      co[2] = (KT)(q.g * cd.VT / mu);
+      ((KT*)cd.cond_ca)[f] = co[2];
+    }
+  }
+}
+
 template <bool LIN, typename KT>
 __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2* __restrict__ blk) {
   const int2 bb = block_of(blk);
@@ -145,7 +223,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
     const int L = lab_of(mi);
     const double ci = cd.c_try[i], pi = cd.phi_try[i];
     const double A = cd.A, h = cd.h, dt = cd.dt;
-    const bool plate = cd.plating != 0;
+    const size_t F = (size_t)cd.F_an + cd.F_ca;
     double Rc = cd.Vol * (ci - cd.c_old[i]) / dt;
     double Rp = 0.0;
     const double lci = (L == PORE) ? log(ci) : 0.0;   // ln c of this voxel, shared by its pore faces
@@ -162,13 +240,13 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
       }
       const uint32_t mk = cd.meta[k];
       const int Lk = lab_of(mk);
-      const double ck = cd.c_try[k], pk = cd.phi_try[k];
       const bool lo = i < k;
       const double sgn = lo ? 1.0 : -1.0;
-      const double ca = lo ? ci : ck, cb = lo ? ck : ci;
-      const double pa = lo ? pi : pk, pb = lo ? pk : pi;
       weight_add(cd, L, Lk, wc, wp);
       if (L == PORE && Lk == PORE) {
+        const double ck = cd.c_try[k], pk = cd.phi_try[k];
+        const double ca = lo ? ci : ck, cb = lo ? ck : ci;
+        const double pa = lo ? pi : pk, pb = lo ? pk : pi;
         const double lck = log(ck);
         const double lca = lo ? lci : lck, lcb = lo ? lck : lci;
         const double j = -cd.kappa * (pb - pa) / h + cd.Kd * (lcb - lca);
@@ -176,59 +254,32 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
         Rc += sgn * (A * Nf);
         Rp += sgn * (A * j);
       } else if (L == Lk) {
+        const double ck = cd.c_try[k], pk = cd.phi_try[k];
+        const double ca = lo ? ci : ck, cb = lo ? ck : ci;
+        const double pa = lo ? pi : pk, pb = lo ? pk : pi;
         const int s = L - 1;
         const double Nf = -cd.Ds[s] * (cb - ca) / h;
         const double j = -cd.sigma[s] * (pb - pa) / h;
         Rc += sgn * (A * Nf);
         Rp += sgn * (A * j);
       } else if (L == PORE) {
-        const bool an = Lk == ANODE;
-        const uint32_t f = face_rank(mk, d ^ 1);
-        double nf = an ? cd.n_try[f] : 0.0;
-        if (an && cd.elim_n) nf = plate ? plated_root(cd, ci, pk, pi, cd.n_old[f], cd.n[f]) : cd.n_old[f];
-        const Kin q = interface_kinetics(cd, Lk, ck, ci, pk, pi, nf, an && plate, LIN);
-        const double it = q.ii + q.ip;
+        // interface face seen from the pore: its total current leaves the solid
+        const uint32_t f = face_rank(mk, d ^ 1) + (Lk == ANODE ? 0u : (uint32_t)cd.F_an);
+        const double it = cd.fres[F + f];
         Rc -= A * it / kFaraday;
         Rp -= A * it;
       } else {
         const bool an = L == ANODE;
-        const uint32_t f = face_rank(mi, d);
-        double nf = an ? cd.n_try[f] : 0.0;
-        if (an && cd.elim_n) {
-          nf = plate ? plated_root(cd, ck, pi, pk, cd.n_old[f], cd.n[f]) : cd.n_old[f];
-          cd.n_try[f] = nf;
-          dnmax = fmax(dnmax, fabs(nf - cd.n[f]) / cd.n_c);
-        }
-        const Kin q = interface_kinetics(cd, L, ci, ck, pi, pk, nf, an && plate, LIN);
-        Rc += A * q.ii / kFaraday;
-        Rp += A * (q.ii + q.ip);
+        const uint32_t fr = face_rank(mi, d);
+        const uint32_t f = fr + (an ? 0u : (uint32_t)cd.F_an);
+        Rc += A * cd.fres[f] / kFaraday;
+        Rp += A * cd.fres[F + f];
         if (an) {
-          const double Rn = A * (nf - cd.n_old[f]) / dt + A * q.ip / kFaraday;
-          cd.Rn[f] = Rn;
+          const double Rn = cd.Rn[fr];
           const double rs = Rn * dt / (A * cd.n_c);
           rsq += rs * rs;
           rmax = fmax(rmax, fabs(rs));
-          if (LIN) {
-            const double jnn = A / dt + A * q.p_n / kFaraday;
-            const double kap = (A / dt) / jnn;
-            const double mu = cd.mu_ref;
-            KT* co = (KT*)cd.coef_an + 5 * (size_t)f;
-            co[0] = (KT)(q.d_cs * cd.cmax[0] / mu);
-            co[1] = (KT)(q.d_ce * cd.c0 / mu);
-            co[2] = (KT)(q.g * cd.VT / mu);
-            co[3] = (KT)(kap * q.p_ce * cd.c0 / mu);
-            co[4] = (KT)(kap * q.g_p * cd.VT / mu);
-            cd.rn_jnn[f] = Rn / jnn;
-            cd.sq[f] = q.p_n * Rn / (jnn * mu);
-            ((KT*)cd.cond_an)[f] = (KT)((q.g + kap * q.g_p) * cd.VT / mu);
-          }
-        } else if (LIN) {
-          const double mu = cd.mu_ref;
-          KT* co = (KT*)cd.coef_ca + 3 * (size_t)f;
-          co[0] = (KT)(q.d_cs * cd.cmax[1] / mu);
-          co[1] = (KT)(q.d_ce * cd.c0 / mu);
-          co[2] = (KT)(q.g * cd.VT / mu);
-          ((KT*)cd.cond_ca)[f] = co[2];
+          if (cd.elim_n) dnmax = fmax(dnmax, fabs(cd.n_try[fr] - cd.n[fr]) / cd.n_c);
         }
       }
     }
@@ -303,20 +354,32 @@ __global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __re
 }
 
 // ----------------------------------------------------------------- J * v
+// y = J v with the row sums accumulated in FP64 in both modes: in an FP32
+// vector the differences of neighbouring potentials in high-conductance
+// regions would otherwise cancel away.  keep >= 0 also stores the operand
+// as preconditioned basis vector `keep` of the flexible GMRES (the exact
+// values the product was applied to).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* __restrict__ blk, int src, int dst,
-                                                   int need) {
+                                                   int need, int keep) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
-  KT yc, yp;
-  jv_row<KT, KT, KT>(cd, i, vec<KT>(cd, src), yc, yp);
+  const KT* v = vec<KT>(cd, src);
+  double yc, yp;
+  jv_row<KT, KT, double>(cd, i, v, yc, yp);
   if (cd.ictl[CTL_DONE] != need) return;
+  const size_t N = cd.N;
   KT* y = vec<KT>(cd, dst);
-  y[i] = yc;
-  y[(size_t)cd.N + i] = yp;
+  y[i] = (KT)yc;
+  y[N + i] = (KT)yp;
+  if (keep >= 0) {
+    KT* zk = (KT*)cd.Zb + (size_t)keep * 2 * N;
+    zk[i] = v[i];
+    zk[N + i] = v[N + i];
+  }
 }
 
 // ------------------------------------------------------------------- GMRES
@@ -475,14 +538,16 @@ __global__ void __launch_bounds__(kBlock) k_finalize_norm(CellDev* cells, int nc
 
 // Second pass of the voxel-block reductions: partial columns 0..K-1 into
 // red[slot..slot+K) (bit j of maxmask: max, else sum).  need: -3 any active
-// cell, otherwise only cells whose GMRES state equals need.
+// cell, -4 cells whose GMRES cycle just closed (state 1 or 2), otherwise only
+// cells whose GMRES state equals need.
 __global__ void __launch_bounds__(kBlock) k_finalize_red(CellDev* cells, int ncell, int slot, int K, unsigned maxmask,
                                                          int need) {
   const int ci = blockIdx.x;
   if (ci >= ncell) return;
   const CellDev& cd = cells[ci];
   if (!cd.active) return;
-  if (need != -3 && cd.ictl[CTL_DONE] != need) return;
+  const int st = cd.ictl[CTL_DONE];
+  if (need == -4 ? (st != 1 && st != 2) : (need != -3 && st != need)) return;
   __shared__ double lds4[4];
   __shared__ double res;
   for (int j = 0; j < K; ++j) {
@@ -568,8 +633,10 @@ __global__ void k_backsolve(CellDev* cells, int ncell) {
 }
 
 // w = sum_{j<k} y_j V_j (cycle end; runs for converged cells too)
+// End of a cycle (flexible GMRES): x += sum_j y_j Z_j over the cycle's
+// preconditioned basis vectors, accumulated in FP64.
 template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_combine(CellDev* cells, const int2* __restrict__ blk) {
+__global__ void __launch_bounds__(kBlock) k_update_x(CellDev* cells, const int2* __restrict__ blk) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
@@ -583,36 +650,15 @@ __global__ void __launch_bounds__(kBlock) k_combine(CellDev* cells, const int2* 
   const int kk = cd.ictl[CTL_K];
   const double* y = cd.gm + gm_y(m);
   const size_t N = cd.N;
-  KT ac = (KT)0, ap = (KT)0;
+  const KT* Z = (const KT*)cd.Zb;
+  double ac = 0.0, ap = 0.0;
   for (int j = 0; j < kk; ++j) {
-    const KT* vj = vec<KT>(cd, j);
-    const KT yj = (KT)y[j];
-    ac += yj * vj[i];
-    ap += yj * vj[N + i];
+    const KT* zj = Z + (size_t)j * 2 * N;
+    ac += y[j] * (double)zj[i];
+    ap += y[j] * (double)zj[N + i];
   }
-  KT* w = (KT*)cd.w;
-  w[i] = ac;
-  w[N + i] = ap;
-}
-
-
-// x += z
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_add_z_to_x(CellDev* cells, const int2* __restrict__ blk) {
-  const int2 bb = block_of(blk);
-  const CellDev& cd = cells[bb.x];
-  if (!cd.active) return;
-  {
-    const int st = cd.ictl[CTL_DONE];
-    if (st != 1 && st != 2) return;
-  }
-  const int i = bb.y * kBlock + threadIdx.x;
-  if (i >= cd.N) return;
-  const size_t N = cd.N;
-  const KT* z = (const KT*)cd.z;
-  double* x = cd.x;
-  x[i] += (double)z[i];
-  x[N + i] += (double)z[N + i];
+  cd.x[i] += ac;
+  cd.x[N + i] += ap;
 }
 
 // Restart: w = b - J x with ||w||^2.  The iterate x is kept in FP64 and the
@@ -620,11 +666,22 @@ __global__ void __launch_bounds__(kBlock) k_add_z_to_x(CellDev* cells, const int
 // the rows with large conductance would otherwise turn the FP32 rounding of
 // a large common potential shift into a residual floor far above the
 // tolerance (restarted GMRES then acts as iterative refinement).
+// With an FP32 basis (the mixed mode) a cycle that converged by the Givens
+// estimate (state 1) also computes its true residual: the FP32 rounding of
+// the preconditioned correction can leave the true residual above the
+// tolerance, and such a cell then restarts from it (iterative refinement).
+template <typename KT>
+__device__ constexpr bool refine_on_convergence() { return sizeof(KT) < sizeof(double); }
+template <typename KT>
+__device__ inline bool needs_true_residual(int st) {
+  return st == 2 || (refine_on_convergence<KT>() && st == 1);
+}
+
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_true_residual(CellDev* cells, const int2* __restrict__ blk) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!cd.active || cd.ictl[CTL_DONE] != 2) return;
+  if (!cd.active || !needs_true_residual<KT>(cd.ictl[CTL_DONE])) return;
   const int i = bb.y * kBlock + threadIdx.x;
   double ss = 0.0;
   if (i < cd.N) {
@@ -649,7 +706,7 @@ __global__ void __launch_bounds__(kBlock) k_gm_start(CellDev* cells, const int2*
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
-  if (!first && cd.ictl[CTL_DONE] != 2) return;
+  if (!first && !needs_true_residual<KT>(cd.ictl[CTL_DONE])) return;
   const double beta = sqrt(cd.red[RED_BSQ]);
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
@@ -663,9 +720,10 @@ __global__ void __launch_bounds__(kBlock) k_gm_start(CellDev* cells, const int2*
 
 // Per-cell GMRES bookkeeping after k_gm_start (one thread per cell):
 // first cycle: tolerance = rtol * beta0; later: a cell that converged in the
-// cycle just closed is finished (state 3), a cell that ran out of basis
-// restarts from the true residual.
-__global__ void k_gm_flags(CellDev* cells, int ncell, int first) {
+// cycle just closed is finished (state 3) -- with refine, only if its true
+// residual meets the tolerance, else it restarts from it -- and a cell that
+// ran out of basis restarts from the true residual.
+__global__ void k_gm_flags(CellDev* cells, int ncell, int first, int refine) {
   const int ci = blockIdx.x * blockDim.x + threadIdx.x;
   if (ci >= ncell) return;
   const CellDev& cd = cells[ci];
@@ -679,11 +737,11 @@ __global__ void k_gm_flags(CellDev* cells, int ncell, int first) {
     cd.ictl[CTL_ITERS] = 0;
   } else {
     const int st = cd.ictl[CTL_DONE];
-    if (st == 1 || st == 3) {
+    if (st == 3 || (st == 1 && (!refine || beta <= cd.red[RED_TOL]))) {
       cd.ictl[CTL_DONE] = 3;
       return;
     }
-    if (st != 2) return;
+    if (st != 1 && st != 2) return;
   }
   for (int j = 0; j <= m; ++j) g[j] = 0.0;
   g[0] = beta;
@@ -937,10 +995,17 @@ void launch_init_state(const BatchLaunch& b, hipStream_t s) {
 template <typename KT>
 void launch_residual(const BatchLaunch& b, bool lin, hipStream_t s) {
   prof_begin(PK_RESIDUAL, s);
-  if (lin)
+  // a single cell launches only the blocks its faces need; a batch uses the
+  // voxel block table and strides each cell's faces over its own blocks
+  const int fgrid = b.blk ? b.nblk : std::max(1, std::min(b.nblk, (b.faces_single + kBlock - 1) / kBlock));
+  const int stride = b.blk ? 0 : fgrid;
+  if (lin) {
+    k_iface<true, KT><<<grid_of(fgrid), kBlock, 0, s>>>(b.cells, b.blk, stride);
     k_residual<true, KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
-  else
+  } else {
+    k_iface<false, KT><<<grid_of(fgrid), kBlock, 0, s>>>(b.cells, b.blk, stride);
     k_residual<false, KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+  }
   if (prof_on(PK_RESIDUAL)) prof_end(PK_RESIDUAL, s, b.bytes_residual[lin ? 1 : 0]);
   k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_RSQ, 4, 0xAu, -3);
 }
@@ -950,9 +1015,9 @@ void launch_rhs(const BatchLaunch& b, hipStream_t s) {
   k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_BSQ, 1, 0u, -3);
 }
 template <typename KT>
-void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t s) {
+void launch_matvec(const BatchLaunch& b, int src, int dst, int need, int keep, hipStream_t s) {
   prof_begin(PK_MATVEC, s);
-  k_matvec<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need);
+  k_matvec<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need, keep);
   if (prof_on(PK_MATVEC)) prof_end(PK_MATVEC, s, b.bytes_matvec);
 }
 template <typename KT>
@@ -981,24 +1046,20 @@ void launch_backsolve(const BatchLaunch& b, hipStream_t s) {
   k_backsolve<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell);
 }
 template <typename KT>
-void launch_combine(const BatchLaunch& b, hipStream_t s) {
-  k_combine<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
-}
-template <typename KT>
-void launch_add_z_to_x(const BatchLaunch& b, hipStream_t s) {
-  k_add_z_to_x<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
+void launch_update_x(const BatchLaunch& b, hipStream_t s) {
+  k_update_x<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
 }
 template <typename KT>
 void launch_true_residual(const BatchLaunch& b, hipStream_t s) {
   k_true_residual<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);
-  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_BSQ, 1, 0u, 2);
+  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_BSQ, 1, 0u, sizeof(KT) < sizeof(double) ? -4 : 2);
 }
 template <typename KT>
 void launch_gm_start(const BatchLaunch& b, int first, hipStream_t s) {
   k_gm_start<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, first);
 }
-void launch_gm_flags(const BatchLaunch& b, int first, hipStream_t s) {
-  k_gm_flags<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell, first);
+void launch_gm_flags(const BatchLaunch& b, int first, int refine, hipStream_t s) {
+  k_gm_flags<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell, first, refine);
 }
 void launch_gather_ctl(const BatchLaunch& b, double* out, hipStream_t s) {
   k_gather_ctl<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell, out);
@@ -1036,7 +1097,7 @@ void launch_outputs(const BatchLaunch& b, hipStream_t s) {
 #define MBX_INST(KT)                                                             \
   template void launch_residual<KT>(const BatchLaunch&, bool, hipStream_t);      \
   template void launch_rhs<KT>(const BatchLaunch&, hipStream_t);                 \
-  template void launch_matvec<KT>(const BatchLaunch&, int, int, int, hipStream_t);  \
+  template void launch_matvec<KT>(const BatchLaunch&, int, int, int, int, hipStream_t);  \
   template void launch_convert<KT>(const BatchLaunch&, int, int, hipStream_t);      \
   template void launch_zero_x<KT>(const BatchLaunch&, hipStream_t);                  \
   template void launch_norm_w<KT>(const BatchLaunch&, hipStream_t);                  \
@@ -1044,8 +1105,7 @@ void launch_outputs(const BatchLaunch& b, hipStream_t s) {
   template void launch_orth<KT>(const BatchLaunch&, int, int, hipStream_t);      \
   template void launch_orth_dots<KT>(const BatchLaunch&, int, hipStream_t);     \
   template void launch_scale_next<KT>(const BatchLaunch&, int, hipStream_t);     \
-  template void launch_combine<KT>(const BatchLaunch&, hipStream_t);             \
-  template void launch_add_z_to_x<KT>(const BatchLaunch&, hipStream_t);          \
+  template void launch_update_x<KT>(const BatchLaunch&, hipStream_t);            \
   template void launch_true_residual<KT>(const BatchLaunch&, hipStream_t);       \
   template void launch_gm_start<KT>(const BatchLaunch&, int, hipStream_t);       \
   template void launch_direction<KT>(const BatchLaunch&, hipStream_t);

@@ -90,9 +90,13 @@ struct CellDev {
   double *Rc, *Rp, *Rn;              // residual rows at the trial state
   double *dc, *dp, *dn;              // Newton direction (raw units)
   double *rn_jnn, *sq;               // per anode face: R^n/J_nn, condensation term
+  const int *faces_an, *faces_ca;    // compacted interface faces per phase: solid voxel * 8 + direction
+  double *fres;                      // per interface face (anode faces, then cathode faces): intercalation
+                                     // current [0, F), total current [F, 2F), A/m^2, solid -> pore > 0
   void *coef_an, *coef_ca;           // KT: 5 per anode face, 3 per cathode face
   void *wpore;                       // KT: c0/c on pore voxels
   void *Vb;                          // KT: (m+1) Krylov basis vectors of 2N
+  void *Zb;                          // KT: m preconditioned basis vectors of 2N (flexible GMRES)
   void *w, *z, *b;                   // KT: 2N each (Krylov work vector, preconditioned vector, rhs)
   double *x;                         // 2N: GMRES iterate, FP64 in both modes
   void *dint;                        // KT: N, interface part of the concentration preconditioner's diagonal

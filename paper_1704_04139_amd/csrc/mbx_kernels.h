@@ -17,6 +17,7 @@ struct BatchLaunch {
   const int2* blk;
   int nblk;
   int ncell;
+  int faces_single;                      // interface faces of the cell of a single-cell launch (blk == nullptr)
   int maxlev;                            // max multigrid levels over the batch
   int maxfuse;                           // max first fused level over the batch
   size_t fused_lds;                      // LDS elements (KT) of the fused coarse cycle, max over the batch
@@ -43,7 +44,8 @@ hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* ou
 
 template <typename KT> void launch_residual(const BatchLaunch& b, bool lin, hipStream_t s);
 template <typename KT> void launch_rhs(const BatchLaunch& b, hipStream_t s);
-template <typename KT> void launch_matvec(const BatchLaunch& b, int src, int dst, int need, hipStream_t s);
+// y_dst = J v_src; keep >= 0 stores v_src as preconditioned basis vector `keep` (flexible GMRES)
+template <typename KT> void launch_matvec(const BatchLaunch& b, int src, int dst, int need, int keep, hipStream_t s);
 template <typename KT> void launch_convert(const BatchLaunch& b, int sel, int dir, hipStream_t s);
 template <typename KT> void launch_zero_x(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_norm_w(const BatchLaunch& b, hipStream_t s);
@@ -55,11 +57,12 @@ template <typename KT> void launch_orth_dots(const BatchLaunch& b, int k, hipStr
 template <typename KT> void launch_scale_next(const BatchLaunch& b, int k, hipStream_t s);
 void launch_givens(const BatchLaunch& b, int k, hipStream_t s);
 void launch_backsolve(const BatchLaunch& b, hipStream_t s);
-template <typename KT> void launch_combine(const BatchLaunch& b, hipStream_t s);
-template <typename KT> void launch_add_z_to_x(const BatchLaunch& b, hipStream_t s);
+// x += Z y for the cells whose cycle just closed
+template <typename KT> void launch_update_x(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_true_residual(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_gm_start(const BatchLaunch& b, int first, hipStream_t s);
-void launch_gm_flags(const BatchLaunch& b, int first, hipStream_t s);
+// refine: a cell whose cycle converged restarts if its true residual misses the tolerance
+void launch_gm_flags(const BatchLaunch& b, int first, int refine, hipStream_t s);
 void launch_gather_ctl(const BatchLaunch& b, double* out, hipStream_t s);
 template <typename KT> void launch_direction(const BatchLaunch& b, hipStream_t s);
 void launch_trial(const BatchLaunch& b, hipStream_t s);

@@ -27,6 +27,10 @@
 
 #include "../../include/mbx.h"
 
+namespace mbx {
+bool cutoff_reached(const mbx_params& p, double V);   // cell.cpp
+}
+
 namespace {
 
 using Clock = std::chrono::steady_clock;
@@ -82,6 +86,7 @@ struct mbx_server {
   std::deque<Request*> queue;
   std::vector<Request*> running;     // touched by the worker only (read under mu by stats)
   int admitting = 0;                 // taken off the queue, cell not created yet (under mu)
+  int retiring = 0;                  // left `running`, final state not yet copied out (under mu)
   std::unordered_map<int64_t, std::unique_ptr<Request>> all;
   int64_t next_id = 1;
   bool stop = false;
@@ -91,11 +96,21 @@ struct mbx_server {
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
   void loop();
-  void retire(Request* r, int status);
+  void retire(Request* r, int status, bool was_running);
+  bool idle() const { return queue.empty() && running.empty() && admitting == 0 && retiring == 0; }
 };
 
-void mbx_server::retire(Request* r, int status) {
+// Copies a finished request's outputs, releases its cell and stamps its
+// final status.  was_running: the request left `running` and is counted in
+// `retiring` until this returns.
+void mbx_server::retire(Request* r, int status, bool was_running) {
   if (r->cell) {
+    double sac[2] = {0.0, 0.0};
+    if (mbx_cell_mean_solid(r->cell, sac) == MBX_OK) {
+      std::lock_guard<std::mutex> lk(mu);
+      r->info.s_ac[0] = sac[0];
+      r->info.s_ac[1] = sac[1];
+    }
     if (keep_state && status == MBX_REQ_DONE) {
       int64_t N = 0, Fa = 0;
       mbx_cell_counts(r->cell, &N, &Fa, nullptr, nullptr);
@@ -114,6 +129,7 @@ void mbx_server::retire(Request* r, int status) {
   r->info.status = status;
   r->info.t_done = now();
   used -= r->footprint;
+  if (was_running) --retiring;
 }
 
 void mbx_server::loop() {
@@ -122,7 +138,7 @@ void mbx_server::loop() {
     std::vector<Request*> admit;
     {
       std::unique_lock<std::mutex> lk(mu);
-      if (running.empty() && queue.empty() && admitting == 0) idle_cv.notify_all();
+      if (idle()) idle_cv.notify_all();
       cv.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
       if (stop) break;
       // first-come first-served: the head waits until it fits
@@ -139,18 +155,19 @@ void mbx_server::loop() {
       if (rc != MBX_OK) {
         r->err = mbx_last_error();
         r->cell = nullptr;
-        retire(r, rc);
+        retire(r, rc, false);
         std::lock_guard<std::mutex> lk(mu);
         --admitting;
         continue;
       }
       std::vector<uint8_t>().swap(r->labels);   // the cell holds its own copy
-      int64_t N = 0;
-      mbx_cell_counts(r->cell, &N, nullptr, nullptr, nullptr);
+      int64_t N = 0, Fa = 0;
+      mbx_cell_counts(r->cell, &N, &Fa, nullptr, nullptr);
       std::lock_guard<std::mutex> lk(mu);
       r->info.status = MBX_REQ_RUNNING;
       r->info.t_admit = now();
       r->info.n_vox = N;
+      r->info.n_an_faces = Fa;
       running.push_back(r);
       --admitting;
     }
@@ -172,24 +189,31 @@ void mbx_server::loop() {
       for (int i = 0; i < n; ++i) {
         Request* r = running[i];
         const int s = rc != MBX_OK ? rc : st[i];
+        bool cut = false;
         if (s == MBX_OK) {
           ++steps_run;
           r->info.steps_done++;
           r->info.V = inf[i].V;
           r->info.newton_iters += inf[i].newton_iters;
           r->info.krylov_iters += inf[i].krylov_iters;
+          if (inf[i].substeps > 1) r->info.retried++;
+          cut = mbx::cutoff_reached(r->p, inf[i].V);
+          if (cut) r->info.cutoff = 1;
         } else {
           r->info.status = s;   // provisional; retire() stamps the time
           r->err = rc != MBX_OK ? berr : "step failed";
         }
-        if (s != MBX_OK || r->info.steps_done >= r->n_steps)
+        if (s != MBX_OK || cut || r->info.steps_done >= r->n_steps)
           done.push_back(r);
         else
           keep.push_back(r);
       }
+      // requests leave `running` and enter `retiring` in one critical
+      // section, so drain never sees the server idle in between
       running.swap(keep);
+      retiring += (int)done.size();
     }
-    for (Request* r : done) retire(r, r->info.status < 0 ? r->info.status : MBX_REQ_DONE);
+    for (Request* r : done) retire(r, r->info.status < 0 ? r->info.status : MBX_REQ_DONE, true);
   }
   // shutdown: release whatever is still resident
   for (Request* r : running)
@@ -287,8 +311,7 @@ int mbx_server_result(mbx_server* s, int64_t id, double* cfield, double* phi, do
 int mbx_server_drain(mbx_server* s, double timeout_s) {
   if (!s) return MBX_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
-  const bool ok = s->idle_cv.wait_for(lk, std::chrono::duration<double>(timeout_s),
-                                      [&] { return s->queue.empty() && s->running.empty() && s->admitting == 0; });
+  const bool ok = s->idle_cv.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return s->idle(); });
   return ok ? MBX_OK : MBX_ESTATE;
 }
 

@@ -33,7 +33,7 @@ class Params(ctypes.Structure):
                 ("Ds", _d * 2), ("sigma", _d * 2), ("cmax", _d * 2), ("i00", _d * 2),
                 ("U0", _d * 2), ("U1", _d * 2), ("i00_pl", _d), ("n_c", _d),
                 ("plating", _i), ("precision", _i), ("newton_tol", _d), ("res_tol", _d),
-                ("krylov_rtol", _d), ("newton_max", _i), ("krylov_max", _i)]
+                ("krylov_rtol", _d), ("newton_max", _i), ("krylov_max", _i), ("V_cut", _d)]
 
 
 class StepInfo(ctypes.Structure):
@@ -47,10 +47,13 @@ class StepInfo(ctypes.Structure):
 class RequestInfo(ctypes.Structure):
     _fields_ = [("status", _i), ("steps_done", _i), ("V", _d), ("t_submit", _d), ("t_admit", _d),
                 ("t_done", _d), ("newton_iters", ctypes.c_int64), ("krylov_iters", ctypes.c_int64),
-                ("n_vox", ctypes.c_int64)]
+                ("n_vox", ctypes.c_int64), ("n_an_faces", ctypes.c_int64), ("cutoff", _i), ("retried", _i),
+                ("s_ac", _d * 2)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["s_ac"] = (self.s_ac[0], self.s_ac[1])
+        return d
 
 
 class ServerInfo(ctypes.Structure):
@@ -85,6 +88,8 @@ SIGNATURES = {
     "mbx_cell_set_state": (_i, [_vp, _vp, _vp, _vp, _i]),
     "mbx_cell_voltage": (_i, [_vp, _dp]),
     "mbx_cell_inventory": (_i, [_vp, _dp]),
+    "mbx_cell_mean_solid": (_i, [_vp, _dp]),
+    "mbx_cell_run": (_i, [_vp, _d, _i, _dp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "mbx_cell_residual": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp]),
     "mbx_cell_jvp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]),
     "mbx_cell_precond": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]),
@@ -259,6 +264,21 @@ class Cell:
         _check(load().mbx_cell_inventory(self._h, out))
         return {"electrolyte": out[0], "anode": out[1], "cathode": out[2], "plated": out[3]}
 
+    def mean_solid(self):
+        """s_ac: mean solid concentration of the anode and the cathode, mol/m^3."""
+        out = (ctypes.c_double * 2)()
+        _check(load().mbx_cell_mean_solid(self._h, out))
+        return out[0], out[1]
+
+    def run(self, dt: float, max_steps: int):
+        """Step loop with the voltage cutoff params.V_cut: returns
+        (V after each step taken, cutoff fired, steps retried as half steps)."""
+        V = np.empty(max(int(max_steps), 1))
+        n, cut, ret = _i(), _i(), _i()
+        _check(load().mbx_cell_run(self._h, float(dt), int(max_steps), V.ctypes.data_as(_dp), ctypes.byref(n),
+                                   ctypes.byref(cut), ctypes.byref(ret)))
+        return V[:n.value].copy(), bool(cut.value), ret.value
+
     def residual(self, c, p, n, c_old, n_old, dt):
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (c, p, n, c_old, n_old)]
         Rc = np.empty(self.counts.n_vox)
@@ -368,7 +388,6 @@ class Server:
                                      _vp(stream) if stream else None, ctypes.byref(h)))
         self._h = h
         self.precision = precision
-        self._sizes = {}
 
     def submit(self, labels: np.ndarray, params, n_steps: int, **knobs) -> int:
         lab = np.ascontiguousarray(labels, dtype=np.uint8)
@@ -377,7 +396,6 @@ class Server:
         rid = ctypes.c_int64()
         _check(load().mbx_server_submit(self._h, _ptr(lab), nx, ny, nz, ctypes.byref(p), int(n_steps),
                                         ctypes.byref(rid)))
-        self._sizes[rid.value] = lab
         return rid.value
 
     def poll(self, rid: int) -> dict:
@@ -393,9 +411,8 @@ class Server:
 
     def result(self, rid: int):
         """Final (c, phi, n) of a finished request (keep_state servers)."""
-        lab = self._sizes[rid]
-        N = lab.size
-        n_an = int(_count_anode_faces(lab))
+        info = self.poll(rid)
+        N, n_an = int(info["n_vox"]), int(info["n_an_faces"])
         c, phi, n = np.empty(N), np.empty(N), np.empty(n_an)
         _check(load().mbx_server_result(self._h, int(rid), _ptr(c), _ptr(phi), _ptr(n) if n_an else None))
         return c, phi, n
@@ -421,19 +438,3 @@ class Server:
             self.close()
         except Exception:
             pass
-
-
-def _count_anode_faces(lab: np.ndarray) -> int:
-    """Anode/pore faces of a label image (layout (nz, ny, nx)): the length of
-    the plated-amount array."""
-    an = lab == 1
-    pore = lab == 0
-    n = 0
-    for ax in range(3):
-        a0 = [slice(None)] * 3
-        a1 = [slice(None)] * 3
-        a0[ax] = slice(0, -1)
-        a1[ax] = slice(1, None)
-        n += int(np.count_nonzero(an[tuple(a0)] & pore[tuple(a1)]))
-        n += int(np.count_nonzero(pore[tuple(a0)] & an[tuple(a1)]))
-    return n

@@ -38,21 +38,12 @@ def solo(mbx, w, precision, n_steps):
 
 
 def footprint(mbx, w, precision):
-    lab = np.ascontiguousarray(w.labels, dtype=np.uint8)
-    nz, ny, nx = lab.shape
-    fa = mbx._count_anode_faces(lab)
-    solid_ca = lab == 2
-    pore = lab == 0
-    fc = 0
-    for ax in range(3):
-        a0 = [slice(None)] * 3
-        a1 = [slice(None)] * 3
-        a0[ax] = slice(0, -1)
-        a1[ax] = slice(1, None)
-        fc += int(np.count_nonzero(solid_ca[tuple(a0)] & pore[tuple(a1)]))
-        fc += int(np.count_nonzero(pore[tuple(a0)] & solid_ca[tuple(a1)]))
-    return mbx.load().mbx_cell_footprint(nx, ny, nz, mbx.MBX_MIXED if precision == "mixed" else mbx.MBX_FP64,
-                                         fa, fc)
+    """Device bytes of the request's cell, from the library's own face counts."""
+    c = mbx.Cell(w.labels, w.params, precision=precision)
+    nx, ny, nz = c.shape
+    k = c.counts
+    c.close()
+    return mbx.footprint(nx, ny, nz, precision, k.n_an_faces, k.n_ca_faces)
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
@@ -111,3 +102,27 @@ def test_budget_admission(mbx):
     for a, b in zip(infos, infos[1:]):
         assert b["t_admit"] >= a["t_done"]
     assert all(i["status"] == mbx.MBX_REQ_DONE and i["steps_done"] == 2 for i in infos)
+
+
+def test_drain_returns_only_when_every_result_is_ready(mbx):
+    """drain() polled with short time-outs: once it reports the server idle,
+    every request is DONE and its result can be read (requests leave the
+    running set and have their final state copied out under one count)."""
+    ws = I.config4_requests(3, scale=4)
+    srv = mbx.Server(budget_bytes=64 << 30, precision="mixed", dt=ws[0].dt, keep_state=True)
+    ids = [srv.submit(w.labels, w.params, n) for w, n in zip(ws, (2, 1, 3))]
+    polls = 0
+    while True:
+        polls += 1
+        try:
+            srv.drain(0.001)
+            break
+        except mbx.MbxError as e:
+            assert e.code == mbx.MBX_ESTATE
+            assert polls < 200000
+    for rid in ids:
+        assert srv.poll(rid)["status"] == mbx.MBX_REQ_DONE
+        c, phi, n = srv.result(rid)
+        assert np.all(np.isfinite(c)) and np.all(np.isfinite(phi))
+    srv.close()
+    say("drain polls", polls)
