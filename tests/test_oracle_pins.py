@@ -462,3 +462,54 @@ def test_cutoff_stops_after_the_first_crossing():
     assert not oracle.cutoff_reached(V[4], V_cut, prm["I_app"]) and oracle.cutoff_reached(V[5], V_cut, prm["I_app"])
     assert oracle.cutoff_reached(3.0, 3.1, -1.0) and not oracle.cutoff_reached(3.2, 3.1, -1.0)   # discharge
     assert not oracle.cutoff_reached(9.0, None, 1.0) and not oracle.cutoff_reached(9.0, 0.0, 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Reading R-1 (generator cleanup): under reading C-9 the applied current is
+# spread evenly over the cathode solid voxels of the collector plane.  A solid
+# cluster that touches only that plane then carries I/n_top through its own
+# interface faces and, by charge and mass balance, loses exactly
+# I dt / (n_top F h^3) of concentration per step -- until no admissible state
+# (c_s > 0) carries the current and the implicit step has no solution.  The
+# same cell with the cluster joined to the electrode reaches the 4.2 V cutoff.
+# ---------------------------------------------------------------------------
+def r1_cell(connected):
+    lab = np.zeros((12, 4, 4), np.uint8)
+    lab[0:4] = I.ANODE
+    lab[0:4, 1, 1] = I.PORE
+    lab[1:4, 2, 2] = I.PORE
+    lab[8:12, 0:2, :] = I.CATHODE            # the electrode body, spanning z = 8..11
+    lab[11, 3, 3] = I.CATHODE                # a cluster on the collector plane
+    if connected:
+        lab[10:12, 3, 3] = I.CATHODE
+        lab[10, 1:3, 3] = I.CATHODE
+    return lab
+
+
+def test_reading_r1_collector_only_cluster_has_no_admissible_step():
+    dt = 5.0
+    lab = r1_cell(False)
+    p = I.CellParams()
+    p.I_app = 3.0 * I.one_c_current(lab, p)
+    g = Geometry(lab)
+    model = Model(g, p.as_dict())
+    iso = 11 * 16 + 3 * 4 + 3
+    loss = p.I_app * dt / (g.top.size * FARADAY * p.h ** 3)      # per step
+    k_empty = int(np.ceil(p.y0 * p.cmax_ca / loss))
+    u = model.initial_state()
+    failed_at = None
+    for k in range(1, k_empty + 2):
+        try:
+            u, _ = newton_step(model, u, dt)
+        except oracle.NewtonFailure:
+            failed_at = k
+            break
+        assert u[iso] == pytest.approx(p.y0 * p.cmax_ca - k * loss, rel=1e-6)
+    assert failed_at is not None and failed_at <= k_empty
+    assert model.voltage(u) < 4.0                      # far from the cutoff
+    # joined to the electrode, the cluster shares the load: the cell charges to 4.2 V
+    labc = r1_cell(True)
+    pc = I.CellParams()
+    pc.I_app = 3.0 * I.one_c_current(labc, pc)
+    mc, states, _ = oracle.simulate(labc, pc.as_dict(), dt, 400, V_cut=4.2)
+    assert mc.voltage(states[-1]) >= 4.2 and len(states) - 1 > 3 * failed_at
