@@ -188,6 +188,8 @@ size_t half_cells(const LevelDims& ld, int l) { return (size_t)((ld.nx[l] + 1) /
 
 size_t kt_size(int precision) { return precision == MBX_MIXED ? sizeof(float) : sizeof(double); }
 
+int nx_of(const LevelDims& ld) { return ld.nx[0]; }
+
 Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const LevelDims& ld) {
   Layout L;
   L.add(4 * (size_t)N);                       // 0 meta
@@ -197,7 +199,8 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   L.add(5 * kt * std::max(F_an, 1));          // 17 coef_an
   L.add(3 * kt * std::max(F_ca, 1));          // 18 coef_ca
   L.add(kt * (size_t)N);                      // 19 wpore
-  L.add(kt * (size_t)N);                      // 20 dint
+  const size_t Np = 2 * (size_t)((nx_of(ld) + 1) / 2) * ld.ny[0] * ld.nz[0];   // colour-split length
+  L.add(kt * Np);                             // 20 dint (colour-split)
   L.add((size_t)(m + 1) * 2 * N * kt);        // 21 Vb
   for (int k = 0; k < 3; ++k) L.add(2 * (size_t)N * kt);  // 22..24 w z b
   L.add(2 * (size_t)N * 8);                   // 25 x (FP64)
@@ -211,7 +214,7 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   L.add(sizeof(CellDev));                     // 33 desc
   L.add(sizeof(int2) * (size_t)nblk);         // 34 blk
   L.add(8 * kGather);                         // 35 gather
-  L.add(kt * (size_t)N);                      // 36 b0
+  L.add(kt * Np);                             // 36 b0 (colour-split)
   L.add(kt * std::max(F_an, 1));              // 37 cond_an
   L.add(kt * std::max(F_ca, 1));              // 38 cond_ca
   const int nc = ld.ncell[ld.n - 1];
@@ -230,6 +233,8 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   L.add(sizeof(int2) * ((half_cells(ld, 0) + kBlock - 1) / kBlock));   // 41 + 7(n-1): level-0 blkh
   L.add(16 * (size_t)std::max(F_an + F_ca, 1));                        // 42 + 7(n-1): face results
   L.add((size_t)m * 2 * N * kt);                                       // 43 + 7(n-1): flexible-GMRES basis Z
+  L.add(4 * Np);                                                       // 44 + 7(n-1): meta, colour-split
+  L.add(kt * Np);                                                      // 45 + 7(n-1): level-0 iterate, colour-split
   return L;
 }
 
@@ -1143,6 +1148,10 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   c->lvlh_blk[0] = (int2*)(b + L.off[41 + 7 * (c->ld.n - 1)]);
   h.fres = (double*)(b + L.off[42 + 7 * (c->ld.n - 1)]);
   h.Zb = b + L.off[43 + 7 * (c->ld.n - 1)];
+  h.rbhx = (nx + 1) / 2;
+  h.rbH = h.rbhx * ny * nz;
+  h.meta_rb = (const uint32_t*)(b + L.off[44 + 7 * (c->ld.n - 1)]);
+  h.x_rb = b + L.off[45 + 7 * (c->ld.n - 1)];
   h.faces_an = c->faces_an;
   h.faces_ca = c->faces_ca;
   c->lvlh_nblk[0] = (int)((half_cells(c->ld, 0) + kBlock - 1) / kBlock);
@@ -1160,6 +1169,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   if (e == hipSuccess) {
     launch_finish_meta(N, (uint32_t*)h.meta, (const int*)(tmp + o_oa), (const int*)(tmp + o_oc), c->faces_an,
                        c->faces_ca, s);
+    launch_meta_rb(h, s);
   }
   if (e == hipSuccess) e = hipMemsetAsync(h.ictl, 0, 4 * CTL_NSLOT, s);
   if (e == hipSuccess) e = hipMemsetAsync(h.red, 0, 8 * RED_NSLOT, s);

@@ -87,6 +87,15 @@ __global__ void __launch_bounds__(kBlock) k_finish_meta(int N, uint32_t* __restr
     if ((mask_of(m) >> d) & 1u) fl[base + r++] = i * 8 + d;
 }
 
+// Colour-split copy of the meta words (padding slots of odd nx stay zero
+// and are never read: no voxel has them as a neighbour).
+__global__ void __launch_bounds__(kBlock) k_meta_rb(CellDev cd) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const VoxCoord v = coord_of(cd, i);
+  ((uint32_t*)cd.meta_rb)[rb_index(cd, v.x, v.y, v.z)] = cd.meta[i];
+}
+
 // Zero-current equilibrium (every interface current vanishes; the plated
 // amount makes the plating current zero: f_pre(n) = exp(-F U_an(x0)/RT)).
 __global__ void __launch_bounds__(kBlock) k_init_state(CellDev* cells, const int2* __restrict__ blk) {
@@ -987,6 +996,10 @@ void launch_finish_meta(int N, uint32_t* meta, const int* off_an, const int* off
 }
 hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* out, int n, hipStream_t s) {
   return hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, in, out, n, s);
+}
+void launch_meta_rb(const CellDev& cd, hipStream_t s) {
+  (void)hipMemsetAsync((void*)cd.meta_rb, 0, 8 * (size_t)cd.rbH, s);
+  k_meta_rb<<<(cd.N + kBlock - 1) / kBlock, kBlock, 0, s>>>(cd);
 }
 void launch_init_state(const BatchLaunch& b, hipStream_t s) {
   k_init_state<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);

@@ -99,7 +99,7 @@ struct CellDev {
   void *Zb;                          // KT: m preconditioned basis vectors of 2N (flexible GMRES)
   void *w, *z, *b;                   // KT: 2N each (Krylov work vector, preconditioned vector, rhs)
   double *x;                         // 2N: GMRES iterate, FP64 in both modes
-  void *dint;                        // KT: N, interface part of the concentration preconditioner's diagonal
+  void *dint;                        // KT [2 rbH]: interface part of the concentration preconditioner's diagonal (colour-split)
   double *part;                      // nblk * kPartStride partial sums
   double *red;                       // RED_NSLOT outputs (device-written)
   int *ictl;                         // CTL_NSLOT flags (device-written)
@@ -118,7 +118,14 @@ struct CellDev {
   int nlev, lfuse;                   // levels incl. the voxel level; coarsest = nlev-1;
                                      // levels >= lfuse run in one workgroup (k_mg_coarse_cycle)
   MGLevel lv[kMaxLevels];
-  void *b0;                          // KT [N] right-hand side of a level-0 solve
+  // Level-0 multigrid arrays in colour-split (red-black) order: voxel (x,y,z)
+  // of colour c = (x+y+z)&1 sits at c*rbH + (y + ny*z)*rbhx + (x>>1), with
+  // rbhx = ceil(nx/2) and rbH = rbhx*ny*nz (odd nx leaves padding slots), so a
+  // half sweep reads and writes whole cache lines of one colour.
+  int rbhx, rbH;
+  const uint32_t* meta_rb;           // meta words in colour-split order
+  void *x_rb;                        // KT [2 rbH] level-0 iterate of the V-cycle being run
+  void *b0;                          // KT [2 rbH] right-hand side of a level-0 solve (colour-split)
   void *cond_an, *cond_ca;           // KT potential-operator conductance per interface face
   double *cinv[2];                   // coarsest-level dense inverses (FP64), (3*ncell)^2 each
   double alpha;                      // coarse-correction scale
@@ -149,6 +156,11 @@ __device__ inline VoxCoord coord_of(const CellDev& cd, int i) {
   v.y = t % cd.ny;
   v.z = t / cd.ny;
   return v;
+}
+
+// Colour-split index of voxel (x, y, z) (see CellDev::rbhx).
+__host__ __device__ inline int rb_index(const CellDev& cd, int x, int y, int z) {
+  return ((x + y + z) & 1) * cd.rbH + (y + cd.ny * z) * cd.rbhx + (x >> 1);
 }
 
 __device__ inline int neighbour(const CellDev& cd, int i, int x, int y, int z, int d) {

@@ -39,6 +39,8 @@ void launch_build_meta(const uint8_t* lab, int nx, int ny, int nz, uint32_t* met
 void launch_finish_meta(int N, uint32_t* meta, const int* off_an, const int* off_ca, int* faces_an, int* faces_ca,
                         hipStream_t s);
 void launch_init_state(const BatchLaunch& b, hipStream_t s);
+// colour-split copy of the finished meta words (cd: host copy of the descriptor, device pointers)
+void launch_meta_rb(const CellDev& cd, hipStream_t s);
 // hipCUB exclusive prefix sum (temp == nullptr: query temp_bytes)
 hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* out, int n, hipStream_t s);
 

@@ -177,23 +177,40 @@ __device__ inline void neighbours6(int c, const C3& q, int nx, int ny, int nz, i
   nb[4] = ex[4] ? c + sz : c; nb[5] = ex[5] ? c - sz : c;
 }
 
-// Row of the level-0 operator `op` at voxel i: diagonal D (extra term plus
-// all couplings) and S = sum_k g_ik x_k over the neighbours (x_k read from
-// xsrc, plus alpha times the level-1 solution of k's slot when corr).  All
-// loads are issued before any arithmetic depends on them.
+// Colour-split indices of the six neighbours (+x, -x, +y, -y, +z, -z) of
+// voxel c at colour-split index p (absent neighbours: p itself, flagged false).
+__device__ inline void neighbours6_rb(const CellDev& cd, int p, const C3& c, int (&nb)[6], bool (&ex)[6]) {
+  const int base = (1 - ((c.x + c.y + c.z) & 1)) * cd.rbH;
+  const int row = c.y + cd.ny * c.z, hx = cd.rbhx;
+  ex[0] = c.x + 1 < cd.nx; ex[1] = c.x > 0;
+  ex[2] = c.y + 1 < cd.ny; ex[3] = c.y > 0;
+  ex[4] = c.z + 1 < cd.nz; ex[5] = c.z > 0;
+  nb[0] = ex[0] ? base + row * hx + ((c.x + 1) >> 1) : p;
+  nb[1] = ex[1] ? base + row * hx + ((c.x - 1) >> 1) : p;
+  nb[2] = ex[2] ? base + (row + 1) * hx + (c.x >> 1) : p;
+  nb[3] = ex[3] ? base + (row - 1) * hx + (c.x >> 1) : p;
+  nb[4] = ex[4] ? base + (row + cd.ny) * hx + (c.x >> 1) : p;
+  nb[5] = ex[5] ? base + (row - cd.ny) * hx + (c.x >> 1) : p;
+}
+
+// Row of the level-0 operator `op` at voxel c (colour-split index p):
+// diagonal D (extra term plus all couplings) and S = sum_k g_ik x_k over the
+// neighbours (x_k read from the colour-split iterate xsrc, plus alpha times
+// the level-1 solution of k's slot when corr).  All loads are issued before
+// any arithmetic depends on them.
 template <typename KT>
-__device__ inline void voxel_row(const CellDev& cd, int op, int i, const C3& c, uint32_t mi, const KT* __restrict__ xsrc,
+__device__ inline void voxel_row(const CellDev& cd, int op, int p, const C3& c, uint32_t mi, const KT* __restrict__ xsrc,
                                  bool zero, bool corr, KT& D, KT& S) {
   int k[6];
   bool ex[6];
-  neighbours6(i, c, cd.nx, cd.ny, cd.nz, k, ex);
+  neighbours6_rb(cd, p, c, k, ex);
   const int dmap[6] = {1, 0, 3, 2, 5, 4};   // neighbour slot -> face direction (0:-x 1:+x ...)
   uint32_t mk[6];
   KT xk[6];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) mk[j] = cd.meta[k[j]];
+  for (int j = 0; j < 6; ++j) mk[j] = cd.meta_rb[k[j]];
   if (!zero) {
-    // absent neighbours read voxel i itself, which may not be written yet in
+    // absent neighbours read voxel p itself, which may not be written yet in
     // this sweep: select zero (a product with a zero coupling would keep NaN)
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
@@ -204,7 +221,7 @@ __device__ inline void voxel_row(const CellDev& cd, int op, int i, const C3& c, 
   const int L = lab_of(mi);
   KT g[6];
   // interface part of the concentration diagonal (per voxel, from the setup)
-  const KT dint = op == 0 ? ((const KT*)cd.dint)[i] : (KT)0;
+  const KT dint = op == 0 ? ((const KT*)cd.dint)[p] : (KT)0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     const int Lk = lab_of(mk[j]);
@@ -382,7 +399,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_assemble0(CellDev* cells, const i
             }
           }
           E[Li] += di;
-          ((KT*)cd.dint)[i] = di;   // for the level-0 smoother and restriction
+          ((KT*)cd.dint)[rb_index(cd, fx, fy, fz)] = di;   // for the level-0 smoother and restriction
         }
         for (int d = 1; d < 6; d += 2) {   // + directions only: each face counted once
           const int k = fine_nbr(i, fc, cd.nx, cd.ny, cd.nz, d);
@@ -547,21 +564,30 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int 
 // Krylov vector z (concentration part for op 0, potential part for op 1), the
 // right-hand side in b0.  mode SM_ZERO: first sweep (x treated as zero);
 // SM_CORR: neighbours corrected by alpha * (level-1 solution); else plain.
+// The iterate, right-hand side and meta words are read in colour-split order
+// (thread t of colour `color` is colour-split slot color*rbH + t), so a half
+// sweep touches whole cache lines of each colour.  On a cell's last
+// post-smoothing sweep (post, it == nu-1) the new values also go to the
+// Krylov vector z in natural order: the black values of that sweep are final,
+// and the red ones of the following half sweep.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg0_smooth(CellDev* cells, const int2* __restrict__ blk, int op,
-                                                       int color, int mode, int it, int need) {
+                                                       int color, int mode, int it, int need, int post) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || it >= cd.nu) return;   // cells that asked for fewer sweeps skip this one
   C3 c;
-  if (!color_cell(bb.y * kBlock + threadIdx.x, color, cd.nx, cd.ny, cd.nz, c)) return;
-  const int i = c.x + cd.nx * (c.y + cd.ny * c.z);
-  KT* x0 = (KT*)cd.z + (size_t)op * cd.N;
-  const KT bi = ((const KT*)cd.b0)[i];
+  const int t = bb.y * kBlock + threadIdx.x;
+  if (!color_cell(t, color, cd.nx, cd.ny, cd.nz, c)) return;
+  const int p = color * cd.rbH + t;
+  KT* x0 = (KT*)cd.x_rb;
+  const KT bi = ((const KT*)cd.b0)[p];
   KT D, S;
-  voxel_row<KT>(cd, op, i, c, cd.meta[i], x0, mode == SM_ZERO, mode == SM_CORR, D, S);
+  voxel_row<KT>(cd, op, p, c, cd.meta_rb[p], x0, mode == SM_ZERO, mode == SM_CORR, D, S);
   if (!gate_state(cd, need)) return;
-  x0[i] = D > (KT)0 ? (bi + S) / D : (KT)0;
+  const KT xn = D > (KT)0 ? (bi + S) / D : (KT)0;
+  x0[p] = xn;
+  if (post && it == cd.nu - 1) ((KT*)cd.z)[(size_t)op * cd.N + c.x + cd.nx * (c.y + cd.ny * c.z)] = xn;
 }
 
 // Sum over the 8 lanes of an aligned lane group (xor butterfly: every lane
@@ -596,12 +622,12 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
     const C3 q = c3_of(C, L1.nx, L1.ny);
     const C3 fc{2 * q.x + (ch & 1), 2 * q.y + ((ch >> 1) & 1), 2 * q.z + (ch >> 2)};
     if (fc.x < cd.nx && fc.y < cd.ny && fc.z < cd.nz) {
-      const KT* x0 = (const KT*)cd.z + (size_t)op * cd.N;
-      const int i = fc.x + cd.nx * (fc.y + cd.ny * fc.z);
-      const uint32_t mi = cd.meta[i];
-      const KT xi = x0[i], bi = ((const KT*)cd.b0)[i];
+      const KT* x0 = (const KT*)cd.x_rb;
+      const int p = rb_index(cd, fc.x, fc.y, fc.z);
+      const uint32_t mi = cd.meta_rb[p];
+      const KT xi = x0[p], bi = ((const KT*)cd.b0)[p];
       KT D, S;
-      voxel_row<KT>(cd, op, i, fc, mi, x0, false, false, D, S);
+      voxel_row<KT>(cd, op, p, fc, mi, x0, false, false, D, S);
       const int L = lab_of(mi);
       const KT r = bi + S - D * xi;
       rs[0] = L == 0 ? r : (KT)0;
@@ -822,7 +848,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
 }
 
 // ----------------------------------------------------- block-triangular glue
-// b0 = v_c - tau * v_phi on pore voxels (row operation removing migration).
+// b0 = v_c - tau * v_phi on pore voxels (row operation removing migration);
+// b0 is stored in colour-split order.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_pc_pre(CellDev* cells, const int2* __restrict__ blk, int src, int need) {
   const int2 bb = block_of(blk);
@@ -835,7 +862,8 @@ __global__ void __launch_bounds__(kBlock) k_pc_pre(CellDev* cells, const int2* _
   const KT vc = v[i], vp = v[(size_t)cd.N + i];
   const KT r = lab_of(mi) == PORE ? vc - (KT)cd.tau * vp : vc;
   if (!gate_state(cd, need)) return;
-  ((KT*)cd.b0)[i] = r;
+  const C3 c = c3_of(i, cd.nx, cd.ny);
+  ((KT*)cd.b0)[rb_index(cd, c.x, c.y, c.z)] = r;
 }
 
 // b0 = v_phi - (J [z_c; 0])_phi: the potential rows' dependence on the
@@ -892,7 +920,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* _
     yp += ex[j] ? t : (KT)0;
   }
   if (!gate_state(cd, need)) return;
-  ((KT*)cd.b0)[i] = vpi - yp;
+  ((KT*)cd.b0)[rb_index(cd, c.x, c.y, c.z)] = vpi - yp;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -911,9 +939,9 @@ void launch_mg_setup(const BatchLaunch& b, hipStream_t s) {
 }
 
 template <typename KT>
-static void smooth0(const BatchLaunch& b, int op, int color, int mode, int it, int need, hipStream_t s) {
+static void smooth0(const BatchLaunch& b, int op, int color, int mode, int it, int need, int post, hipStream_t s) {
   if (b.lvlh_nblk[0] <= 0) return;
-  k_mg0_smooth<KT><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, it, need);
+  k_mg0_smooth<KT><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, it, need, post);
 }
 
 template <typename KT>
@@ -935,8 +963,8 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
     if (l == 0) prof_begin(PK_SMOOTH0, s);   // the 2 nu level-0 half sweeps run back to back
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
-        smooth0<KT>(b, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, it, need, s);
-        smooth0<KT>(b, op, 1, SM_PLAIN, it, need, s);
+        smooth0<KT>(b, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, it, need, 0, s);
+        smooth0<KT>(b, op, 1, SM_PLAIN, it, need, 0, s);
       } else {
         smoothl<KT>(b, l, op, 0, it == 0 ? SM_ZERO : SM_PLAIN, it, need, s);
         smoothl<KT>(b, l, op, 1, it == 0 ? SM_OWNZERO : SM_PLAIN, it, need, s);
@@ -954,8 +982,8 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
     if (l == 0) prof_begin(PK_SMOOTH0, s);
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
-        smooth0<KT>(b, op, 1, it == 0 ? SM_CORR : SM_PLAIN, it, need, s);
-        smooth0<KT>(b, op, 0, SM_PLAIN, it, need, s);
+        smooth0<KT>(b, op, 1, it == 0 ? SM_CORR : SM_PLAIN, it, need, 1, s);
+        smooth0<KT>(b, op, 0, SM_PLAIN, it, need, 1, s);
       } else {
         smoothl<KT>(b, l, op, 1, it == 0 ? SM_CORR : SM_PLAIN, it, need, s);
         smoothl<KT>(b, l, op, 0, it == 0 ? SM_OWNCORR : SM_PLAIN, it, need, s);
