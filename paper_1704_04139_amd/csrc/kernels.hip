@@ -392,7 +392,9 @@ __global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* _
 }
 
 // ------------------------------------------------------------------- GMRES
-// Dots of w with basis vectors 0..k: block partials (first pass).
+// Dots of w with basis vectors 0..k: block partials (first pass).  The
+// basis loads are issued eight vectors at a time (indices past k clamp to k
+// and are not used), then the eight products are reduced.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_multidot(CellDev* cells, const int2* __restrict__ blk, int k) {
   const int2 bb = block_of(blk);
@@ -401,20 +403,27 @@ __global__ void __launch_bounds__(kBlock) k_multidot(CellDev* cells, const int2*
   __shared__ double lds[4 * kPartStride];
   const int i = bb.y * kBlock + threadIdx.x;
   const size_t N = cd.N;
-  double wc = 0.0, wp = 0.0;
   const bool in = i < cd.N;
+  const size_t ii = in ? (size_t)i : 0;
+  double wc = 0.0, wp = 0.0;
   if (in) {
     const KT* w = (const KT*)cd.w;
     wc = (double)w[i];
     wp = (double)w[N + i];
   }
-  for (int j = 0; j <= k; ++j) {
-    double s = 0.0;
-    if (in) {
-      const KT* vj = vec<KT>(cd, j);
-      s = (double)vj[i] * wc + (double)vj[N + i] * wp;
+  const KT* V = (const KT*)cd.Vb;
+  const size_t n2 = 2 * N;
+  for (int c = 0; c <= k; c += 8) {
+    KT vc[8], vp[8];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int j = c + jj < k ? c + jj : k;
+      vc[jj] = V[(size_t)j * n2 + ii];
+      vp[jj] = V[(size_t)j * n2 + N + ii];
     }
-    wave_to_lds(s, false, lds, kPartStride, j);
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj)
+      if (c + jj <= k) wave_to_lds((double)vc[jj] * wc + (double)vp[jj] * wp, false, lds, kPartStride, c + jj);
   }
   __syncthreads();
   for (int j = threadIdx.x; j <= k; j += kBlock)
@@ -436,9 +445,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize_dots(CellDev* cells, int nc
   if (threadIdx.x == 0) out[j] = r;
 }
 
-// First Gram-Schmidt pass and the second pass's dot products in one sweep
-// over the basis: w -= sum_j H(j,k) V_j, then block partials of V_j . w for
-// j <= k.  The thread's basis entries stay in registers between the two.
+// First Gram-Schmidt pass and the second pass's dot products in one kernel:
+// w -= sum_j H(j,k) V_j, then block partials of V_j . w for j <= k.  The
+// thread's basis entries are read again for the dots (the block's slice of
+// the basis was just fetched and mostly comes from cache): holding all of
+// them in registers would cut the occupancy to two waves per SIMD.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2* __restrict__ blk, int k) {
   const int2 bb = block_of(blk);
@@ -450,47 +461,51 @@ __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2
   const int i = bb.y * kBlock + threadIdx.x;
   const size_t N = cd.N;
   const bool in = i < cd.N;
+  const size_t ii = in ? (size_t)i : 0;
   KT* w = (KT*)cd.w;
-  KT vc[kMaxRestart], vp[kMaxRestart];
   KT wc = (KT)0, wp = (KT)0;
   if (in) {
     wc = w[i];
     wp = w[N + i];
   }
-  // chunks of 8 basis vectors: one uniform branch per chunk, the chunk's 16
-  // loads issued together (indices past k are clamped to k and not used)
   const KT* V = (const KT*)cd.Vb;
   const size_t n2 = 2 * N;
-  const size_t ii = in ? (size_t)i : 0;
+  for (int c = 0; c <= k; c += 8) {
+    KT vc[8], vp[8];
 #pragma unroll
-  for (int c = 0; c < kMaxRestart; c += 8) {
-    if (c <= k) {
-#pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        const int j = c + jj < k ? c + jj : k;
-        vc[c + jj] = V[(size_t)j * n2 + ii];
-        vp[c + jj] = V[(size_t)j * n2 + N + ii];
-      }
-#pragma unroll
-      for (int jj = 0; jj < 8; ++jj)
-        if (c + jj <= k) {
-          const KT hj = (KT)hc[c + jj];
-          wc -= hj * vc[c + jj];
-          wp -= hj * vp[c + jj];
-        }
+    for (int jj = 0; jj < 8; ++jj) {
+      const int j = c + jj < k ? c + jj : k;
+      vc[jj] = V[(size_t)j * n2 + ii];
+      vp[jj] = V[(size_t)j * n2 + N + ii];
     }
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj)
+      if (c + jj <= k) {
+        const KT hj = (KT)hc[c + jj];
+        wc -= hj * vc[jj];
+        wp -= hj * vp[jj];
+      }
   }
   if (in) {
     w[i] = wc;
     w[N + i] = wp;
-  }
-  if (!in) {
+  } else {
     wc = (KT)0;
     wp = (KT)0;
   }
+  const double dwc = (double)wc, dwp = (double)wp;
+  for (int c = 0; c <= k; c += 8) {
+    KT vc[8], vp[8];
 #pragma unroll
-  for (int j = 0; j < kMaxRestart; ++j)
-    if (j <= k) wave_to_lds((double)vc[j] * (double)wc + (double)vp[j] * (double)wp, false, lds, kPartStride, j);
+    for (int jj = 0; jj < 8; ++jj) {
+      const int j = c + jj < k ? c + jj : k;
+      vc[jj] = V[(size_t)j * n2 + ii];
+      vp[jj] = V[(size_t)j * n2 + N + ii];
+    }
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj)
+      if (c + jj <= k) wave_to_lds((double)vc[jj] * dwc + (double)vp[jj] * dwp, false, lds, kPartStride, c + jj);
+  }
   __syncthreads();
   for (int j = threadIdx.x; j <= k; j += kBlock)
     cd.part[(size_t)j * cd.nblk + bb.y] = combine4(lds, kPartStride, j, false);
@@ -511,11 +526,23 @@ __global__ void __launch_bounds__(kBlock) k_orth(CellDev* cells, const int2* __r
   if (i < cd.N) {
     KT* w = (KT*)cd.w;
     KT wc = w[i], wp = w[N + i];
-    for (int j = 0; j <= k; ++j) {
-      const KT* vj = vec<KT>(cd, j);
-      const KT hj = (KT)hc[j];
-      wc -= hj * vj[i];
-      wp -= hj * vj[N + i];
+    const KT* V = (const KT*)cd.Vb;
+    const size_t n2 = 2 * N;
+    for (int c = 0; c <= k; c += 8) {
+      KT vc[8], vp[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const int j = c + jj < k ? c + jj : k;
+        vc[jj] = V[(size_t)j * n2 + i];
+        vp[jj] = V[(size_t)j * n2 + N + i];
+      }
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj)
+        if (c + jj <= k) {
+          const KT hj = (KT)hc[c + jj];
+          wc -= hj * vc[jj];
+          wp -= hj * vp[jj];
+        }
     }
     w[i] = wc;
     w[N + i] = wp;

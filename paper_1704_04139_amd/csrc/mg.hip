@@ -606,7 +606,10 @@ __device__ inline double lane8_sum(double v) {
 }
 
 // Level-0 residual restricted to level 1: 8 lanes per level-1 cell, one per
-// child voxel; the per-slot sums are formed across the lanes.
+// child voxel; the per-slot sums are formed across the lanes.  The last
+// pre-smoothing half sweep solved every black row exactly for the current red
+// values, so only red rows carry a residual (the black ones are zero up to
+// rounding and are not evaluated).
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const int2* __restrict__ blk, int op,
                                                          int need) {
@@ -621,7 +624,7 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
   if (live) {
     const C3 q = c3_of(C, L1.nx, L1.ny);
     const C3 fc{2 * q.x + (ch & 1), 2 * q.y + ((ch >> 1) & 1), 2 * q.z + (ch >> 2)};
-    if (fc.x < cd.nx && fc.y < cd.ny && fc.z < cd.nz) {
+    if (fc.x < cd.nx && fc.y < cd.ny && fc.z < cd.nz && ((fc.x + fc.y + fc.z) & 1) == 0) {
       const KT* x0 = (const KT*)cd.x_rb;
       const int p = rb_index(cd, fc.x, fc.y, fc.z);
       const uint32_t mi = cd.meta_rb[p];
