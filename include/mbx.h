@@ -91,6 +91,9 @@ typedef struct {
   double V_cut;          /* cell-voltage cutoff, V (0: none).  A run (mbx_cell_run, a served request) stops
                             after the first step whose voltage reaches it: V >= V_cut while charging
                             (I_app > 0), V <= V_cut while discharging; no interpolation within the step */
+  int graphs;            /* 1 (mbx_params_default): the GMRES iterations between two host checks run as a
+                            captured HIP graph, replayed with one launch; 0: direct kernel launches.  Same
+                            kernels and results either way.  A batch uses graphs if all its cells do. */
 } mbx_params;
 
 typedef struct {

@@ -22,6 +22,7 @@
 #include "../../include/mbx.h"
 #include "mbx_dev.h"
 #include "mbx_kernels.h"
+#include "prof.h"
 
 using namespace mbx;
 
@@ -129,6 +130,27 @@ LevelDims level_dims(int nx, int ny, int nz, size_t kt) {
   return d;
 }
 
+// Captured HIP graphs of the GMRES iterations between two host checks: one
+// executable graph per chunk start, each valid for the launch configuration
+// (block counts, tables, sweep counts) it was captured with.  Captured on a
+// private stream and replayed on the cells' stream.
+struct ChunkGraphs {
+  std::vector<hipGraphExec_t> exec;
+  std::vector<uint64_t> key;
+  hipStream_t cap = nullptr;
+  void clear() {
+    for (hipGraphExec_t& e : exec)
+      if (e) (void)hipGraphExecDestroy(e);
+    exec.clear();
+    key.clear();
+  }
+  void release() {
+    clear();
+    if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
+  }
+};
+
 }  // namespace
 
 namespace mbx {
@@ -163,6 +185,7 @@ struct mbx_cell {
   double* cap_phi = nullptr;
   int64_t cap_ld = 0;
   int cap_capacity = 0, cap_count = 0, cap_dropped = 0;
+  ChunkGraphs graphs;          // GMRES iterations of single-cell steps, replayed as HIP graphs
 };
 
 namespace {
@@ -270,6 +293,7 @@ int check_params(const mbx_params* p) {
   if (p->precision != MBX_FP64 && p->precision != MBX_MIXED) return fail(MBX_EINVAL, "unknown precision mode");
   if (p->plating != 0 && p->plating != 1) return fail(MBX_EINVAL, "plating must be 0 or 1");
   if (!(std::isfinite(p->V_cut) && p->V_cut >= 0.0)) return fail(MBX_EINVAL, "V_cut must be finite and >= 0");
+  if (p->graphs != 0 && p->graphs != 1) return fail(MBX_EINVAL, "graphs must be 0 or 1");
   return MBX_OK;
 }
 
@@ -332,6 +356,8 @@ struct Batch {
   int nblk = 0;
   bool owned = false;
   bool mixed = false;
+  bool use_graphs = false;      // replay the GMRES iterations as captured HIP graphs
+  ChunkGraphs* graphs = nullptr;
   int m = kRestart;
   int maxlev = 0;
   int maxfuse = 1;
@@ -462,6 +488,8 @@ Batch single(mbx_cell* c) {
   b.nblk = c->nblk;
   b.mixed = c->mixed;
   b.m = c->m;
+  b.graphs = &c->graphs;
+  b.use_graphs = c->p.graphs != 0;
   b.maxlev = c->ld.n;
   b.maxfuse = c->ld.lfuse;
   for (int l = 0; l < c->ld.n; ++l) {
@@ -479,6 +507,7 @@ Batch single(mbx_cell* c) {
 struct BatchCache {
   std::vector<uint64_t> ids;
   Batch b;
+  ChunkGraphs graphs;
 } g_batch_cache;
 // guards g_batch_cache: batched steps from different threads (a server's
 // worker and a caller) run one at a time, and destroying a cell that the
@@ -495,8 +524,12 @@ int make_batch(mbx_cell* const* cells, int n, Batch*& out) {
     return MBX_OK;
   }
   g_batch_cache.b.release();
+  g_batch_cache.graphs.clear();
   Batch b;
   b.cells.assign(cells, cells + n);
+  b.graphs = &g_batch_cache.graphs;
+  b.use_graphs = true;
+  for (int c = 0; c < n; ++c) b.use_graphs = b.use_graphs && cells[c]->p.graphs != 0;
   b.s = cells[0]->s;
   b.mixed = cells[0]->mixed;
   b.m = cells[0]->m;
@@ -542,39 +575,123 @@ int make_batch(mbx_cell* const* cells, int n, Batch*& out) {
 }
 
 // ------------------------------------------------------------------ GMRES
+// Launch configuration a captured chunk depends on (everything the kernel
+// arguments and grid sizes are made of).
+uint64_t launch_key(const Batch& B, const BatchLaunch& b, int k0, int k1) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+  mix((uint64_t)(uintptr_t)b.cells);
+  mix((uint64_t)(uintptr_t)b.blk);
+  mix((uint64_t)b.nblk);
+  mix((uint64_t)b.ncell);
+  mix((uint64_t)b.maxlev);
+  mix((uint64_t)b.maxfuse);
+  mix((uint64_t)b.fused_lds);
+  mix((uint64_t)b.max_nu);
+  mix((uint64_t)b.faces_single);
+  for (int l = 0; l < kMaxLevels; ++l) {
+    mix((uint64_t)(uintptr_t)b.lvl_blk[l] ^ ((uint64_t)b.lvl_nblk[l] << 48));
+    mix((uint64_t)(uintptr_t)b.lvl8_blk[l] ^ ((uint64_t)b.lvl8_nblk[l] << 48));
+    mix((uint64_t)(uintptr_t)b.lvlh_blk[l] ^ ((uint64_t)b.lvlh_nblk[l] << 48));
+  }
+  mix((uint64_t)(uintptr_t)B.d_gather);
+  mix((uint64_t)(uintptr_t)B.h_gather);
+  mix((uint64_t)B.cells.size());
+  mix((uint64_t)B.m);
+  mix((uint64_t)k0 | ((uint64_t)k1 << 32));
+  return h;
+}
+
+// GMRES iterations k0 .. k1-1 of every running cell of the batch, then the
+// flags and reduction slots gathered to the host.
+template <typename KT>
+void launch_chunk(const BatchLaunch& bl, int k0, int k1, double* d_gather, int ncells, double* h_gather,
+                  hipStream_t s, bool copy_out) {
+  for (int k = k0; k < k1; ++k) {
+    launch_precond<KT>(bl, k, 0, s);
+    launch_matvec<KT>(bl, VEC_Z, VEC_W, 0, k, s);
+    // classical Gram-Schmidt with one re-orthogonalisation (CGS2)
+    launch_multidot<KT>(bl, k, 0, s);   // H(:,k) = V^T w
+    launch_orth_dots<KT>(bl, k, s);     // w -= V H(:,k); tmp = V^T w
+    launch_orth<KT>(bl, k, 1, s);       // w -= V tmp; H(:,k) += tmp; H(k+1,k) = |w|
+    launch_scale_next<KT>(bl, k, s);
+    launch_givens(bl, k, s);
+  }
+  if (copy_out) {
+    launch_gather_ctl(bl, d_gather, s);
+    (void)hipMemcpyAsync(h_gather, d_gather, sizeof(double) * kGather * ncells, hipMemcpyDeviceToHost, s);
+  }
+}
+
+// The chunk as a HIP graph: captured on the first use of a configuration,
+// replayed afterwards (one launch and one synchronisation per chunk).
+template <typename KT>
+int run_chunk_graph(Batch& B, int k0, int k1) {
+  ChunkGraphs& G = *B.graphs;
+  const BatchLaunch bl = B.bl();
+  const uint64_t key = launch_key(B, bl, k0, k1);
+  const size_t slot = (size_t)k0;
+  if (G.exec.size() <= slot) {
+    G.exec.resize(slot + 1, nullptr);
+    G.key.resize(slot + 1, 0);
+  }
+  if (!G.exec[slot] || G.key[slot] != key) {
+    if (G.exec[slot]) {
+      (void)hipGraphExecDestroy(G.exec[slot]);
+      G.exec[slot] = nullptr;
+    }
+    if (!G.cap) HIPCHK(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+    launch_chunk<KT>(bl, k0, k1, B.d_gather, (int)B.cells.size(), B.h_gather, G.cap, true);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(G.cap, &g);
+    if (ec != hipSuccess || !g) return fail(MBX_EHIP, "GMRES graph capture: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&G.exec[slot], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      G.exec[slot] = nullptr;
+      return fail(MBX_EHIP, "GMRES graph instantiation: %s", hipGetErrorString(ei));
+    }
+    G.key[slot] = key;
+  }
+  HIPCHK(hipGraphLaunch(G.exec[slot], B.s));
+  HIPCHK(hipStreamSynchronize(B.s));
+  return MBX_OK;
+}
+
 template <typename KT>
 int gmres(Batch& B, int max_iters, int* iters_out) {
   const int m = B.m;
   const int check = 4;
+  // kernel timing records events between launches: direct launches then
+  const bool graphs = B.use_graphs && B.graphs && !prof_active();
   int total = 0;
   launch_gm_start<KT>(B.bl(), 1, B.s);
   const int refine = sizeof(KT) < sizeof(double);
   launch_gm_flags(B.bl(), 1, refine, B.s);
   while (total < max_iters) {
     int k = 0;
-    for (; k < m; ++k) {
-      launch_precond<KT>(B.bl(), k, 0, B.s);
-      launch_matvec<KT>(B.bl(), VEC_Z, VEC_W, 0, k, B.s);
-      // classical Gram-Schmidt with one re-orthogonalisation (CGS2)
-      launch_multidot<KT>(B.bl(), k, 0, B.s);   // H(:,k) = V^T w
-      launch_orth_dots<KT>(B.bl(), k, B.s);     // w -= V H(:,k); tmp = V^T w
-      launch_orth<KT>(B.bl(), k, 1, B.s);       // w -= V tmp; H(:,k) += tmp; H(k+1,k) = |w|
-      launch_scale_next<KT>(B.bl(), k, B.s);
-      launch_givens(B.bl(), k, B.s);
-      if ((k + 1) % check == 0 || k + 1 == m) {
+    for (int k0 = 0; k0 < m;) {
+      const int k1 = std::min(k0 + check, m);
+      if (graphs) {
+        if (int e = run_chunk_graph<KT>(B, k0, k1)) return e;
+      } else {
+        launch_chunk<KT>(B.bl(), k0, k1, B.d_gather, (int)B.cells.size(), B.h_gather, B.s, false);
         if (int e = B.gather()) return e;
-        bool running = false;
-        std::vector<char> on(B.cells.size());
-        for (size_t c = 0; c < B.cells.size(); ++c) {
-          on[c] = B.cells[c]->h.active && B.ctl(c, CTL_DONE) == 0;
-          running = running || on[c];
-        }
-        if (!running) {
-          ++k;
-          break;
-        }
-        if (int e = B.set_active(on)) return e;   // launch only the cells still iterating
       }
+      k = k1;
+      bool running = false;
+      std::vector<char> on(B.cells.size());
+      for (size_t c = 0; c < B.cells.size(); ++c) {
+        on[c] = B.cells[c]->h.active && B.ctl(c, CTL_DONE) == 0;
+        running = running || on[c];
+      }
+      if (!running) break;
+      // launch only the cells still iterating (a captured graph keeps its
+      // tables: cells that finished leave its kernels at their flag test)
+      if (!graphs)
+        if (int e = B.set_active(on)) return e;
+      k0 = k1;
     }
     total += k;
     {
@@ -952,6 +1069,7 @@ int mbx_params_default(mbx_params* p) {
   p->newton_max = 30;
   p->krylov_max = 600;
   p->thermo = 1.0;
+  p->graphs = 1;
   return MBX_OK;
 }
 
@@ -1214,9 +1332,11 @@ void mbx_cell_destroy(mbx_cell* c) {
   for (size_t k = 0; k < g_batch_cache.ids.size(); ++k)
     if (g_batch_cache.ids[k] == c->id) {
       g_batch_cache.b.release();
+      g_batch_cache.graphs.clear();
       g_batch_cache.ids.clear();
       break;
     }
+  c->graphs.release();
   (void)hipFree(c->dmem);
   (void)hipHostFree(c->h_gather);
   (void)hipHostFree(c->h_desc_pinned);

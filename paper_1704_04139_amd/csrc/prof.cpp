@@ -35,6 +35,7 @@ hipEvent_t take_event() {
 }  // namespace
 
 bool prof_on(int k) { return k != PK_NONE && g_kernel == k; }
+bool prof_active() { return g_kernel != PK_NONE; }
 
 void prof_begin(int k, hipStream_t s) {
   if (!prof_on(k)) return;

@@ -9,6 +9,8 @@ enum ProfKernel { PK_NONE = 0, PK_RESIDUAL = 1, PK_MATVEC = 2, PK_SMOOTH0 = 3, P
 
 // True when launches of kernel class k are being timed.
 bool prof_on(int k);
+// True while any kernel class is being timed.
+bool prof_active();
 // Brackets one launch: records an event pair on stream s and the launch's
 // algorithmic bytes.
 void prof_begin(int k, hipStream_t s);

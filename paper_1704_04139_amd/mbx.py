@@ -33,7 +33,8 @@ class Params(ctypes.Structure):
                 ("Ds", _d * 2), ("sigma", _d * 2), ("cmax", _d * 2), ("i00", _d * 2),
                 ("U0", _d * 2), ("U1", _d * 2), ("i00_pl", _d), ("n_c", _d),
                 ("plating", _i), ("precision", _i), ("newton_tol", _d), ("res_tol", _d),
-                ("krylov_rtol", _d), ("newton_max", _i), ("krylov_max", _i), ("V_cut", _d)]
+                ("krylov_rtol", _d), ("newton_max", _i), ("krylov_max", _i), ("V_cut", _d),
+                ("graphs", _i)]
 
 
 class StepInfo(ctypes.Structure):

@@ -35,7 +35,7 @@ def test_params_default_and_footprint():
     lib = mbx.load()
     p = mbx.Params()
     assert lib.mbx_params_default(ctypes.byref(p)) == 0
-    assert p.newton_tol == 0.0 and p.newton_max == 30 and p.thermo == 1.0 and p.V_cut == 0.0
+    assert p.newton_tol == 0.0 and p.newton_max == 30 and p.thermo == 1.0 and p.V_cut == 0.0 and p.graphs == 1
     assert lib.mbx_params_default(None) == mbx.MBX_EINVAL
     f64 = mbx.footprint(64, 64, 160, "fp64", 90000, 90000)
     f32 = mbx.footprint(64, 64, 160, "mixed", 90000, 90000)
