@@ -200,6 +200,15 @@ int mbx_cell_mean_solid(const mbx_cell *c, double out[2]);
 int mbx_cell_run(mbx_cell *c, double dt, int max_steps, double *V_out, int *steps_out, int *cutoff_out,
                  int *retried);
 
+/* Workgroup sizes (threads) the library picked for this cell's single-cell
+ * launches of the level-0 multigrid smoother and of J*v: at creation it times
+ * 256, 128 and 64 threads on the cell's own arrays and keeps the fastest
+ * (a smaller size must be 3% faster), once per grid size and precision per
+ * process (environment MBX_TUNE_FILE: read and append the choices to that
+ * file; MBX_TUNE=0: always 256; MBX_TUNE=64/128/256: that size).  Results do not depend on the choice.
+ * Batched launches use 256.  Either pointer may be null. */
+int mbx_cell_launch_shape(const mbx_cell *c, int *smooth0_threads, int *matvec_threads);
+
 /* Lithium inventories (mol) in electrolyte, anode solid, cathode solid and
  * the plated layer (Sec. 2.4 conservative scheme: at convergence the total
  * changes only through the applied current).  out[4]. */

@@ -9,7 +9,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -186,6 +188,8 @@ struct mbx_cell {
   int64_t cap_ld = 0;
   int cap_capacity = 0, cap_count = 0, cap_dropped = 0;
   ChunkGraphs graphs;          // GMRES iterations of single-cell steps, replayed as HIP graphs
+  int bs_smooth0 = kBlock;     // workgroup sizes of single-cell launches picked by the tuner
+  int bs_matvec = kBlock;
 };
 
 namespace {
@@ -389,6 +393,9 @@ struct Batch {
     b.nblk = nblk;
     b.ncell = (int)cells.size();
     b.faces_single = one ? cells[0]->F_an + cells[0]->F_ca : 0;
+    b.n_single = one ? cells[0]->N : 0;
+    b.bs_smooth0 = one ? cells[0]->bs_smooth0 : kBlock;
+    b.bs_matvec = one ? cells[0]->bs_matvec : kBlock;
     b.maxlev = maxlev;
     b.maxfuse = maxfuse;
     b.fused_lds = 0;
@@ -1045,6 +1052,90 @@ int step_recover(std::vector<mbx_cell*> cells, double dt, int* status, mbx_step_
   return MBX_OK;
 }
 
+// ------------------------------------------------------------ launch tuner
+// Workgroup size of the single-cell launches of the level-0 smoother and of
+// J*v, picked per grid size and precision by timing 256, 128 and 64 threads
+// on the new cell's own arrays (one warm-up and three timed launches each;
+// a smaller size must be 3% faster to be taken).  The kernels compute the
+// same values with any size, so results do not depend on the choice.  Kept
+// per process; with MBX_TUNE_FILE the choices are read from and appended to
+// that file.  MBX_TUNE=0 keeps 256; MBX_TUNE=64, 128 or 256 fixes that size.
+std::mutex g_tune_mu;
+std::map<std::array<int, 4>, std::array<int, 2>> g_tune;
+bool g_tune_loaded = false;
+
+bool tune_valid(int bs) { return bs == 64 || bs == 128 || bs == kBlock; }
+
+template <typename KT>
+int time_shapes(mbx_cell* c, bool smooth, int& best) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best_ms = 1e30;
+  best = kBlock;
+  int rc = MBX_OK;
+  for (int bs : {kBlock, 128, 64}) {
+    Batch b = single(c);
+    BatchLaunch bl = b.bl();
+    (smooth ? bl.bs_smooth0 : bl.bs_matvec) = bs;
+    for (int r = 0; r < 4; ++r) {
+      if (r == 1 && hipEventRecord(e0, c->s) != hipSuccess) rc = MBX_EHIP;
+      if (smooth)
+        launch_smooth0_probe<KT>(bl, c->s);
+      else
+        launch_matvec<KT>(bl, VEC_Z, VEC_W, 0, -1, c->s);
+    }
+    float ms = 0.f;
+    if (hipEventRecord(e1, c->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess)
+      rc = MBX_EHIP;
+    if (rc != MBX_OK) break;
+    if (best_ms >= 1e30 || ms < 0.97 * best_ms) {
+      best = bs;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc == MBX_OK ? MBX_OK : fail(MBX_EHIP, "launch-shape tuning failed");
+}
+
+int tune_launch_shape(mbx_cell* c) {
+  if (const char* fix = std::getenv("MBX_TUNE")) {
+    const int v = std::atoi(fix);
+    if (v == 0 || tune_valid(v)) {
+      c->bs_smooth0 = c->bs_matvec = v == 0 ? kBlock : v;
+      return MBX_OK;
+    }
+  }
+  const std::array<int, 4> key = {c->nx, c->ny, c->nz, c->p.precision};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const char* file = std::getenv("MBX_TUNE_FILE");
+  if (!g_tune_loaded) {
+    g_tune_loaded = true;
+    if (FILE* fp = file ? std::fopen(file, "r") : nullptr) {
+      int nx, ny, nz, pr, a, b;
+      while (std::fscanf(fp, "%d %d %d %d %d %d", &nx, &ny, &nz, &pr, &a, &b) == 6)
+        if (tune_valid(a) && tune_valid(b)) g_tune[{nx, ny, nz, pr}] = {a, b};
+      std::fclose(fp);
+    }
+  }
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) {
+    int a = kBlock, b = kBlock;
+    if (int e = c->mixed ? time_shapes<float>(c, true, a) : time_shapes<double>(c, true, a)) return e;
+    if (int e = c->mixed ? time_shapes<float>(c, false, b) : time_shapes<double>(c, false, b)) return e;
+    it = g_tune.emplace(key, std::array<int, 2>{a, b}).first;
+    if (FILE* fp = file ? std::fopen(file, "a") : nullptr) {
+      std::fprintf(fp, "%d %d %d %d %d %d\n", c->nx, c->ny, c->nz, c->p.precision, a, b);
+      std::fclose(fp);
+    }
+  }
+  c->bs_smooth0 = it->second[0];
+  c->bs_matvec = it->second[1];
+  return MBX_OK;
+}
+
 int sync_outputs(mbx_cell* c) {
   Batch b = single(c);
   c->h.active = 1;
@@ -1315,6 +1406,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
       launch_init_state(bt.bl(), s);
       rc = sync_outputs(c);
     }
+    if (rc == MBX_OK) rc = tune_launch_shape(c);
   }
   if (rc != MBX_OK) {
     mbx_cell_destroy(c);
@@ -1445,6 +1537,13 @@ int mbx_cell_inventory(const mbx_cell* cc, double out[4]) {
   mbx_cell* c = const_cast<mbx_cell*>(cc);
   if (int e = sync_outputs(c)) return e;
   for (int k = 0; k < 4; ++k) out[k] = c->h_gather[RED_INV0 + k];
+  return MBX_OK;
+}
+
+int mbx_cell_launch_shape(const mbx_cell* c, int* smooth0_threads, int* matvec_threads) {
+  if (!c) return fail(MBX_EINVAL, "null cell");
+  if (smooth0_threads) *smooth0_threads = c->bs_smooth0;
+  if (matvec_threads) *matvec_threads = c->bs_matvec;
   return MBX_OK;
 }
 

@@ -368,13 +368,15 @@ __global__ void __launch_bounds__(kBlock) k_rhs(CellDev* cells, const int2* __re
 // regions would otherwise cancel away.  keep >= 0 also stores the operand
 // as preconditioned basis vector `keep` of the flexible GMRES (the exact
 // values the product was applied to).
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_matvec(CellDev* cells, const int2* __restrict__ blk, int src, int dst,
-                                                   int need, int keep) {
+// BS threads per workgroup (kBlock in table launches; a single-cell launch
+// takes the size the tuner picked for the cell).
+template <typename KT, int BS>
+__global__ void __launch_bounds__(BS) k_matvec(CellDev* cells, const int2* __restrict__ blk, int src, int dst,
+                                               int need, int keep) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
-  const int i = bb.y * kBlock + threadIdx.x;
+  const int i = bb.y * BS + threadIdx.x;
   if (i >= cd.N) return;
   const KT* v = vec<KT>(cd, src);
   double yc, yp;
@@ -1057,7 +1059,13 @@ void launch_rhs(const BatchLaunch& b, hipStream_t s) {
 template <typename KT>
 void launch_matvec(const BatchLaunch& b, int src, int dst, int need, int keep, hipStream_t s) {
   prof_begin(PK_MATVEC, s);
-  k_matvec<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need, keep);
+  const int bs = b.blk ? kBlock : b.bs_matvec;
+  if (bs == 64)
+    k_matvec<KT, 64><<<(b.n_single + 63) / 64, 64, 0, s>>>(b.cells, nullptr, src, dst, need, keep);
+  else if (bs == 128)
+    k_matvec<KT, 128><<<(b.n_single + 127) / 128, 128, 0, s>>>(b.cells, nullptr, src, dst, need, keep);
+  else
+    k_matvec<KT, kBlock><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need, keep);
   if (prof_on(PK_MATVEC)) prof_end(PK_MATVEC, s, b.bytes_matvec);
 }
 template <typename KT>

@@ -18,6 +18,9 @@ struct BatchLaunch {
   int nblk;
   int ncell;
   int faces_single;                      // interface faces of the cell of a single-cell launch (blk == nullptr)
+  int n_single;                          // voxels of that cell
+  int bs_smooth0, bs_matvec;             // threads per workgroup of the level-0 smoother and of J*v in a
+                                         // single-cell launch (64, 128 or 256; table launches use kBlock)
   int maxlev;                            // max multigrid levels over the batch
   int maxfuse;                           // max first fused level over the batch
   size_t fused_lds;                      // LDS elements (KT) of the fused coarse cycle, max over the batch
@@ -72,6 +75,9 @@ void launch_copy_state(const BatchLaunch& b, int mode, hipStream_t s);
 void launch_outputs(const BatchLaunch& b, hipStream_t s);
 
 // multigrid preconditioner (mg.hip)
+// one level-0 red-black half sweep (operator op, colour 0, no GMRES gate) on
+// the cell's current arrays: the workgroup-size tuner's probe
+template <typename KT> void launch_smooth0_probe(const BatchLaunch& b, hipStream_t s);
 template <typename KT> void launch_mg_setup(const BatchLaunch& b, hipStream_t s);
 // z = M^-1 v_src; need: GMRES state gate (>= 0 equal, -1 cycle end, -2 always)
 template <typename KT> void launch_precond(const BatchLaunch& b, int src, int need, hipStream_t s);

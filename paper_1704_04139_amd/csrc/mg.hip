@@ -570,14 +570,16 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int 
 // post-smoothing sweep (post, it == nu-1) the new values also go to the
 // Krylov vector z in natural order: the black values of that sweep are final,
 // and the red ones of the following half sweep.
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_mg0_smooth(CellDev* cells, const int2* __restrict__ blk, int op,
-                                                       int color, int mode, int it, int need, int post) {
+// BS threads per workgroup (kBlock in table launches; a single-cell launch
+// takes the size the tuner picked for the cell).
+template <typename KT, int BS>
+__global__ void __launch_bounds__(BS) k_mg0_smooth(CellDev* cells, const int2* __restrict__ blk, int op, int color,
+                                                   int mode, int it, int need, int post) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || it >= cd.nu) return;   // cells that asked for fewer sweeps skip this one
   C3 c;
-  const int t = bb.y * kBlock + threadIdx.x;
+  const int t = bb.y * BS + threadIdx.x;
   if (!color_cell(t, color, cd.nx, cd.ny, cd.nz, c)) return;
   const int p = color * cd.rbH + t;
   KT* x0 = (KT*)cd.x_rb;
@@ -944,7 +946,20 @@ void launch_mg_setup(const BatchLaunch& b, hipStream_t s) {
 template <typename KT>
 static void smooth0(const BatchLaunch& b, int op, int color, int mode, int it, int need, int post, hipStream_t s) {
   if (b.lvlh_nblk[0] <= 0) return;
-  k_mg0_smooth<KT><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, it, need, post);
+  const int bs = b.lvlh_blk[0] ? kBlock : b.bs_smooth0;
+  const int nh = b.lvlh_nblk[0] * kBlock;   // single cell: one colour's cells, rounded up to kBlock
+  if (bs == 64)
+    k_mg0_smooth<KT, 64><<<nh / 64, 64, 0, s>>>(b.cells, nullptr, op, color, mode, it, need, post);
+  else if (bs == 128)
+    k_mg0_smooth<KT, 128><<<nh / 128, 128, 0, s>>>(b.cells, nullptr, op, color, mode, it, need, post);
+  else
+    k_mg0_smooth<KT, kBlock><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, it, need,
+                                                               post);
+}
+
+template <typename KT>
+void launch_smooth0_probe(const BatchLaunch& b, hipStream_t s) {
+  smooth0<KT>(b, 1, 0, SM_PLAIN, 0, -2, 0, s);
 }
 
 template <typename KT>
@@ -1009,6 +1024,8 @@ void launch_precond(const BatchLaunch& b, int src, int need, hipStream_t s) {
 template void launch_mg_setup<float>(const BatchLaunch&, hipStream_t);
 template void launch_mg_setup<double>(const BatchLaunch&, hipStream_t);
 template void launch_precond<float>(const BatchLaunch&, int, int, hipStream_t);
+template void launch_smooth0_probe<float>(const BatchLaunch&, hipStream_t);
+template void launch_smooth0_probe<double>(const BatchLaunch&, hipStream_t);
 template void launch_precond<double>(const BatchLaunch&, int, int, hipStream_t);
 
 }  // namespace mbx

@@ -90,6 +90,7 @@ SIGNATURES = {
     "mbx_cell_voltage": (_i, [_vp, _dp]),
     "mbx_cell_inventory": (_i, [_vp, _dp]),
     "mbx_cell_mean_solid": (_i, [_vp, _dp]),
+    "mbx_cell_launch_shape": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "mbx_cell_run": (_i, [_vp, _d, _i, _dp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "mbx_cell_residual": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp]),
     "mbx_cell_jvp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]),
@@ -270,6 +271,12 @@ class Cell:
         out = (ctypes.c_double * 2)()
         _check(load().mbx_cell_mean_solid(self._h, out))
         return out[0], out[1]
+
+    def launch_shape(self):
+        """(level-0 smoother, J*v) workgroup sizes the library's tuner picked for this cell."""
+        a, b = _i(), _i()
+        _check(load().mbx_cell_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def run(self, dt: float, max_steps: int):
         """Step loop with the voltage cutoff params.V_cut: returns
