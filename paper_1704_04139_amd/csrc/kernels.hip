@@ -12,7 +12,7 @@
 #include "reduce.h"
 #include "prof.h"
 
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
 
@@ -230,16 +230,54 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
     const VoxCoord v = coord_of(cd, i);
     const uint32_t mi = cd.meta[i];
     const int L = lab_of(mi);
-    const double ci = cd.c_try[i], pi = cd.phi_try[i];
+    const double ci = cd.c_try[i], pi = cd.phi_try[i], cold = cd.c_old[i];
     const double A = cd.A, h = cd.h, dt = cd.dt;
     const size_t F = (size_t)cd.F_an + cd.F_ca;
-    double Rc = cd.Vol * (ci - cd.c_old[i]) / dt;
+    // every load of the row issued before the arithmetic: the neighbours'
+    // meta words and states (absent neighbours read voxel i), then the
+    // interface faces' results, whose indices need the meta words
+    int kk[6];
+    bool ex[6];
+    uint32_t mk[6];
+    double ck[6], pk[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      const int k = neighbour(cd, i, v.x, v.y, v.z, d);
+      ex[d] = k >= 0;
+      kk[d] = ex[d] ? k : i;
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      mk[d] = cd.meta[kk[d]];
+      ck[d] = cd.c_try[kk[d]];
+      pk[d] = cd.phi_try[kk[d]];
+    }
+    double fi[6], ft[6], rnf[6], dnf[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      const int Lk = lab_of(mk[d]);
+      const bool iface = ex[d] && ((L == PORE) != (Lk == PORE));
+      const bool pore_side = L == PORE;
+      const bool an = (pore_side ? Lk : L) == ANODE;
+      const uint32_t fr = iface ? face_rank(pore_side ? mk[d] : mi, pore_side ? (d ^ 1) : d) : 0u;
+      const uint32_t f = fr + (an ? 0u : (uint32_t)cd.F_an);
+      const double t = cd.fres[F + (iface ? f : 0u)];
+      const double s1 = cd.fres[iface ? f : 0u];
+      ft[d] = t;
+      fi[d] = s1;
+      // plated-amount row and update of an anode face, read on the solid side
+      const bool own_an = iface && !pore_side && L == ANODE;
+      const uint32_t fa = own_an ? fr : 0u;
+      rnf[d] = own_an ? cd.Rn[fa] : 0.0;
+      dnf[d] = (own_an && cd.elim_n) ? fabs(cd.n_try[fa] - cd.n[fa]) / cd.n_c : 0.0;
+    }
+    double Rc = cd.Vol * (ci - cold) / dt;
     double Rp = 0.0;
     const double lci = (L == PORE) ? log(ci) : 0.0;   // ln c of this voxel, shared by its pore faces
     double wc = 1.0, wp = 0.0;   // state-independent diagonal of the scaled rows (merit weights)
+#pragma unroll
     for (int d = 0; d < 6; ++d) {
-      const int k = neighbour(cd, i, v.x, v.y, v.z, d);
-      if (k < 0) {
+      if (!ex[d]) {
         if (d == 4 && L == ANODE) {
           Rp += 2.0 * A * cd.sigma[0] * pi / h;
         } else if (d == 5 && L == CATHODE) {
@@ -247,25 +285,23 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
         }
         continue;
       }
-      const uint32_t mk = cd.meta[k];
-      const int Lk = lab_of(mk);
+      const int k = kk[d];
+      const int Lk = lab_of(mk[d]);
       const bool lo = i < k;
       const double sgn = lo ? 1.0 : -1.0;
       weight_add(cd, L, Lk, wc, wp);
       if (L == PORE && Lk == PORE) {
-        const double ck = cd.c_try[k], pk = cd.phi_try[k];
-        const double ca = lo ? ci : ck, cb = lo ? ck : ci;
-        const double pa = lo ? pi : pk, pb = lo ? pk : pi;
-        const double lck = log(ck);
+        const double ca = lo ? ci : ck[d], cb = lo ? ck[d] : ci;
+        const double pa = lo ? pi : pk[d], pb = lo ? pk[d] : pi;
+        const double lck = log(ck[d]);
         const double lca = lo ? lci : lck, lcb = lo ? lck : lci;
         const double j = -cd.kappa * (pb - pa) / h + cd.Kd * (lcb - lca);
         const double Nf = -cd.De * (cb - ca) / h + cd.tplus / kFaraday * j;
         Rc += sgn * (A * Nf);
         Rp += sgn * (A * j);
       } else if (L == Lk) {
-        const double ck = cd.c_try[k], pk = cd.phi_try[k];
-        const double ca = lo ? ci : ck, cb = lo ? ck : ci;
-        const double pa = lo ? pi : pk, pb = lo ? pk : pi;
+        const double ca = lo ? ci : ck[d], cb = lo ? ck[d] : ci;
+        const double pa = lo ? pi : pk[d], pb = lo ? pk[d] : pi;
         const int s = L - 1;
         const double Nf = -cd.Ds[s] * (cb - ca) / h;
         const double j = -cd.sigma[s] * (pb - pa) / h;
@@ -273,22 +309,16 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
         Rp += sgn * (A * j);
       } else if (L == PORE) {
         // interface face seen from the pore: its total current leaves the solid
-        const uint32_t f = face_rank(mk, d ^ 1) + (Lk == ANODE ? 0u : (uint32_t)cd.F_an);
-        const double it = cd.fres[F + f];
-        Rc -= A * it / kFaraday;
-        Rp -= A * it;
+        Rc -= A * ft[d] / kFaraday;
+        Rp -= A * ft[d];
       } else {
-        const bool an = L == ANODE;
-        const uint32_t fr = face_rank(mi, d);
-        const uint32_t f = fr + (an ? 0u : (uint32_t)cd.F_an);
-        Rc += A * cd.fres[f] / kFaraday;
-        Rp += A * cd.fres[F + f];
-        if (an) {
-          const double Rn = cd.Rn[fr];
-          const double rs = Rn * dt / (A * cd.n_c);
+        Rc += A * fi[d] / kFaraday;
+        Rp += A * ft[d];
+        if (L == ANODE) {
+          const double rs = rnf[d] * dt / (A * cd.n_c);
           rsq += rs * rs;
           rmax = fmax(rmax, fabs(rs));
-          if (cd.elim_n) dnmax = fmax(dnmax, fabs(cd.n_try[fr] - cd.n[fr]) / cd.n_c);
+          dnmax = fmax(dnmax, dnf[d]);
         }
       }
     }
@@ -1024,7 +1054,7 @@ void launch_finish_meta(int N, uint32_t* meta, const int* off_an, const int* off
   k_finish_meta<<<(N + kBlock - 1) / kBlock, kBlock, 0, s>>>(N, meta, off_an, off_ca, faces_an, faces_ca);
 }
 hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* out, int n, hipStream_t s) {
-  return hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, in, out, n, s);
+  return rocprim::exclusive_scan(temp, temp_bytes, in, out, 0, (size_t)n, rocprim::plus<int>(), s);
 }
 void launch_meta_rb(const CellDev& cd, hipStream_t s) {
   (void)hipMemsetAsync((void*)cd.meta_rb, 0, 8 * (size_t)cd.rbH, s);

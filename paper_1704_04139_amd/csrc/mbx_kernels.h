@@ -44,7 +44,7 @@ void launch_finish_meta(int N, uint32_t* meta, const int* off_an, const int* off
 void launch_init_state(const BatchLaunch& b, hipStream_t s);
 // colour-split copy of the finished meta words (cd: host copy of the descriptor, device pointers)
 void launch_meta_rb(const CellDev& cd, hipStream_t s);
-// hipCUB exclusive prefix sum (temp == nullptr: query temp_bytes)
+// rocPRIM exclusive prefix sum of n ints (temp == nullptr: query temp_bytes)
 hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* out, int n, hipStream_t s);
 
 template <typename KT> void launch_residual(const BatchLaunch& b, bool lin, hipStream_t s);
