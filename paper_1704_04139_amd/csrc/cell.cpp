@@ -76,6 +76,13 @@ int g_sweeps_min() {
   const int v = e ? std::atoi(e) : 2;
   return v < 1 ? 1 : (v > 6 ? 6 : v);
 }
+// sweeps on launched levels >= 2, at most the cell's nu (MBX_MG_NU_COARSE;
+// default: no limit beyond nu)
+int g_sweeps_coarse() {
+  const char* e = std::getenv("MBX_MG_NU_COARSE");
+  const int v = e ? std::atoi(e) : 6;
+  return v < 1 ? 1 : (v > 6 ? 6 : v);
+}
 constexpr int kGather = RED_NSLOT + CTL_NSLOT;
 uint64_t g_next_id = 1;
 
@@ -400,9 +407,11 @@ struct Batch {
     b.maxfuse = maxfuse;
     b.fused_lds = 0;
     b.max_nu = 1;
+    b.max_nu_c = 1;
     for (const mbx_cell* c : cells) {
       b.fused_lds = std::max(b.fused_lds, fused_elems(c->ld, c->ld.lfuse));
       b.max_nu = std::max(b.max_nu, c->h.nu);
+      b.max_nu_c = std::max(b.max_nu_c, std::min(c->h.nu, c->h.nu_c));
     }
     for (int l = 0; l < kMaxLevels; ++l) {
       b.lvl_blk[l] = one ? nullptr : lvl_blk[l];
@@ -595,6 +604,7 @@ uint64_t launch_key(const Batch& B, const BatchLaunch& b, int k0, int k1) {
   mix((uint64_t)b.maxfuse);
   mix((uint64_t)b.fused_lds);
   mix((uint64_t)b.max_nu);
+  mix((uint64_t)b.max_nu_c);
   mix((uint64_t)b.faces_single);
   for (int l = 0; l < kMaxLevels; ++l) {
     mix((uint64_t)(uintptr_t)b.lvl_blk[l] ^ ((uint64_t)b.lvl_nblk[l] << 48));
@@ -1332,6 +1342,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.alpha = g_mg_alpha();
   h.nu = g_sweeps_min();
   h.nu_f = h.nu;
+  h.nu_c = g_sweeps_coarse();
   h.lv[0].nx = nx;
   h.lv[0].ny = ny;
   h.lv[0].nz = nz;

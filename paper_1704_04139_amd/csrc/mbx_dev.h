@@ -130,6 +130,7 @@ struct CellDev {
   double *cinv[2];                   // coarsest-level dense inverses (FP64), (3*ncell)^2 each
   double alpha;                      // coarse-correction scale
   int nu, nu_f;                      // smoothing sweeps (red+black pairs) per side: launched levels / fused levels
+  int nu_c;                          // sweeps on launched levels >= 2 (at most nu)
   // scaled-operator constants
   double Kd;                         // kappa (1-t+) theta RT/(F h)
   double Gk, tth, Dh, tau, Ke, Gcol;

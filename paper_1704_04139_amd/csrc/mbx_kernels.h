@@ -25,6 +25,7 @@ struct BatchLaunch {
   int maxfuse;                           // max first fused level over the batch
   size_t fused_lds;                      // LDS elements (KT) of the fused coarse cycle, max over the batch
   int max_nu;                            // most smoothing sweeps any cell of the batch asks for
+  int max_nu_c;                          // ... on launched levels >= 2
   const int2* lvl_blk[kMaxLevels];       // block tables over each level's cells (index >= 1)
   int lvl_nblk[kMaxLevels];
   const int2* lvl8_blk[kMaxLevels];      // block tables with 8 lanes per level cell (index >= 1)

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 
+#include <algorithm>
+
 #include "mbx_dev.h"
 #include "mbx_kernels.h"
 #include "prof.h"
@@ -707,7 +709,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int
                                                        int color, int mode, int it, int need) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!cd.active || l >= cd.lfuse || it >= cd.nu) return;
+  if (!cd.active || l >= cd.lfuse || it >= (l >= 2 ? min(cd.nu, cd.nu_c) : cd.nu)) return;
   const MGLevel& L = cd.lv[l];
   C3 q;
   if (!color_cell(bb.y * kBlock + threadIdx.x, color, L.nx, L.ny, L.nz, q)) return;
@@ -976,8 +978,8 @@ static void smoothl(const BatchLaunch& b, int l, int op, int color, int mode, in
 template <typename KT>
 static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
   const int top = b.maxfuse;   // levels >= a cell's lfuse run inside k_mg_coarse_cycle
-  const int nu = b.max_nu;
   for (int l = 0; l < top; ++l) {
+    const int nu = l >= 2 ? std::min(b.max_nu, b.max_nu_c) : b.max_nu;
     if (l == 0) prof_begin(PK_SMOOTH0, s);   // the 2 nu level-0 half sweeps run back to back
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
@@ -997,6 +999,7 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
   }
   k_mg_coarse_cycle<KT><<<b.ncell, kBlock, b.fused_lds * sizeof(KT), s>>>(b.cells, b.ncell, op, need);
   for (int l = top - 1; l >= 0; --l) {
+    const int nu = l >= 2 ? std::min(b.max_nu, b.max_nu_c) : b.max_nu;
     if (l == 0) prof_begin(PK_SMOOTH0, s);
     for (int it = 0; it < nu; ++it) {
       if (l == 0) {
