@@ -450,3 +450,67 @@ def simulate(labels, prm: dict, dt: float, steps: int, u0=None, V_cut=None, **kw
         if cutoff_reached(model.voltage(u), V_cut, prm["I_app"]):
             break
     return model, states, infos
+
+
+def lte_estimate(model: Model, u_new, u_old, u_prev, dt, dt_prev) -> float:
+    """Local-error estimate of an implicit Euler step (reading R-5 of the
+    adaptive stepping of Sec. 2.4).  On an implicit Euler trajectory the
+    backward difference (u_old - u_prev)/dt_prev is exactly the time
+    derivative the previous step solved for at u_old, so the linear
+    extrapolation
+        u_pred = u_old + (dt/dt_prev) (u_old - u_prev)
+    is the explicit Euler step from u_old.  The two Euler steps carry local
+    errors of +-(dt^2/2) u'', hence the implicit step's local error is
+        |u_new - u_pred| / 2
+    to leading order, whatever dt_prev.  Only the unknowns with a time
+    derivative enter: the concentrations, relative to c0 / c_max, and the
+    plated amounts, relative to n_c.  The potentials are algebraic (charge
+    conservation holds at every instant, so they jump with the applied
+    current) and carry no truncation error of their own."""
+    N = model.N
+    w = dt / dt_prev
+    c = u_new[:N] - (u_old[:N] + w * (u_old[:N] - u_prev[:N]))
+    n = u_new[2 * N:] - (u_old[2 * N:] + w * (u_old[2 * N:] - u_prev[2 * N:]))
+    e = np.abs(c) / model.c_ref
+    if n.size:
+        e = np.concatenate([e, np.abs(n) / model.p["n_c"]])
+    return float(0.5 * np.max(e))
+
+
+def simulate_adaptive(labels, prm: dict, t_end: float, dt0: float, dt_min: float, dt_max: float, tol: float,
+                      max_steps: int = 10000, **kw):
+    """Adaptive implicit Euler from the equilibrium to t_end (reading R-5).
+
+    Step sizes change by factors of 2 only: a step whose Newton iteration
+    fails, or whose error estimate exceeds tol, is rejected and redone with
+    half the step (failure below dt_min); an accepted step whose estimate is
+    at most tol/4 doubles the next step (at most dt_max); a step that would
+    pass t_end is shortened to end there.  The first step has no estimate.
+    Returns the model, the accepted times, states and step sizes, the
+    estimates of the accepted steps and the number of rejected steps."""
+    model = Model(Geometry(labels), prm)
+    u = model.initial_state()
+    t, dt, dt_prev, u_prev = 0.0, dt0, None, None
+    times, states, dts, ests = [0.0], [u], [], []
+    rejected = 0
+    while t < t_end and len(dts) < max_steps:
+        h = min(dt, t_end - t)
+        try:
+            u_new, _ = newton_step(model, u, h, **kw)
+            est = None if u_prev is None else lte_estimate(model, u_new, u, u_prev, h, dt_prev)
+        except NewtonFailure:
+            u_new, est = None, np.inf
+        if u_new is None or (est is not None and est > tol):
+            rejected += 1
+            dt = h / 2.0
+            if dt < dt_min:
+                raise NewtonFailure(f"adaptive step below dt_min at t = {t}")
+            continue
+        u_prev, u, dt_prev = u, u_new, h
+        t = t + h if t + h < t_end else t_end
+        times.append(t)
+        states.append(u)
+        dts.append(h)
+        ests.append(est)
+        dt = min(2.0 * h, dt_max) if (est is not None and est <= tol / 4.0) else h
+    return model, times, states, dts, ests, rejected

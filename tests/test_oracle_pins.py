@@ -513,3 +513,108 @@ def test_reading_r1_collector_only_cluster_has_no_admissible_step():
     pc.I_app = 3.0 * I.one_c_current(labc, pc)
     mc, states, _ = oracle.simulate(labc, pc.as_dict(), dt, 400, V_cut=4.2)
     assert mc.voltage(states[-1]) >= 4.2 and len(states) - 1 > 3 * failed_at
+
+
+# ---------------------------------------------------------------------------
+# Reading R-5 (adaptive stepping of Sec. 2.4): the local-error estimate of an
+# implicit Euler step and the factor-of-2 step controller.
+# ---------------------------------------------------------------------------
+class _Unknowns:
+    """Scaling data of a state vector [c (N), phi (N), n (F)], as lte_estimate reads it."""
+
+    def __init__(self, c_ref, n_c=1.0):
+        self.c_ref = np.asarray(c_ref, dtype=float)
+        self.N = self.c_ref.size
+        self.p = {"n_c": n_c}
+
+
+@pytest.mark.parametrize("ratio", [1.0, 0.5, 2.0, 4.0])
+def test_lte_estimate_is_the_implicit_euler_local_error(ratio):
+    # u' = -lam u along an implicit Euler trajectory with steps dt_prev, dt:
+    # the exact local error of the last step is u_old (1/(1 + lam dt) - exp(-lam dt))
+    lam, dt, c_ref = 3.0, 1e-3, 2.0
+    dtp = ratio * dt
+    u_prev = 1.0
+    u_old = u_prev / (1.0 + lam * dtp)
+    u_new = u_old / (1.0 + lam * dt)
+    true = abs(u_new - u_old * np.exp(-lam * dt)) / c_ref
+    st = lambda c: np.array([c, 7.0])                     # noqa: E731 (phi arbitrary)
+    est = oracle.lte_estimate(_Unknowns([c_ref]), st(u_new), st(u_old), st(u_prev), dt, dtp)
+    assert est == pytest.approx(true, rel=1e-2)
+
+
+def test_lte_estimate_scaling_and_algebraic_potentials():
+    # states exact on u(t) = a + b t + q t^2: u_new - u_pred = q dt (dt + dt_prev)
+    dt, dtp = 2.0, 0.5
+    t = np.array([-dtp, 0.0, dt])
+    a = np.array([1.0, 5.0, 3.0, -4.0, 0.2, 0.1])             # c c | phi phi | n n
+    b = np.array([0.3, -0.2, 9.0, 1.0, 0.01, -0.02])
+    q = np.array([0.0, 0.0, 50.0, -80.0, 1e-3, 0.0])          # potentials curve hard, they must not count
+    u_prev, u_old, u_new = (a + b * s + q * s * s for s in t)
+    m = _Unknowns([1.0, 4.0], n_c=0.25)
+    expect = 0.5 * 1e-3 * dt * (dt + dtp) / 0.25
+    assert oracle.lte_estimate(m, u_new, u_old, u_prev, dt, dtp) == pytest.approx(expect, rel=1e-12)
+    # a curved concentration of the same size is divided by its own c_ref
+    q2 = q.copy()
+    q2[1] = 4e-2
+    u_prev, u_old, u_new = (a + b * s + q2 * s * s for s in t)
+    assert oracle.lte_estimate(m, u_new, u_old, u_prev, dt, dtp) == pytest.approx(
+        0.5 * 4e-2 * dt * (dt + dtp) / 4.0, rel=1e-12)
+
+
+def _adaptive_cell():
+    lab = tiny_labels(4, 4, 10, 5)
+    p = I.CellParams()
+    p.I_app = 2.0 * I.one_c_current(lab, p)
+    return lab, p
+
+
+def test_adaptive_estimate_tracks_a_fine_integration():
+    # the estimate against the local error measured by redoing each accepted
+    # step with 32 steps of h/32 (Richardson-corrected for their own error)
+    lab, p = _adaptive_cell()
+    model, times, states, dts, ests, rej = oracle.simulate_adaptive(lab, p.as_dict(), 60.0, 2.0, 0.25, 50.0, 1e-3)
+    N = model.N
+    M = 32
+    for k in range(2, len(dts)):
+        v = states[k]
+        for _ in range(M):
+            v, _ = newton_step(model, v, dts[k] / M)
+        d = states[k + 1] - v
+        true = max(np.max(np.abs(d[:N]) / model.c_ref), np.max(np.abs(d[2 * N:]) / p.n_c)) * M / (M - 1)
+        assert 0.8 < ests[k] / true < 2.5, (k, dts[k], ests[k], true)
+
+
+def test_adaptive_controller_rules():
+    lab, p = _adaptive_cell()
+    t_end, dt0, tol = 150.0, 2.0, 1e-3
+    model, times, states, dts, ests, rej = oracle.simulate_adaptive(lab, p.as_dict(), t_end, dt0, 0.25, 50.0, tol)
+    assert times[-1] == t_end and np.all(np.diff(times) > 0)
+    np.testing.assert_allclose(np.diff(times), dts, rtol=0, atol=1e-12)
+    # steps are dt0 times powers of 2 (the last one may be cut to end at t_end)
+    k = np.log2(np.array(dts[:-1]) / dt0)
+    np.testing.assert_array_equal(k, np.round(k))
+    assert ests[0] is None and all(e <= tol for e in ests[1:])
+    for i in range(1, len(dts) - 1):          # doubling only after an estimate <= tol/4
+        if dts[i + 1] > dts[i]:
+            assert dts[i + 1] == 2 * dts[i] and ests[i] is not None and ests[i] <= tol / 4
+    assert max(dts) > 8 * dt0                 # the step grows as the transient decays
+    # the first step is one implicit Euler step of dt0 from the equilibrium
+    u1, _ = newton_step(model, model.initial_state(), dt0)
+    np.testing.assert_array_equal(states[1], u1)
+    # lithium: every accepted step moves I dt / F from the cathode to the anode side
+    inv0, inv1 = model.inventories(states[0]), model.inventories(states[-1])
+    tot = lambda v: v["electrolyte"] + v["anode"] + v["cathode"] + v["plated"]   # noqa: E731
+    assert tot(inv1) == pytest.approx(tot(inv0), rel=1e-9)
+    assert inv1["cathode"] == pytest.approx(inv0["cathode"] - p.I_app * t_end / FARADAY, rel=1e-6)
+
+
+def test_adaptive_controller_limits():
+    lab, p = _adaptive_cell()
+    # no error control: the step doubles after every estimate (the first step
+    # has none), up to dt_max
+    _, _, _, dts, _, rej = oracle.simulate_adaptive(lab, p.as_dict(), 100.0, 2.0, 0.25, 16.0, 1e9)
+    assert rej == 0 and dts[:6] == [2.0, 2.0, 4.0, 8.0, 16.0, 16.0]
+    # an unreachable tolerance with dt_min = dt0 fails at the first estimate
+    with pytest.raises(oracle.NewtonFailure):
+        oracle.simulate_adaptive(lab, p.as_dict(), 100.0, 2.0, 2.0, 16.0, 1e-12)
