@@ -200,6 +200,32 @@ int mbx_cell_mean_solid(const mbx_cell *c, double out[2]);
 int mbx_cell_run(mbx_cell *c, double dt, int max_steps, double *V_out, int *steps_out, int *cutoff_out,
                  int *retried);
 
+/* Adaptive implicit Euler from the cell's current state over [0, t_end]
+ * (time-step control of Sec. 2.4; the error estimate and controller are a
+ * reading of it).  Each step is one mbx_cell_step without its internal retry.
+ * Its local error is estimated from the linear extrapolation of the two
+ * previous accepted states, u_pred = u^n + (dt/dt_prev)(u^n - u^(n-1)), which
+ * on an implicit Euler trajectory is the explicit Euler step from u^n:
+ *   est = max |u^(n+1) - u_pred| / 2
+ * over the concentrations (relative to c0 in the electrolyte, c_max in the
+ * solid) and the plated amounts (relative to n_c); the potentials are
+ * algebraic and do not enter.  The first step has no estimate.  A step whose
+ * Newton iteration fails, or whose est > tol, is rolled back and redone with
+ * half the step; an accepted step with est <= tol/4 doubles the next step (at
+ * most dt_max); a step that would pass t_end is shortened to end there.  The
+ * run stops at t_end, after max_steps accepted steps, or after the first step
+ * whose voltage reaches p->V_cut.
+ *   t_out, V_out : host, max_steps doubles each or null; the time and cell
+ *                  voltage after each accepted step
+ *   steps_out    : accepted steps (required); rejected_out: rejected steps
+ *   cutoff_out   : 1 if the voltage cutoff stopped the run (may be null)
+ * Returns MBX_EINVAL for t_end < 0, dt0 <= 0, dt_min <= 0, dt_max < dt_min,
+ * tol <= 0 or max_steps < 0; MBX_ENEWTON when the step would have to fall
+ * below dt_min (the state then stays at the last accepted step). */
+int mbx_cell_run_adaptive(mbx_cell *c, double t_end, double dt0, double dt_min, double dt_max, double tol,
+                          int max_steps, double *t_out, double *V_out, int *steps_out, int *rejected_out,
+                          int *cutoff_out);
+
 /* Workgroup sizes (threads) the library picked for this cell's single-cell
  * launches of the level-0 multigrid smoother and of J*v: at creation it times
  * 256, 128 and 64 threads on the cell's own arrays and keeps the fastest

@@ -269,6 +269,8 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   L.add((size_t)m * 2 * N * kt);                                       // 43 + 7(n-1): flexible-GMRES basis Z
   L.add(4 * Np);                                                       // 44 + 7(n-1): meta, colour-split
   L.add(kt * Np);                                                      // 45 + 7(n-1): level-0 iterate, colour-split
+  L.add(8 * (size_t)N);                                                // 46 + 7(n-1): c at the step before u^n (adaptive runs)
+  L.add(8 * (size_t)std::max(F_an, 1));                                // 47 + 7(n-1): n at the step before u^n
   return L;
 }
 
@@ -1372,6 +1374,8 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.rbH = h.rbhx * ny * nz;
   h.meta_rb = (const uint32_t*)(b + L.off[44 + 7 * (c->ld.n - 1)]);
   h.x_rb = b + L.off[45 + 7 * (c->ld.n - 1)];
+  h.c_prev = (double*)(b + L.off[46 + 7 * (c->ld.n - 1)]);
+  h.n_prev = (double*)(b + L.off[47 + 7 * (c->ld.n - 1)]);
   h.faces_an = c->faces_an;
   h.faces_ca = c->faces_ca;
   c->lvlh_nblk[0] = (int)((half_cells(c->ld, 0) + kBlock - 1) / kBlock);
@@ -1585,6 +1589,82 @@ int mbx_cell_run(mbx_cell* c, double dt, int max_steps, double* V_out, int* step
       break;
     }
   }
+  return MBX_OK;
+}
+
+// Adaptive implicit Euler (reading R-5 of the time-step control of Sec.
+// 2.4): step sizes change by factors of 2; a step whose Newton iteration
+// fails or whose error estimate exceeds tol is rolled back and redone with
+// half the step; an accepted step whose estimate is at most tol/4 doubles the
+// next one.  The estimate is half the distance of the step from the linear
+// extrapolation of the two previous accepted states, the explicit Euler step
+// on an implicit Euler trajectory (the first step has none).
+int mbx_cell_run_adaptive(mbx_cell* c, double t_end, double dt0, double dt_min, double dt_max, double tol,
+                          int max_steps, double* t_out, double* V_out, int* steps_out, int* rejected_out,
+                          int* cutoff_out) {
+  if (!c || !steps_out) return fail(MBX_EINVAL, "null cell or steps_out");
+  if (!(std::isfinite(t_end) && t_end >= 0.0)) return fail(MBX_EINVAL, "t_end must be finite and >= 0");
+  if (!(std::isfinite(dt0) && dt0 > 0.0 && std::isfinite(dt_min) && dt_min > 0.0 && std::isfinite(dt_max) &&
+        dt_max >= dt_min))
+    return fail(MBX_EINVAL, "need dt0 > 0 and 0 < dt_min <= dt_max");
+  if (!(std::isfinite(tol) && tol > 0.0)) return fail(MBX_EINVAL, "tol must be finite and > 0");
+  if (max_steps < 0) return fail(MBX_EINVAL, "max_steps must be >= 0");
+  *steps_out = 0;
+  if (rejected_out) *rejected_out = 0;
+  if (cutoff_out) *cutoff_out = 0;
+  double t = 0.0, dt = dt0, dt_prev = 0.0;
+  int steps = 0;
+  Batch one = single(c);
+  while (t < t_end && steps < max_steps) {
+    const double h = std::min(dt, t_end - t);
+    const int cap = c->cap_count, capd = c->cap_dropped;
+    int st = 0;
+    mbx_step_info info{};   // iteration counts only: a step without retry leaves V unset
+    // one try without the internal half-step retry: rejection is this loop's
+    if (int e = step_recover({c}, h, &st, &info, kMaxHalvings)) return e;
+    double est = -1.0;   // < 0: no estimate (first step)
+    if (st == MBX_OK && steps > 0) {
+      if (int e = one.upload()) return e;
+      launch_lte(one.bl(), h / dt_prev, c->s);
+      if (int e = one.gather()) return e;
+      est = 0.5 * one.red(0, RED_LTE);   // implicit minus explicit Euler: twice the local error
+      if (!std::isfinite(est)) est = INFINITY;
+    }
+    if (st != MBX_OK || est > tol) {
+      if (st == MBX_OK) {
+        // converged but too inaccurate: back to u^n, snapshot column dropped
+        c->h.active = 1;
+        if (int e = one.upload()) return e;
+        launch_copy_state(one.bl(), 3, c->s);
+        launch_outputs(one.bl(), c->s);
+        if (int e = one.gather()) return e;
+        c->cap_count = cap;
+        c->cap_dropped = capd;
+      }
+      if (rejected_out) ++*rejected_out;
+      dt = h / 2.0;
+      if (dt < dt_min) return fail(MBX_ENEWTON, "adaptive step below dt_min at t = %g; state left at t", t);
+      continue;
+    }
+    // accepted: u^n becomes the history of the next estimate
+    c->h.active = 1;
+    if (int e = one.upload()) return e;
+    launch_copy_state(one.bl(), 5, c->s);
+    t = t + h < t_end ? t + h : t_end;
+    double V = 0.0;
+    if (int e = mbx_cell_voltage(c, &V)) return e;
+    if (t_out) t_out[steps] = t;
+    if (V_out) V_out[steps] = V;
+    ++steps;
+    *steps_out = steps;
+    dt_prev = h;
+    dt = (est >= 0.0 && est <= tol / 4.0) ? std::min(2.0 * h, dt_max) : h;
+    if (cutoff_reached(c->p, V)) {
+      if (cutoff_out) *cutoff_out = 1;
+      break;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(c->s));
   return MBX_OK;
 }
 

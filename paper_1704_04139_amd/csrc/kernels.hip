@@ -915,8 +915,37 @@ __global__ void __launch_bounds__(kBlock) k_trial(CellDev* cells, const int2* __
   reduce_block<2>(cd, bb.y, vals, 0x2u);
 }
 
+// Local-error indicator of an adaptive step (differential unknowns only):
+// max |u - (u_old + w (u_old - u_prev))| over the concentrations (relative to
+// c0 / c_max) and the plated amounts (relative to n_c), w = dt / dt_prev.
+__global__ void __launch_bounds__(kBlock) k_lte(CellDev* cells, const int2* __restrict__ blk, double w) {
+  const int2 bb = block_of(blk);
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  double e = 0.0;
+  if (i < cd.N) {
+    const uint32_t mi = cd.meta[i];
+    const int L = lab_of(mi);
+    const double co = cd.c_old[i];
+    e = fabs(cd.c[i] - (co + w * (co - cd.c_prev[i]))) / cref_of(cd, L);
+    if (L == ANODE) {
+      const uint32_t cnt = __popc(mask_of(mi));
+      for (uint32_t r = 0; r < cnt; ++r) {
+        const uint32_t f = base_of(mi) + r;
+        const double no = cd.n_old[f];
+        e = fmax(e, fabs(cd.n[f] - (no + w * (no - cd.n_prev[f]))) / cd.n_c);
+      }
+    }
+  }
+  const double vals[1] = {e};
+  reduce_block<1>(cd, bb.y, vals, 0x1u);
+}
+
 // State copies: 0 try -> iterate, 1 iterate -> try, 2 iterate -> old (step
-// start), 3 old -> iterate and try (rollback), 4 old -> try (step start).
+// start), 3 old -> iterate and try (rollback), 4 old -> try (step start),
+// 5 old -> previous (an adaptive run's history; concentrations and plated
+// amounts).
 __global__ void __launch_bounds__(kBlock) k_copy_state(CellDev* cells, const int2* __restrict__ blk, int mode) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
@@ -938,6 +967,11 @@ __global__ void __launch_bounds__(kBlock) k_copy_state(CellDev* cells, const int
       sc = cd.c_old; sp = cd.phi_old; sn = cd.n_old; dc = cd.c; dp = cd.phi; dn = cd.n;
       dc2 = cd.c_try; dp2 = cd.phi_try; dn2 = cd.n_try;
       break;
+    case 5: {
+      cd.c_prev[i] = cd.c_old[i];
+      for (uint32_t r = 0; r < cnt; ++r) cd.n_prev[f0 + r] = cd.n_old[f0 + r];
+      return;
+    }
     default: sc = cd.c_old; sp = cd.phi_old; sn = cd.n_old; dc = cd.c_try; dp = cd.phi_try; dn = cd.n_try; break;
   }
   dc[i] = sc[i];
@@ -1166,6 +1200,10 @@ void launch_trial(const BatchLaunch& b, hipStream_t s) {
 }
 void launch_copy_state(const BatchLaunch& b, int mode, hipStream_t s) {
   k_copy_state<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, mode);
+}
+void launch_lte(const BatchLaunch& b, double w, hipStream_t s) {
+  k_lte<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, w);
+  k_finalize_red<<<b.ncell, kBlock, 0, s>>>(b.cells, b.ncell, RED_LTE, 1, 0x1u, -3);
 }
 void launch_outputs(const BatchLaunch& b, hipStream_t s) {
   k_outputs<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);

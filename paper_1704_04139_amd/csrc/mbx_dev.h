@@ -70,7 +70,8 @@ enum {
   RED_VSUM = 11,   // sum over cathode top voxels of phi (must follow the inventories)
   RED_TOL = 12,    // GMRES absolute tolerance of the current solve
   RED_BETA0 = 13,  // norm of the first GMRES residual of the current solve
-  RED_NSLOT = 14
+  RED_LTE = 14,    // max over the differential unknowns of |u - u_pred| (scaled), adaptive stepping
+  RED_NSLOT = 15
 };
 // Slots of the per-cell device-written integer array `ictl`.
 enum { CTL_DONE = 0, CTL_K = 1, CTL_ITERS = 2, CTL_NSLOT = 4 };
@@ -87,6 +88,7 @@ struct CellDev {
   double *c, *phi, *n;               // Newton iterate
   double *c_try, *phi_try, *n_try;   // trial state (residual kernels read these)
   double *c_old, *phi_old, *n_old;   // u^n
+  double *c_prev, *n_prev;           // u^(n-1) of an adaptive run (concentrations, plated amounts)
   double *Rc, *Rp, *Rn;              // residual rows at the trial state
   double *dc, *dp, *dn;              // Newton direction (raw units)
   double *rn_jnn, *sq;               // per anode face: R^n/J_nn, condensation term

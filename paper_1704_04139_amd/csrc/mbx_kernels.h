@@ -74,6 +74,8 @@ template <typename KT> void launch_direction(const BatchLaunch& b, hipStream_t s
 void launch_trial(const BatchLaunch& b, hipStream_t s);
 void launch_copy_state(const BatchLaunch& b, int mode, hipStream_t s);
 void launch_outputs(const BatchLaunch& b, hipStream_t s);
+// adaptive stepping: scaled max |u - u_pred| of the differential unknowns into red[RED_LTE]
+void launch_lte(const BatchLaunch& b, double w, hipStream_t s);
 
 // multigrid preconditioner (mg.hip)
 // one level-0 red-black half sweep (operator op, colour 0, no GMRES gate) on

@@ -92,6 +92,8 @@ SIGNATURES = {
     "mbx_cell_mean_solid": (_i, [_vp, _dp]),
     "mbx_cell_launch_shape": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "mbx_cell_run": (_i, [_vp, _d, _i, _dp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "mbx_cell_run_adaptive": (_i, [_vp, _d, _d, _d, _d, _d, _i, _dp, _dp, ctypes.POINTER(_i), ctypes.POINTER(_i),
+                                   ctypes.POINTER(_i)]),
     "mbx_cell_residual": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp, _vp]),
     "mbx_cell_jvp": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]),
     "mbx_cell_precond": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _d, _vp, _vp]),
@@ -286,6 +288,20 @@ class Cell:
         _check(load().mbx_cell_run(self._h, float(dt), int(max_steps), V.ctypes.data_as(_dp), ctypes.byref(n),
                                    ctypes.byref(cut), ctypes.byref(ret)))
         return V[:n.value].copy(), bool(cut.value), ret.value
+
+    def run_adaptive(self, t_end: float, dt0: float, dt_min: float, dt_max: float, tol: float,
+                     max_steps: int = 10000):
+        """Adaptive implicit Euler to t_end with factor-of-2 step control:
+        returns (times, voltages after each accepted step, rejected steps,
+        cutoff fired)."""
+        k = max(int(max_steps), 1)
+        t, V = np.empty(k), np.empty(k)
+        n, rej, cut = _i(), _i(), _i()
+        _check(load().mbx_cell_run_adaptive(self._h, float(t_end), float(dt0), float(dt_min), float(dt_max),
+                                            float(tol), int(max_steps), t.ctypes.data_as(_dp),
+                                            V.ctypes.data_as(_dp), ctypes.byref(n), ctypes.byref(rej),
+                                            ctypes.byref(cut)))
+        return t[:n.value].copy(), V[:n.value].copy(), rej.value, bool(cut.value)
 
     def residual(self, c, p, n, c_old, n_old, dt):
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (c, p, n, c_old, n_old)]

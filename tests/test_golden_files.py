@@ -1,0 +1,64 @@
+"""CPU checks of the stored oracle trajectories in tests/golden/ (written by
+make_oracle_refs.py from the oracle alone): they belong to the inputs the GPU
+tests rebuild, they satisfy the oracle's conservation law, and the cutoff run
+is well posed."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.cellmodel import FARADAY
+from paper_1704_04139_amd import inputs as I
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load(name):
+    path = os.path.join(GOLD, name)
+    if not os.path.exists(path):
+        pytest.fail(f"{name} missing: run tests/golden/make_oracle_refs.py")
+    return np.load(path)
+
+
+def conserved(inv, I_app, dt, rel):
+    """Li inventories step to step (Sec. 2.4 conservative scheme): electrolyte
+    constant, anode + plated gain I dt/F, cathode loses it."""
+    q = I_app * dt / FARADAY
+    d = np.diff(inv, axis=0)
+    assert np.all(np.abs(d[:, 0]) <= rel * q)
+    np.testing.assert_allclose(d[:, 1] + d[:, 3], q, rtol=rel)
+    np.testing.assert_allclose(d[:, 2], -q, rtol=rel)
+
+
+def test_c2cut_golden_is_well_posed():
+    """Voltages of the crossing step and its predecessor clear the cutoff by far
+    more than the 1e-6 V voltage bar, so any path that meets the bar stops at
+    the same step."""
+    r = load("c2cut_oracle.npz")
+    w = I.config2(seed=2, scale=8)
+    assert np.array_equal(r["labels"], w.labels) and r["T"] == 268.0 and r["dt"] == 2.0
+    k = int(r["cutoff_step"])
+    V, Vc = r["V"], float(r["V_cut"])
+    assert Vc == 4.2 and V[k] >= Vc > V[k - 1] and np.all(V[1:k] < Vc)
+    assert min(V[k] - Vc, Vc - V[k - 1]) > 1e-5
+    assert int(r["state_steps"][-1]) == k
+    conserved(r["inv"], float(r["I_app"]), float(r["dt"]), 1e-7)
+
+
+def test_c0adapt_golden():
+    """The adaptive run's record: times end at t_end, steps are dt0 times powers
+    of 2 (the last may be cut short), estimates within tol, Li conserved over
+    the non-uniform grid."""
+    r = load("c0adapt_oracle.npz")
+    w = I.config0()
+    assert np.array_equal(r["labels"], w.labels) and r["I_app"] == w.params.I_app
+    t, dts = r["times"], r["dts"]
+    assert t[0] == 0.0 and t[-1] == r["t_end"] and np.allclose(np.diff(t), dts, rtol=0, atol=1e-12)
+    k = np.log2(dts[:-1] / float(r["dt0"]))
+    assert np.array_equal(k, np.round(k)) and dts.min() >= r["dt_min"] and dts.max() <= r["dt_max"]
+    assert np.isnan(r["ests"][0]) and np.all(r["ests"][1:] <= r["tol"])
+    assert r["rejected"] > 0 and dts.max() >= 16 * dts.min()   # the controller both cut and grew the step
+    q = float(r["I_app"]) * dts / FARADAY
+    d = np.diff(r["inv"], axis=0)
+    np.testing.assert_allclose(d[:, 2], -q, rtol=1e-7)
+    np.testing.assert_allclose(d[:, 1] + d[:, 3], q, rtol=1e-7)

@@ -1,0 +1,189 @@
+"""GPU parity against stored oracle trajectories (tests/golden/, written by
+make_oracle_refs.py from the oracle alone), through the C ABI:
+
+  * a 16 x 16 x 40 copy of the 128 x 128 x 320 fast charge (3C at 268 K,
+    2 s steps) run to its 4.2 V cutoff: per-step voltage, the index of the
+    step at which the cutoff fires, alone (step loop and mbx_cell_run) and
+    served;
+  * the 12 x 12 x 40 cell under adaptive implicit Euler: the same accepted
+    time grid and rejection count as the oracle's controller.
+
+Bars (the workload definition): |dV| <= 1e-6 V; relative L2 error per field
+(c_e, c_s, phi, n; Sec. 3.3's relative error in space) <= 1e-8 in FP64 and
+<= 1e-6 in mixed precision.  Every step must be taken at the oracle's dt:
+no step may have been retried as two half steps.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.cellmodel import Geometry, Model
+from paper_1704_04139_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+BARS = [("fp64", 1e-8), ("mixed", 1e-6)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mbx(lib):
+    from paper_1704_04139_amd import mbx as m
+    return m
+
+
+def rel_l2(a, b, floor=0.0):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), floor)
+
+
+def field_errors(lab, n_c, c, phi, n, rc, rphi, rn):
+    pore = lab.ravel() == 0
+    e = {"c_e": rel_l2(c[pore], rc[pore]), "c_s": rel_l2(c[~pore], rc[~pore]), "phi": rel_l2(phi, rphi)}
+    if rn.size:
+        e["n"] = rel_l2(n, rn, floor=n_c * np.sqrt(rn.size))
+    return e
+
+
+def check_state(tag, lab, n_c, got, ref, k, bar, worst):
+    """got = (c, phi, n); ref = npz-like with c/phi/n stacked over ref['state_steps'] (row k)."""
+    e = field_errors(lab, n_c, *got, ref["c"][k], ref["phi"][k], ref["n"][k])
+    for f, v in e.items():
+        worst[f] = max(worst.get(f, 0.0), v)
+        assert v <= bar, (tag, k, f, v)
+
+
+# ------------------------------------------------ fast charge to the cutoff
+def c2cut_workload(ref):
+    w = I.config2(seed=2, scale=8)
+    assert np.array_equal(ref["labels"], w.labels)
+    return w, float(ref["V_cut"])
+
+
+@pytest.mark.parametrize("prec,bar", BARS)
+def test_c2cut_alone_matches_oracle(mbx, prec, bar):
+    ref = np.load(os.path.join(GOLD, "c2cut_oracle.npz"))
+    w, V_cut = c2cut_workload(ref)
+    kcut = int(ref["cutoff_step"])
+    keep = {int(s): j for j, s in enumerate(ref["state_steps"])}
+    say("3C/268K copy to the cutoff", w.labels.shape, prec, "oracle cutoff after step", kcut)
+    # step by step: voltage at every step, state where stored
+    cell = mbx.Cell(w.labels, w.params, precision=prec, V_cut=V_cut)
+    worst, Vg = {}, []
+    for s in range(1, 4 * kcut):
+        info = cell.step(w.dt)
+        assert info["substeps"] == 1, s
+        Vg.append(info["V"])
+        if s <= kcut:
+            assert abs(info["V"] - ref["V"][s]) <= 1e-6, (s, info["V"], ref["V"][s])
+        if s in keep:
+            check_state("c2cut", w.labels, w.params.n_c, cell.get_state(), ref, keep[s], bar, worst)
+            np.testing.assert_allclose(cell.mean_solid(), ref["s_ac"][s], rtol=bar)
+        if info["V"] >= V_cut:
+            break
+    assert s == kcut
+    final = cell.get_state()
+    cell.close()
+    # the library's step loop stops at the same step and reproduces the trajectory
+    cell = mbx.Cell(w.labels, w.params, precision=prec, V_cut=V_cut)
+    V, cut, retried = cell.run(w.dt, 500)
+    assert cut and retried == 0 and len(V) == kcut
+    np.testing.assert_array_equal(V, Vg)
+    for a, b in zip(cell.get_state(), final):
+        np.testing.assert_array_equal(a, b)
+    # a run with a step budget below the crossing stops on the budget
+    cell2 = mbx.Cell(w.labels, w.params, precision=prec, V_cut=V_cut)
+    V2, cut2, _ = cell2.run(w.dt, kcut - 1)
+    assert not cut2 and len(V2) == kcut - 1
+    cell.close()
+    cell2.close()
+    say("worst", prec, worst)
+
+
+@pytest.mark.parametrize("prec,bar", BARS)
+def test_c2cut_served_stops_at_the_cutoff(mbx, prec, bar):
+    ref = np.load(os.path.join(GOLD, "c2cut_oracle.npz"))
+    w, V_cut = c2cut_workload(ref)
+    kcut = int(ref["cutoff_step"])
+    srv = mbx.Server(budget_bytes=8 << 30, precision=prec, dt=w.dt, keep_state=True)
+    p = mbx.make_params(w.params, prec, V_cut=V_cut)
+    rid = srv.submit(w.labels, p, 500)
+    srv.drain(600.0)
+    info = srv.poll(rid)
+    c, phi, n = srv.result(rid)
+    srv.close()
+    say("served to the cutoff", prec, {k: info[k] for k in ("status", "steps_done", "cutoff", "retried", "V")})
+    assert info["status"] == mbx.MBX_REQ_DONE and info["cutoff"] == 1 and info["retried"] == 0
+    assert info["steps_done"] == kcut
+    assert abs(info["V"] - ref["V"][kcut]) <= 1e-6
+    check_state("c2cut served", w.labels, w.params.n_c, (c, phi, n), ref, len(ref["state_steps"]) - 1, bar, {})
+    np.testing.assert_allclose(info["s_ac"], ref["s_ac"][kcut], rtol=bar)
+
+
+# ------------------------------------------------ adaptive implicit Euler (reading R-5)
+@pytest.mark.parametrize("prec,bar", BARS)
+def test_adaptive_run_matches_oracle(mbx, prec, bar):
+    """Same accepted time grid and rejection count as the oracle's controller,
+    |dV| <= 1e-6 V after every accepted step, final fields within the bar;
+    a rejected step leaves no snapshot column behind."""
+    import torch
+    ref = np.load(os.path.join(GOLD, "c0adapt_oracle.npz"))
+    w = I.config0()
+    assert np.array_equal(ref["labels"], w.labels)
+    # every accept / double decision of the oracle is clear of its threshold
+    assert float(ref["margin"]) > 1e-4
+    say("adaptive 12x12x40", prec)
+    cell = mbx.Cell(w.labels, w.params, precision=prec)
+    N = cell.counts.n_vox
+    cap = 16 * len(ref["times"])
+    snaps = torch.zeros((cap, N), dtype=torch.float64, device="cuda")
+    cell.capture(snaps.data_ptr(), 0, N, cap)
+    t, V, rej, cut = cell.run_adaptive(float(ref["t_end"]), float(ref["dt0"]), float(ref["dt_min"]),
+                                       float(ref["dt_max"]), float(ref["tol"]))
+    np.testing.assert_array_equal(t, ref["times"][1:])
+    assert rej == int(ref["rejected"]) and not cut
+    np.testing.assert_allclose(V, ref["V"][1:], rtol=0, atol=1e-6)
+    got = cell.get_state()
+    e = field_errors(w.labels, w.params.n_c, *got, ref["c"], ref["phi"], ref["n"])
+    for f, v in e.items():
+        assert v <= bar, (prec, f, v)
+    # snapshots (one per Newton update): the same columns as the accepted
+    # steps replayed one by one, so rejected steps left none behind
+    count, dropped = cell.captured()
+    assert dropped == 0 and count > len(t)
+    replay = mbx.Cell(w.labels, w.params, precision=prec)
+    snaps2 = torch.zeros((cap, N), dtype=torch.float64, device="cuda")
+    replay.capture(snaps2.data_ptr(), 0, N, cap)
+    for h in ref["dts"]:
+        assert replay.step(float(h))["substeps"] == 1
+    assert replay.captured() == (count, 0)
+    torch.cuda.synchronize()
+    torch.testing.assert_close(snaps[:count], snaps2[:count], rtol=1e-12, atol=0)
+    np.testing.assert_array_equal(snaps[count - 1].cpu().numpy(), got[0])
+    say("adaptive", prec, {k: f"{v:.2e}" for k, v in e.items()})
+
+
+def test_adaptive_run_below_dt_min_keeps_the_last_accepted_state(mbx):
+    """An unreachable tolerance with dt_min = dt0: the first step is accepted
+    (it has no estimate), the second is rejected and may not halve, and the
+    run fails with the state at the first step."""
+    w = I.config0()
+    cell = mbx.Cell(w.labels, w.params, precision="fp64")
+    with pytest.raises(mbx.MbxError) as ei:
+        cell.run_adaptive(100.0, 5.0, 5.0, 20.0, 1e-12)
+    assert ei.value.code == mbx.MBX_ENEWTON
+    one = mbx.Cell(w.labels, w.params, precision="fp64")
+    one.step(5.0)
+    for a, b in zip(cell.get_state(), one.get_state()):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=0)
+    V = cell.voltage()
+    assert V == pytest.approx(one.voltage(), abs=1e-12)
+    with pytest.raises(mbx.MbxError):
+        cell.run_adaptive(100.0, 5.0, 10.0, 5.0, 1e-3)       # dt_max < dt_min
+    t, V, rej, cut = cell.run_adaptive(0.0, 5.0, 1.0, 20.0, 1e-3)
+    assert t.size == 0 and rej == 0 and not cut
