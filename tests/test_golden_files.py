@@ -30,6 +30,14 @@ def conserved(inv, I_app, dt, rel):
     np.testing.assert_allclose(d[:, 2], -q, rtol=rel)
 
 
+def test_c1s2_golden():
+    r = load("c1s2_oracle.npz")
+    w = I.config1(seed=1, scale=2)
+    assert np.array_equal(r["labels"], w.labels) and r["I_app"] == w.params.I_app
+    assert list(r["state_steps"]) == [1, 2, 3] and r["c"].shape == (3, w.labels.size)
+    conserved(r["inv"], float(r["I_app"]), float(r["dt"]), 1e-7)
+
+
 def test_c2cut_golden_is_well_posed():
     """Voltages of the crossing step and its predecessor clear the cutoff by far
     more than the 1e-6 V voltage bar, so any path that meets the bar stops at
@@ -43,6 +51,25 @@ def test_c2cut_golden_is_well_posed():
     assert min(V[k] - Vc, Vc - V[k - 1]) > 1e-5
     assert int(r["state_steps"][-1]) == k
     conserved(r["inv"], float(r["I_app"]), float(r["dt"]), 1e-7)
+
+
+def test_queries_golden():
+    r = load("queries_oracle.npz")
+    n = int(r["n_queries"])
+    Ts, rates, pls = [], [], []
+    for k in range(n):
+        fam, seed = str(r["families"][k]), int(r["seeds"][k])
+        w = I.sampled_query(seed, list(range(32, 97, 8)) if fam == "batched" else list(range(48, 129, 8)), scale=4)
+        assert np.array_equal(r[f"q{k}_labels"], w.labels)
+        assert r[f"q{k}_I_app"] == w.params.I_app and r[f"q{k}_T"] == w.params.T
+        conserved(r[f"q{k}_inv"], float(r[f"q{k}_I_app"]), float(r[f"q{k}_dt"]), 1e-7)
+        Ts.append(float(r[f"q{k}_T"]))
+        rates.append(float(r[f"q{k}_crate"]))
+        pls.append(float(r[f"q{k}_i00_pl"]) / I.CellParams().i00_pl)
+    # the sample spans the sampled ranges: temperature, C-rate, plating rate constant
+    assert min(Ts) < 275 and max(Ts) > 300
+    assert min(rates) < 1.2 and max(rates) > 3.0
+    assert min(pls) < 0.05 and max(pls) > 10
 
 
 def test_c0adapt_golden():

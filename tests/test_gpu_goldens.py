@@ -1,10 +1,15 @@
 """GPU parity against stored oracle trajectories (tests/golden/, written by
 make_oracle_refs.py from the oracle alone), through the C ABI:
 
+  * a 32 x 32 x 80 copy of the 64 x 64 x 160 benchmark cell, stepped alone;
   * a 16 x 16 x 40 copy of the 128 x 128 x 320 fast charge (3C at 268 K,
     2 s steps) run to its 4.2 V cutoff: per-step voltage, the index of the
     step at which the cutoff fires, alone (step loop and mbx_cell_run) and
     served;
+  * sampled parameter queries of the batched and served workloads (each with
+    its own grid, C-rate, temperature and plating rate constant), stepped
+    together through mbx_batch_step and through the continuous-batching
+    server;
   * the 12 x 12 x 40 cell under adaptive implicit Euler: the same accepted
     time grid and rejection count as the oracle's controller.
 
@@ -56,6 +61,30 @@ def check_state(tag, lab, n_c, got, ref, k, bar, worst):
     for f, v in e.items():
         worst[f] = max(worst.get(f, 0.0), v)
         assert v <= bar, (tag, k, f, v)
+
+
+# ------------------------------------------------ 32 x 32 x 80 copy, alone
+@pytest.mark.parametrize("prec,bar", BARS)
+def test_c1_copy_32x32x80_matches_oracle(mbx, prec, bar):
+    ref = np.load(os.path.join(GOLD, "c1s2_oracle.npz"))
+    w = I.config1(seed=1, scale=2)
+    assert np.array_equal(ref["labels"], w.labels)
+    say("32x32x80 copy", prec)
+    cell = mbx.Cell(w.labels, w.params, precision=prec)
+    worst = {}
+    steps = ref["state_steps"]
+    for k, s in enumerate(steps):
+        info = cell.step(w.dt)
+        assert info["substeps"] == 1
+        assert abs(info["V"] - ref["V"][s]) <= 1e-6, (s, info["V"], ref["V"][s])
+        check_state("c1s2", w.labels, w.params.n_c, cell.get_state(), ref, k, bar, worst)
+        sac = cell.mean_solid()
+        np.testing.assert_allclose(sac, ref["s_ac"][s], rtol=bar)
+        inv = cell.inventory()
+        np.testing.assert_allclose([inv[x] for x in ("electrolyte", "anode", "cathode", "plated")], ref["inv"][s],
+                                   rtol=bar)
+    say("worst", prec, worst)
+    cell.close()
 
 
 # ------------------------------------------------ fast charge to the cutoff
@@ -123,6 +152,61 @@ def test_c2cut_served_stops_at_the_cutoff(mbx, prec, bar):
     assert abs(info["V"] - ref["V"][kcut]) <= 1e-6
     check_state("c2cut served", w.labels, w.params.n_c, (c, phi, n), ref, len(ref["state_steps"]) - 1, bar, {})
     np.testing.assert_allclose(info["s_ac"], ref["s_ac"][kcut], rtol=bar)
+
+
+# ------------------------------------------------ sampled queries
+def queries():
+    ref = np.load(os.path.join(GOLD, "queries_oracle.npz"))
+    out = []
+    for k in range(int(ref["n_queries"])):
+        fam, seed = str(ref["families"][k]), int(ref["seeds"][k])
+        w = I.sampled_query(seed, list(range(32, 97, 8)) if fam == "batched" else list(range(48, 129, 8)), scale=4)
+        r = {key[len(f"q{k}_"):]: ref[key] for key in ref.files if key.startswith(f"q{k}_")}
+        assert np.array_equal(r["labels"], w.labels) and r["I_app"] == w.params.I_app and r["T"] == w.params.T
+        out.append((w, r))
+    return out
+
+
+@pytest.mark.parametrize("prec,bar", BARS)
+def test_sampled_queries_batched_match_oracle(mbx, prec, bar):
+    qs = queries()
+    say("batched queries", prec, [(w.shape, round(float(r["crate"]), 2), round(float(r["T"]), 1),
+                                    float(r["i00_pl"])) for w, r in qs])
+    cells = [mbx.Cell(w.labels, w.params, precision=prec) for w, _ in qs]
+    steps = len(qs[0][1]["V"]) - 1
+    worst = {}
+    for s in range(1, steps + 1):
+        st, infos = mbx.batch_step(cells, qs[0][0].dt)
+        assert st == [0] * len(cells), (s, st)
+        for (w, r), cell, info in zip(qs, cells, infos):
+            assert info["substeps"] == 1, (s, w.name)
+            assert abs(info["V"] - r["V"][s]) <= 1e-6, (s, w.name, info["V"], r["V"][s])
+            j = list(r["state_steps"]).index(s) if s in r["state_steps"] else None
+            if j is not None:
+                check_state(w.name, w.labels, w.params.n_c, cell.get_state(), r, j, bar, worst)
+                np.testing.assert_allclose(cell.mean_solid(), r["s_ac"][s], rtol=bar)
+    say("worst", prec, worst)
+    for c in cells:
+        c.close()
+
+
+@pytest.mark.parametrize("prec,bar", BARS)
+def test_sampled_queries_served_match_oracle(mbx, prec, bar):
+    qs = queries()
+    steps = len(qs[0][1]["V"]) - 1
+    srv = mbx.Server(budget_bytes=16 << 30, precision=prec, dt=qs[0][0].dt, keep_state=True)
+    ids = [srv.submit(w.labels, w.params, steps) for w, _ in qs]
+    srv.drain(600.0)
+    worst = {}
+    for rid, (w, r) in zip(ids, qs):
+        info = srv.poll(rid)
+        assert info["status"] == mbx.MBX_REQ_DONE and info["steps_done"] == steps, (w.name, info)
+        assert info["retried"] == 0 and info["cutoff"] == 0
+        assert abs(info["V"] - r["V"][steps]) <= 1e-6, (w.name, info["V"], r["V"][steps])
+        check_state(w.name, w.labels, w.params.n_c, srv.result(rid), r, len(r["state_steps"]) - 1, bar, worst)
+        np.testing.assert_allclose(info["s_ac"], r["s_ac"][steps], rtol=bar)
+    srv.close()
+    say("worst", prec, worst)
 
 
 # ------------------------------------------------ adaptive implicit Euler (reading R-5)
