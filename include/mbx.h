@@ -228,10 +228,11 @@ int mbx_cell_run_adaptive(mbx_cell *c, double t_end, double dt0, double dt_min, 
 
 /* Workgroup sizes (threads) the library picked for this cell's single-cell
  * launches of the level-0 multigrid smoother and of J*v: at creation it times
- * 256, 128 and 64 threads on the cell's own arrays and keeps the fastest
- * (a smaller size must be 3% faster), once per grid size and precision per
- * process (environment MBX_TUNE_FILE: read and append the choices to that
- * file; MBX_TUNE=0: always 256; MBX_TUNE=64/128/256: that size).  Results do not depend on the choice.
+ * 256, 512, 1024, 128 and 64 threads on the cell's own arrays and keeps the
+ * fastest (another size must be 3% faster than 256), once per grid size and
+ * precision per process (environment MBX_TUNE_FILE: read and append the
+ * choices to that file; MBX_TUNE=0: always 256; MBX_TUNE=64/128/256/512/1024:
+ * that size).  Results do not depend on the choice.
  * Batched launches use 256.  Either pointer may be null. */
 int mbx_cell_launch_shape(const mbx_cell *c, int *smooth0_threads, int *matvec_threads);
 

@@ -1068,15 +1068,15 @@ int step_recover(std::vector<mbx_cell*> cells, double dt, int* status, mbx_step_
 // Workgroup size of the single-cell launches of the level-0 smoother and of
 // J*v, picked per grid size and precision by timing 256, 128 and 64 threads
 // on the new cell's own arrays (one warm-up and three timed launches each;
-// a smaller size must be 3% faster to be taken).  The kernels compute the
+// another size must be 3% faster to be taken).  The kernels compute the
 // same values with any size, so results do not depend on the choice.  Kept
 // per process; with MBX_TUNE_FILE the choices are read from and appended to
-// that file.  MBX_TUNE=0 keeps 256; MBX_TUNE=64, 128 or 256 fixes that size.
+// that file.  MBX_TUNE=0 keeps 256; MBX_TUNE=64, 128, 256, 512 or 1024 fixes that size.
 std::mutex g_tune_mu;
 std::map<std::array<int, 4>, std::array<int, 2>> g_tune;
 bool g_tune_loaded = false;
 
-bool tune_valid(int bs) { return bs == 64 || bs == 128 || bs == kBlock; }
+bool tune_valid(int bs) { return bs == 64 || bs == 128 || bs == kBlock || bs == 512 || bs == 1024; }
 
 template <typename KT>
 int time_shapes(mbx_cell* c, bool smooth, int& best) {
@@ -1086,7 +1086,7 @@ int time_shapes(mbx_cell* c, bool smooth, int& best) {
   double best_ms = 1e30;
   best = kBlock;
   int rc = MBX_OK;
-  for (int bs : {kBlock, 128, 64}) {
+  for (int bs : {kBlock, 512, 1024, 128, 64}) {
     Batch b = single(c);
     BatchLaunch bl = b.bl();
     (smooth ? bl.bs_smooth0 : bl.bs_matvec) = bs;
@@ -1349,6 +1349,12 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.lv[0].ny = ny;
   h.lv[0].nz = nz;
   h.lv[0].ncell = N;
+  for (int l = 0; l < c->ld.n; ++l) {
+    MGLevel& lv = h.lv[l];
+    const int lnx = l == 0 ? nx : c->ld.nx[l], lny = l == 0 ? ny : c->ld.ny[l];
+    lv.inv_hx = 1.0 / ((lnx + 1) / 2);
+    lv.inv_ny = 1.0 / lny;
+  }
   for (int l = 1; l < c->ld.n; ++l) {
     const int o = 41 + 7 * (l - 1);
     MGLevel& lv = h.lv[l];
@@ -1372,6 +1378,9 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.Zb = b + L.off[43 + 7 * (c->ld.n - 1)];
   h.rbhx = (nx + 1) / 2;
   h.rbH = h.rbhx * ny * nz;
+  h.inv_nx = 1.0 / nx;
+  h.inv_ny = 1.0 / ny;
+  h.inv_rbhx = 1.0 / h.rbhx;
   h.meta_rb = (const uint32_t*)(b + L.off[44 + 7 * (c->ld.n - 1)]);
   h.x_rb = b + L.off[45 + 7 * (c->ld.n - 1)];
   h.c_prev = (double*)(b + L.off[46 + 7 * (c->ld.n - 1)]);

@@ -1128,6 +1128,10 @@ void launch_matvec(const BatchLaunch& b, int src, int dst, int need, int keep, h
     k_matvec<KT, 64><<<(b.n_single + 63) / 64, 64, 0, s>>>(b.cells, nullptr, src, dst, need, keep);
   else if (bs == 128)
     k_matvec<KT, 128><<<(b.n_single + 127) / 128, 128, 0, s>>>(b.cells, nullptr, src, dst, need, keep);
+  else if (bs == 512)
+    k_matvec<KT, 512><<<(b.n_single + 511) / 512, 512, 0, s>>>(b.cells, nullptr, src, dst, need, keep);
+  else if (bs == 1024)
+    k_matvec<KT, 1024><<<(b.n_single + 1023) / 1024, 1024, 0, s>>>(b.cells, nullptr, src, dst, need, keep);
   else
     k_matvec<KT, kBlock><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, src, dst, need, keep);
   if (prof_on(PK_MATVEC)) prof_end(PK_MATVEC, s, b.bytes_matvec);

@@ -37,6 +37,7 @@ constexpr double kToBoundary = 0.1;   // a Newton update leaves at least this fr
 constexpr int kOpStride = 33;   // per coarse cell: E[3], X[3], G[3 dirs][3][3] (SoA)
 struct MGLevel {
   int nx, ny, nz, ncell;
+  double inv_hx, inv_ny;   // 1 / ceil(nx/2) and 1 / ny (red-black thread mapping)
   void* x;       // KT [3*ncell] (slot-major)
   void* b;       // KT [3*ncell]
   void* op[2];   // KT [kOpStride*ncell] for the concentration (0) and potential (1) operators
@@ -125,6 +126,7 @@ struct CellDev {
   // rbhx = ceil(nx/2) and rbH = rbhx*ny*nz (odd nx leaves padding slots), so a
   // half sweep reads and writes whole cache lines of one colour.
   int rbhx, rbH;
+  double inv_nx, inv_ny, inv_rbhx;  // reciprocals for the index arithmetic (divmod)
   const uint32_t* meta_rb;           // meta words in colour-split order
   void *x_rb;                        // KT [2 rbH] level-0 iterate of the V-cycle being run
   void *b0;                          // KT [2 rbH] right-hand side of a level-0 solve (colour-split)
@@ -152,12 +154,26 @@ __host__ __device__ inline int gm_size(int m) { return (m + 1) * m + 2 * (m + 1)
 struct VoxCoord {
   int x, y, z;
 };
+// Quotient and remainder of n / d (0 <= n < 2^31, d >= 1) from the FP64
+// reciprocal inv = 1/d: the product is within 2^-20 of the exact n/d, so its
+// truncation is off by at most one, and one correction step makes it exact.
+// A few instructions instead of the integer division sequence.
+__device__ inline int divmod(int n, int d, double inv, int& r) {
+  int q = (int)((double)n * inv);
+  r = n - q * d;
+  if (r >= d) {
+    ++q;
+    r -= d;
+  } else if (r < 0) {
+    --q;
+    r += d;
+  }
+  return q;
+}
 __device__ inline VoxCoord coord_of(const CellDev& cd, int i) {
   VoxCoord v;
-  v.x = i % cd.nx;
-  const int t = i / cd.nx;
-  v.y = t % cd.ny;
-  v.z = t / cd.ny;
+  const int t = divmod(i, cd.nx, cd.inv_nx, v.x);
+  v.z = divmod(t, cd.ny, cd.inv_ny, v.y);
   return v;
 }
 

@@ -157,13 +157,16 @@ __device__ inline bool nbr_corr(int m) { return m == SM_CORR; }
 // Red-black thread mapping: thread t of a level with extents (nx, ny, nz)
 // handles the t-th cell of colour `color` ((x + y + z) & 1 == color) in
 // row-major order; false when t is past the end.
-__device__ inline bool color_cell(int t, int color, int nx, int ny, int nz, C3& q) {
+__device__ inline bool color_cell(int t, int color, int nx, int ny, int nz, double inv_hx, double inv_ny, C3& q) {
   const int hx = (nx + 1) >> 1;
-  const int j = t % hx, row = t / hx;
-  q.y = row % ny;
-  q.z = row / ny;
+  int j;
+  const int row = divmod(t, hx, inv_hx, j);
+  q.z = divmod(row, ny, inv_ny, q.y);
   q.x = 2 * j + ((color + q.y + q.z) & 1);
   return q.z < nz && q.x < nx;
+}
+__device__ inline bool color_cell(int t, int color, const MGLevel& L, C3& q) {
+  return color_cell(t, color, L.nx, L.ny, L.nz, L.inv_hx, L.inv_ny, q);
 }
 
 // Neighbour cells (+x, -x, +y, -y, +z, -z) of cell c at q; absent neighbours
@@ -195,22 +198,32 @@ __device__ inline void neighbours6_rb(const CellDev& cd, int p, const C3& c, int
   nb[5] = ex[5] ? base + (row - cd.ny) * hx + (c.x >> 1) : p;
 }
 
-// Row of the level-0 operator `op` at voxel c (colour-split index p):
+// Row of the level-0 operator OP at voxel c (colour-split index p):
 // diagonal D (extra term plus all couplings) and S = sum_k g_ik x_k over the
 // neighbours (x_k read from the colour-split iterate xsrc, plus alpha times
-// the level-1 solution of k's slot when corr).  All loads are issued before
-// any arithmetic depends on them.
-template <typename KT>
-__device__ inline void voxel_row(const CellDev& cd, int op, int p, const C3& c, uint32_t mi, const KT* __restrict__ xsrc,
+// the level-1 solution of k's slot when corr).  The voxel's own interface
+// mask tells same-phase neighbours from interface ones (anode and cathode
+// never touch); only a pore voxel's interface faces need the solid
+// neighbour's meta word (its face records and phase).  All loads are issued
+// before any arithmetic depends on them.
+template <typename KT, int OP>
+__device__ inline void voxel_row(const CellDev& cd, int p, const C3& c, uint32_t mi, const KT* __restrict__ xsrc,
                                  bool zero, bool corr, KT& D, KT& S) {
   int k[6];
   bool ex[6];
   neighbours6_rb(cd, p, c, k, ex);
   const int dmap[6] = {1, 0, 3, 2, 5, 4};   // neighbour slot -> face direction (0:-x 1:+x ...)
+  const int L = lab_of(mi);
+  const bool pore = L == PORE;
+  const uint32_t msk = mask_of(mi);
+  bool ifc[6];
   uint32_t mk[6];
   KT xk[6];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) mk[j] = cd.meta_rb[k[j]];
+  for (int j = 0; j < 6; ++j) {
+    ifc[j] = (msk >> dmap[j]) & 1u;   // set only for existing neighbours
+    mk[j] = (OP != 0 && pore && ifc[j]) ? cd.meta_rb[k[j]] : 0u;
+  }
   if (!zero) {
     // absent neighbours read voxel p itself, which may not be written yet in
     // this sweep: select zero (a product with a zero coupling would keep NaN)
@@ -220,25 +233,21 @@ __device__ inline void voxel_row(const CellDev& cd, int op, int p, const C3& c, 
       xk[j] = ex[j] ? v : (KT)0;
     }
   }
-  const int L = lab_of(mi);
   KT g[6];
   // interface part of the concentration diagonal (per voxel, from the setup)
-  const KT dint = op == 0 ? ((const KT*)cd.dint)[p] : (KT)0;
+  const KT dint = OP == 0 ? ((const KT*)cd.dint)[p] : (KT)0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const int Lk = lab_of(mk[j]);
     const int d = dmap[j];
     KT v;
-    if (op == 0) {
-      v = L == Lk ? (KT)(L == PORE ? cd.Dh : cd.Dsh[L == CATHODE]) : (KT)0;
+    if (OP == 0) {
+      v = ifc[j] ? (KT)0 : (KT)(pore ? cd.Dh : cd.Dsh[L == CATHODE]);
     } else {
-      const bool iface = (L == PORE) != (Lk == PORE);
-      const bool pore_side = L == PORE;
-      const uint32_t f = iface ? face_rank(pore_side ? mk[j] : mi, pore_side ? (d ^ 1) : d) : 0u;
-      const int Ls = pore_side ? Lk : L;
+      const uint32_t f = ifc[j] ? face_rank(pore ? mk[j] : mi, pore ? (d ^ 1) : d) : 0u;
+      const int Ls = pore ? lab_of(mk[j]) : L;
       const KT* arr = (const KT*)(Ls == CATHODE ? cd.cond_ca : cd.cond_an);
       const KT gi = arr[f];
-      v = L == Lk ? (KT)(L == PORE ? cd.Gk : cd.Gs[L == CATHODE]) : (iface ? gi : (KT)0);
+      v = ifc[j] ? gi : (KT)(pore ? cd.Gk : cd.Gs[L == CATHODE]);
     }
     g[j] = ex[j] ? v : (KT)0;
   }
@@ -253,12 +262,15 @@ __device__ inline void voxel_row(const CellDev& cd, int op, int p, const C3& c, 
     const KT* x1 = (const KT*)L1.x;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
+      // the neighbour's phase slot (an interface neighbour of the
+      // concentration operator has a zero coupling: its own slot serves)
+      const int slot = (OP != 0 && ifc[j]) ? (pore ? lab_of(mk[j]) : PORE) : L;
       const int pcj = ex[j] ? pc + pq[j] * pst[j] : pc;
-      const KT v = x1[(size_t)lab_of(mk[j]) * L1.ncell + pcj];
+      const KT v = x1[(size_t)slot * L1.ncell + pcj];
       xk[j] += ex[j] ? alpha * v : (KT)0;
     }
   }
-  D = op == 0 ? (KT)1 + dint : ((L == ANODE && c.z == 0) ? (KT)cd.Gcol : (KT)0);
+  D = OP == 0 ? (KT)1 + dint : ((L == ANODE && c.z == 0) ? (KT)cd.Gcol : (KT)0);
   S = (KT)0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
@@ -300,7 +312,7 @@ struct CoarseRow {
 // L: the level, Lp: the next coarser level (read in the corrected modes),
 // alpha: the coarse-correction factor.  The level descriptors may point into
 // device memory or into LDS.
-template <typename KT>
+template <typename KT, int OP>
 __device__ inline void gather_coarse(const LV<KT>& L, const LV<KT>& Lp, KT alpha, int C, const C3& q, int mode,
                                      CoarseRow<KT>& R) {
   const size_t n = L.ncell;
@@ -310,7 +322,7 @@ __device__ inline void gather_coarse(const LV<KT>& L, const LV<KT>& Lp, KT alpha
   int nb[6];
   bool ex[6];
   neighbours6(C, q, L.nx, L.ny, L.nz, nb, ex);
-  const bool cross = L.op != 0;
+  constexpr bool cross = OP != 0;
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     R.E[s] = A[s * n + C];
@@ -574,24 +586,24 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_build(CellDev* cells, int 
 // and the red ones of the following half sweep.
 // BS threads per workgroup (kBlock in table launches; a single-cell launch
 // takes the size the tuner picked for the cell).
-template <typename KT, int BS>
-__global__ void __launch_bounds__(BS) k_mg0_smooth(CellDev* cells, const int2* __restrict__ blk, int op, int color,
-                                                   int mode, int it, int need, int post) {
+template <typename KT, int BS, int OP>
+__global__ void __launch_bounds__(BS) k_mg0_smooth(CellDev* cells, const int2* __restrict__ blk, int color, int mode,
+                                                   int it, int need, int post) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || it >= cd.nu) return;   // cells that asked for fewer sweeps skip this one
   C3 c;
   const int t = bb.y * BS + threadIdx.x;
-  if (!color_cell(t, color, cd.nx, cd.ny, cd.nz, c)) return;
+  if (!color_cell(t, color, cd.lv[0], c)) return;
   const int p = color * cd.rbH + t;
   KT* x0 = (KT*)cd.x_rb;
   const KT bi = ((const KT*)cd.b0)[p];
   KT D, S;
-  voxel_row<KT>(cd, op, p, c, cd.meta_rb[p], x0, mode == SM_ZERO, mode == SM_CORR, D, S);
+  voxel_row<KT, OP>(cd, p, c, cd.meta_rb[p], x0, mode == SM_ZERO, mode == SM_CORR, D, S);
   if (!gate_state(cd, need)) return;
   const KT xn = D > (KT)0 ? (bi + S) / D : (KT)0;
   x0[p] = xn;
-  if (post && it == cd.nu - 1) ((KT*)cd.z)[(size_t)op * cd.N + c.x + cd.nx * (c.y + cd.ny * c.z)] = xn;
+  if (post && it == cd.nu - 1) ((KT*)cd.z)[(size_t)OP * cd.N + c.x + cd.nx * (c.y + cd.ny * c.z)] = xn;
 }
 
 // Sum over the 8 lanes of an aligned lane group (xor butterfly: every lane
@@ -614,9 +626,8 @@ __device__ inline double lane8_sum(double v) {
 // pre-smoothing half sweep solved every black row exactly for the current red
 // values, so only red rows carry a residual (the black ones are zero up to
 // rounding and are not evaluated).
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const int2* __restrict__ blk, int op,
-                                                         int need) {
+template <typename KT, int OP>
+__global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const int2* __restrict__ blk, int need) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active) return;
@@ -634,7 +645,7 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
       const uint32_t mi = cd.meta_rb[p];
       const KT xi = x0[p], bi = ((const KT*)cd.b0)[p];
       KT D, S;
-      voxel_row<KT>(cd, op, p, fc, mi, x0, false, false, D, S);
+      voxel_row<KT, OP>(cd, p, fc, mi, x0, false, false, D, S);
       const int L = lab_of(mi);
       const KT r = bi + S - D * xi;
       rs[0] = L == 0 ? r : (KT)0;
@@ -652,11 +663,11 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
 
 // Coarse-level (l >= 1) red-black Gauss-Seidel update of cell C; the slots
 // of one cell are relaxed in order (slot-wise Gauss-Seidel inside the cell).
-template <typename KT>
+template <typename KT, int OP>
 __device__ inline void smooth_cell(const CellDev& cd, const LV<KT>& L, const LV<KT>& Lp, KT alpha, int C, const C3& q,
                                    int mode, int need) {
   CoarseRow<KT> R;
-  gather_coarse<KT>(L, Lp, alpha, C, q, mode, R);
+  gather_coarse<KT, OP>(L, Lp, alpha, C, q, mode, R);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     KT D = R.E[s], S = R.b[s];
@@ -684,10 +695,10 @@ __device__ inline void smooth_cell(const CellDev& cd, const LV<KT>& L, const LV<
 }
 
 // Residual (per slot) of coarse cell c at level l.
-template <typename KT>
+template <typename KT, int OP>
 __device__ inline void residual_cell(const LV<KT>& L, int c, const C3& q, KT (&r)[3]) {
   CoarseRow<KT> R;
-  gather_coarse<KT>(L, L, (KT)0, c, q, SM_PLAIN, R);
+  gather_coarse<KT, OP>(L, L, (KT)0, c, q, SM_PLAIN, R);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const KT xs = R.xo[s];
@@ -704,23 +715,22 @@ __device__ inline void residual_cell(const LV<KT>& L, int c, const C3& q, KT (&r
   }
 }
 
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int2* __restrict__ blk, int l, int op,
-                                                       int color, int mode, int it, int need) {
+template <typename KT, int OP>
+__global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int2* __restrict__ blk, int l, int color,
+                                                       int mode, int it, int need) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || l >= cd.lfuse || it >= (l >= 2 ? min(cd.nu, cd.nu_c) : cd.nu)) return;
   const MGLevel& L = cd.lv[l];
   C3 q;
-  if (!color_cell(bb.y * kBlock + threadIdx.x, color, L.nx, L.ny, L.nz, q)) return;
-  smooth_cell<KT>(cd, view<KT>(L, op), view<KT>(cd.lv[l + 1], op), (KT)cd.alpha, lvl_cell(L, q.x, q.y, q.z), q,
+  if (!color_cell(bb.y * kBlock + threadIdx.x, color, L, q)) return;
+  smooth_cell<KT, OP>(cd, view<KT>(L, OP), view<KT>(cd.lv[l + 1], OP), (KT)cd.alpha, lvl_cell(L, q.x, q.y, q.z), q,
                   mode, need);
 }
 
 // Level-l residual restricted to level l+1: 8 lanes per parent, one per child.
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const int2* __restrict__ blk, int l, int op,
-                                                         int need) {
+template <typename KT, int OP>
+__global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const int2* __restrict__ blk, int l, int need) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || l >= cd.lfuse) return;
@@ -734,7 +744,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
     const C3 q = c3_of(P, Lp.nx, Lp.ny);
     const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
     if (cx < L.nx && cy < L.ny && cz < L.nz)
-      residual_cell<KT>(view<KT>(L, op), lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
+      residual_cell<KT, OP>(view<KT>(L, OP), lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
   if (!gate_state(cd, need)) return;   // uniform over the block (one cell)
@@ -752,8 +762,9 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
 // fused_lds_bytes); the coarsest inverse stays in device memory (symmetric:
 // read column-wise, coalesced).  Only the level-lfuse solution is written
 // back: the launched level above reads it for its coarse correction.
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int op, int need) {
+template <typename KT, int OP>
+__global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int need) {
+  constexpr int op = OP;
   extern __shared__ __align__(16) unsigned char smem[];
   const int ci = blockIdx.x;
   if (ci >= ncells) return;
@@ -799,8 +810,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         const int mode = it == 0 ? (color == 0 ? SM_ZERO : SM_OWNZERO) : SM_PLAIN;
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
-          if (color_cell(t, color, L.nx, L.ny, L.nz, q))
-            smooth_cell<KT>(cd, L, Lp, alpha, q.x + L.nx * (q.y + L.ny * q.z), q, mode, -2);
+          if (color_cell(t, color, L.nx, L.ny, L.nz, cd.lv[l].inv_hx, cd.lv[l].inv_ny, q))
+            smooth_cell<KT, OP>(cd, L, Lp, alpha, q.x + L.nx * (q.y + L.ny * q.z), q, mode, -2);
         }
         __syncthreads();
       }
@@ -811,7 +822,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
         if (cx >= L.nx || cy >= L.ny || cz >= L.nz) continue;
         KT r[3];
-        residual_cell<KT>(L, cx + L.nx * (cy + L.ny * cz), C3{cx, cy, cz}, r);
+        residual_cell<KT, OP>(L, cx + L.nx * (cy + L.ny * cz), C3{cx, cy, cz}, r);
         for (int s = 0; s < 3; ++s) acc[s] += r[s];
       }
       for (int s = 0; s < 3; ++s) Lp.b[(size_t)s * Lp.ncell + P] = acc[s];
@@ -840,8 +851,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         const int mode = it == 0 ? (color == 1 ? SM_CORR : SM_OWNCORR) : SM_PLAIN;
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
-          if (color_cell(t, color, L.nx, L.ny, L.nz, q))
-            smooth_cell<KT>(cd, L, Lp, alpha, q.x + L.nx * (q.y + L.ny * q.z), q, mode, -2);
+          if (color_cell(t, color, L.nx, L.ny, L.nz, cd.lv[l].inv_hx, cd.lv[l].inv_ny, q))
+            smooth_cell<KT, OP>(cd, L, Lp, alpha, q.x + L.nx * (q.y + L.ny * q.z), q, mode, -2);
         }
         __syncthreads();
       }
@@ -945,18 +956,30 @@ void launch_mg_setup(const BatchLaunch& b, hipStream_t s) {
   }
 }
 
-template <typename KT>
-static void smooth0(const BatchLaunch& b, int op, int color, int mode, int it, int need, int post, hipStream_t s) {
-  if (b.lvlh_nblk[0] <= 0) return;
+template <typename KT, int OP>
+static void smooth0_op(const BatchLaunch& b, int color, int mode, int it, int need, int post, hipStream_t s) {
   const int bs = b.lvlh_blk[0] ? kBlock : b.bs_smooth0;
   const int nh = b.lvlh_nblk[0] * kBlock;   // single cell: one colour's cells, rounded up to kBlock
   if (bs == 64)
-    k_mg0_smooth<KT, 64><<<nh / 64, 64, 0, s>>>(b.cells, nullptr, op, color, mode, it, need, post);
+    k_mg0_smooth<KT, 64, OP><<<nh / 64, 64, 0, s>>>(b.cells, nullptr, color, mode, it, need, post);
   else if (bs == 128)
-    k_mg0_smooth<KT, 128><<<nh / 128, 128, 0, s>>>(b.cells, nullptr, op, color, mode, it, need, post);
+    k_mg0_smooth<KT, 128, OP><<<nh / 128, 128, 0, s>>>(b.cells, nullptr, color, mode, it, need, post);
+  else if (bs == 512)   // the grid rounds up: threads past the colour's last cell return at once
+    k_mg0_smooth<KT, 512, OP><<<(nh + 511) / 512, 512, 0, s>>>(b.cells, nullptr, color, mode, it, need, post);
+  else if (bs == 1024)
+    k_mg0_smooth<KT, 1024, OP><<<(nh + 1023) / 1024, 1024, 0, s>>>(b.cells, nullptr, color, mode, it, need, post);
   else
-    k_mg0_smooth<KT, kBlock><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], op, color, mode, it, need,
-                                                               post);
+    k_mg0_smooth<KT, kBlock, OP><<<b.lvlh_nblk[0], kBlock, 0, s>>>(b.cells, b.lvlh_blk[0], color, mode, it, need,
+                                                                   post);
+}
+
+template <typename KT>
+static void smooth0(const BatchLaunch& b, int op, int color, int mode, int it, int need, int post, hipStream_t s) {
+  if (b.lvlh_nblk[0] <= 0) return;
+  if (op == 0)
+    smooth0_op<KT, 0>(b, color, mode, it, need, post, s);
+  else
+    smooth0_op<KT, 1>(b, color, mode, it, need, post, s);
 }
 
 template <typename KT>
@@ -967,7 +990,10 @@ void launch_smooth0_probe(const BatchLaunch& b, hipStream_t s) {
 template <typename KT>
 static void smoothl(const BatchLaunch& b, int l, int op, int color, int mode, int it, int need, hipStream_t s) {
   if (b.lvlh_nblk[l] <= 0) return;
-  k_mgl_smooth<KT><<<b.lvlh_nblk[l], kBlock, 0, s>>>(b.cells, b.lvlh_blk[l], l, op, color, mode, it, need);
+  if (op == 0)
+    k_mgl_smooth<KT, 0><<<b.lvlh_nblk[l], kBlock, 0, s>>>(b.cells, b.lvlh_blk[l], l, color, mode, it, need);
+  else
+    k_mgl_smooth<KT, 1><<<b.lvlh_nblk[l], kBlock, 0, s>>>(b.cells, b.lvlh_blk[l], l, color, mode, it, need);
 }
 
 // One V-cycle on operator op: red-black sweeps (red then black) down to the
@@ -993,11 +1019,14 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
     if (l == 0 && prof_on(PK_SMOOTH0)) prof_end_n(PK_SMOOTH0, s, 2.0 * nu * b.bytes_smooth0, 2 * nu);
     if (b.lvl8_nblk[l + 1] <= 0) continue;
     if (l == 0)
-      k_mg0_restrict<KT><<<b.lvl8_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl8_blk[1], op, need);
+      (op == 0 ? k_mg0_restrict<KT, 0> : k_mg0_restrict<KT, 1>)<<<b.lvl8_nblk[1], kBlock, 0, s>>>(
+          b.cells, b.lvl8_blk[1], need);
     else
-      k_mgl_restrict<KT><<<b.lvl8_nblk[l + 1], kBlock, 0, s>>>(b.cells, b.lvl8_blk[l + 1], l, op, need);
+      (op == 0 ? k_mgl_restrict<KT, 0> : k_mgl_restrict<KT, 1>)<<<b.lvl8_nblk[l + 1], kBlock, 0, s>>>(
+          b.cells, b.lvl8_blk[l + 1], l, need);
   }
-  k_mg_coarse_cycle<KT><<<b.ncell, kBlock, b.fused_lds * sizeof(KT), s>>>(b.cells, b.ncell, op, need);
+  (op == 0 ? k_mg_coarse_cycle<KT, 0> : k_mg_coarse_cycle<KT, 1>)<<<b.ncell, kBlock, b.fused_lds * sizeof(KT), s>>>(
+      b.cells, b.ncell, need);
   for (int l = top - 1; l >= 0; --l) {
     const int nu = l >= 2 ? std::min(b.max_nu, b.max_nu_c) : b.max_nu;
     if (l == 0) prof_begin(PK_SMOOTH0, s);

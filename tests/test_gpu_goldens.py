@@ -77,6 +77,7 @@ def test_c1_copy_32x32x80_matches_oracle(mbx, prec, bar):
         info = cell.step(w.dt)
         assert info["substeps"] == 1
         assert abs(info["V"] - ref["V"][s]) <= 1e-6, (s, info["V"], ref["V"][s])
+        worst["V"] = max(worst.get("V", 0.0), abs(info["V"] - ref["V"][s]))
         check_state("c1s2", w.labels, w.params.n_c, cell.get_state(), ref, k, bar, worst)
         sac = cell.mean_solid()
         np.testing.assert_allclose(sac, ref["s_ac"][s], rtol=bar)
@@ -110,6 +111,7 @@ def test_c2cut_alone_matches_oracle(mbx, prec, bar):
         Vg.append(info["V"])
         if s <= kcut:
             assert abs(info["V"] - ref["V"][s]) <= 1e-6, (s, info["V"], ref["V"][s])
+            worst["V"] = max(worst.get("V", 0.0), abs(info["V"] - ref["V"][s]))
         if s in keep:
             check_state("c2cut", w.labels, w.params.n_c, cell.get_state(), ref, keep[s], bar, worst)
             np.testing.assert_allclose(cell.mean_solid(), ref["s_ac"][s], rtol=bar)
@@ -181,6 +183,7 @@ def test_sampled_queries_batched_match_oracle(mbx, prec, bar):
         for (w, r), cell, info in zip(qs, cells, infos):
             assert info["substeps"] == 1, (s, w.name)
             assert abs(info["V"] - r["V"][s]) <= 1e-6, (s, w.name, info["V"], r["V"][s])
+            worst["V"] = max(worst.get("V", 0.0), abs(info["V"] - r["V"][s]))
             j = list(r["state_steps"]).index(s) if s in r["state_steps"] else None
             if j is not None:
                 check_state(w.name, w.labels, w.params.n_c, cell.get_state(), r, j, bar, worst)
@@ -232,6 +235,7 @@ def test_adaptive_run_matches_oracle(mbx, prec, bar):
     np.testing.assert_array_equal(t, ref["times"][1:])
     assert rej == int(ref["rejected"]) and not cut
     np.testing.assert_allclose(V, ref["V"][1:], rtol=0, atol=1e-6)
+    e_V = float(np.max(np.abs(V - ref["V"][1:])))
     got = cell.get_state()
     e = field_errors(w.labels, w.params.n_c, *got, ref["c"], ref["phi"], ref["n"])
     for f, v in e.items():
@@ -249,7 +253,7 @@ def test_adaptive_run_matches_oracle(mbx, prec, bar):
     torch.cuda.synchronize()
     torch.testing.assert_close(snaps[:count], snaps2[:count], rtol=1e-12, atol=0)
     np.testing.assert_array_equal(snaps[count - 1].cpu().numpy(), got[0])
-    say("adaptive", prec, {k: f"{v:.2e}" for k, v in e.items()})
+    say("adaptive", prec, {k: f"{v:.2e}" for k, v in {**e, "V": e_V}.items()})
 
 
 def test_adaptive_run_below_dt_min_keeps_the_last_accepted_state(mbx):

@@ -403,12 +403,12 @@ def test_graph_replay_equals_direct_launches(mbx, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_launch_shapes_give_identical_steps(mbx, prec, monkeypatch):
-    """The tuner's workgroup sizes (64, 128, 256 threads for the level-0
+    """The tuner's workgroup sizes (64 to 1024 threads for the level-0
     smoother and J*v) change only the grouping of the same per-voxel work:
     steps are bit-identical; the tuned choice is one of them."""
     w = I.config1(seed=1, scale=4)
     states = {}
-    for bs in ("256", "128", "64"):
+    for bs in ("256", "1024", "512", "128", "64"):
         monkeypatch.setenv("MBX_TUNE", bs)
         cell = mbx.Cell(w.labels, w.params, precision=prec)
         assert cell.launch_shape() == (int(bs), int(bs))
@@ -416,11 +416,11 @@ def test_launch_shapes_give_identical_steps(mbx, prec, monkeypatch):
             cell.step(w.dt)
         states[bs] = cell.get_state()
         cell.close()
-    for bs in ("128", "64"):
+    for bs in ("1024", "512", "128", "64"):
         for x, y in zip(states[bs], states["256"]):
             assert np.array_equal(x, y), bs
     monkeypatch.delenv("MBX_TUNE")
     cell = mbx.Cell(w.labels, w.params, precision=prec)
     say("tuned launch shape", w.labels.shape, prec, cell.launch_shape())
-    assert all(b in (64, 128, 256) for b in cell.launch_shape())
+    assert all(b in (64, 128, 256, 512, 1024) for b in cell.launch_shape())
     cell.close()
