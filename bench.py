@@ -14,7 +14,8 @@ Both precision modes run (mixed: FP32 Krylov and preconditioner with FP64
 residual and refinement; fp64): the configured mixed mode is the headline,
 the other is reported beside it, with the difference of their states after
 the same steps.  After the timed steps each cell runs a short event-timed
-region for the roofline, then continues to the cutoff (`to_cutoff`).
+region for the roofline; the headline precision then continues to the cutoff
+(`to_cutoff`; --cutoff all: both precisions).
 
 Further objects: `batched` (32 sampled queries of 32x32x80 .. 96x96x240,
 stepped together in mixed precision), `serve` (parameter queries of
@@ -110,6 +111,7 @@ def run_gpu(w, precision, steps, warmup, stream, prof_steps=4, V_cut=None, to_cu
                "reached": bool(infos[-1]["V"] >= V_cut),
                "retried_steps": sum(1 for i in infos if i["substeps"] > 1)}
     counts = cell.counts
+    shape = cell.launch_shape()
     cell.close()
     wall = t1 - t0
     dof = 2 * counts.n_vox
@@ -124,6 +126,7 @@ def run_gpu(w, precision, steps, warmup, stream, prof_steps=4, V_cut=None, to_cu
         "V_end": V_timed,
         "kernel": {"launches": launches, "ms": ms, "bytes": nbytes},
         "counts": counts,
+        "launch_shape": {"smooth0_threads": shape[0], "matvec_threads": shape[1]},
         "state": state,
         "s_ac": mean_solid,
         "to_cutoff": cut,
@@ -376,10 +379,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--mode", choices=["step", "serve"], default="step")
-    ap.add_argument("--no-cutoff", action="store_true", help="stop after the timed and profiled steps")
+    ap.add_argument("--cutoff", choices=["headline", "all", "none"], default="headline",
+                    help="which precisions continue to the 4.2 V cutoff after the timed steps")
+    ap.add_argument("--no-cutoff", action="store_true", help="same as --cutoff none")
     ap.add_argument("--batch-cells", type=int, default=32)
     ap.add_argument("--batch-steps", type=int, default=2, help="timed batched steps (0: skip the batched run)")
-    ap.add_argument("--serve-requests", type=int, default=60, help="Poisson-run requests per precision (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=24, help="Poisson-run requests per precision (0: skip)")
     ap.add_argument("--serve-capacity-requests", type=int, default=8,
                     help="requests of the closed burst that measures the server's capacity")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="offered arrival rate, requests/s")
@@ -428,7 +433,9 @@ def main():
     print(f"[bench] workload {w.name}, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
     res = {}
     for prec in precs:
-        res[prec] = run_gpu(w, prec, args.steps, args.warmup, stream, V_cut=V_cut, to_cutoff=not args.no_cutoff)
+        cutoff = "none" if args.no_cutoff else args.cutoff
+        to_cut = cutoff == "all" or (cutoff == "headline" and prec == HEADLINE_PRECISION)
+        res[prec] = run_gpu(w, prec, args.steps, args.warmup, stream, V_cut=V_cut, to_cutoff=to_cut)
         cut = res[prec]["to_cutoff"]
         print(f"[bench] {prec}: {res[prec]['ms_per_step']:.1f} ms/step" +
               (f", {cut['steps']} steps to the cutoff in {cut['wall_s']:.1f} s" if cut else ""),
@@ -458,6 +465,7 @@ def main():
         "newton_per_step": r["newton_per_step"],
         "krylov_per_step": r["krylov_per_step"],
         "retried_steps": r["retried_steps"],
+        "launch_shape": r["launch_shape"],
         "to_cutoff": r["to_cutoff"],
         "roofline": {"bound": "hbm", "kernel": PROFILED_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
