@@ -42,7 +42,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILED_KERNEL = "smooth0"     # the kernel class with the largest share of GPU time
+PROFILED_KERNEL = "smooth0"     # the largest single kernel by GPU time
 
 
 def committed_traffic(summary, sources, precision):
