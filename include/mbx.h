@@ -22,9 +22,11 @@
  * Conventions
  *   - SI units everywhere (m, s, mol, A, V, K).
  *   - Labels: uint8, 0 = pore/electrolyte, 1 = anode active material,
- *     2 = cathode active material.  Voxel (i, j, k) has flat index
+ *     2 = cathode active material, 3 = Li-metal foil: the counter electrode
+ *     of a half cell (Sec. 2.2), which takes the cathode's place (a cell
+ *     holds 2 or 3, not both).  Voxel (i, j, k) has flat index
  *     i + nx*(j + ny*k); k = 0 touches the anode collector, k = nz-1 the
- *     cathode collector.
+ *     cathode (foil) collector.
  *   - Interface faces are numbered per phase in canonical order: by solid
  *     voxel flat index, then by direction 0:-x 1:+x 2:-y 3:+y 4:-z 5:+z as
  *     seen from the solid voxel.  Plated amounts n_pl[] follow the anode
@@ -49,7 +51,8 @@ extern "C" {
 enum {
   MBX_OK = 0,
   MBX_EINVAL = -1,   /* bad argument (null pointer, size, parameter out of range) */
-  MBX_ELABEL = -2,   /* labels invalid: anode touches cathode, or a collector plane holds no solid of its electrode */
+  MBX_ELABEL = -2,   /* labels invalid: anode touches cathode (or foil), cathode and foil labels mixed, or a
+                        collector plane holds no solid of its electrode */
   MBX_ENEWTON = -3,  /* Newton did not converge within newton_max iterations */
   MBX_ENAN = -4,     /* non-finite value in the state or residual */
   MBX_ENOMEM = -5,   /* device allocation failed */
@@ -94,6 +97,11 @@ typedef struct {
   int graphs;            /* 1 (mbx_params_default): the GMRES iterations between two host checks run as a
                             captured HIP graph, replayed with one launch; 0: direct kernel launches.  Same
                             kernels and results either way.  A batch uses graphs if all its cells do. */
+  double i00_ce;         /* half cell (labels 3, Sec. 2.2): rate constant of the Li-foil counter electrode,
+                            A/m^2, i = 2 i00_ce sinh(F (Phi_foil - phi_e) / 2RT); required > 0 when the
+                            labels hold foil voxels, unused otherwise.  The foil takes the cathode's
+                            conductivity sigma[1]; its concentration unknown carries no equation (it keeps
+                            y0 cmax[1]); the cathode's Ds[1], i00[1], U0[1], U1[1] are unused */
 } mbx_params;
 
 typedef struct {
@@ -121,8 +129,9 @@ int mbx_params_default(mbx_params *p);
  *   out    : receives the handle; the cell owns its device memory
  * The state is set to the zero-current equilibrium: c = c0 in pores,
  * x0*c_max / y0*c_max in the solids, phi_anode = 0, phi_e = -U_an(x0),
- * phi_cathode = U_ca(y0) - U_an(x0), n_f = n_c (f/(1-f))^(1/4) with
- * f = exp(-F U_an(x0)/RT), which makes every interface current vanish.
+ * phi_cathode = U_ca(y0) - U_an(x0) (a half cell's foil: -U_an(x0)),
+ * n_f = n_c (f/(1-f))^(1/4) with f = exp(-F U_an(x0)/RT), which makes every
+ * interface current vanish.
  * Errors: MBX_EINVAL (bad sizes/parameters), MBX_ELABEL, MBX_ENOMEM, MBX_EHIP. */
 int mbx_cell_create(const uint8_t *labels, int nx, int ny, int nz,
                     const mbx_params *p, void *stream, mbx_cell **out);

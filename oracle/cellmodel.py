@@ -40,6 +40,7 @@ FARADAY = 96485.33212      # C/mol (CODATA 2018)
 GAS_R = 8.314462618        # J/(mol K) (CODATA 2018)
 
 PORE, ANODE, CATHODE = 0, 1, 2
+FOIL = 3            # Li-metal counter electrode of a half cell (Sec. 2.2), held in the cathode slot
 # direction index seen from a voxel: 0:-x 1:+x 2:-y 3:+y 4:-z 5:+z
 _AXIS_DIRS = ((0, 1), (2, 3), (4, 5))
 
@@ -54,9 +55,15 @@ class Geometry:
             raise ValueError("labels must be (nz, ny, nx)")
         self.nz, self.ny, self.nx = lab.shape
         self.N = lab.size
-        self.lab = lab.ravel()
-        if np.any(self.lab > 2):
-            raise ValueError("labels must be 0 (pore), 1 (anode) or 2 (cathode)")
+        flat = lab.ravel()
+        if np.any(flat > FOIL):
+            raise ValueError("labels must be 0 (pore), 1 (anode), 2 (cathode) or 3 (Li foil)")
+        # a half cell (graphite against a Li foil, Sec. 2.2) holds its foil in
+        # the counter-electrode slot; a cell is either full or half
+        self.half = bool(np.any(flat == FOIL))
+        if self.half and np.any(flat == CATHODE):
+            raise ValueError("a cell holds either cathode (2) or Li foil (3) voxels, not both")
+        self.lab = np.where(flat == FOIL, CATHODE, flat).astype(np.uint8)
         idx = np.arange(self.N).reshape(lab.shape)
         lo_list, hi_list, ax_list = [], [], []
         for axis, sl_lo, sl_hi in ((0, np.s_[:, :, :-1], np.s_[:, :, 1:]),
@@ -72,7 +79,7 @@ class Geometry:
         ax = np.concatenate(ax_list)
         la, lb = self.lab[lo], self.lab[hi]
         if np.any(((la == ANODE) & (lb == CATHODE)) | ((la == CATHODE) & (lb == ANODE))):
-            raise ValueError("anode and cathode voxels may not share a face")
+            raise ValueError("the two electrodes may not share a face (no such interface, Sec. 2.2)")
         pp = (la == PORE) & (lb == PORE)
         self.pp_lo, self.pp_hi = lo[pp], hi[pp]
         ss = (la != PORE) & (la == lb)
@@ -139,7 +146,9 @@ class Model:
         self.V = self.h ** 3
         self.RT = GAS_R * p["T"]
         self.beta = FARADAY / (2.0 * self.RT)
-        self.Ds = {ANODE: p["Ds_an"], CATHODE: p["Ds_ca"]}
+        # Li foil (half cell): no Li diffusion or intercalation in the metal
+        self.half = geom.half
+        self.Ds = {ANODE: p["Ds_an"], CATHODE: 0.0 if self.half else p["Ds_ca"]}
         self.sig = {ANODE: p["sigma_an"], CATHODE: p["sigma_ca"]}
         self.cmax = {ANODE: p["cmax_an"], CATHODE: p["cmax_ca"]}
         self.i00 = {ANODE: p["i00_an"], CATHODE: p["i00_ca"]}
@@ -159,7 +168,7 @@ class Model:
         g, p = self.g, self.p
         x0, y0 = p["x0"], p["y0"]
         Uan = ocp(self.U[ANODE], x0)
-        Uca = ocp(self.U[CATHODE], y0)
+        Uca = 0.0 if self.half else ocp(self.U[CATHODE], y0)   # Li foil: eta = Phi - phi_e (Sec. 2.2)
         c = np.where(g.lab == PORE, p["c0"],
                      np.where(g.lab == ANODE, x0 * p["cmax_an"], y0 * p["cmax_ca"])).astype(float)
         phi = np.where(g.lab == PORE, -Uan, np.where(g.lab == ANODE, 0.0, Uca - Uan)).astype(float)
@@ -175,9 +184,11 @@ class Model:
 
     # ------------------------------------------------------------- kinetics
     def interface_currents(self, u):
-        """Per interface face: intercalation current i_int (eq. 2.5) and,
-        on anode faces with plating on, plating current i_pl (eq. 2.8).
-        Positive = current from solid into electrolyte."""
+        """Per interface face: intercalation current i_int (eq. 2.5; on the
+        Li foil of a half cell the counter-electrode law 2 i00_ce
+        sinh(F eta / 2RT) with eta = Phi - phi_e) and, on anode faces with
+        plating on, plating current i_pl (eq. 2.8).  Positive = current from
+        solid into electrolyte."""
         g = self.g
         c, phi, n = self.split(u)
         cs, ce = c[g.if_s], c[g.if_p]
@@ -189,6 +200,9 @@ class Model:
         i00 = np.where(ph == ANODE, self.i00[ANODE], self.i00[CATHODE])
         eta = ps - U - pe
         i_int = 2.0 * i00 * np.sqrt(cs * ce) * np.sinh(self.beta * eta)
+        if self.half:
+            foil = ph == CATHODE
+            i_int[foil] = 2.0 * self.p["i00_ce"] * np.sinh(self.beta * (ps[foil] - pe[foil]))
         i_pl = np.zeros(g.F_if)
         if self.p["plating"] and g.F_pl:
             f = g.pl_face
@@ -226,7 +240,9 @@ class Model:
         np.add.at(Rp, b, -A * j)
         # interface faces, eq. (2.4) interface conditions with (2.5) and (2.8)/(2.12)
         i_int, i_pl = self.interface_currents(u)
-        np.add.at(Rc, g.if_s, A * i_int / FARADAY)
+        # the Li foil carries no concentration equation (Sec. 2.2): no molar flux into it
+        solid_mol = np.where(g.if_phase == CATHODE, 0.0, i_int) if self.half else i_int
+        np.add.at(Rc, g.if_s, A * solid_mol / FARADAY)
         np.add.at(Rp, g.if_s, A * (i_int + i_pl))
         np.add.at(Rc, g.if_p, -A * (i_int + i_pl) / FARADAY)
         np.add.at(Rp, g.if_p, -A * (i_int + i_pl))
@@ -290,10 +306,19 @@ class Model:
         pre = 2.0 * i00 * np.sqrt(cs * ce)
         i_int = pre * np.sinh(self.beta * eta)
         gcond = pre * self.beta * np.cosh(self.beta * eta)
-        d_int = [(iC(s), i_int / (2 * cs) - gcond * dU), (iC(e), i_int / (2 * ce)),
-                 (iP(s), gcond), (iP(e), -gcond)]
+        d_cs, d_ce = i_int / (2 * cs) - gcond * dU, i_int / (2 * ce)
+        mol_s = np.ones(s.size)                    # share of the face's molar flux in the solid's c row
+        if self.half:
+            foil = ph == CATHODE
+            ef = ps[foil] - pe[foil]
+            i_int[foil] = 2.0 * p["i00_ce"] * np.sinh(self.beta * ef)
+            gcond[foil] = 2.0 * p["i00_ce"] * self.beta * np.cosh(self.beta * ef)
+            d_cs[foil] = 0.0
+            d_ce[foil] = 0.0
+            mol_s[foil] = 0.0
+        d_int = [(iC(s), d_cs), (iC(e), d_ce), (iP(s), gcond), (iP(e), -gcond)]
         for col, dv in d_int:
-            add(iC(s), col, A * dv / FARADAY)
+            add(iC(s), col, A * dv * mol_s / FARADAY)
             add(iP(s), col, A * dv)
             add(iC(e), col, -A * dv / FARADAY)
             add(iP(e), col, -A * dv)

@@ -307,6 +307,7 @@ int check_params(const mbx_params* p) {
   if (p->plating != 0 && p->plating != 1) return fail(MBX_EINVAL, "plating must be 0 or 1");
   if (!(std::isfinite(p->V_cut) && p->V_cut >= 0.0)) return fail(MBX_EINVAL, "V_cut must be finite and >= 0");
   if (p->graphs != 0 && p->graphs != 1) return fail(MBX_EINVAL, "graphs must be 0 or 1");
+  if (!(std::isfinite(p->i00_ce) && p->i00_ce >= 0.0)) return fail(MBX_EINVAL, "i00_ce must be finite and >= 0");
   return MBX_OK;
 }
 
@@ -325,7 +326,8 @@ void fill_constants(CellDev& h, const mbx_params& p, int nx, int ny) {
   h.tplus = p.tplus;
   h.thermo = p.thermo;
   for (int s = 0; s < 2; ++s) {
-    h.Ds[s] = p.Ds[s];
+    // no Li diffusion in a half cell's foil (Sec. 2.2: eq. 2.1 holds in the graphite only)
+    h.Ds[s] = (s == 1 && h.half) ? 0.0 : p.Ds[s];
     h.sigma[s] = p.sigma[s];
     h.cmax[s] = p.cmax[s];
     h.i00[s] = p.i00[s];
@@ -333,6 +335,7 @@ void fill_constants(CellDev& h, const mbx_params& p, int nx, int ny) {
     h.U1[s] = p.U1[s];
   }
   h.i00_pl = p.i00_pl;
+  h.i00_ce = p.i00_ce;
   h.n_c = p.n_c;
   h.I_app = p.I_app;
   h.plating = p.plating;
@@ -353,7 +356,8 @@ void fill_step_constants(CellDev& h, double dt) {
   for (int s = 0; s < 2; ++s) {
     h.Dsh[s] = h.Ds[s] * dt / (hh * hh);
     h.Gs[s] = h.sigma[s] * h.VT / (hh * mu);
-    h.Ks[s] = dt * mu / (hh * kFaraday * h.cmax[s]);
+    // the foil's concentration row carries no interface flux
+    h.Ks[s] = (s == 1 && h.half) ? 0.0 : dt * mu / (hh * kFaraday * h.cmax[s]);
   }
 }
 
@@ -1241,15 +1245,24 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   }
   if (hflags[0] & 1) {
     cleanup_tmp();
-    return fail(MBX_EINVAL, "labels must be 0 (pore), 1 (anode) or 2 (cathode)");
+    return fail(MBX_EINVAL, "labels must be 0 (pore), 1 (anode), 2 (cathode) or 3 (Li foil)");
+  }
+  if ((hflags[0] & 4) && (hflags[0] & 8)) {
+    cleanup_tmp();
+    return fail(MBX_ELABEL, "a cell holds cathode (2) or Li foil (3) voxels, not both");
   }
   if (hflags[0] & 2) {
     cleanup_tmp();
-    return fail(MBX_ELABEL, "an anode voxel shares a face with a cathode voxel");
+    return fail(MBX_ELABEL, "an anode voxel shares a face with a cathode or foil voxel");
   }
   if (hflags[1] == 0 || hflags[2] == 0) {
     cleanup_tmp();
-    return fail(MBX_ELABEL, "the z=0 plane needs anode solid and the z=nz-1 plane cathode solid");
+    return fail(MBX_ELABEL, "the z=0 plane needs anode solid and the z=nz-1 plane cathode (or foil) solid");
+  }
+  const int half = (hflags[0] & 4) ? 1 : 0;
+  if (half && !(p.i00_ce > 0.0)) {
+    cleanup_tmp();
+    return fail(MBX_EINVAL, "a half cell (Li foil voxels) needs i00_ce > 0");
   }
   const int F_an = tail[0] + tail[1], F_ca = tail[2] + tail[3];
   if (F_an >= (1 << 24) || F_ca >= (1 << 24)) {
@@ -1391,6 +1404,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.m = c->m;
   h.lam = 1.0;
   h.rtol = 1e-6;
+  h.half = half;
   fill_constants(h, p, nx, ny);
   fill_step_constants(h, 1.0);
   std::vector<int2> tab(c->nblk);

@@ -42,20 +42,24 @@ __global__ void __launch_bounds__(kBlock) k_build_meta(const uint8_t* __restrict
   const int N = nx * ny * nz;
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= N) return;
-  const int L = lab[i];
-  if (L > 2) {
+  const int Lraw = lab[i];
+  if (Lraw > 3) {
     atomicOr(&flags[0], 1);
     meta[i] = 0;
     cnt_an[i] = cnt_ca[i] = 0;
     return;
   }
+  // a half cell's Li foil (label 3, Sec. 2.2) takes the counter-electrode slot
+  if (Lraw == 3) atomicOr(&flags[0], 4);
+  if (Lraw == CATHODE) atomicOr(&flags[0], 8);
+  const int L = Lraw == 3 ? CATHODE : Lraw;
   const int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
   const int nb[6] = {x > 0 ? i - 1 : -1,      x < nx - 1 ? i + 1 : -1,      y > 0 ? i - nx : -1,
                      y < ny - 1 ? i + nx : -1, z > 0 ? i - nx * ny : -1, z < nz - 1 ? i + nx * ny : -1};
   uint32_t mask = 0;
   for (int d = 0; d < 6; ++d) {
     if (nb[d] < 0) continue;
-    const int Lk = lab[nb[d]];
+    const int Lk = lab[nb[d]] == 3 ? CATHODE : lab[nb[d]];
     if ((L == PORE) != (Lk == PORE)) mask |= 1u << d;
     if ((L == ANODE && Lk == CATHODE) || (L == CATHODE && Lk == ANODE)) atomicOr(&flags[0], 2);
   }
@@ -106,7 +110,8 @@ __global__ void __launch_bounds__(kBlock) k_init_state(CellDev* cells, const int
   const uint32_t m = cd.meta[i];
   const int L = lab_of(m);
   const double Uan = cd.U0[0] + cd.U1[0] * log((1.0 - cd.x0) / cd.x0);
-  const double Uca = cd.U0[1] + cd.U1[1] * log((1.0 - cd.y0) / cd.y0);
+  // a half cell's foil sits at the electrolyte potential (eta = 0 without an OCP)
+  const double Uca = cd.half ? 0.0 : cd.U0[1] + cd.U1[1] * log((1.0 - cd.y0) / cd.y0);
   double c, p;
   if (L == PORE) {
     c = cd.c0;
@@ -273,6 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
     }
     double Rc = cd.Vol * (ci - cold) / dt;
     double Rp = 0.0;
+    const bool foil = cd.half && L == CATHODE;
     const double lci = (L == PORE) ? log(ci) : 0.0;   // ln c of this voxel, shared by its pore faces
     double wc = 1.0, wp = 0.0;   // state-independent diagonal of the scaled rows (merit weights)
 #pragma unroll
@@ -312,7 +318,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
         Rc -= A * ft[d] / kFaraday;
         Rp -= A * ft[d];
       } else {
-        Rc += A * fi[d] / kFaraday;
+        if (!foil) Rc += A * fi[d] / kFaraday;   // the Li foil has no concentration equation
         Rp += A * ft[d];
         if (L == ANODE) {
           const double rs = rnf[d] * dt / (A * cd.n_c);

@@ -116,7 +116,9 @@ struct CellDev {
   double c0, x0, y0, De, kappa, tplus, thermo;
   double Ds[2], sigma[2], cmax[2], i00[2], U0[2], U1[2];
   double i00_pl, n_c, I_app, mu_ref;
-  int plating, pad2;
+  int plating;
+  int half;                          // 1: half cell, the counter-electrode slot holds a Li foil (Sec. 2.2)
+  double i00_ce;                     // Li-foil rate constant, A/m^2
   // multigrid
   int nlev, lfuse;                   // levels incl. the voxel level; coarsest = nlev-1;
                                      // levels >= lfuse run in one workgroup (k_mg_coarse_cycle)
@@ -250,6 +252,16 @@ struct Kin {
 __device__ inline Kin interface_kinetics(const CellDev& cd, int ph, double cs, double ce, double ps,
                                          double pe, double nf, bool plate, bool lin) {
   Kin k;
+  if (cd.half && ph == CATHODE) {
+    // Li-foil counter electrode (Sec. 2.2): i = 2 i00_ce sinh(F eta / 2RT),
+    // eta = Phi_foil - phi_e; no concentration dependence, no plating
+    const double sh = sinh(cd.beta * (ps - pe));
+    k.ii = 2.0 * cd.i00_ce * sh;
+    k.ip = k.p_ce = k.g_p = k.p_n = 0.0;
+    k.d_cs = k.d_ce = 0.0;
+    k.g = lin ? 2.0 * cd.i00_ce * cd.beta * sqrt(1.0 + sh * sh) : 0.0;
+    return k;
+  }
   const int s = ph - 1;
   const double cm = cd.cmax[s];
   const double xs = cs / cm;

@@ -22,7 +22,8 @@ SplitMix64 finaliser.  Uniform doubles take the top 53 bits.
 Label convention: uint8 array of shape (nz, ny, nx) in C order, so the flat
 index of voxel (i, j, k) is i + nx*(j + ny*k); k = 0 touches the anode current
 collector, k = nz-1 the cathode current collector.  0 = pore (electrolyte),
-1 = anode active material, 2 = cathode active material.
+1 = anode active material, 2 = cathode active material, 3 = Li-metal foil (the
+counter electrode of a half cell, Sec. 2.2; a cell holds 2 or 3, not both).
 """
 from __future__ import annotations
 
@@ -31,7 +32,7 @@ from dataclasses import dataclass, field, asdict
 
 import numpy as np
 
-PORE, ANODE, CATHODE = 0, 1, 2
+PORE, ANODE, CATHODE, FOIL = 0, 1, 2, 3
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -155,6 +156,105 @@ def sphere_cell(nx: int, ny: int, nz: int, seed: int, r_min: float, r_max: float
     raise RuntimeError("could not draw a cell with solid on both collector planes")
 
 
+def half_cell(nx: int, ny: int, nz: int, seed: int, r_min: float, r_max: float, porosity: float,
+              layers: tuple[int, int, int]) -> np.ndarray:
+    """Half-cell label image (Sec. 2.2): graphite slab | all-pore separator |
+    Li-foil slab, `layers` = (graphite, separator, foil) thicknesses in voxels.
+    The graphite is drawn and cleaned like a full cell's anode; the foil fills
+    its slab."""
+    if sum(layers) != nz or min(layers) < 1:
+        raise ValueError(f"layers {layers} do not split nz={nz}")
+    z_an, z_sep = layers[0], layers[0] + layers[1]
+    for attempt in range(64):
+        lab = np.zeros((nz, ny, nx), dtype=np.uint8)
+        _fill_slab(lab, 0, z_an, ANODE, porosity, r_min, r_max, Stream(seed, 2 * attempt + 1))
+        _clean_connectivity(lab, z_an, z_sep)
+        lab[z_sep:] = FOIL
+        if np.any(lab[0] == ANODE):
+            return lab
+    raise RuntimeError("could not draw a graphite slab with solid on its collector plane")
+
+
+def anode_faces(labels: np.ndarray):
+    """Anode/pore faces in canonical order (anode voxel index, then direction
+    0:-x 1:+x 2:-y 3:+y 4:-z 5:+z): (voxel index, direction, face centre in
+    voxel units (x, y, z))."""
+    nz, ny, nx = labels.shape
+    lab = labels.ravel()
+    vox, dirs, cen = [], [], []
+    steps = ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1))
+    idx = np.nonzero(lab == ANODE)[0]
+    k, r = np.divmod(idx, nx * ny)
+    j, i = np.divmod(r, nx)
+    for d, (dx, dy, dz) in enumerate(steps):
+        ii, jj, kk = i + dx, j + dy, k + dz
+        inside = (ii >= 0) & (ii < nx) & (jj >= 0) & (jj < ny) & (kk >= 0) & (kk < nz)
+        nb = np.where(inside, ii + nx * (jj + ny * kk), 0)
+        face = inside & (lab[nb] == PORE)
+        vox.append(idx[face])
+        dirs.append(np.full(int(face.sum()), d))
+        cen.append(np.stack([i[face] + 0.5 + 0.5 * dx, j[face] + 0.5 + 0.5 * dy, k[face] + 0.5 + 0.5 * dz], axis=1))
+    vox, dirs, cen = np.concatenate(vox), np.concatenate(dirs), np.concatenate(cen)
+    order = np.lexsort((dirs, vox))
+    return vox[order], dirs[order], cen[order]
+
+
+def germ_grain_plating(labels: np.ndarray, z_sep_face: int, h: float, seed: int, lam_per_m2: float = 0.01e12,
+                       r_s: float = 2.2e-6, molar_volume: float = 1.30e-5):
+    """Initial plated Li by the germ-grain model of Sec. 2.3: germs are a
+    Poisson process of intensity lam on the separator/graphite plane
+    z = z_sep_face; each germ's line towards the graphite collector meets the
+    structure at p* (the top face of the first graphite voxel below it); every
+    graphite/pore face whose centre lies within r_s of p* is plated one voxel
+    thick (h / molar_volume mol/m^2).  Returns (mask over the anode faces in
+    canonical order, plated amount, germ positions in voxel units)."""
+    nz, ny, nx = labels.shape
+    rng = Stream(seed, 7777)
+    area = nx * ny * h * h
+    # Poisson count by inversion of uniforms (product of uniforms below exp(-mean))
+    mean = lam_per_m2 * area
+    count, prod, lim = 0, 1.0, math.exp(-mean)
+    while True:
+        prod *= float(rng.uniform(1)[0])
+        if prod <= lim:
+            break
+        count += 1
+    xy = rng.uniform(2 * count).reshape(count, 2) * np.array([nx, ny]) if count else np.zeros((0, 2))
+    _, _, cen = anode_faces(labels)
+    mask = np.zeros(cen.shape[0], dtype=bool)
+    r_vox = r_s / h
+    germs = []
+    for gx, gy in xy:
+        i, j = min(int(gx), nx - 1), min(int(gy), ny - 1)
+        col = labels[:z_sep_face, j, i]
+        hit = np.nonzero(col == ANODE)[0]
+        if hit.size == 0:
+            continue
+        k = int(hit[-1])
+        p = np.array([gx, gy, k + 1.0])
+        germs.append(p)
+        mask |= np.sum((cen - p) ** 2, axis=1) <= r_vox * r_vox
+    return mask, h / molar_volume, np.array(germs).reshape(-1, 3)
+
+
+def paper_half_cell(seed: int = 3, current_density: float = -250.0, scale: int = 1) -> Workload:
+    """The paper's case study (Sec. 3.2): a 100 x 100 x 149 half cell at
+    h = 0.44 um (44 x 44 x 65.6 um), graphite 100 / separator 40 / foil 9
+    layers, spheres r in [4, 8] voxels, porosity 0.3, initial graphite
+    stoichiometry 0.8 with germ-grain plated Li, delithiated at a constant
+    current density in [2.5, 250] A/m^2 (negative: delithiation) for 60 s.
+    `scale` divides the grid and radii for oracle-sized copies."""
+    nx, nz = 100 // scale, 149 // scale
+    layers = (100 // scale, 40 // scale, nz - 100 // scale - 40 // scale)
+    lab = half_cell(nx, nx, nz, seed, 4.0 / scale, 8.0 / scale, 0.30, layers)
+    p = CellParams(x0=0.8)
+    p.I_app = current_density * nx * nx * p.h * p.h
+    w = Workload(f"half cell {nx}x{nx}x{nz}, {current_density:g} A/m^2 for 60 s", lab, p, 1.0, 60)
+    w.meta["z_sep_face"] = layers[0]
+    w.meta["current_density"] = current_density
+    return w
+
+
 # ---------------------------------------------------------------------------
 # parameter sets (SI units).  The paper prints no material table; these are the
 # synthetic defaults, shared as *inputs* by every solver.
@@ -183,6 +283,7 @@ class CellParams:
     i00_an: float = 1e-4         # A m / mol  (i = 2 i00 sqrt(cs ce) sinh(...))
     i00_ca: float = 1e-4
     i00_pl: float = 1e-2         # A m^-1/2 mol^-1/2
+    i00_ce: float = 10.0         # A/m^2, Li-foil counter electrode of a half cell (i = 2 i00_ce sinh(...))
     n_c: float = 0.48e-9 / 1.30e-5   # mol/m^2: 0.48 nm of Li metal
     U_an: tuple = (0.12, 0.03)   # U = a0 + a1 ln((1-x)/x)   [V]
     U_ca: tuple = (3.95, 0.06)
@@ -196,9 +297,12 @@ class CellParams:
 
 
 def one_c_current(labels: np.ndarray, p: CellParams) -> float:
-    """1C in amperes: the smaller electrode capacity (F c_max V_solid) per hour."""
+    """1C in amperes: the smaller electrode capacity (F c_max V_solid) per hour
+    (a half cell's Li foil is a reservoir: the graphite capacity)."""
     v = p.h ** 3
     cap_an = FARADAY_FOR_CRATE * p.cmax_an * v * np.count_nonzero(labels == ANODE)
+    if not np.any(labels == CATHODE):
+        return float(cap_an / 3600.0)
     cap_ca = FARADAY_FOR_CRATE * p.cmax_ca * v * np.count_nonzero(labels == CATHODE)
     return float(min(cap_an, cap_ca) / 3600.0)
 

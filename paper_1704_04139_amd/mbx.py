@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
                 ("U0", _d * 2), ("U1", _d * 2), ("i00_pl", _d), ("n_c", _d),
                 ("plating", _i), ("precision", _i), ("newton_tol", _d), ("res_tol", _d),
                 ("krylov_rtol", _d), ("newton_max", _i), ("krylov_max", _i), ("V_cut", _d),
-                ("graphs", _i)]
+                ("graphs", _i), ("i00_ce", _d)]
 
 
 class StepInfo(ctypes.Structure):
@@ -170,6 +170,7 @@ def make_params(cp, precision: str = "fp64", **knobs) -> Params:
     p.U0[0], p.U1[0] = cp.U_an
     p.U0[1], p.U1[1] = cp.U_ca
     p.i00_pl, p.n_c, p.plating = cp.i00_pl, cp.n_c, int(cp.plating)
+    p.i00_ce = getattr(cp, "i00_ce", 0.0)
     p.precision = MBX_MIXED if precision == "mixed" else MBX_FP64
     for k, v in knobs.items():
         setattr(p, k, v)

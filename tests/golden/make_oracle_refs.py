@@ -21,12 +21,16 @@ runs in its own process with single-threaded BLAS.  Outputs in tests/golden/:
                       count, the final state, and the smallest relative margin
                       of an estimate to the accept (tol) and doubling (tol/4)
                       thresholds it was compared with.
+  half_oracle.npz     16 x 16 x 24 copy of the paper's half cell (graphite | separator |
+                      Li foil, seed 4) with germ-grain plated Li (seed 4), delithiated
+                      at 250 A/m^2 for 4 steps of 1 s: V, inventories and the state
+                      after every step, the initial plated amounts.
   queries_oracle.npz  sampled parameter queries of the batched and served
                       workloads (own grid, C-rate, temperature and plating
                       rate), 12 steps of 5 s: V, inventories and s_ac after
                       every step, the state after steps 1 and 12.
 Run:  python tests/golden/make_oracle_refs.py [case ...]
-      (cases c0 c0adapt c1s2 c2cut q0 .. q6; default: all but c0 and c0adapt)
+      (cases c0 c0adapt half c1s2 c2cut q0 .. q6; default: all but c0, c0adapt and half)
 """
 import os
 import sys
@@ -131,6 +135,27 @@ def case_c0adapt():
     return f"c0adapt: {len(dts)} steps, {rej} rejected, smallest threshold margin {margin:.2e} tol"
 
 
+def half_workload():
+    w = I.paper_half_cell(seed=4, scale=6)
+    mask, n_plated, _ = I.germ_grain_plating(w.labels, w.meta["z_sep_face"], w.params.h, 4)
+    return w, mask, n_plated
+
+
+def case_half():
+    w, mask, n_plated = half_workload()
+    model = oracle.Model(oracle.Geometry(w.labels), w.params.as_dict())
+    u0 = model.initial_state()
+    u0[2 * model.N:][mask] = n_plated
+    steps = 4
+    model, states, infos = oracle.simulate(w.labels, w.params.as_dict(), w.dt, steps, u0=u0)
+    V, inv, sac = outputs(model, states)
+    np.savez_compressed(os.path.join(HERE, "half_oracle.npz"), labels=w.labels, I_app=w.params.I_app, dt=w.dt,
+                        plated_mask=mask, n_plated=n_plated, V=V, inv=inv, s_ac=sac,
+                        **fields(model, states, list(range(0, steps + 1))),
+                        newton_iters=np.array([i["newton_iters"] for i in infos]))
+    return f"half: {w.labels.shape} {int(mask.sum())} plated faces, V {V[0]:.6f} -> {V[-1]:.6f}"
+
+
 def case_query(k):
     family, seed = QUERIES[k]
     w = query_workload(family, seed)
@@ -143,7 +168,7 @@ def case_query(k):
     return {f"q{k}_{key}": val for key, val in out.items()}
 
 
-CASES = {"c0": case_c0, "c0adapt": case_c0adapt, "c1s2": case_c1s2, "c2cut": case_c2cut}
+CASES = {"c0": case_c0, "c0adapt": case_c0adapt, "half": case_half, "c1s2": case_c1s2, "c2cut": case_c2cut}
 
 
 def run(name):

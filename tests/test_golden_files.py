@@ -89,3 +89,20 @@ def test_c0adapt_golden():
     d = np.diff(r["inv"], axis=0)
     np.testing.assert_allclose(d[:, 2], -q, rtol=1e-7)
     np.testing.assert_allclose(d[:, 1] + d[:, 3], q, rtol=1e-7)
+
+
+def test_half_golden():
+    """The half-cell stripping run: its inputs, the germ-grain plated faces,
+    and the half cell's Li balance (the foil is a reservoir: electrolyte +
+    graphite + plated Li moves by I dt / F, the foil's inventory is fixed)."""
+    r = load("half_oracle.npz")
+    w = I.paper_half_cell(seed=4, scale=6)
+    mask, n_plated, _ = I.germ_grain_plating(w.labels, w.meta["z_sep_face"], w.params.h, 4)
+    assert np.array_equal(r["labels"], w.labels) and np.array_equal(r["plated_mask"], mask)
+    assert float(r["I_app"]) == w.params.I_app < 0          # delithiation
+    np.testing.assert_array_equal(r["n"][0][mask], n_plated)
+    inv = r["inv"]
+    q = float(r["I_app"]) * float(r["dt"]) / FARADAY
+    np.testing.assert_allclose(np.diff(inv[:, 0] + inv[:, 1] + inv[:, 3]), q, rtol=1e-9)
+    assert np.all(np.diff(inv[:, 2]) == 0)
+    assert inv[-1, 3] < inv[0, 3]                               # plated Li is stripped first

@@ -618,3 +618,126 @@ def test_adaptive_controller_limits():
     # an unreachable tolerance with dt_min = dt0 fails at the first estimate
     with pytest.raises(oracle.NewtonFailure):
         oracle.simulate_adaptive(lab, p.as_dict(), 100.0, 2.0, 2.0, 16.0, 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Half cell (Sec. 2.2): graphite against a Li-foil counter electrode (label 3)
+# with the exchange-current law 2 i00_ce sinh(F eta / 2RT), eta = Phi - phi_e,
+# conduction in the foil and no Li equation there.
+# ---------------------------------------------------------------------------
+def half_column(a, s, m):
+    lab = column(a, s, m)
+    lab[a + s:] = I.FOIL
+    return lab
+
+
+@pytest.mark.parametrize("mu", [30.0, -30.0])
+def test_half_column_voltage_closed_form(mu):
+    a, s, m = 4, 6, 5
+    lab = half_column(a, s, m)
+    h = 0.44e-6
+    prm = params(I_app=mu * h * h, plating=0, sigma_an=3.0, sigma_ca=0.7, kappa=0.2, i00_ce=2.0, x0=0.5)
+    model, states = run(lab, prm, 2.0, 3)
+    u = states[-1]
+    N = model.N
+    c, phi = u[:N], u[N:2 * N]
+    RT = GAS_R * prm["T"]
+    J = mu
+    ce = c[a:a + s]
+    drop = J * (s - 1) * h / prm["kappa"] + (1 - prm["tplus"]) * RT / FARADAY * np.log(ce[-1] / ce[0])
+    phi_an_top = J * h / (2 * prm["sigma_an"]) + (a - 1) * J * h / prm["sigma_an"]
+    cs_an = c[a - 1]
+    eta_an = 2 * RT / FARADAY * np.arcsinh(-J / (2 * prm["i00_an"] * np.sqrt(cs_an * ce[0])))
+    phi_el = phi_an_top - ocp(prm["U_an"], cs_an / prm["cmax_an"]) - eta_an + drop
+    # the foil: no open-circuit potential, no concentration factor
+    eta_ce = 2 * RT / FARADAY * np.arcsinh(J / (2 * prm["i00_ce"]))
+    V = phi_el + eta_ce + (m - 1) * J * h / prm["sigma_ca"] + J * h / (2 * prm["sigma_ca"])
+    assert model.voltage(u) == pytest.approx(V, abs=1e-12)
+    # no Li equation in the foil: its concentration unknowns keep their start value
+    np.testing.assert_array_equal(c[a + s:], prm["y0"] * prm["cmax_ca"])
+
+
+def test_half_cell_equilibrium_and_conservation():
+    lab = tiny_labels(4, 4, 10, 5)
+    lab[lab == I.CATHODE] = I.FOIL
+    lab[-1] = I.FOIL
+    prm = params(I_app=0.0)
+    model = Model(Geometry(lab), prm)
+    u0 = model.initial_state()
+    assert np.max(np.abs(model.scaled_residual(model.residual(u0, u0, 5.0), 5.0))) < 1e-12
+    u, _ = newton_step(model, u0, 5.0)
+    assert np.max(np.abs(u - u0)[:2 * model.N]) < 1e-12 * np.max(np.abs(u0))
+    # under current the foil is a Li reservoir: electrolyte + graphite + plated
+    # Li moves by exactly I dt / F per step, the foil's unknowns stay put
+    prm = params(I_app=-40.0 * 16 * (0.44e-6) ** 2, x0=0.6)   # delithiation of a lithiated graphite
+    model = Model(Geometry(lab), prm)
+    u = model.initial_state()
+    u[2 * model.N:] = 5.0 * prm["n_c"]                 # some plated metal to strip
+    tot = lambda v: v["electrolyte"] + v["anode"] + v["plated"]   # noqa: E731
+    for _ in range(3):
+        un, _ = newton_step(model, u, 2.0)
+        a, b = model.inventories(u), model.inventories(un)
+        assert tot(b) - tot(a) == pytest.approx(prm["I_app"] * 2.0 / FARADAY, rel=1e-9)
+        assert b["cathode"] == a["cathode"]
+        u = un
+
+
+def test_half_cell_jacobian_matches_finite_differences():
+    lab = tiny_labels(3, 2, 10, 6)
+    lab[lab == I.CATHODE] = I.FOIL
+    lab[-1] = I.FOIL
+    prm = params(I_app=-20.0 * 6 * (0.44e-6) ** 2, i00_ce=3.0, x0=0.6)
+    model = Model(Geometry(lab), prm)
+    rng = np.random.default_rng(6)
+    u_old = model.initial_state()
+    N = model.N
+    u = u_old.copy()
+    u[:N] *= 1.0 + 0.03 * np.clip(rng.standard_normal(N), -1.5, 1.5)
+    u[N:2 * N] += 0.02 * rng.standard_normal(N)
+    u[2 * N:] = prm["n_c"] * 2.0 * (1.0 + 0.3 * rng.random(model.g.F_pl))
+    dt = 3.0
+    J = model.jacobian(u, dt).toarray()
+    scale = np.concatenate([np.maximum(np.abs(u[:N]), 1.0) * 1e-6, np.full(N, 1e-7),
+                            np.full(model.g.F_pl, prm["n_c"] * 1e-6)])
+    Jfd = np.zeros_like(J)
+    for k in range(u.size):
+        e = np.zeros(u.size)
+        e[k] = scale[k]
+        Jfd[:, k] = (model.residual(u + e, u_old, dt) - model.residual(u - e, u_old, dt)) / (2 * scale[k])
+    rowmax = np.maximum(np.max(np.abs(J), axis=1, keepdims=True), 1e-300)
+    assert np.max(np.abs(J - Jfd) / rowmax) < 1e-6
+
+
+def test_half_cell_labels():
+    lab = half_column(3, 3, 3)
+    g = Geometry(lab)
+    assert g.half and g.top.size == 1
+    mixed = lab.copy()
+    mixed[-2] = I.CATHODE
+    with pytest.raises(ValueError):
+        Geometry(mixed)
+    touching = half_column(3, 1, 3)
+    touching[3] = I.FOIL                          # foil on the graphite
+    with pytest.raises(ValueError):
+        Geometry(touching)
+
+
+def test_germ_grain_plating_geometry():
+    """The seeded plated phase of Sec. 2.3: every plated face lies within r_s
+    of a germ's hit point p*, each p* sits on top of a graphite voxel below
+    its germ, and every graphite/pore face within r_s of a p* is plated."""
+    w = I.paper_half_cell(seed=4, scale=6)
+    lab = w.labels
+    mask, npl, germs = I.germ_grain_plating(lab, w.meta["z_sep_face"], w.params.h, 4)
+    assert npl == pytest.approx(w.params.h / 1.30e-5)
+    assert len(germs) >= 1 and mask.any()
+    vox, dirs, cen = I.anode_faces(lab)
+    assert cen.shape[0] == Geometry(lab).F_pl == mask.size
+    r = 2.2e-6 / w.params.h
+    d2 = np.min(np.sum((cen[:, None, :] - germs[None, :, :]) ** 2, axis=2), axis=1)
+    np.testing.assert_array_equal(mask, d2 <= r * r)
+    nz, ny, nx = lab.shape
+    for gx, gy, gz in germs:
+        i, j, k = int(gx), int(gy), int(gz) - 1
+        assert lab[k, j, i] == I.ANODE
+        assert np.all(lab[k + 1:w.meta["z_sep_face"], j, i] == I.PORE)
