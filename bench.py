@@ -25,7 +25,10 @@ p50/p99 latency and completed requests/s, mixed and fp64), `roofline` (the
 dominant kernel's algorithmic bytes per launch over its event-timed average
 launch duration, on the headline cell), `cpu_baseline` (the CPU oracle on a
 16x16x40 copy of the headline workload, one core), `pod` (the POD of Sec.
-2.5 by the method of snapshots on captured states and Newton stages).
+2.5 by the method of snapshots on captured states and Newton stages),
+`half_cell` (the paper's own case study, Sec. 3.2: the 100x100x149 graphite /
+Li-foil half cell with germ-grain plated Li, delithiated for 60 s under
+adaptive implicit Euler; the paper's one-core full-order time is context).
 
 --mode serve runs the serving leg alone.
 """
@@ -131,6 +134,53 @@ def run_gpu(w, precision, steps, warmup, stream, prof_steps=4, V_cut=None, to_cu
         "s_ac": mean_solid,
         "to_cutoff": cut,
     }
+
+
+PAPER_FULL_ORDER_S = 56315.0    # Sec. 3.2: 15 h 38 min 35 s, one Xeon E5-2698 v3 core, the paper's own constants
+
+
+def run_half_cell(precision, current_density, stream, t_end=60.0, tol=1e-3):
+    """The paper's case study (Sec. 3.2) at its size: the 100 x 100 x 149
+    half cell (graphite | separator | Li foil) with germ-grain plated Li,
+    delithiated at a constant current density for 60 s under adaptive
+    implicit Euler (dt0 0.25 s, dt in [1e-3, 10] s, tol 1e-3)."""
+    import torch
+    from paper_1704_04139_amd import inputs as I
+    from paper_1704_04139_amd import mbx
+    w = I.paper_half_cell(seed=3, current_density=current_density)
+    mask, n_plated, germs = I.germ_grain_plating(w.labels, w.meta["z_sep_face"], w.params.h, 3)
+    cell = mbx.Cell(w.labels, w.params, precision=precision, stream=stream)
+    c, p, n = cell.get_state()
+    n = n.copy()
+    n[mask] = n_plated
+    cell.set_state(c, p, n)
+    inv0 = cell.inventory()
+    counts = cell.counts
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        t, V, rejected, _ = cell.run_adaptive(t_end, 0.25, 1e-3, 10.0, tol)
+        status = "ok"
+    except mbx.MbxError as e:
+        t, V, rejected, status = np.zeros(0), np.zeros(0), -1, str(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    inv = cell.inventory()
+    cell.close()
+    dof = 2 * counts.n_vox
+    steps = int(t.size)
+    dts = np.diff(np.concatenate([[0.0], t])) if steps else np.zeros(0)
+    return {"workload": f"half cell 100x100x149 (graphite 100 / separator 40 / Li foil 9), germ-grain plated Li, "
+                        f"{current_density:g} A/m^2 for {t_end:g} s, adaptive implicit Euler",
+            "precision": precision, "status": status, "voxels": counts.n_vox, "dof": dof,
+            "germs": int(len(germs)), "plated_faces": int(mask.sum()), "current_density_A_m2": current_density,
+            "t_reached_s": float(t[-1]) if steps else 0.0, "steps": steps, "rejected": rejected, "wall_s": wall,
+            "dof_steps_per_s": dof * steps / wall if steps else None,
+            "dt_min_s": float(dts.min()) if steps else None, "dt_max_s": float(dts.max()) if steps else None,
+            "V_first": float(V[0]) if steps else None, "V_end": float(V[-1]) if steps else None,
+            "plated_mol": [inv0["plated"], inv["plated"]],
+            "paper_full_order_wall_s": PAPER_FULL_ORDER_S,
+            "note": "the paper's figure is its own 60 s full-order run on one CPU core with its own constants: context"}
 
 
 def state_difference(w, a, b):
@@ -389,6 +439,9 @@ def main():
                     help="requests of the closed burst that measures the server's capacity")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="offered arrival rate, requests/s")
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--half-cell-densities", default="-250",
+                    help="comma-separated current densities (A/m^2, negative: delithiation) of the paper's half-cell "
+                         "case run for 60 s ('' to skip)")
     ap.add_argument("--pod-snapshots", type=int, default=96,
                     help="snapshots per field for the POD measurement (0: skip it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -498,6 +551,14 @@ def main():
             print(f"[bench] serve {prec}: p50 {sv['p50_s']:.2f} s, p99 {sv['p99_s']:.2f} s, "
                   f"{sv['completed_per_s']:.3f} req/s", file=sys.stderr, flush=True)
         del reqs
+    dens = [float(x) for x in args.half_cell_densities.split(",") if x.strip()]
+    if dens:
+        line["half_cell"] = []
+        for mu in dens:
+            r = run_half_cell(HEADLINE_PRECISION, mu, stream)
+            line["half_cell"].append(r)
+            print(f"[bench] half cell {mu:g} A/m^2: {r['steps']} steps ({r['rejected']} rejected) to "
+                  f"{r['t_reached_s']:.1f} s in {r['wall_s']:.1f} s, {r['status']}", file=sys.stderr, flush=True)
     if args.pod_snapshots > 0:
         line["pod"] = run_pod(I.config1(), args.pod_snapshots, 3, stream, not args.no_cpu_baseline)
         print(f"[bench] pod: {line['pod']['ms_per_pod']:.2f} ms per field, Gram "

@@ -241,13 +241,16 @@ def paper_half_cell(seed: int = 3, current_density: float = -250.0, scale: int =
     """The paper's case study (Sec. 3.2): a 100 x 100 x 149 half cell at
     h = 0.44 um (44 x 44 x 65.6 um), graphite 100 / separator 40 / foil 9
     layers, spheres r in [4, 8] voxels, porosity 0.3, initial graphite
-    stoichiometry 0.8 with germ-grain plated Li, delithiated at a constant
+    stoichiometry 0.9 with germ-grain plated Li, delithiated at a constant
     current density in [2.5, 250] A/m^2 (negative: delithiation) for 60 s.
-    `scale` divides the grid and radii for oracle-sized copies."""
+    The graphite's solid diffusivity is 1e-13 m^2/s (the paper does not
+    print its material constants; with 1e-14 the particle surfaces near the
+    separator empty before 60 s at 250 A/m^2).  `scale` divides the grid
+    and radii for oracle-sized copies."""
     nx, nz = 100 // scale, 149 // scale
     layers = (100 // scale, 40 // scale, nz - 100 // scale - 40 // scale)
     lab = half_cell(nx, nx, nz, seed, 4.0 / scale, 8.0 / scale, 0.30, layers)
-    p = CellParams(x0=0.8)
+    p = CellParams(x0=0.9, Ds_an=1e-13)
     p.I_app = current_density * nx * nx * p.h * p.h
     w = Workload(f"half cell {nx}x{nx}x{nz}, {current_density:g} A/m^2 for 60 s", lab, p, 1.0, 60)
     w.meta["z_sep_face"] = layers[0]
