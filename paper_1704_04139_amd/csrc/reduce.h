@@ -43,9 +43,22 @@ __device__ inline void reduce_block(const CellDev& cd, int blk, const double (&v
 // Second pass (inside a one-block-per-cell kernel): column j of the partial
 // rows summed (or max-reduced) in block order; result valid in all threads.
 __device__ inline double finalize_column(const CellDev& cd, int j, bool mx, double* lds4, double* result) {
+  // each thread combines blocks t, t + kBlock, t + 2 kBlock, ... in that
+  // order; the loads are issued eight at a time so that they are in flight
+  // together (the additions keep their order: the same bits as one at a time)
+  constexpr int kU = 8;
+  const double* col = cd.part + (size_t)j * cd.nblk;
   double acc = 0.0;
-  for (int b = threadIdx.x; b < cd.nblk; b += kBlock) {
-    const double p = cd.part[(size_t)j * cd.nblk + b];
+  int b = threadIdx.x;
+  for (; b + (kU - 1) * kBlock < cd.nblk; b += kU * kBlock) {
+    double p[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) p[u] = col[b + u * kBlock];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc = mx ? fmax(acc, p[u]) : acc + p[u];
+  }
+  for (; b < cd.nblk; b += kBlock) {
+    const double p = col[b];
     acc = mx ? fmax(acc, p) : acc + p;
   }
   __syncthreads();
