@@ -44,9 +44,9 @@ __device__ inline void reduce_block(const CellDev& cd, int blk, const double (&v
 // rows summed (or max-reduced) in block order; result valid in all threads.
 __device__ inline double finalize_column(const CellDev& cd, int j, bool mx, double* lds4, double* result) {
   // each thread combines blocks t, t + kBlock, t + 2 kBlock, ... in that
-  // order; the loads are issued eight at a time so that they are in flight
+  // order; the loads are issued sixteen at a time so that they are in flight
   // together (the additions keep their order: the same bits as one at a time)
-  constexpr int kU = 8;
+  constexpr int kU = 16;
   const double* col = cd.part + (size_t)j * cd.nblk;
   double acc = 0.0;
   int b = threadIdx.x;
