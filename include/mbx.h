@@ -440,8 +440,10 @@ int mbx_pod_noalloc(const double *S, int64_t n, int m, int64_t lds, const double
 /* The eigen-decomposition step of mbx_pod on its own (host memory): A is a
  * symmetric m x m matrix (column-major; exactly symmetric, else
  * MBX_EINVAL), lam receives the m eigenvalues in descending order and V
- * (m x m, column-major) the eigenvectors, signed as in mbx_pod.  Cyclic
- * Jacobi rotations.  Errors: MBX_EINVAL, MBX_ENAN. */
+ * (m x m, column-major) the eigenvectors, signed as in mbx_pod.  Householder
+ * reduction to tridiagonal form, then implicit symmetric QR steps with the
+ * Wilkinson shift.  Errors: MBX_EINVAL, MBX_ENAN (non-finite entry or no
+ * convergence). */
 int mbx_sym_eig(int m, const double *A, double *lam, double *V);
 
 /* Device bytes a cell of this size would allocate (for admission control). */

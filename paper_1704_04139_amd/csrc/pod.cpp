@@ -1,12 +1,13 @@
 // pod.cpp — POD of a snapshot set by the method of snapshots (Sec. 2.5):
 // Gram matrix on the GPU (pod.hip), its eigen-decomposition on the host
-// (cyclic Jacobi), modes on the GPU.  C ABI: mbx_pod, mbx_sym_eig.
+// (Householder tridiagonalisation and implicit QR), modes on the GPU.  C ABI: mbx_pod, mbx_sym_eig.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <limits>
 #include <mutex>
 #include <vector>
 
@@ -49,63 +50,129 @@ int scratch_address(char** out) {
   return MBX_OK;
 }
 
-// Eigen-decomposition of a symmetric m x m matrix by cyclic Jacobi rotations
-// (Jacobi 1846; the rotation that zeroes a_pq is chosen with |angle| <= pi/4,
-// t = sgn(tau) / (|tau| + sqrt(1 + tau^2)), tau = (a_qq - a_pp) / (2 a_pq)).
-// A is column-major and overwritten; on return lam holds the eigenvalues in
-// descending order and V (column-major) the matching eigenvectors, each
-// signed so that its entry of largest magnitude (the first on ties) is
-// positive.  Returns false if A holds a non-finite value.
-bool jacobi_eig(int m, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V) {
+// Eigen-decomposition of a symmetric m x m matrix in two stages (Golub and
+// Van Loan, Matrix Computations, Sec. 8.3):
+//   1. Householder reduction to tridiagonal form, A = Q T Q^T: reflector k
+//      maps column k below the subdiagonal onto its first entry and is
+//      applied from both sides to the trailing block as the rank-2 update
+//      A <- A - v w^T - w v^T (w = p - (v^T p) v, p = 2 A v, |v| = 1);
+//      Q accumulates the reflectors;
+//   2. implicit symmetric QR steps with the Wilkinson shift on T: the
+//      shift's first Givens rotation creates a bulge below the subdiagonal
+//      that further rotations chase to the end of the unreduced block;
+//      subdiagonal entries below 4u (|d_i| + |d_i+1|) are set to zero.
+// Every rotation touches rows and columns k-1 .. k+2 of the banded T and
+// two columns of the eigenvector matrix Q.  O(m^3) work with a small
+// constant.  A is column-major and overwritten; on return lam holds the
+// eigenvalues in descending order and V (column-major) the matching
+// eigenvectors, each signed so that its entry of largest magnitude (the
+// first on ties) is positive.  Returns false if A holds a non-finite value
+// or the iteration does not converge.
+bool sym_eig(int m, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V) {
   auto a = [&](int i, int j) -> double& { return A[(size_t)j * m + i]; };
   for (double x : A)
     if (!std::isfinite(x)) return false;
-  std::vector<double> W((size_t)m * m, 0.0);
-  for (int i = 0; i < m; ++i) W[(size_t)i * m + i] = 1.0;
-  double fro = 0.0;
-  for (double x : A) fro += x * x;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0;
-    for (int q = 1; q < m; ++q)
-      for (int p = 0; p < q; ++p) off += a(p, q) * a(p, q);
-    if (off == 0.0 || off <= 1e-34 * fro) break;
-    for (int p = 0; p < m - 1; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        const double apq = a(p, q);
-        if (apq == 0.0) continue;
-        const double app = a(p, p), aqq = a(q, q);
-        // after a few sweeps an entry below the rounding of both diagonal
-        // entries is set to zero without a rotation
-        const double g = 100.0 * std::fabs(apq);
-        if (sweep > 3 && std::fabs(app) + g == std::fabs(app) && std::fabs(aqq) + g == std::fabs(aqq)) {
-          a(p, q) = a(q, p) = 0.0;
-          continue;
-        }
-        const double tau = (aqq - app) / (2.0 * apq);
-        double t;
-        if (std::fabs(tau) > 1e150)
-          t = 0.5 / tau;
-        else
-          t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
-        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
-        for (int r = 0; r < m; ++r) {
-          if (r == p || r == q) continue;
-          const double arp = a(r, p), arq = a(r, q);
-          const double np = c * arp - s * arq, nq = s * arp + c * arq;
-          a(r, p) = a(p, r) = np;
-          a(r, q) = a(q, r) = nq;
-        }
-        a(p, p) = app - t * apq;
-        a(q, q) = aqq + t * apq;
-        a(p, q) = a(q, p) = 0.0;
-        double* vp = &W[(size_t)p * m];
-        double* vq = &W[(size_t)q * m];
-        for (int r = 0; r < m; ++r) {
-          const double x = vp[r], y = vq[r];
-          vp[r] = c * x - s * y;
-          vq[r] = s * x + c * y;
-        }
+  std::vector<double> Q((size_t)m * m, 0.0);
+  auto q = [&](int i, int j) -> double& { return Q[(size_t)j * m + i]; };
+  for (int i = 0; i < m; ++i) q(i, i) = 1.0;
+  // ---- 1. Householder tridiagonalisation
+  std::vector<double> v(m), p(m), w(m);
+  for (int k = 0; k + 2 < m; ++k) {
+    const int n = m - k - 1;   // length of the column below the diagonal
+    double norm2 = 0.0;
+    for (int r = 0; r < n; ++r) norm2 += a(k + 1 + r, k) * a(k + 1 + r, k);
+    const double x0 = a(k + 1, k);
+    const double alpha = -(x0 >= 0.0 ? 1.0 : -1.0) * std::sqrt(norm2);
+    // v = x - alpha e1, normalised
+    for (int r = 0; r < n; ++r) v[r] = a(k + 1 + r, k);
+    v[0] -= alpha;
+    double vn = 0.0;
+    for (int r = 0; r < n; ++r) vn += v[r] * v[r];
+    if (vn == 0.0) continue;   // the column is already reduced
+    vn = std::sqrt(vn);
+    for (int r = 0; r < n; ++r) v[r] /= vn;
+    // p = 2 A_sub v, w = p - (v^T p) v: H A H = A - v w^T - w v^T
+    for (int r = 0; r < n; ++r) {
+      double acc = 0.0;
+      for (int c = 0; c < n; ++c) acc += a(k + 1 + r, k + 1 + c) * v[c];
+      p[r] = 2.0 * acc;
+    }
+    double vp = 0.0;
+    for (int r = 0; r < n; ++r) vp += v[r] * p[r];
+    for (int r = 0; r < n; ++r) w[r] = p[r] - vp * v[r];
+    for (int c = 0; c < n; ++c)
+      for (int r = 0; r < n; ++r) a(k + 1 + r, k + 1 + c) -= v[r] * w[c] + w[r] * v[c];
+    a(k + 1, k) = a(k, k + 1) = alpha;
+    for (int r = 1; r < n; ++r) a(k + 1 + r, k) = a(k, k + 1 + r) = 0.0;
+    // Q <- Q H, H = I - 2 v v^T on indices k+1 ..
+    for (int r = 0; r < m; ++r) {
+      double acc = 0.0;
+      for (int c = 0; c < n; ++c) acc += q(r, k + 1 + c) * v[c];
+      acc *= 2.0;
+      for (int c = 0; c < n; ++c) q(r, k + 1 + c) -= acc * v[c];
+    }
+  }
+  // ---- 2. implicit symmetric QR with the Wilkinson shift on the band of A
+  auto rotate = [&](int k, double c, double s) {
+    // A <- G^T A G with G acting on (k, k+1): G = [[c, s], [-s, c]]
+    const int lo = std::max(0, k - 1), hi = std::min(m - 1, k + 2);
+    for (int j = lo; j <= hi; ++j) {
+      const double x = a(k, j), y = a(k + 1, j);
+      a(k, j) = c * x - s * y;
+      a(k + 1, j) = s * x + c * y;
+    }
+    for (int i = lo; i <= hi; ++i) {
+      const double x = a(i, k), y = a(i, k + 1);
+      a(i, k) = c * x - s * y;
+      a(i, k + 1) = s * x + c * y;
+    }
+    for (int r = 0; r < m; ++r) {
+      const double x = q(r, k), y = q(r, k + 1);
+      q(r, k) = c * x - s * y;
+      q(r, k + 1) = s * x + c * y;
+    }
+  };
+  // rotation with [c s; -s c]^T [x; z] = [*; 0]
+  auto givens = [](double x, double z, double& c, double& s) {
+    if (z == 0.0) {
+      c = 1.0;
+      s = 0.0;
+    } else if (std::fabs(z) > std::fabs(x)) {
+      const double t = -x / z;
+      s = 1.0 / std::sqrt(1.0 + t * t);
+      c = s * t;
+    } else {
+      const double t = -z / x;
+      c = 1.0 / std::sqrt(1.0 + t * t);
+      s = c * t;
+    }
+  };
+  const double u4 = 4.0 * std::numeric_limits<double>::epsilon();
+  int hi = m - 1;
+  for (int iter = 0; hi > 0; ++iter) {
+    if (iter > 60 * m) return false;
+    // deflate negligible subdiagonal entries
+    for (int i = 0; i < hi; ++i)
+      if (std::fabs(a(i + 1, i)) <= u4 * (std::fabs(a(i, i)) + std::fabs(a(i + 1, i + 1))))
+        a(i + 1, i) = a(i, i + 1) = 0.0;
+    while (hi > 0 && a(hi, hi - 1) == 0.0) --hi;
+    if (hi == 0) break;
+    int lo = hi - 1;
+    while (lo > 0 && a(lo, lo - 1) != 0.0) --lo;
+    // Wilkinson shift from the trailing 2x2 block of [lo, hi]
+    const double dd = 0.5 * (a(hi - 1, hi - 1) - a(hi, hi));
+    const double e2 = a(hi, hi - 1) * a(hi, hi - 1);
+    const double mu = a(hi, hi) - e2 / (dd + (dd >= 0.0 ? 1.0 : -1.0) * std::sqrt(dd * dd + e2));
+    double x = a(lo, lo) - mu, z = a(lo + 1, lo);
+    for (int k = lo; k < hi; ++k) {
+      double c, s;
+      givens(x, z, c, s);
+      rotate(k, c, s);
+      if (k + 1 < hi) {
+        x = a(k + 1, k);
+        z = a(k + 2, k);
       }
+    }
   }
   std::vector<int> order(m);
   for (int i = 0; i < m; ++i) order[i] = i;
@@ -115,12 +182,12 @@ bool jacobi_eig(int m, std::vector<double>& A, std::vector<double>& lam, std::ve
   for (int k = 0; k < m; ++k) {
     const int src = order[k];
     lam[k] = a(src, src);
-    const double* v = &W[(size_t)src * m];
+    const double* col = &Q[(size_t)src * m];
     int big = 0;
     for (int r = 1; r < m; ++r)
-      if (std::fabs(v[r]) > std::fabs(v[big])) big = r;
-    const double sg = v[big] < 0.0 ? -1.0 : 1.0;
-    for (int r = 0; r < m; ++r) V[(size_t)k * m + r] = sg * v[r];
+      if (std::fabs(col[r]) > std::fabs(col[big])) big = r;
+    const double sg = col[big] < 0.0 ? -1.0 : 1.0;
+    for (int r = 0; r < m; ++r) V[(size_t)k * m + r] = sg * col[r];
   }
   return true;
 }
@@ -200,7 +267,7 @@ int pod_run(const double* S, int64_t n, int m, int64_t lds, const double* w, dou
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return report_error(MBX_EHIP, hipGetErrorString(e));
   std::vector<double> lam, V;
-  if (!jacobi_eig(m, K, lam, V)) return report_error(MBX_ENAN, "mbx_pod: non-finite Gram matrix");
+  if (!sym_eig(m, K, lam, V)) return report_error(MBX_ENAN, "mbx_pod: non-finite Gram matrix or no convergence");
   for (int i = 0; i < m; ++i) sigma[i] = std::sqrt(std::max(lam[i], 0.0));
   int k = 0;
   while (k < std::min(k_max, m) && sigma[k] > rtol * sigma[0] && sigma[k] > 0.0) ++k;
@@ -245,7 +312,7 @@ int mbx_sym_eig(int m, const double* A, double* lam, double* V) {
     for (int i = 0; i < j; ++i)
       if (a[(size_t)j * m + i] != a[(size_t)i * m + j])
         return report_error(MBX_EINVAL, "mbx_sym_eig: the matrix is not symmetric");
-  if (!jacobi_eig(m, a, l, v)) return report_error(MBX_ENAN, "mbx_sym_eig: non-finite entry");
+  if (!sym_eig(m, a, l, v)) return report_error(MBX_ENAN, "mbx_sym_eig: non-finite entry or no convergence");
   std::copy(l.begin(), l.end(), lam);
   std::copy(v.begin(), v.end(), V);
   return MBX_OK;

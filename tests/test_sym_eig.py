@@ -1,4 +1,5 @@
-"""Host-side eigen-decomposition of the POD (mbx_sym_eig, cyclic Jacobi):
+"""Host-side eigen-decomposition of the POD (mbx_sym_eig: Householder
+tridiagonalisation and implicit QR with the Wilkinson shift):
 checked on the CPU against LAPACK's symmetric solver, the reconstruction
 A = V diag(lam) V^T, orthonormality, repeated eigenvalues, the sign rule and
 the argument checks.  No GPU is involved."""
