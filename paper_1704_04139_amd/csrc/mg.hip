@@ -661,33 +661,45 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
   }
 }
 
-// Coarse-level (l >= 1) red-black Gauss-Seidel update of cell C; the slots
-// of one cell are relaxed in order (slot-wise Gauss-Seidel inside the cell).
+// Coarse-level (l >= 1) red-black block Gauss-Seidel update of cell C: the
+// cell's slots are solved together, D_s x_s - sum_t X_st x_t = N_s with
+// N_s = b_s + the neighbours' couplings.  Slots 1 and 2 (anode, cathode) are
+// never coupled, so eliminating x_1 and x_2 leaves
+//   x_0 = (N_0 + X_01 N_1 / D_1 + X_02 N_2 / D_2) / (D_0 - X_01^2 / D_1 - X_02^2 / D_2)
+// and then x_1, x_2 from their rows (an absent slot has D = 0 and x = 0).
+// Every cell of the colour then meets its equations exactly: after a half
+// sweep its residual is zero up to rounding.
 template <typename KT, int OP>
 __device__ inline void smooth_cell(const CellDev& cd, const LV<KT>& L, const LV<KT>& Lp, KT alpha, int C, const C3& q,
                                    int mode, int need) {
   CoarseRow<KT> R;
   gather_coarse<KT, OP>(L, Lp, alpha, C, q, mode, R);
+  KT D[3], Nb[3];
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
-    KT D = R.E[s], S = R.b[s];
+    KT d = R.E[s], nb = R.b[s];
 #pragma unroll
     for (int t = 0; t < 3; ++t)
-      if (t != s) {
-        const KT g = R.X[xidx(s, t)];
-        D += g;
-        S += g * R.xo[t];
-      }
+      if (t != s) d += R.X[xidx(s, t)];
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir)
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const KT gp = R.Gp[dir][s * 3 + t], gm = R.Gm[dir][t * 3 + s];
-        D += gp + gm;
-        S += gp * R.xn[2 * dir][t] + gm * R.xn[2 * dir + 1][t];
+        d += gp + gm;
+        nb += gp * R.xn[2 * dir][t] + gm * R.xn[2 * dir + 1][t];
       }
-    R.xo[s] = D > (KT)0 ? S / D : (KT)0;
+    D[s] = d;
+    Nb[s] = nb;
   }
+  const KT x01 = R.X[xidx(0, 1)], x02 = R.X[xidx(0, 2)];
+  const bool h1 = D[1] > (KT)0, h2 = D[2] > (KT)0;
+  const KT i1 = h1 ? (KT)1 / D[1] : (KT)0, i2 = h2 ? (KT)1 / D[2] : (KT)0;
+  const KT d0 = D[0] - x01 * x01 * i1 - x02 * x02 * i2;
+  const KT r0 = Nb[0] + x01 * Nb[1] * i1 + x02 * Nb[2] * i2;
+  R.xo[0] = (D[0] > (KT)0 && d0 > (KT)0) ? r0 / d0 : (KT)0;
+  R.xo[1] = h1 ? (Nb[1] + x01 * R.xo[0]) * i1 : (KT)0;
+  R.xo[2] = h2 ? (Nb[2] + x02 * R.xo[0]) * i2 : (KT)0;
   if (!gate_state(cd, need)) return;
   KT* x = L.x;
 #pragma unroll
@@ -743,7 +755,9 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
   if (live) {
     const C3 q = c3_of(P, Lp.nx, Lp.ny);
     const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
-    if (cx < L.nx && cy < L.ny && cz < L.nz)
+    // the last pre-smoothing half sweep solved every black cell exactly for
+    // the current red values: only red cells carry a residual
+    if (cx < L.nx && cy < L.ny && cz < L.nz && ((cx + cy + cz) & 1) == 0)
       residual_cell<KT, OP>(view<KT>(L, OP), lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
@@ -820,7 +834,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
       KT acc[3] = {0, 0, 0};
       for (int ch = 0; ch < 8; ++ch) {
         const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
-        if (cx >= L.nx || cy >= L.ny || cz >= L.nz) continue;
+        if (cx >= L.nx || cy >= L.ny || cz >= L.nz || ((cx + cy + cz) & 1)) continue;   // black: solved exactly
         KT r[3];
         residual_cell<KT, OP>(L, cx + L.nx * (cy + L.ny * cz), C3{cx, cy, cz}, r);
         for (int s = 0; s < 3; ++s) acc[s] += r[s];
