@@ -271,6 +271,7 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   L.add(kt * Np);                                                      // 45 + 7(n-1): level-0 iterate, colour-split
   L.add(8 * (size_t)N);                                                // 46 + 7(n-1): c at the step before u^n (adaptive runs)
   L.add(8 * (size_t)std::max(F_an, 1));                                // 47 + 7(n-1): n at the step before u^n
+  L.add(kt * (size_t)std::max(2 * (F_an + F_ca), 1));                  // 48 + 7(n-1): cond_rb
   return L;
 }
 
@@ -1208,13 +1209,17 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   hipStream_t s = (hipStream_t)stream;
 
   // ---- phase 1: labels -> masks, face counts, prefix sums (device)
-  size_t scan_bytes = 0;
-  if (exclusive_scan(nullptr, scan_bytes, nullptr, nullptr, N, s) != hipSuccess)
+  const int Np = 2 * ((nx + 1) / 2) * ny * nz;   // colour-split slots (padding included)
+  size_t scan_bytes = 0, scan_bytes_rb = 0;
+  if (exclusive_scan(nullptr, scan_bytes, nullptr, nullptr, N, s) != hipSuccess ||
+      exclusive_scan(nullptr, scan_bytes_rb, nullptr, nullptr, Np, s) != hipSuccess)
     return fail(MBX_EHIP, "scan size query failed");
+  scan_bytes = std::max(scan_bytes, scan_bytes_rb);
   Layout T;
   const size_t o_lab = T.add(N), o_meta = T.add(4 * (size_t)N), o_ca = T.add(4 * (size_t)N),
                o_cc = T.add(4 * (size_t)N), o_oa = T.add(4 * (size_t)N), o_oc = T.add(4 * (size_t)N),
-               o_fl = T.add(64), o_scan = T.add(scan_bytes);
+               o_fl = T.add(64), o_scan = T.add(scan_bytes), o_rbc = T.add(4 * (size_t)Np),
+               o_rbo = T.add(4 * (size_t)Np);
   char* tmp = nullptr;
   if (hipMalloc(&tmp, T.total) != hipSuccess) return fail(MBX_ENOMEM, "device allocation of %zu bytes failed", T.total);
   auto cleanup_tmp = [&]() { (void)hipFree(tmp); };
@@ -1265,9 +1270,15 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
     return fail(MBX_EINVAL, "a half cell (Li foil voxels) needs i00_ce > 0");
   }
   const int F_an = tail[0] + tail[1], F_ca = tail[2] + tail[3];
-  if (F_an >= (1 << 24) || F_ca >= (1 << 24)) {
+  if (F_an + F_ca >= (1 << 24)) {
     cleanup_tmp();
     return fail(MBX_EINVAL, "too many interface faces for the 24-bit face index");
+  }
+  // arrays the level-0 smoother reads through 32-bit buffer offsets (largest: the
+  // colour-split iterate, 8 bytes per slot in FP64)
+  if (8 * (size_t)Np >= (size_t)kNoOff - 4096) {
+    cleanup_tmp();
+    return fail(MBX_EINVAL, "grid too large for the 32-bit offsets of the level-0 smoother");
   }
 
   // ---- phase 2: the cell's memory
@@ -1398,6 +1409,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.x_rb = b + L.off[45 + 7 * (c->ld.n - 1)];
   h.c_prev = (double*)(b + L.off[46 + 7 * (c->ld.n - 1)]);
   h.n_prev = (double*)(b + L.off[47 + 7 * (c->ld.n - 1)]);
+  h.cond_rb = b + L.off[48 + 7 * (c->ld.n - 1)];
   h.faces_an = c->faces_an;
   h.faces_ca = c->faces_ca;
   c->lvlh_nblk[0] = (int)((half_cells(c->ld, 0) + kBlock - 1) / kBlock);
@@ -1416,8 +1428,18 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   if (e == hipSuccess) {
     launch_finish_meta(N, (uint32_t*)h.meta, (const int*)(tmp + o_oa), (const int*)(tmp + o_oc), c->faces_an,
                        c->faces_ca, s);
-    launch_meta_rb(h, s);
+    launch_meta_rb(h, (int*)(tmp + o_rbc), s);
+    size_t sb = scan_bytes;
+    e = exclusive_scan(tmp + o_scan, sb, (const int*)(tmp + o_rbc), (int*)(tmp + o_rbo), Np, s);
+    if (e == hipSuccess) launch_meta_rb_base(h, (const int*)(tmp + o_rbo), s);
   }
+  // every face joins a voxel of each colour: each colour's lists hold F_an + F_ca entries
+  int rbt[3] = {0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(&rbt[0], tmp + o_rbo + 4 * (size_t)h.rbH, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&rbt[1], tmp + o_rbo + 4 * (size_t)(Np - 1), 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&rbt[2], tmp + o_rbc + 4 * (size_t)(Np - 1), 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const bool lists_ok = rbt[0] == F_an + F_ca && rbt[1] + rbt[2] == 2 * (F_an + F_ca);
   if (e == hipSuccess) e = hipMemsetAsync(h.ictl, 0, 4 * CTL_NSLOT, s);
   if (e == hipSuccess) e = hipMemsetAsync(h.red, 0, 8 * RED_NSLOT, s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->d_blk, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice, s);
@@ -1437,6 +1459,9 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   cleanup_tmp();
   if (e != hipSuccess) {
     rc = fail(MBX_EHIP, "cell setup: %s", hipGetErrorString(e));
+  } else if (!lists_ok) {
+    rc = fail(MBX_EHIP, "colour-split face lists hold %d + %d entries for %d faces", rbt[0],
+              rbt[1] + rbt[2] - rbt[0], F_an + F_ca);
   } else {
     Batch bt = single(c);
     rc = bt.upload();

@@ -92,12 +92,29 @@ __global__ void __launch_bounds__(kBlock) k_finish_meta(int N, uint32_t* __restr
 }
 
 // Colour-split copy of the meta words (padding slots of odd nx stay zero
-// and are never read: no voxel has them as a neighbour).
-__global__ void __launch_bounds__(kBlock) k_meta_rb(CellDev cd) {
+// and are never read: no voxel has them as a neighbour), label and mask
+// only; cnt gets each slot's interface-face count for the base scan.
+__global__ void __launch_bounds__(kBlock) k_meta_rb(CellDev cd, int* __restrict__ cnt) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= cd.N) return;
   const VoxCoord v = coord_of(cd, i);
-  ((uint32_t*)cd.meta_rb)[rb_index(cd, v.x, v.y, v.z)] = cd.meta[i];
+  const uint32_t m = cd.meta[i];
+  const int p = rb_index(cd, v.x, v.y, v.z);
+  ((uint32_t*)cd.meta_rb)[p] = m & 0xFFu;
+  cnt[p] = __popc(mask_of(m));
+}
+
+// Face-base field of the colour-split meta words: the start of the slot's
+// list in its colour's part of cond_rb (off = exclusive scan of the counts
+// over both colours; colour 1's part starts at off[rbH]).
+__global__ void __launch_bounds__(kBlock) k_meta_rb_base(CellDev cd, const int* __restrict__ off) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= 2 * cd.rbH) return;
+  uint32_t* mrb = (uint32_t*)cd.meta_rb;
+  const uint32_t m = mrb[p];
+  if (!mask_of(m)) return;
+  const int base = off[p] - (p >= cd.rbH ? off[cd.rbH] : 0);
+  mrb[p] = m | ((uint32_t)base << 8);
 }
 
 // Zero-current equilibrium (every interface current vanishes; the plated
@@ -1096,9 +1113,14 @@ void launch_finish_meta(int N, uint32_t* meta, const int* off_an, const int* off
 hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* out, int n, hipStream_t s) {
   return rocprim::exclusive_scan(temp, temp_bytes, in, out, 0, (size_t)n, rocprim::plus<int>(), s);
 }
-void launch_meta_rb(const CellDev& cd, hipStream_t s) {
+void launch_meta_rb(const CellDev& cd, int* cnt, hipStream_t s) {
   (void)hipMemsetAsync((void*)cd.meta_rb, 0, 8 * (size_t)cd.rbH, s);
-  k_meta_rb<<<(cd.N + kBlock - 1) / kBlock, kBlock, 0, s>>>(cd);
+  (void)hipMemsetAsync(cnt, 0, 8 * (size_t)cd.rbH, s);
+  k_meta_rb<<<(cd.N + kBlock - 1) / kBlock, kBlock, 0, s>>>(cd, cnt);
+}
+
+void launch_meta_rb_base(const CellDev& cd, const int* off, hipStream_t s) {
+  k_meta_rb_base<<<(2 * cd.rbH + kBlock - 1) / kBlock, kBlock, 0, s>>>(cd, off);
 }
 void launch_init_state(const BatchLaunch& b, hipStream_t s) {
   k_init_state<<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk);

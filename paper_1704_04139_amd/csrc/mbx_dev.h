@@ -129,10 +129,14 @@ struct CellDev {
   // half sweep reads and writes whole cache lines of one colour.
   int rbhx, rbH;
   double inv_nx, inv_ny, inv_rbhx;  // reciprocals for the index arithmetic (divmod)
-  const uint32_t* meta_rb;           // meta words in colour-split order
+  const uint32_t* meta_rb;           // meta words in colour-split order; the face-base field (bits 8-31)
+                                     // holds the start of the voxel's list in its colour's part of cond_rb
   void *x_rb;                        // KT [2 rbH] level-0 iterate of the V-cycle being run
   void *b0;                          // KT [2 rbH] right-hand side of a level-0 solve (colour-split)
   void *cond_an, *cond_ca;           // KT potential-operator conductance per interface face
+  void *cond_rb;                     // KT [2 (F_an + F_ca)]: the same conductances listed per voxel in
+                                     // colour-split order (each face once from each side; colour c's
+                                     // lists start at c (F_an + F_ca)); cathode faces stored negated
   double *cinv[2];                   // coarsest-level dense inverses (FP64), (3*ncell)^2 each
   double alpha;                      // coarse-correction scale
   int nu, nu_f;                      // smoothing sweeps (red+black pairs) per side: launched levels / fused levels
@@ -163,13 +167,9 @@ struct VoxCoord {
 __device__ inline int divmod(int n, int d, double inv, int& r) {
   int q = (int)((double)n * inv);
   r = n - q * d;
-  if (r >= d) {
-    ++q;
-    r -= d;
-  } else if (r < 0) {
-    --q;
-    r += d;
-  }
+  const bool hi = r >= d, lo = r < 0;   // selects, not branches
+  q += hi ? 1 : (lo ? -1 : 0);
+  r += hi ? -d : (lo ? d : 0);
   return q;
 }
 __device__ inline VoxCoord coord_of(const CellDev& cd, int i) {
@@ -177,6 +177,42 @@ __device__ inline VoxCoord coord_of(const CellDev& cd, int i) {
   const int t = divmod(i, cd.nx, cd.inv_nx, v.x);
   v.z = divmod(t, cd.ny, cd.inv_ny, v.y);
   return v;
+}
+
+// Raw buffer loads: the array's base and size sit in a scalar descriptor and
+// each lane supplies a 32-bit byte offset, so an indexed load needs no 64-bit
+// address arithmetic.  The buffer unit checks every offset against the size:
+// a load at or past the end returns zero without touching memory, so an
+// absent neighbour is read at kNoOff instead of being selected away.  Arrays
+// read this way hold fewer than kNoOff - 4096 bytes (checked at cell
+// creation), so kNoOff plus any immediate offset stays out of range.
+constexpr uint32_t kNoOff = 0x80000000u;
+using BufRes = __amdgpu_buffer_rsrc_t;
+__device__ inline BufRes buf_of(const void* p, uint32_t bytes) {
+  // descriptor word 3 = 0x00020000: 32-bit data format, which raw (untyped)
+  // loads and the range check use on this architecture family
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ inline T buf_ld(BufRes r, uint32_t off);
+template <>
+__device__ inline float buf_ld<float>(BufRes r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ inline double buf_ld<double>(BufRes r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ inline uint32_t buf_ld<uint32_t>(BufRes r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ inline void buf_st(BufRes r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+__device__ inline void buf_st(BufRes r, uint32_t off, double v) {
+  typedef uint32_t u32x2 __attribute__((__vector_size__(8)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
 
 // Colour-split index of voxel (x, y, z) (see CellDev::rbhx).

@@ -43,8 +43,11 @@ void launch_build_meta(const uint8_t* lab, int nx, int ny, int nz, uint32_t* met
 void launch_finish_meta(int N, uint32_t* meta, const int* off_an, const int* off_ca, int* faces_an, int* faces_ca,
                         hipStream_t s);
 void launch_init_state(const BatchLaunch& b, hipStream_t s);
-// colour-split copy of the finished meta words (cd: host copy of the descriptor, device pointers)
-void launch_meta_rb(const CellDev& cd, hipStream_t s);
+// colour-split copy of the finished meta words (cd: host copy of the descriptor, device pointers);
+// cnt (2 rbH ints) receives each slot's interface-face count
+void launch_meta_rb(const CellDev& cd, int* cnt, hipStream_t s);
+// face-base fields of the colour-split meta words from off = exclusive scan of cnt
+void launch_meta_rb_base(const CellDev& cd, const int* off, hipStream_t s);
 // rocPRIM exclusive prefix sum of n ints (temp == nullptr: query temp_bytes)
 hipError_t exclusive_scan(void* temp, size_t& temp_bytes, const int* in, int* out, int n, hipStream_t s);
 

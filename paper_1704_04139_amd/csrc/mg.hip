@@ -182,92 +182,94 @@ __device__ inline void neighbours6(int c, const C3& q, int nx, int ny, int nz, i
   nb[4] = ex[4] ? c + sz : c; nb[5] = ex[5] ? c - sz : c;
 }
 
-// Colour-split indices of the six neighbours (+x, -x, +y, -y, +z, -z) of
-// voxel c at colour-split index p (absent neighbours: p itself, flagged false).
-__device__ inline void neighbours6_rb(const CellDev& cd, int p, const C3& c, int (&nb)[6], bool (&ex)[6]) {
-  const int base = (1 - ((c.x + c.y + c.z) & 1)) * cd.rbH;
+// Row of the level-0 operator OP at voxel c (colour-split index p, colour
+// `color`): diagonal D (extra term plus all couplings) and
+// S = sum_k g_ik x_k over the neighbours (x_k read from the colour-split
+// iterate xsrc, plus alpha times the level-1 solution of k's slot when corr).
+// The voxel's own interface mask tells same-phase neighbours from interface
+// ones (anode and cathode never touch); the potential operator's interface
+// conductances come from the voxel's own list in cond_rb, whose sign also
+// gives a pore voxel its solid neighbour's phase.  Every load is a buffer
+// load issued before any arithmetic depends on it; absent neighbours and
+// faces the voxel does not have are read at kNoOff (zero).
+template <typename KT, int OP>
+__device__ inline void voxel_row(const CellDev& cd, int color, int p, const C3& c, uint32_t mi,
+                                 const KT* __restrict__ xsrc, bool zero, bool corr, KT& D, KT& S) {
+  constexpr uint32_t kt = sizeof(KT);
+  // colour-split neighbours (+x, -x, +y, -y, +z, -z): the other colour, at
+  // q0 = the slot of (x, y, z) in that colour's rows
   const int row = c.y + cd.ny * c.z, hx = cd.rbhx;
+  const int q0 = (1 - color) * cd.rbH + row * hx + (c.x >> 1);
+  const int odd = c.x & 1;
+  bool ex[6];
   ex[0] = c.x + 1 < cd.nx; ex[1] = c.x > 0;
   ex[2] = c.y + 1 < cd.ny; ex[3] = c.y > 0;
   ex[4] = c.z + 1 < cd.nz; ex[5] = c.z > 0;
-  nb[0] = ex[0] ? base + row * hx + ((c.x + 1) >> 1) : p;
-  nb[1] = ex[1] ? base + row * hx + ((c.x - 1) >> 1) : p;
-  nb[2] = ex[2] ? base + (row + 1) * hx + (c.x >> 1) : p;
-  nb[3] = ex[3] ? base + (row - 1) * hx + (c.x >> 1) : p;
-  nb[4] = ex[4] ? base + (row + cd.ny) * hx + (c.x >> 1) : p;
-  nb[5] = ex[5] ? base + (row - cd.ny) * hx + (c.x >> 1) : p;
-}
-
-// Row of the level-0 operator OP at voxel c (colour-split index p):
-// diagonal D (extra term plus all couplings) and S = sum_k g_ik x_k over the
-// neighbours (x_k read from the colour-split iterate xsrc, plus alpha times
-// the level-1 solution of k's slot when corr).  The voxel's own interface
-// mask tells same-phase neighbours from interface ones (anode and cathode
-// never touch); only a pore voxel's interface faces need the solid
-// neighbour's meta word (its face records and phase).  All loads are issued
-// before any arithmetic depends on them.
-template <typename KT, int OP>
-__device__ inline void voxel_row(const CellDev& cd, int p, const C3& c, uint32_t mi, const KT* __restrict__ xsrc,
-                                 bool zero, bool corr, KT& D, KT& S) {
-  int k[6];
-  bool ex[6];
-  neighbours6_rb(cd, p, c, k, ex);
+  const int kq[6] = {q0 + odd, q0 + odd - 1, q0 + hx, q0 - hx, q0 + cd.ny * hx, q0 - cd.ny * hx};
   const int dmap[6] = {1, 0, 3, 2, 5, 4};   // neighbour slot -> face direction (0:-x 1:+x ...)
   const int L = lab_of(mi);
   const bool pore = L == PORE;
   const uint32_t msk = mask_of(mi);
   bool ifc[6];
-  uint32_t mk[6];
-  KT xk[6];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    ifc[j] = (msk >> dmap[j]) & 1u;   // set only for existing neighbours
-    mk[j] = (OP != 0 && pore && ifc[j]) ? cd.meta_rb[k[j]] : 0u;
-  }
+  for (int j = 0; j < 6; ++j) ifc[j] = (msk >> dmap[j]) & 1u;   // set only for existing neighbours
+  KT xk[6], gf[6];
   if (!zero) {
-    // absent neighbours read voxel p itself, which may not be written yet in
-    // this sweep: select zero (a product with a zero coupling would keep NaN)
+    const BufRes rx = buf_of(xsrc, 2u * (uint32_t)cd.rbH * kt);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) xk[j] = buf_ld<KT>(rx, ex[j] ? (uint32_t)kq[j] * kt : kNoOff);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) xk[j] = (KT)0;
+  }
+  if (OP != 0) {
+    const uint32_t F = (uint32_t)(cd.F_an + cd.F_ca);
+    const BufRes rc = buf_of((const KT*)cd.cond_rb + (size_t)color * F, F * kt);
+    const uint32_t fb = base_of(mi);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      const KT v = xsrc[k[j]];
-      xk[j] = ex[j] ? v : (KT)0;
+      const uint32_t r = (uint32_t)__popc(msk & ((1u << dmap[j]) - 1u));
+      gf[j] = buf_ld<KT>(rc, ifc[j] ? (fb + r) * kt : kNoOff);
     }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) gf[j] = (KT)0;
+  }
+  // interface part of the concentration diagonal (per voxel, from the setup)
+  const KT dint = OP == 0 ? buf_ld<KT>(buf_of(cd.dint, 2u * (uint32_t)cd.rbH * kt), (uint32_t)p * kt) : (KT)0;
+  // same-phase coupling (the per-cell constants converted before the select)
+  KT gsame;
+  if (OP == 0) {
+    const KT gp = (KT)cd.Dh, ga = (KT)cd.Dsh[0], gc = (KT)cd.Dsh[1];
+    gsame = pore ? gp : (L == CATHODE ? gc : ga);
+  } else {
+    const KT gp = (KT)cd.Gk, ga = (KT)cd.Gs[0], gc = (KT)cd.Gs[1];
+    gsame = pore ? gp : (L == CATHODE ? gc : ga);
   }
   KT g[6];
-  // interface part of the concentration diagonal (per voxel, from the setup)
-  const KT dint = OP == 0 ? ((const KT*)cd.dint)[p] : (KT)0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const int d = dmap[j];
-    KT v;
-    if (OP == 0) {
-      v = ifc[j] ? (KT)0 : (KT)(pore ? cd.Dh : cd.Dsh[L == CATHODE]);
-    } else {
-      const uint32_t f = ifc[j] ? face_rank(pore ? mk[j] : mi, pore ? (d ^ 1) : d) : 0u;
-      const int Ls = pore ? lab_of(mk[j]) : L;
-      const KT* arr = (const KT*)(Ls == CATHODE ? cd.cond_ca : cd.cond_an);
-      const KT gi = arr[f];
-      v = ifc[j] ? gi : (KT)(pore ? cd.Gk : cd.Gs[L == CATHODE]);
-    }
+    const KT v = ifc[j] ? (OP == 0 ? (KT)0 : (KT)fabs(gf[j])) : gsame;
     g[j] = ex[j] ? v : (KT)0;
   }
   if (corr) {
     const MGLevel& L1 = cd.lv[1];
     const KT alpha = (KT)cd.alpha;
+    const BufRes r1 = buf_of(L1.x, 3u * (uint32_t)L1.ncell * kt);
     const int px = c.x >> 1, py = c.y >> 1, pz = c.z >> 1;
     const int pq[6] = {((c.x + 1) >> 1) - px, ((c.x - 1) >> 1) - px, ((c.y + 1) >> 1) - py,
                        ((c.y - 1) >> 1) - py, ((c.z + 1) >> 1) - pz, ((c.z - 1) >> 1) - pz};
     const int pc = px + L1.nx * (py + L1.ny * pz);
     const int pst[6] = {1, 1, L1.nx, L1.nx, L1.nx * L1.ny, L1.nx * L1.ny};
-    const KT* x1 = (const KT*)L1.x;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       // the neighbour's phase slot (an interface neighbour of the
       // concentration operator has a zero coupling: its own slot serves)
-      const int slot = (OP != 0 && ifc[j]) ? (pore ? lab_of(mk[j]) : PORE) : L;
-      const int pcj = ex[j] ? pc + pq[j] * pst[j] : pc;
-      const KT v = x1[(size_t)slot * L1.ncell + pcj];
-      xk[j] += ex[j] ? alpha * v : (KT)0;
+      const int ns = pore ? (__builtin_signbit(gf[j]) ? CATHODE : ANODE) : PORE;
+      const int slot = (OP != 0 && ifc[j]) ? ns : L;
+      const uint32_t off = (uint32_t)(slot * L1.ncell + pc + pq[j] * pst[j]) * kt;
+      const KT cv = alpha * buf_ld<KT>(r1, ex[j] ? off : kNoOff);   // rounded before the sum (no fused form)
+      xk[j] += cv;
     }
   }
   D = OP == 0 ? (KT)1 + dint : ((L == ANODE && c.z == 0) ? (KT)cd.Gcol : (KT)0);
@@ -380,6 +382,43 @@ __device__ inline void gather_coarse(const LV<KT>& L, const LV<KT>& Lp, KT alpha
 }  // namespace
 
 // ---------------------------------------------------------------- assembly
+// The potential operator's interface conductances in the order the level-0
+// smoother reads them (cond_rb): voxel i's interface faces in direction
+// order at the start of its list, from whichever side i is on, negated for
+// cathode (or foil) faces.  One thread per voxel; run after every
+// linearisation, which rewrites cond_an and cond_ca.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_cond_rb(CellDev* cells, const int2* __restrict__ blk) {
+  const int2 bb = block_of(blk);
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const uint32_t mi = cd.meta[i];
+  const uint32_t msk = mask_of(mi);
+  if (!msk) return;
+  const C3 c = c3_of(i, cd.nx, cd.ny);
+  const int color = (c.x + c.y + c.z) & 1;
+  KT* out = (KT*)cd.cond_rb + (size_t)color * (cd.F_an + cd.F_ca) + base_of(cd.meta_rb[rb_index(cd, c.x, c.y, c.z)]);
+  const int L = lab_of(mi);
+  int r = 0;
+  for (int d = 0; d < 6; ++d) {
+    if (!((msk >> d) & 1u)) continue;
+    int Ls = L;
+    uint32_t f;
+    if (L == PORE) {   // the face record sits with the solid neighbour (the mask marks existing neighbours only)
+      const int k = fine_nbr(i, c, cd.nx, cd.ny, cd.nz, d);
+      const uint32_t mk = cd.meta[k >= 0 ? k : i];
+      Ls = lab_of(mk);
+      f = face_rank(mk, d ^ 1);
+    } else {
+      f = face_rank(mi, d);
+    }
+    const KT g = Ls == CATHODE ? ((const KT*)cd.cond_ca)[f] : ((const KT*)cd.cond_an)[f];
+    out[r++] = Ls == CATHODE ? -g : g;
+  }
+}
+
 // Level-1 operator from the voxel level: extras summed per slot; faces inside
 // the cell between different slots -> X; faces to the +dir neighbour cell -> G.
 template <typename KT>
@@ -597,12 +636,14 @@ __global__ void __launch_bounds__(BS) k_mg0_smooth(CellDev* cells, const int2* _
   if (!color_cell(t, color, cd.lv[0], c)) return;
   const int p = color * cd.rbH + t;
   KT* x0 = (KT*)cd.x_rb;
-  const KT bi = ((const KT*)cd.b0)[p];
+  const uint32_t nrb = 2u * (uint32_t)cd.rbH;
+  const uint32_t mi = buf_ld<uint32_t>(buf_of(cd.meta_rb, nrb * 4u), (uint32_t)p * 4u);
+  const KT bi = buf_ld<KT>(buf_of(cd.b0, nrb * (uint32_t)sizeof(KT)), (uint32_t)p * (uint32_t)sizeof(KT));
   KT D, S;
-  voxel_row<KT, OP>(cd, p, c, cd.meta_rb[p], x0, mode == SM_ZERO, mode == SM_CORR, D, S);
+  voxel_row<KT, OP>(cd, color, p, c, mi, x0, mode == SM_ZERO, mode == SM_CORR, D, S);
   if (!gate_state(cd, need)) return;
   const KT xn = D > (KT)0 ? (bi + S) / D : (KT)0;
-  x0[p] = xn;
+  buf_st(buf_of(x0, nrb * (uint32_t)sizeof(KT)), (uint32_t)p * (uint32_t)sizeof(KT), xn);
   if (post && it == cd.nu - 1) ((KT*)cd.z)[(size_t)OP * cd.N + c.x + cd.nx * (c.y + cd.ny * c.z)] = xn;
 }
 
@@ -645,7 +686,7 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
       const uint32_t mi = cd.meta_rb[p];
       const KT xi = x0[p], bi = ((const KT*)cd.b0)[p];
       KT D, S;
-      voxel_row<KT, OP>(cd, p, fc, mi, x0, false, false, D, S);
+      voxel_row<KT, OP>(cd, 0, p, fc, mi, x0, false, false, D, S);
       const int L = lab_of(mi);
       const KT r = bi + S - D * xi;
       rs[0] = L == 0 ? r : (KT)0;
@@ -961,6 +1002,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* _
 // launch of zero workgroups is a configuration error.
 template <typename KT>
 void launch_mg_setup(const BatchLaunch& b, hipStream_t s) {
+  k_cond_rb<KT><<<b.nblk, kBlock, 0, s>>>(b.cells, b.blk);
   for (int op = 0; op < 2; ++op) {
     if (b.lvl_nblk[1] > 0) k_mg_assemble0<KT><<<b.lvl_nblk[1], kBlock, 0, s>>>(b.cells, b.lvl_blk[1], op);
     for (int l = 1; l + 1 < b.maxlev; ++l)
