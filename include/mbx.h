@@ -132,9 +132,9 @@ int mbx_params_default(mbx_params *p);
  * phi_cathode = U_ca(y0) - U_an(x0) (a half cell's foil: -U_an(x0)),
  * n_f = n_c (f/(1-f))^(1/4) with f = exp(-F U_an(x0)/RT), which makes every
  * interface current vanish.
- * Size limits: nz >= 2, nx*ny*nz <= 2^28 voxels and below 2^31 bytes for the
- * colour-split iterate (8 bytes per voxel in FP64), fewer than 2^24 interface
- * faces (anode plus cathode).
+ * Size limits: nz >= 2, nx*ny*nz below 2^27 voxels (the kernels address
+ * the FP64 GMRES iterate, 16 bytes per voxel, with 32-bit byte offsets), fewer
+ * than 2^24 interface faces (anode plus cathode).
  * Errors: MBX_EINVAL (bad sizes/parameters), MBX_ELABEL, MBX_ENOMEM, MBX_EHIP. */
 int mbx_cell_create(const uint8_t *labels, int nx, int ny, int nz,
                     const mbx_params *p, void *stream, mbx_cell **out);

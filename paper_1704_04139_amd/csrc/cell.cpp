@@ -185,8 +185,8 @@ struct mbx_cell {
   LevelDims ld;
   int2* lvl_blk[kMaxLevels] = {};
   int lvl_nblk[kMaxLevels] = {};
-  int2* lvl8_blk[kMaxLevels] = {};
-  int lvl8_nblk[kMaxLevels] = {};
+  int2* lvlr_blk[kMaxLevels] = {};
+  int lvlr_nblk[kMaxLevels] = {};
   int2* lvlh_blk[kMaxLevels] = {};   // one colour of a red-black sweep (index >= 0)
   int lvlh_nblk[kMaxLevels] = {};
   // snapshot capture (caller-owned device columns)
@@ -254,14 +254,14 @@ Layout make_layout(int N, int F_an, int F_ca, int nblk, int m, size_t kt, const 
   const int nc = ld.ncell[ld.n - 1];
   L.add(8 * (size_t)9 * nc * nc);             // 39 cinv[0]
   L.add(8 * (size_t)9 * nc * nc);             // 40 cinv[1]
-  for (int l = 1; l < ld.n; ++l) {            // 41 + 7(l-1): x, b, op0, op1, blk, blk8, blkh
+  for (int l = 1; l < ld.n; ++l) {            // 41 + 7(l-1): x, b, op0, op1, blk, blkr, blkh
     const size_t n = ld.ncell[l];
     L.add(3 * n * kt);
     L.add(3 * n * kt);
     L.add(kOpStride * n * kt);
     L.add(kOpStride * n * kt);
     L.add(sizeof(int2) * ((n + kBlock - 1) / kBlock));
-    L.add(sizeof(int2) * ((8 * n + kBlock - 1) / kBlock));
+    L.add(sizeof(int2) * ((4 * n + kBlock - 1) / kBlock));
     L.add(sizeof(int2) * ((half_cells(ld, l) + kBlock - 1) / kBlock));
   }
   L.add(sizeof(int2) * ((half_cells(ld, 0) + kBlock - 1) / kBlock));   // 41 + 7(n-1): level-0 blkh
@@ -381,8 +381,8 @@ struct Batch {
   int maxfuse = 1;
   int2* lvl_blk[kMaxLevels] = {};
   int lvl_nblk[kMaxLevels] = {};
-  int2* lvl8_blk[kMaxLevels] = {};
-  int lvl8_nblk[kMaxLevels] = {};
+  int2* lvlr_blk[kMaxLevels] = {};
+  int lvlr_nblk[kMaxLevels] = {};
   int2* lvlh_blk[kMaxLevels] = {};
   int lvlh_nblk[kMaxLevels] = {};
   BatchLaunch bl() const {
@@ -423,8 +423,8 @@ struct Batch {
     for (int l = 0; l < kMaxLevels; ++l) {
       b.lvl_blk[l] = one ? nullptr : lvl_blk[l];
       b.lvl_nblk[l] = lvl_nblk[l];
-      b.lvl8_blk[l] = one ? nullptr : lvl8_blk[l];
-      b.lvl8_nblk[l] = lvl8_nblk[l];
+      b.lvlr_blk[l] = one ? nullptr : lvlr_blk[l];
+      b.lvlr_nblk[l] = lvlr_nblk[l];
       b.lvlh_blk[l] = one ? nullptr : lvlh_blk[l];
       b.lvlh_nblk[l] = lvlh_nblk[l];
     }
@@ -463,7 +463,7 @@ struct Batch {
     int e = filt(full_blk, cur_tab[0], d_blk, nblk);
     for (int l = 0; l < maxlev && e == MBX_OK; ++l) {
       if (lvl_blk[l]) e = filt(full_lvl[0][l], cur_tab[1 + l], lvl_blk[l], lvl_nblk[l]);
-      if (lvl8_blk[l] && e == MBX_OK) e = filt(full_lvl[1][l], cur_tab[1 + kMaxLevels + l], lvl8_blk[l], lvl8_nblk[l]);
+      if (lvlr_blk[l] && e == MBX_OK) e = filt(full_lvl[1][l], cur_tab[1 + kMaxLevels + l], lvlr_blk[l], lvlr_nblk[l]);
       if (lvlh_blk[l] && e == MBX_OK)
         e = filt(full_lvl[2][l], cur_tab[1 + 2 * kMaxLevels + l], lvlh_blk[l], lvlh_nblk[l]);
     }
@@ -490,7 +490,7 @@ struct Batch {
     (void)hipFree(d_gather);
     for (int l = 0; l < kMaxLevels; ++l) {
       if (lvl_blk[l]) (void)hipFree(lvl_blk[l]);
-      if (lvl8_blk[l]) (void)hipFree(lvl8_blk[l]);
+      if (lvlr_blk[l]) (void)hipFree(lvlr_blk[l]);
       if (lvlh_blk[l]) (void)hipFree(lvlh_blk[l]);
     }
     (void)hipHostFree(h_desc);
@@ -518,8 +518,8 @@ Batch single(mbx_cell* c) {
   for (int l = 0; l < c->ld.n; ++l) {
     b.lvl_blk[l] = c->lvl_blk[l];
     b.lvl_nblk[l] = c->lvl_nblk[l];
-    b.lvl8_blk[l] = c->lvl8_blk[l];
-    b.lvl8_nblk[l] = c->lvl8_nblk[l];
+    b.lvlr_blk[l] = c->lvlr_blk[l];
+    b.lvlr_nblk[l] = c->lvlr_nblk[l];
     b.lvlh_blk[l] = c->lvlh_blk[l];
     b.lvlh_nblk[l] = c->lvlh_nblk[l];
   }
@@ -571,11 +571,11 @@ int make_batch(mbx_cell* const* cells, int n, Batch*& out) {
       for (int c = 0; c < n; ++c)
         if (l < cells[c]->ld.n) {
           const int nb =
-              pass == 0 ? cells[c]->lvl_nblk[l] : pass == 1 ? cells[c]->lvl8_nblk[l] : cells[c]->lvlh_nblk[l];
+              pass == 0 ? cells[c]->lvl_nblk[l] : pass == 1 ? cells[c]->lvlr_nblk[l] : cells[c]->lvlh_nblk[l];
           for (int k = 0; k < nb; ++k) lt.push_back(make_int2(c, k));
         }
-      int2*& dst = pass == 0 ? b.lvl_blk[l] : pass == 1 ? b.lvl8_blk[l] : b.lvlh_blk[l];
-      (pass == 0 ? b.lvl_nblk[l] : pass == 1 ? b.lvl8_nblk[l] : b.lvlh_nblk[l]) = (int)lt.size();
+      int2*& dst = pass == 0 ? b.lvl_blk[l] : pass == 1 ? b.lvlr_blk[l] : b.lvlh_blk[l];
+      (pass == 0 ? b.lvl_nblk[l] : pass == 1 ? b.lvlr_nblk[l] : b.lvlh_nblk[l]) = (int)lt.size();
       b.full_lvl[pass][l] = lt;
       HIPCHK(hipMalloc(&dst, sizeof(int2) * std::max<size_t>(lt.size(), 1)));
       HIPCHK(hipMemcpyAsync(dst, lt.data(), sizeof(int2) * lt.size(), hipMemcpyHostToDevice, b.s));
@@ -615,7 +615,7 @@ uint64_t launch_key(const Batch& B, const BatchLaunch& b, int k0, int k1) {
   mix((uint64_t)b.faces_single);
   for (int l = 0; l < kMaxLevels; ++l) {
     mix((uint64_t)(uintptr_t)b.lvl_blk[l] ^ ((uint64_t)b.lvl_nblk[l] << 48));
-    mix((uint64_t)(uintptr_t)b.lvl8_blk[l] ^ ((uint64_t)b.lvl8_nblk[l] << 48));
+    mix((uint64_t)(uintptr_t)b.lvlr_blk[l] ^ ((uint64_t)b.lvlr_nblk[l] << 48));
     mix((uint64_t)(uintptr_t)b.lvlh_blk[l] ^ ((uint64_t)b.lvlh_nblk[l] << 48));
   }
   mix((uint64_t)(uintptr_t)B.d_gather);
@@ -1274,11 +1274,11 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
     cleanup_tmp();
     return fail(MBX_EINVAL, "too many interface faces for the 24-bit face index");
   }
-  // arrays the level-0 smoother reads through 32-bit buffer offsets (largest: the
-  // colour-split iterate, 8 bytes per slot in FP64)
-  if (8 * (size_t)Np >= (size_t)kNoOff - 4096) {
+  // arrays read through 32-bit buffer offsets (largest: the FP64 GMRES iterate,
+  // 16 bytes per voxel; the colour-split arrays hold at most 8 per slot)
+  if (16 * (size_t)N >= (size_t)kNoOff - 4096 || 8 * (size_t)Np >= (size_t)kNoOff - 4096) {
     cleanup_tmp();
-    return fail(MBX_EINVAL, "grid too large for the 32-bit offsets of the level-0 smoother");
+    return fail(MBX_EINVAL, "grid too large for 32-bit buffer offsets (at most about 2^27 voxels)");
   }
 
   // ---- phase 2: the cell's memory
@@ -1392,8 +1392,8 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
     lv.op[1] = b + L.off[o + 3];
     c->lvl_blk[l] = (int2*)(b + L.off[o + 4]);
     c->lvl_nblk[l] = (lv.ncell + kBlock - 1) / kBlock;
-    c->lvl8_blk[l] = (int2*)(b + L.off[o + 5]);
-    c->lvl8_nblk[l] = (8 * lv.ncell + kBlock - 1) / kBlock;
+    c->lvlr_blk[l] = (int2*)(b + L.off[o + 5]);
+    c->lvlr_nblk[l] = (4 * lv.ncell + kBlock - 1) / kBlock;
     c->lvlh_blk[l] = (int2*)(b + L.off[o + 6]);
     c->lvlh_nblk[l] = (int)((half_cells(c->ld, l) + kBlock - 1) / kBlock);
   }
@@ -1447,11 +1447,11 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   for (int l = 0; l < c->ld.n && e == hipSuccess; ++l) {
     for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
       if (l == 0 && pass < 2) continue;
-      const int nb = pass == 0 ? c->lvl_nblk[l] : pass == 1 ? c->lvl8_nblk[l] : c->lvlh_nblk[l];
+      const int nb = pass == 0 ? c->lvl_nblk[l] : pass == 1 ? c->lvlr_nblk[l] : c->lvlh_nblk[l];
       std::vector<int2>& t = ltabs[3 * l + pass];
       t.resize(nb);
       for (int k = 0; k < nb; ++k) t[k] = make_int2(0, k);
-      e = hipMemcpyAsync(pass == 0 ? c->lvl_blk[l] : pass == 1 ? c->lvl8_blk[l] : c->lvlh_blk[l], t.data(),
+      e = hipMemcpyAsync(pass == 0 ? c->lvl_blk[l] : pass == 1 ? c->lvlr_blk[l] : c->lvlh_blk[l], t.data(),
                          sizeof(int2) * t.size(), hipMemcpyHostToDevice, s);
     }
   }

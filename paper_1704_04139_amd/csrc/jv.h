@@ -8,44 +8,56 @@ namespace mbx {
 // Row i of the matrix-free product with the scaled, condensed Jacobian of
 // the residual: same stencil as k_residual, linear in v, coefficients (type
 // KT) from the last linearisation, v of type VT, accumulated in AT.  Every
-// load of the row is issued before the arithmetic (absent neighbours read
-// voxel i and are zeroed by select).
+// load of the row is a buffer load issued before the arithmetic; absent
+// neighbours are read at element kNoIdx, past the end of every array (zero),
+// and their terms are dropped by select.  The anode and cathode face records
+// are read through one descriptor that starts at the anode records (the
+// cathode records follow them in the cell's allocation).
+constexpr uint32_t kNoIdx = 1u << 28;   // element index past every array read here (cells hold < 2^27 voxels)
 template <typename KT, typename VT, typename AT>
 __device__ inline void jv_row(const CellDev& cd, int i, const VT* __restrict__ v, AT& yc_out, AT& yp_out) {
-  const size_t N = cd.N;
-  const KT* wpo = (const KT*)cd.wpore;
-  const KT* can = (const KT*)cd.coef_an;
-  const KT* cca = (const KT*)cd.coef_ca;
+  constexpr uint32_t kt = sizeof(KT), vt = sizeof(VT);
+  const uint32_t N = (uint32_t)cd.N;
+  const BufRes rm = buf_of(cd.meta, N * 4u);
+  const BufRes rv = buf_of(v, 2u * N * vt);
+  const BufRes rw = buf_of(cd.wpore, N * kt);
+  const uint32_t ca_off = (uint32_t)((const char*)cd.coef_ca - (const char*)cd.coef_an);
+  const BufRes rco = buf_of(cd.coef_an, ca_off + 3u * (uint32_t)(cd.F_ca > 0 ? cd.F_ca : 1) * kt);
   const VoxCoord c3 = coord_of(cd, i);
-  int k[6];
+  uint32_t k[6];
   bool ex[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     const int kk = neighbour(cd, i, c3.x, c3.y, c3.z, d);
     ex[d] = kk >= 0;
-    k[d] = ex[d] ? kk : i;
+    k[d] = ex[d] ? (uint32_t)kk : kNoIdx;
   }
-  const uint32_t mi = cd.meta[i];
-  const AT vc = (AT)v[i], vp = (AT)v[N + i];
-  const AT wiv = (AT)wpo[i];
+  const uint32_t ui = (uint32_t)i;
+  const uint32_t mi = buf_ld<uint32_t>(rm, ui * 4u);
+  const AT vc = (AT)buf_ld<VT>(rv, ui * vt), vp = (AT)buf_ld<VT>(rv, ui * vt, N * vt);
+  const AT wiv = (AT)buf_ld<KT>(rw, ui * kt);
   uint32_t mk[6];
   AT vck[6], vpk[6], wk[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
-    mk[d] = cd.meta[k[d]];
-    vck[d] = (AT)v[k[d]];
-    vpk[d] = (AT)v[N + k[d]];
-    wk[d] = (AT)wpo[k[d]];
+    mk[d] = buf_ld<uint32_t>(rm, k[d] * 4u);
+    vck[d] = (AT)buf_ld<VT>(rv, k[d] * vt);
+    vpk[d] = (AT)buf_ld<VT>(rv, k[d] * vt, N * vt);
+    wk[d] = (AT)buf_ld<KT>(rw, k[d] * kt);
   }
   const int L = lab_of(mi);
   const AT wi = (L == PORE) ? wiv : (AT)0;
   const AT Gk = (AT)(KT)cd.Gk, tth = (AT)(KT)cd.tth, Dh = (AT)(KT)cd.Dh, tau = (AT)(KT)cd.tau, Ke = (AT)(KT)cd.Ke;
-  const AT Dsh = (AT)(KT)cd.Dsh[L == CATHODE], Gs = (AT)(KT)cd.Gs[L == CATHODE], Ks = (AT)(KT)cd.Ks[L == CATHODE];
+  // per-phase constants loaded as scalars, then selected per lane
+  const AT Dsh0 = (AT)(KT)cd.Dsh[0], Dsh1 = (AT)(KT)cd.Dsh[1], Gs0 = (AT)(KT)cd.Gs[0], Gs1 = (AT)(KT)cd.Gs[1];
+  const AT Ks0 = (AT)(KT)cd.Ks[0], Ks1 = (AT)(KT)cd.Ks[1];
+  const bool cat = L == CATHODE;
+  const AT Dsh = cat ? Dsh1 : Dsh0, Gs = cat ? Gs1 : Gs0, Ks = cat ? Ks1 : Ks0;
   AT yc = vc, yp = (AT)0;
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     const int Lk = lab_of(mk[d]);
-    const bool lo = i < k[d];
+    const bool lo = ui < k[d];
     const AT vk = vck[d], pk = vpk[d];
     // electrolyte face (oriented low index -> high index, as in the residual)
     const AT vca = lo ? vc : vk, vcb = lo ? vk : vc;
@@ -58,9 +70,9 @@ __device__ inline void jv_row(const CellDev& cd, int i, const VT* __restrict__ v
     const bool iface = (L == PORE) != (Lk == PORE);
     const uint32_t f = iface ? face_rank(pore_side ? mk[d] : mi, pore_side ? (d ^ 1) : d) : 0u;
     const bool an = (pore_side ? Lk : L) == ANODE;
-    const KT* co = an ? can + 5 * (size_t)f : cca + 3 * (size_t)f;
-    const AT c0 = (AT)co[0], c1 = (AT)co[1], c2 = (AT)co[2];
-    const AT c3v = an ? (AT)co[3] : (AT)0, c4v = an ? (AT)co[4] : (AT)0;
+    const uint32_t co = an ? 5u * f * kt : ca_off + 3u * f * kt;
+    const AT c0 = (AT)buf_ld<KT>(rco, co), c1 = (AT)buf_ld<KT>(rco, co + kt), c2 = (AT)buf_ld<KT>(rco, co + 2 * kt);
+    const AT c3v = (AT)buf_ld<KT>(rco, an ? co + 3 * kt : kNoOff), c4v = (AT)buf_ld<KT>(rco, an ? co + 4 * kt : kNoOff);
     const AT vs = pore_side ? vk : vc, ve = pore_side ? vc : vk;     // solid / pore values
     const AT ps = pore_side ? pk : vp, pe = pore_side ? vp : pk;
     const AT q = c0 * vs + c1 * ve + c2 * (ps - pe);

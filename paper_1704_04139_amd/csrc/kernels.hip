@@ -447,42 +447,78 @@ __global__ void __launch_bounds__(BS) k_matvec(CellDev* cells, const int2* __res
 }
 
 // ------------------------------------------------------------------- GMRES
+// Basis vector j as a buffer of 2N entries: a lane reads its concentration
+// entry at its byte offset and its potential entry through the uniform
+// offset N * sizeof(KT), so a basis load needs no address arithmetic.
+// Block partials of up to eight dot products: t[jj] is this thread's term
+// for basis vector c + jj; partials go to part[(c + jj) * nblk + blk] for
+// c + jj <= k.  The terms are transposed through LDS, so no cross-lane
+// shuffles are needed: lane group g of 32 threads sums vector g's 256 terms
+// eight at a time (strided by 32, fixed order), then one thread per vector
+// adds the group's 32 sums in lane order.
+__device__ inline void block_dots8(const CellDev& cd, int blk, int c, int k, const double (&t)[8], double* lds) {
+  double* s1 = lds;                // [8][kBlock]
+  double* s2 = lds + 8 * kBlock;   // [8][32]
+  __syncthreads();                 // the previous chunk is done with the buffers
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj) s1[jj * kBlock + threadIdx.x] = t[jj];
+  __syncthreads();
+  {
+    const int jj = threadIdx.x >> 5, l = threadIdx.x & 31;
+    double a = 0.0;
+#pragma unroll
+    for (int r = 0; r < kBlock / 32; ++r) a += s1[jj * kBlock + l + 32 * r];
+    s2[jj * 32 + l] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && c + (int)threadIdx.x <= k) {
+    const int jj = threadIdx.x;
+    double a = 0.0;
+#pragma unroll
+    for (int l = 0; l < 32; ++l) a += s2[jj * 32 + l];
+    cd.part[(size_t)(c + jj) * cd.nblk + blk] = a;
+  }
+}
+constexpr int kDotsLds = 8 * kBlock + 8 * 32;   // doubles of LDS for block_dots8
+
+template <typename KT>
+__device__ inline BufRes basis_buf(const CellDev& cd, int j) {
+  const size_t n2 = 2 * (size_t)cd.N;
+  return buf_of((const KT*)cd.Vb + (size_t)j * n2, (uint32_t)(n2 * sizeof(KT)));
+}
+
 // Dots of w with basis vectors 0..k: block partials (first pass).  The
 // basis loads are issued eight vectors at a time (indices past k clamp to k
-// and are not used), then the eight products are reduced.
+// and are not used), then the eight products are reduced through LDS.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_multidot(CellDev* cells, const int2* __restrict__ blk, int k) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE]) return;
-  __shared__ double lds[4 * kPartStride];
+  __shared__ double lds[kDotsLds];
   const int i = bb.y * kBlock + threadIdx.x;
   const size_t N = cd.N;
   const bool in = i < cd.N;
-  const size_t ii = in ? (size_t)i : 0;
   double wc = 0.0, wp = 0.0;
   if (in) {
     const KT* w = (const KT*)cd.w;
     wc = (double)w[i];
     wp = (double)w[N + i];
   }
-  const KT* V = (const KT*)cd.Vb;
-  const size_t n2 = 2 * N;
+  const uint32_t off = in ? (uint32_t)i * (uint32_t)sizeof(KT) : kNoOff, soff = (uint32_t)(N * sizeof(KT));
   for (int c = 0; c <= k; c += 8) {
     KT vc[8], vp[8];
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
-      const int j = c + jj < k ? c + jj : k;
-      vc[jj] = V[(size_t)j * n2 + ii];
-      vp[jj] = V[(size_t)j * n2 + N + ii];
+      const BufRes r = basis_buf<KT>(cd, c + jj < k ? c + jj : k);
+      vc[jj] = buf_ld<KT>(r, off);
+      vp[jj] = buf_ld<KT>(r, off, soff);
     }
+    double t[8];
 #pragma unroll
-    for (int jj = 0; jj < 8; ++jj)
-      if (c + jj <= k) wave_to_lds((double)vc[jj] * wc + (double)vp[jj] * wp, false, lds, kPartStride, c + jj);
+    for (int jj = 0; jj < 8; ++jj) t[jj] = (double)vc[jj] * wc + (double)vp[jj] * wp;
+    block_dots8(cd, bb.y, c, k, t, lds);
   }
-  __syncthreads();
-  for (int j = threadIdx.x; j <= k; j += kBlock)
-    cd.part[(size_t)j * cd.nblk + bb.y] = combine4(lds, kPartStride, j, false);
 }
 
 // Second pass of the dot products: column j = blockIdx.x of cell blockIdx.y
@@ -502,9 +538,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize_dots(CellDev* cells, int nc
 
 // First Gram-Schmidt pass and the second pass's dot products in one kernel:
 // w -= sum_j H(j,k) V_j, then block partials of V_j . w for j <= k.  The
-// thread's basis entries are read again for the dots (the block's slice of
-// the basis was just fetched and mostly comes from cache): holding all of
-// them in registers would cut the occupancy to two waves per SIMD.
+// thread's basis entries are read a second time for the dots: holding all
+// of them in registers would cut the occupancy to two waves per SIMD.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2* __restrict__ blk, int k) {
   const int2 bb = block_of(blk);
@@ -516,22 +551,20 @@ __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2
   const int i = bb.y * kBlock + threadIdx.x;
   const size_t N = cd.N;
   const bool in = i < cd.N;
-  const size_t ii = in ? (size_t)i : 0;
   KT* w = (KT*)cd.w;
   KT wc = (KT)0, wp = (KT)0;
   if (in) {
     wc = w[i];
     wp = w[N + i];
   }
-  const KT* V = (const KT*)cd.Vb;
-  const size_t n2 = 2 * N;
+  const uint32_t off = in ? (uint32_t)i * (uint32_t)sizeof(KT) : kNoOff, soff = (uint32_t)(N * sizeof(KT));
   for (int c = 0; c <= k; c += 8) {
     KT vc[8], vp[8];
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
-      const int j = c + jj < k ? c + jj : k;
-      vc[jj] = V[(size_t)j * n2 + ii];
-      vp[jj] = V[(size_t)j * n2 + N + ii];
+      const BufRes r = basis_buf<KT>(cd, c + jj < k ? c + jj : k);
+      vc[jj] = buf_ld<KT>(r, off);
+      vp[jj] = buf_ld<KT>(r, off, soff);
     }
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj)
@@ -553,10 +586,12 @@ __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2
     KT vc[8], vp[8];
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
-      const int j = c + jj < k ? c + jj : k;
-      vc[jj] = V[(size_t)j * n2 + ii];
-      vp[jj] = V[(size_t)j * n2 + N + ii];
+      const BufRes r = basis_buf<KT>(cd, c + jj < k ? c + jj : k);
+      vc[jj] = buf_ld<KT>(r, off);
+      vp[jj] = buf_ld<KT>(r, off, soff);
     }
+    // (the LDS-transposed block_dots8 measured slower here than per-wave
+    // reductions: this kernel's second pass is bandwidth-bound)
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj)
       if (c + jj <= k) wave_to_lds((double)vc[jj] * dwc + (double)vp[jj] * dwp, false, lds, kPartStride, c + jj);
@@ -581,15 +616,14 @@ __global__ void __launch_bounds__(kBlock) k_orth(CellDev* cells, const int2* __r
   if (i < cd.N) {
     KT* w = (KT*)cd.w;
     KT wc = w[i], wp = w[N + i];
-    const KT* V = (const KT*)cd.Vb;
-    const size_t n2 = 2 * N;
+    const uint32_t off = (uint32_t)i * (uint32_t)sizeof(KT), soff = (uint32_t)(N * sizeof(KT));
     for (int c = 0; c <= k; c += 8) {
       KT vc[8], vp[8];
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj) {
-        const int j = c + jj < k ? c + jj : k;
-        vc[jj] = V[(size_t)j * n2 + i];
-        vp[jj] = V[(size_t)j * n2 + N + i];
+        const BufRes r = basis_buf<KT>(cd, c + jj < k ? c + jj : k);
+        vc[jj] = buf_ld<KT>(r, off);
+        vp[jj] = buf_ld<KT>(r, off, soff);
       }
 #pragma unroll
       for (int jj = 0; jj < 8; ++jj)

@@ -193,26 +193,28 @@ __device__ inline BufRes buf_of(const void* p, uint32_t bytes) {
   // loads and the range check use on this architecture family
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
+// off: per-lane byte offset; soff: a uniform byte offset (scalar register)
+// added to it, e.g. the start of a row of a structure-of-arrays block.
 template <typename T>
-__device__ inline T buf_ld(BufRes r, uint32_t off);
+__device__ inline T buf_ld(BufRes r, uint32_t off, uint32_t soff = 0);
 template <>
-__device__ inline float buf_ld<float>(BufRes r, uint32_t off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-template <>
-__device__ inline double buf_ld<double>(BufRes r, uint32_t off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+__device__ inline float buf_ld<float>(BufRes r, uint32_t off, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
 }
 template <>
-__device__ inline uint32_t buf_ld<uint32_t>(BufRes r, uint32_t off) {
-  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+__device__ inline double buf_ld<double>(BufRes r, uint32_t off, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
 }
-__device__ inline void buf_st(BufRes r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+template <>
+__device__ inline uint32_t buf_ld<uint32_t>(BufRes r, uint32_t off, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0);
 }
-__device__ inline void buf_st(BufRes r, uint32_t off, double v) {
+__device__ inline void buf_st(BufRes r, uint32_t off, float v, uint32_t soff = 0) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, soff, 0);
+}
+__device__ inline void buf_st(BufRes r, uint32_t off, double v, uint32_t soff = 0) {
   typedef uint32_t u32x2 __attribute__((__vector_size__(8)));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, 0);
 }
 
 // Colour-split index of voxel (x, y, z) (see CellDev::rbhx).

@@ -28,8 +28,8 @@ struct BatchLaunch {
   int max_nu_c;                          // ... on launched levels >= 2
   const int2* lvl_blk[kMaxLevels];       // block tables over each level's cells (index >= 1)
   int lvl_nblk[kMaxLevels];
-  const int2* lvl8_blk[kMaxLevels];      // block tables with 8 lanes per level cell (index >= 1)
-  int lvl8_nblk[kMaxLevels];
+  const int2* lvlr_blk[kMaxLevels];      // block tables with 4 lanes per level cell, one per red child (index >= 1)
+  int lvlr_nblk[kMaxLevels];
   const int2* lvlh_blk[kMaxLevels];      // block tables over one colour of a red-black sweep (index >= 0)
   int lvlh_nblk[kMaxLevels];
   // algorithmic bytes per launch (summed over the batch), for timing records

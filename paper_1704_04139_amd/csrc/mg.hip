@@ -647,26 +647,28 @@ __global__ void __launch_bounds__(BS) k_mg0_smooth(CellDev* cells, const int2* _
   if (post && it == cd.nu - 1) ((KT*)cd.z)[(size_t)OP * cd.N + c.x + cd.nx * (c.y + cd.ny * c.z)] = xn;
 }
 
-// Sum over the 8 lanes of an aligned lane group (xor butterfly: every lane
+// Sum over the 4 lanes of an aligned lane group (xor butterfly: every lane
 // ends with the identical value).
-__device__ inline float lane8_sum(float v) {
+template <typename T>
+__device__ inline T lane4_sum(T v) {
   v += __shfl_xor(v, 1, 64);
   v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  return v;
-}
-__device__ inline double lane8_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
   return v;
 }
 
-// Level-0 residual restricted to level 1: 8 lanes per level-1 cell, one per
-// child voxel; the per-slot sums are formed across the lanes.  The last
-// pre-smoothing half sweep solved every black row exactly for the current red
-// values, so only red rows carry a residual (the black ones are zero up to
-// rounding and are not evaluated).
+// Child c (0..3) of a parent cell among its red children (offsets with an
+// even sum: parent cells sit at even coordinates, so these are the children
+// of colour 0), in the order of the child index dx + 2 dy + 4 dz.
+__device__ inline C3 red_child(const C3& q, int c) {
+  const int dx = c == 1 || c == 2, dy = c == 1 || c == 3, dz = c >= 2;
+  return C3{2 * q.x + dx, 2 * q.y + dy, 2 * q.z + dz};
+}
+
+// Level-0 residual restricted to level 1.  The last pre-smoothing half sweep
+// solved every black row exactly for the current red values, so only red
+// rows carry a residual (the black ones are zero up to rounding and are not
+// evaluated): 4 lanes per level-1 cell, one per red child voxel; the
+// per-slot sums are formed across the lanes.
 template <typename KT, int OP>
 __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const int2* __restrict__ blk, int need) {
   const int2 bb = block_of(blk);
@@ -674,13 +676,12 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
   if (!cd.active) return;
   const MGLevel& L1 = cd.lv[1];
   const int t = bb.y * kBlock + threadIdx.x;
-  const int C = t >> 3, ch = t & 7;
-  const bool live = C < L1.ncell;   // whole 8-lane groups share C: shuffles stay within live groups
+  const int C = t >> 2, ch = t & 3;
+  const bool live = C < L1.ncell;   // whole 4-lane groups share C: shuffles stay within live groups
   KT rs[3] = {0, 0, 0};
   if (live) {
-    const C3 q = c3_of(C, L1.nx, L1.ny);
-    const C3 fc{2 * q.x + (ch & 1), 2 * q.y + ((ch >> 1) & 1), 2 * q.z + (ch >> 2)};
-    if (fc.x < cd.nx && fc.y < cd.ny && fc.z < cd.nz && ((fc.x + fc.y + fc.z) & 1) == 0) {
+    const C3 fc = red_child(c3_of(C, L1.nx, L1.ny), ch);
+    if (fc.x < cd.nx && fc.y < cd.ny && fc.z < cd.nz) {
       const KT* x0 = (const KT*)cd.x_rb;
       const int p = rb_index(cd, fc.x, fc.y, fc.z);
       const uint32_t mi = cd.meta_rb[p];
@@ -694,7 +695,7 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
       rs[2] = L == 2 ? r : (KT)0;
     }
   }
-  for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
+  for (int s = 0; s < 3; ++s) rs[s] = lane4_sum(rs[s]);
   if (!gate_state(cd, need)) return;   // uniform over the block (one cell)
   if (live && ch == 0) {
     KT* b1 = (KT*)L1.b;
@@ -781,7 +782,8 @@ __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int
                   mode, need);
 }
 
-// Level-l residual restricted to level l+1: 8 lanes per parent, one per child.
+// Level-l residual restricted to level l+1: 4 lanes per parent, one per red
+// child (the black children's residuals are zero after the last half sweep).
 template <typename KT, int OP>
 __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const int2* __restrict__ blk, int l, int need) {
   const int2 bb = block_of(blk);
@@ -790,18 +792,14 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
   const MGLevel& L = cd.lv[l];
   const MGLevel& Lp = cd.lv[l + 1];
   const int t = bb.y * kBlock + threadIdx.x;
-  const int P = t >> 3, ch = t & 7;
-  const bool live = P < Lp.ncell;
+  const int P = t >> 2, ch = t & 3;
+  const bool live = P < Lp.ncell;   // whole 4-lane groups share P
   KT rs[3] = {0, 0, 0};
   if (live) {
-    const C3 q = c3_of(P, Lp.nx, Lp.ny);
-    const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
-    // the last pre-smoothing half sweep solved every black cell exactly for
-    // the current red values: only red cells carry a residual
-    if (cx < L.nx && cy < L.ny && cz < L.nz && ((cx + cy + cz) & 1) == 0)
-      residual_cell<KT, OP>(view<KT>(L, OP), lvl_cell(L, cx, cy, cz), C3{cx, cy, cz}, rs);
+    const C3 c = red_child(c3_of(P, Lp.nx, Lp.ny), ch);
+    if (c.x < L.nx && c.y < L.ny && c.z < L.nz) residual_cell<KT, OP>(view<KT>(L, OP), lvl_cell(L, c.x, c.y, c.z), c, rs);
   }
-  for (int s = 0; s < 3; ++s) rs[s] = lane8_sum(rs[s]);
+  for (int s = 0; s < 3; ++s) rs[s] = lane4_sum(rs[s]);
   if (!gate_state(cd, need)) return;   // uniform over the block (one cell)
   if (live && ch == 0) {
     KT* bp = (KT*)Lp.b;
@@ -1073,13 +1071,13 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
       }
     }
     if (l == 0 && prof_on(PK_SMOOTH0)) prof_end_n(PK_SMOOTH0, s, 2.0 * nu * b.bytes_smooth0, 2 * nu);
-    if (b.lvl8_nblk[l + 1] <= 0) continue;
+    if (b.lvlr_nblk[l + 1] <= 0) continue;
     if (l == 0)
-      (op == 0 ? k_mg0_restrict<KT, 0> : k_mg0_restrict<KT, 1>)<<<b.lvl8_nblk[1], kBlock, 0, s>>>(
-          b.cells, b.lvl8_blk[1], need);
+      (op == 0 ? k_mg0_restrict<KT, 0> : k_mg0_restrict<KT, 1>)<<<b.lvlr_nblk[1], kBlock, 0, s>>>(
+          b.cells, b.lvlr_blk[1], need);
     else
-      (op == 0 ? k_mgl_restrict<KT, 0> : k_mgl_restrict<KT, 1>)<<<b.lvl8_nblk[l + 1], kBlock, 0, s>>>(
-          b.cells, b.lvl8_blk[l + 1], l, need);
+      (op == 0 ? k_mgl_restrict<KT, 0> : k_mgl_restrict<KT, 1>)<<<b.lvlr_nblk[l + 1], kBlock, 0, s>>>(
+          b.cells, b.lvlr_blk[l + 1], l, need);
   }
   (op == 0 ? k_mg_coarse_cycle<KT, 0> : k_mg_coarse_cycle<KT, 1>)<<<b.ncell, kBlock, b.fused_lds * sizeof(KT), s>>>(
       b.cells, b.ncell, need);
