@@ -143,7 +143,23 @@ __device__ inline int fine_nbr(int i, const C3& c, int nx, int ny, int nz, int d
   }
 }
 
-__device__ inline int lvl_cell(const MGLevel& L, int x, int y, int z) { return x + L.nx * (y + L.ny * z); }
+// Storage order of a coarse level (l >= 1): rows of nx cells ((y, z) in
+// row-major order), and inside each row the even-x cells first, then the
+// odd-x cells.  A red-black half sweep visits one x-parity per row, whose
+// cells are then contiguous (whole cache lines instead of every other
+// element); the +-y and +-z neighbours keep the strides nx and nx*ny.
+__device__ inline int xperm(int x, int nx) { return (x & 1) ? ((nx + 1) >> 1) + (x >> 1) : (x >> 1); }
+__device__ inline int lvl_index(int x, int y, int z, int nx, int ny) { return xperm(x, nx) + nx * (y + ny * z); }
+__device__ inline int lvl_cell(const MGLevel& L, int x, int y, int z) { return lvl_index(x, y, z, L.nx, L.ny); }
+// coordinates of the cell stored at index c
+__device__ inline C3 lvl_coords(int c, int nx, int ny) {
+  C3 q = c3_of(c, nx, ny);   // q.x: position in the row
+  const int he = (nx + 1) >> 1;
+  q.x = q.x < he ? 2 * q.x : 2 * (q.x - he) + 1;
+  return q;
+}
+// index of the cell dx in {-1, 0, 1} cells along x from cell c at x
+__device__ inline int lvl_xstep(int c, int x, int dx, int nx) { return c - xperm(x, nx) + xperm(x + dx, nx); }
 
 // Smoothing modes: which values stand for the cell's own slots and for its
 // neighbours.  "corrected" adds alpha times the parent's level l+1 solution
@@ -171,13 +187,24 @@ __device__ inline bool color_cell(int t, int color, const MGLevel& L, C3& q) {
 
 // Neighbour cells (+x, -x, +y, -y, +z, -z) of cell c at q; absent neighbours
 // are replaced by c itself and flagged false (their couplings are zeroed, so
-// every load stays in bounds and can be issued without a branch).
+// every load stays in bounds and can be issued without a branch).  Natural
+// order (the voxel grid).
 __device__ inline void neighbours6(int c, const C3& q, int nx, int ny, int nz, int (&nb)[6], bool (&ex)[6]) {
   const int sx = 1, sy = nx, sz = nx * ny;
   ex[0] = q.x + 1 < nx; ex[1] = q.x > 0;
   ex[2] = q.y + 1 < ny; ex[3] = q.y > 0;
   ex[4] = q.z + 1 < nz; ex[5] = q.z > 0;
   nb[0] = ex[0] ? c + sx : c; nb[1] = ex[1] ? c - sx : c;
+  nb[2] = ex[2] ? c + sy : c; nb[3] = ex[3] ? c - sy : c;
+  nb[4] = ex[4] ? c + sz : c; nb[5] = ex[5] ? c - sz : c;
+}
+// The same for a coarse level's storage order (lvl_index).
+__device__ inline void lvl_neighbours6(int c, const C3& q, int nx, int ny, int nz, int (&nb)[6], bool (&ex)[6]) {
+  const int sy = nx, sz = nx * ny;
+  ex[0] = q.x + 1 < nx; ex[1] = q.x > 0;
+  ex[2] = q.y + 1 < ny; ex[3] = q.y > 0;
+  ex[4] = q.z + 1 < nz; ex[5] = q.z > 0;
+  nb[0] = ex[0] ? lvl_xstep(c, q.x, 1, nx) : c; nb[1] = ex[1] ? lvl_xstep(c, q.x, -1, nx) : c;
   nb[2] = ex[2] ? c + sy : c; nb[3] = ex[3] ? c - sy : c;
   nb[4] = ex[4] ? c + sz : c; nb[5] = ex[5] ? c - sz : c;
 }
@@ -259,15 +286,16 @@ __device__ inline void voxel_row(const CellDev& cd, int color, int p, const C3& 
     const int px = c.x >> 1, py = c.y >> 1, pz = c.z >> 1;
     const int pq[6] = {((c.x + 1) >> 1) - px, ((c.x - 1) >> 1) - px, ((c.y + 1) >> 1) - py,
                        ((c.y - 1) >> 1) - py, ((c.z + 1) >> 1) - pz, ((c.z - 1) >> 1) - pz};
-    const int pc = px + L1.nx * (py + L1.ny * pz);
-    const int pst[6] = {1, 1, L1.nx, L1.nx, L1.nx * L1.ny, L1.nx * L1.ny};
+    const int pc = lvl_cell(L1, px, py, pz);
+    const int pst[6] = {0, 0, L1.nx, L1.nx, L1.nx * L1.ny, L1.nx * L1.ny};   // x steps: lvl_xstep
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       // the neighbour's phase slot (an interface neighbour of the
       // concentration operator has a zero coupling: its own slot serves)
       const int ns = pore ? (__builtin_signbit(gf[j]) ? CATHODE : ANODE) : PORE;
       const int slot = (OP != 0 && ifc[j]) ? ns : L;
-      const uint32_t off = (uint32_t)(slot * L1.ncell + pc + pq[j] * pst[j]) * kt;
+      const int pcj = j < 2 ? lvl_xstep(pc, px, pq[j], L1.nx) : pc + pq[j] * pst[j];
+      const uint32_t off = (uint32_t)(slot * L1.ncell + pcj) * kt;
       const KT cv = alpha * buf_ld<KT>(r1, ex[j] ? off : kNoOff);   // rounded before the sum (no fused form)
       xk[j] += cv;
     }
@@ -323,7 +351,7 @@ __device__ inline void gather_coarse(const LV<KT>& L, const LV<KT>& Lp, KT alpha
   const KT* x = L.x;
   int nb[6];
   bool ex[6];
-  neighbours6(C, q, L.nx, L.ny, L.nz, nb, ex);
+  lvl_neighbours6(C, q, L.nx, L.ny, L.nz, nb, ex);
   constexpr bool cross = OP != 0;
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
@@ -358,17 +386,17 @@ __device__ inline void gather_coarse(const LV<KT>& L, const LV<KT>& Lp, KT alpha
     const size_t np = Lp.ncell;
     const KT* xp = Lp.x;
     const int px = q.x >> 1, py = q.y >> 1, pz = q.z >> 1;
-    const int pc = px + Lp.nx * (py + Lp.ny * pz);
+    const int pc = lvl_index(px, py, pz, Lp.nx, Lp.ny);
     if (own_corr(mode))
 #pragma unroll
       for (int t = 0; t < 3; ++t) R.xo[t] += alpha * xp[t * np + pc];
     if (nbr_corr(mode)) {
       const int pq[6] = {((q.x + 1) >> 1) - px, ((q.x - 1) >> 1) - px, ((q.y + 1) >> 1) - py,
                          ((q.y - 1) >> 1) - py, ((q.z + 1) >> 1) - pz, ((q.z - 1) >> 1) - pz};
-      const int pst[6] = {1, 1, Lp.nx, Lp.nx, Lp.nx * Lp.ny, Lp.nx * Lp.ny};
+      const int pst[6] = {0, 0, Lp.nx, Lp.nx, Lp.nx * Lp.ny, Lp.nx * Lp.ny};   // x steps: lvl_xstep
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
-        const int pcj = ex[j] ? pc + pq[j] * pst[j] : pc;
+        const int pcj = !ex[j] ? pc : j < 2 ? lvl_xstep(pc, px, pq[j], Lp.nx) : pc + pq[j] * pst[j];
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
           const KT v = xp[t * np + pcj];
@@ -429,7 +457,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_assemble0(CellDev* cells, const i
   const MGLevel& L1 = cd.lv[1];
   const int C = bb.y * kBlock + threadIdx.x;
   if (C >= L1.ncell) return;
-  const C3 q = c3_of(C, L1.nx, L1.ny);
+  const C3 q = lvl_coords(C, L1.nx, L1.ny);
   KT E[3] = {0, 0, 0}, X[3] = {0, 0, 0}, G[27];
   for (int k = 0; k < 27; ++k) G[k] = (KT)0;
   for (int dz = 0; dz < 2; ++dz)
@@ -488,7 +516,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_assemble(CellDev* cells, const in
   const MGLevel& Lp = cd.lv[l + 1];
   const int P = bb.y * kBlock + threadIdx.x;
   if (P >= Lp.ncell) return;
-  const C3 q = c3_of(P, Lp.nx, Lp.ny);
+  const C3 q = lvl_coords(P, Lp.nx, Lp.ny);
   const OpV<KT> A{(const KT*)Lc.op[op], Lc.ncell};
   KT E[3] = {0, 0, 0}, X[3] = {0, 0, 0}, G[27];
   for (int k = 0; k < 27; ++k) G[k] = (KT)0;
@@ -535,7 +563,7 @@ __device__ inline void coarse_assemble(const MGLevel& L, const OpV<KT>& A, doubl
   __syncthreads();
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     const int c = r / 3, s = r % 3;
-    const C3 q = c3_of(c, L.nx, L.ny);
+    const C3 q = lvl_coords(c, L.nx, L.ny);
     double D = (double)A.E(c, s);
     for (int t = 0; t < 3; ++t)
       if (t != s) {
@@ -680,7 +708,7 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
   const bool live = C < L1.ncell;   // whole 4-lane groups share C: shuffles stay within live groups
   KT rs[3] = {0, 0, 0};
   if (live) {
-    const C3 fc = red_child(c3_of(C, L1.nx, L1.ny), ch);
+    const C3 fc = red_child(lvl_coords(C, L1.nx, L1.ny), ch);
     if (fc.x < cd.nx && fc.y < cd.ny && fc.z < cd.nz) {
       const KT* x0 = (const KT*)cd.x_rb;
       const int p = rb_index(cd, fc.x, fc.y, fc.z);
@@ -796,7 +824,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
   const bool live = P < Lp.ncell;   // whole 4-lane groups share P
   KT rs[3] = {0, 0, 0};
   if (live) {
-    const C3 c = red_child(c3_of(P, Lp.nx, Lp.ny), ch);
+    const C3 c = red_child(lvl_coords(P, Lp.nx, Lp.ny), ch);
     if (c.x < L.nx && c.y < L.ny && c.z < L.nz) residual_cell<KT, OP>(view<KT>(L, OP), lvl_cell(L, c.x, c.y, c.z), c, rs);
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane4_sum(rs[s]);
@@ -864,18 +892,18 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
           if (color_cell(t, color, L.nx, L.ny, L.nz, cd.lv[l].inv_hx, cd.lv[l].inv_ny, q))
-            smooth_cell<KT, OP>(cd, L, Lp, alpha, q.x + L.nx * (q.y + L.ny * q.z), q, mode, -2);
+            smooth_cell<KT, OP>(cd, L, Lp, alpha, lvl_index(q.x, q.y, q.z, L.nx, L.ny), q, mode, -2);
         }
         __syncthreads();
       }
     for (int P = threadIdx.x; P < Lp.ncell; P += blockDim.x) {
-      const C3 q = c3_of(P, Lp.nx, Lp.ny);
+      const C3 q = lvl_coords(P, Lp.nx, Lp.ny);
       KT acc[3] = {0, 0, 0};
       for (int ch = 0; ch < 8; ++ch) {
         const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
         if (cx >= L.nx || cy >= L.ny || cz >= L.nz || ((cx + cy + cz) & 1)) continue;   // black: solved exactly
         KT r[3];
-        residual_cell<KT, OP>(L, cx + L.nx * (cy + L.ny * cz), C3{cx, cy, cz}, r);
+        residual_cell<KT, OP>(L, lvl_index(cx, cy, cz, L.nx, L.ny), C3{cx, cy, cz}, r);
         for (int s = 0; s < 3; ++s) acc[s] += r[s];
       }
       for (int s = 0; s < 3; ++s) Lp.b[(size_t)s * Lp.ncell + P] = acc[s];
@@ -905,7 +933,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
         for (int t = threadIdx.x; t < nh; t += blockDim.x) {
           C3 q;
           if (color_cell(t, color, L.nx, L.ny, L.nz, cd.lv[l].inv_hx, cd.lv[l].inv_ny, q))
-            smooth_cell<KT, OP>(cd, L, Lp, alpha, q.x + L.nx * (q.y + L.ny * q.z), q, mode, -2);
+            smooth_cell<KT, OP>(cd, L, Lp, alpha, lvl_index(q.x, q.y, q.z, L.nx, L.ny), q, mode, -2);
         }
         __syncthreads();
       }
