@@ -102,7 +102,8 @@ struct Layout {
 
 struct LevelDims {
   int n = 0;                       // number of levels incl. the voxel level
-  int lfuse = 1;                   // first level small enough to run inside one workgroup
+  int lfuse = 1;                   // first level small enough to run inside one workgroup from LDS
+  int lglob = 1;                   // first level run inside that workgroup (from device memory below lfuse)
   int nx[kMaxLevels], ny[kMaxLevels], nz[kMaxLevels], ncell[kMaxLevels];
 };
 
@@ -136,6 +137,8 @@ LevelDims level_dims(int nx, int ny, int nz, size_t kt) {
   while (d.lfuse > 1 && d.ncell[d.lfuse - 1] <= kFuseMaxCells &&
          fused_elems(d, d.lfuse - 1) * kt <= kFusedLdsBytes)
     --d.lfuse;
+  d.lglob = d.lfuse;
+  while (d.lglob > 1 && d.ncell[d.lglob - 1] <= kGlobFuseMaxCells) --d.lglob;
   return d;
 }
 
@@ -379,6 +382,7 @@ struct Batch {
   int m = kRestart;
   int maxlev = 0;
   int maxfuse = 1;
+  int maxglob = 1;
   int2* lvl_blk[kMaxLevels] = {};
   int lvl_nblk[kMaxLevels] = {};
   int2* lvlr_blk[kMaxLevels] = {};
@@ -412,6 +416,7 @@ struct Batch {
     b.bs_matvec = one ? cells[0]->bs_matvec : kBlock;
     b.maxlev = maxlev;
     b.maxfuse = maxfuse;
+    b.maxglob = maxglob;
     b.fused_lds = 0;
     b.max_nu = 1;
     b.max_nu_c = 1;
@@ -515,6 +520,7 @@ Batch single(mbx_cell* c) {
   b.use_graphs = c->p.graphs != 0;
   b.maxlev = c->ld.n;
   b.maxfuse = c->ld.lfuse;
+  b.maxglob = c->ld.lglob;
   for (int l = 0; l < c->ld.n; ++l) {
     b.lvl_blk[l] = c->lvl_blk[l];
     b.lvl_nblk[l] = c->lvl_nblk[l];
@@ -563,6 +569,7 @@ int make_batch(mbx_cell* const* cells, int n, Batch*& out) {
   for (int c = 0; c < n; ++c) {
     b.maxlev = std::max(b.maxlev, cells[c]->ld.n);
     b.maxfuse = std::max(b.maxfuse, cells[c]->ld.lfuse);
+    b.maxglob = std::max(b.maxglob, cells[c]->ld.lglob);
   }
   for (int l = 0; l < b.maxlev; ++l) {
     for (int pass = 0; pass < 3; ++pass) {
@@ -609,6 +616,7 @@ uint64_t launch_key(const Batch& B, const BatchLaunch& b, int k0, int k1) {
   mix((uint64_t)b.ncell);
   mix((uint64_t)b.maxlev);
   mix((uint64_t)b.maxfuse);
+  mix((uint64_t)b.maxglob);
   mix((uint64_t)b.fused_lds);
   mix((uint64_t)b.max_nu);
   mix((uint64_t)b.max_nu_c);
@@ -1365,6 +1373,7 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.cinv[1] = (double*)(b + L.off[40]);
   h.nlev = c->ld.n;
   h.lfuse = c->ld.lfuse;
+  h.lglob = c->ld.lglob;
   h.alpha = g_mg_alpha();
   h.nu = g_sweeps_min();
   h.nu_f = h.nu;

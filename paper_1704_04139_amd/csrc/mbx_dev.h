@@ -31,7 +31,8 @@ enum { PORE = 0, ANODE = 1, CATHODE = 2 };
 // with three slots (pore, anode, cathode aggregates of the finer level).
 constexpr int kMaxLevels = 12;
 constexpr int kCoarseMaxCells = 64;
-constexpr int kFuseMaxCells = 256;    // levels this small run inside one workgroup per cell
+constexpr int kFuseMaxCells = 256;    // levels this small run inside one workgroup per cell, staged in LDS
+constexpr int kGlobFuseMaxCells = 2048;   // ... and levels this small too, from device memory
 constexpr size_t kFusedLdsBytes = 60 * 1024;   // LDS the fused levels may stage
 constexpr double kToBoundary = 0.1;   // a Newton update leaves at least this fraction of the distance to a bound
 constexpr int kOpStride = 33;   // per coarse cell: E[3], X[3], G[3 dirs][3][3] (SoA)
@@ -121,7 +122,8 @@ struct CellDev {
   double i00_ce;                     // Li-foil rate constant, A/m^2
   // multigrid
   int nlev, lfuse;                   // levels incl. the voxel level; coarsest = nlev-1;
-                                     // levels >= lfuse run in one workgroup (k_mg_coarse_cycle)
+                                     // levels >= lfuse run in one workgroup from LDS (k_mg_coarse_cycle)
+  int lglob;                         // levels lglob..lfuse-1 run in that workgroup from device memory
   MGLevel lv[kMaxLevels];
   // Level-0 multigrid arrays in colour-split (red-black) order: voxel (x,y,z)
   // of colour c = (x+y+z)&1 sits at c*rbH + (y + ny*z)*rbhx + (x>>1), with

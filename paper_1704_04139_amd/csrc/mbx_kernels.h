@@ -22,7 +22,8 @@ struct BatchLaunch {
   int bs_smooth0, bs_matvec;             // threads per workgroup of the level-0 smoother and of J*v in a
                                          // single-cell launch (64, 128 or 256; table launches use kBlock)
   int maxlev;                            // max multigrid levels over the batch
-  int maxfuse;                           // max first fused level over the batch
+  int maxfuse;                           // max first LDS-staged fused level over the batch
+  int maxglob;                           // max first fused level (device-memory levels included) over the batch
   size_t fused_lds;                      // LDS elements (KT) of the fused coarse cycle, max over the batch
   int max_nu;                            // most smoothing sweeps any cell of the batch asks for
   int max_nu_c;                          // ... on launched levels >= 2

@@ -802,7 +802,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_smooth(CellDev* cells, const int
                                                        int mode, int it, int need) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!cd.active || l >= cd.lfuse || it >= (l >= 2 ? min(cd.nu, cd.nu_c) : cd.nu)) return;
+  if (!cd.active || l >= cd.lglob || it >= (l >= 2 ? min(cd.nu, cd.nu_c) : cd.nu)) return;
   const MGLevel& L = cd.lv[l];
   C3 q;
   if (!color_cell(bb.y * kBlock + threadIdx.x, color, L, q)) return;
@@ -816,7 +816,7 @@ template <typename KT, int OP>
 __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const int2* __restrict__ blk, int l, int need) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
-  if (!cd.active || l >= cd.lfuse) return;
+  if (!cd.active || l >= cd.lglob) return;
   const MGLevel& L = cd.lv[l];
   const MGLevel& Lp = cd.lv[l + 1];
   const int t = bb.y * kBlock + threadIdx.x;
@@ -835,14 +835,31 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
   }
 }
 
-// Levels lfuse..coarsest of one cell in one workgroup (levels small enough
+// One red-black half sweep of level l inside the fused cycle (all threads
+// of the workgroup; followed by a barrier).
+template <typename KT, int OP>
+__device__ inline void fused_half_sweep(const CellDev& cd, const LV<KT>& L, const LV<KT>& Lp, KT alpha, int l, int color,
+                                        int mode) {
+  const int nh = ((L.nx + 1) >> 1) * L.ny * L.nz;
+  for (int t = threadIdx.x; t < nh; t += blockDim.x) {
+    C3 q;
+    if (color_cell(t, color, L.nx, L.ny, L.nz, cd.lv[l].inv_hx, cd.lv[l].inv_ny, q))
+      smooth_cell<KT, OP>(cd, L, Lp, alpha, lvl_index(q.x, q.y, q.z, L.nx, L.ny), q, mode, -2);
+  }
+  __syncthreads();
+}
+
+// Levels lglob..coarsest of one cell in one workgroup (levels small enough
 // that barriers are cheaper than kernel launches): pre-smoothing and
 // restriction down to the coarsest level, dense coarsest solve, coarse
-// correction and post-smoothing back up to lfuse.  The operators and vectors
-// of these levels are staged in LDS first (the dynamic shared-memory size is
-// fused_lds_bytes); the coarsest inverse stays in device memory (symmetric:
-// read column-wise, coalesced).  Only the level-lfuse solution is written
-// back: the launched level above reads it for its coarse correction.
+// correction and post-smoothing back up to lglob.  Levels lfuse.. are
+// staged in LDS first (operators and vectors; the dynamic shared-memory size
+// is fused_lds_bytes); levels lglob..lfuse-1 (too large for LDS, small enough
+// for one workgroup) stay in device memory and run with the launched levels'
+// sweep counts and restriction sums, so they compute what the launched
+// kernels would.  The coarsest inverse stays in device memory (symmetric:
+// read column-wise, coalesced).  Level lglob's solution ends in device
+// memory: the launched level above reads it for its coarse correction.
 template <typename KT, int OP>
 __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int need) {
   constexpr int op = OP;
@@ -851,9 +868,32 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
   if (ci >= ncells) return;
   const CellDev& cd = cells[ci];
   if (!gate(cd, need)) return;
-  const int lf = cd.lfuse, lc = cd.nlev - 1;
+  const int lg = cd.lglob, lf = cd.lfuse, lc = cd.nlev - 1;
   const int nu = cd.nu_f;
   const KT alpha = (KT)cd.alpha;
+  // device-memory levels: sweeps and restriction as in the launched kernels
+  for (int l = lg; l < lf; ++l) {
+    const LV<KT> L = view<KT>(cd.lv[l], op), Lp = view<KT>(cd.lv[l + 1], op);
+    const int nul = l >= 2 ? min(cd.nu, cd.nu_c) : cd.nu;
+    for (int it = 0; it < nul; ++it) {
+      fused_half_sweep<KT, OP>(cd, L, Lp, alpha, l, 0, it == 0 ? SM_ZERO : SM_PLAIN);
+      fused_half_sweep<KT, OP>(cd, L, Lp, alpha, l, 1, it == 0 ? SM_OWNZERO : SM_PLAIN);
+    }
+    // red children only, summed as the 4-lane restriction kernel sums them
+    for (int P = threadIdx.x; P < Lp.ncell; P += blockDim.x) {
+      const C3 q = lvl_coords(P, Lp.nx, Lp.ny);
+      KT r[4][3];
+      for (int ch = 0; ch < 4; ++ch) {
+        const C3 c = red_child(q, ch);
+        if (c.x < L.nx && c.y < L.ny && c.z < L.nz)
+          residual_cell<KT, OP>(L, lvl_index(c.x, c.y, c.z, L.nx, L.ny), c, r[ch]);
+        else
+          r[ch][0] = r[ch][1] = r[ch][2] = (KT)0;
+      }
+      for (int s = 0; s < 3; ++s) Lp.b[(size_t)s * Lp.ncell + P] = (r[0][s] + r[1][s]) + (r[2][s] + r[3][s]);
+    }
+    __syncthreads();
+  }
   KT* const base = (KT*)smem;
   // LDS element offsets of level l's x, b and operator: levels lf..lc in order
   auto offset = [&](int l) {
@@ -943,6 +983,15 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int 
     const KT* src = base + offset(lf);
     KT* dst = (KT*)cd.lv[lf].x;
     for (size_t e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+  }
+  if (lg < lf) __syncthreads();
+  for (int l = lf - 1; l >= lg; --l) {
+    const LV<KT> L = view<KT>(cd.lv[l], op), Lp = view<KT>(cd.lv[l + 1], op);
+    const int nul = l >= 2 ? min(cd.nu, cd.nu_c) : cd.nu;
+    for (int it = 0; it < nul; ++it) {
+      fused_half_sweep<KT, OP>(cd, L, Lp, alpha, l, 1, it == 0 ? SM_CORR : SM_PLAIN);
+      fused_half_sweep<KT, OP>(cd, L, Lp, alpha, l, 0, it == 0 ? SM_OWNCORR : SM_PLAIN);
+    }
   }
 }
 
@@ -1085,7 +1134,7 @@ static void smoothl(const BatchLaunch& b, int l, int op, int color, int mode, in
 // any cell of the batch asks for and the others skip the surplus.
 template <typename KT>
 static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
-  const int top = b.maxfuse;   // levels >= a cell's lfuse run inside k_mg_coarse_cycle
+  const int top = b.maxglob;   // levels >= a cell's lglob run inside k_mg_coarse_cycle
   for (int l = 0; l < top; ++l) {
     const int nu = l >= 2 ? std::min(b.max_nu, b.max_nu_c) : b.max_nu;
     if (l == 0) prof_begin(PK_SMOOTH0, s);   // the 2 nu level-0 half sweeps run back to back
