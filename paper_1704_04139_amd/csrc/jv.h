@@ -13,7 +13,6 @@ namespace mbx {
 // and their terms are dropped by select.  The anode and cathode face records
 // are read through one descriptor that starts at the anode records (the
 // cathode records follow them in the cell's allocation).
-constexpr uint32_t kNoIdx = 1u << 28;   // element index past every array read here (cells hold < 2^27 voxels)
 template <typename KT, typename VT, typename AT>
 __device__ inline void jv_row(const CellDev& cd, int i, const VT* __restrict__ v, AT& yc_out, AT& yp_out) {
   constexpr uint32_t kt = sizeof(KT), vt = sizeof(VT);

@@ -33,6 +33,7 @@ constexpr int kMaxLevels = 12;
 constexpr int kCoarseMaxCells = 64;
 constexpr int kFuseMaxCells = 256;    // levels this small run inside one workgroup per cell, staged in LDS
 constexpr int kGlobFuseMaxCells = 2048;   // ... and levels this small too, from device memory
+constexpr int kFuseBlock = 1024;          // threads of that workgroup (a 1280-cell level: one cell per thread and colour)
 constexpr size_t kFusedLdsBytes = 60 * 1024;   // LDS the fused levels may stage
 constexpr double kToBoundary = 0.1;   // a Newton update leaves at least this fraction of the distance to a bound
 constexpr int kOpStride = 33;   // per coarse cell: E[3], X[3], G[3 dirs][3][3] (SoA)
@@ -189,6 +190,9 @@ __device__ inline VoxCoord coord_of(const CellDev& cd, int i) {
 // read this way hold fewer than kNoOff - 4096 bytes (checked at cell
 // creation), so kNoOff plus any immediate offset stays out of range.
 constexpr uint32_t kNoOff = 0x80000000u;
+// Element index past every per-voxel array (cells hold fewer than 2^27
+// voxels; times 4 or 8 bytes it stays below 2^32 and at or past the end).
+constexpr uint32_t kNoIdx = 1u << 28;
 using BufRes = __amdgpu_buffer_rsrc_t;
 __device__ inline BufRes buf_of(const void* p, uint32_t bytes) {
   // descriptor word 3 = 0x00020000: 32-bit data format, which raw (untyped)

@@ -861,7 +861,7 @@ __device__ inline void fused_half_sweep(const CellDev& cd, const LV<KT>& L, cons
 // read column-wise, coalesced).  Level lglob's solution ends in device
 // memory: the launched level above reads it for its coarse correction.
 template <typename KT, int OP>
-__global__ void __launch_bounds__(kBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int need) {
+__global__ void __launch_bounds__(kFuseBlock) k_mg_coarse_cycle(CellDev* cells, int ncells, int need) {
   constexpr int op = OP;
   extern __shared__ __align__(16) unsigned char smem[];
   const int ci = blockIdx.x;
@@ -1024,26 +1024,34 @@ __global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* _
   if (!cd.active) return;
   const int i = bb.y * kBlock + threadIdx.x;
   if (i >= cd.N) return;
-  const size_t N = cd.N;
-  const KT* v = vsel<KT>(cd, src);
-  const KT* zc = (const KT*)cd.z;
-  const KT* wpo = (const KT*)cd.wpore;
-  const KT* can = (const KT*)cd.coef_an;
-  const KT* cca = (const KT*)cd.coef_ca;
+  // buffer loads (see jv_row): absent neighbours read at kNoIdx (zero), the
+  // anode and cathode face records through one descriptor
+  constexpr uint32_t kt = sizeof(KT);
+  const uint32_t N = (uint32_t)cd.N;
+  const BufRes rm = buf_of(cd.meta, N * 4u);
+  const BufRes rz = buf_of(cd.z, N * kt);   // concentration part of z
+  const BufRes rw = buf_of(cd.wpore, N * kt);
+  const BufRes rv = buf_of(vsel<KT>(cd, src), 2u * N * kt);
+  const uint32_t ca_off = (uint32_t)((const char*)cd.coef_ca - (const char*)cd.coef_an);
+  const BufRes rco = buf_of(cd.coef_an, ca_off + 3u * (uint32_t)(cd.F_ca > 0 ? cd.F_ca : 1) * kt);
   const C3 c = c3_of(i, cd.nx, cd.ny);
   int k[6];
   bool ex[6];
   neighbours6(i, c, cd.nx, cd.ny, cd.nz, k, ex);
+  uint32_t kk[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) kk[j] = ex[j] ? (uint32_t)k[j] : kNoIdx;
   const int dmap[6] = {1, 0, 3, 2, 5, 4};   // neighbour slot -> face direction
-  const uint32_t mi = cd.meta[i];
-  const KT vc = zc[i], wiv = wpo[i], vpi = v[N + i];
+  const uint32_t ui = (uint32_t)i;
+  const uint32_t mi = buf_ld<uint32_t>(rm, ui * 4u);
+  const KT vc = buf_ld<KT>(rz, ui * kt), wiv = buf_ld<KT>(rw, ui * kt), vpi = buf_ld<KT>(rv, ui * kt, N * kt);
   uint32_t mk[6];
   KT vk[6], wk[6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    mk[j] = cd.meta[k[j]];
-    vk[j] = zc[k[j]];
-    wk[j] = wpo[k[j]];
+    mk[j] = buf_ld<uint32_t>(rm, kk[j] * 4u);
+    vk[j] = buf_ld<KT>(rz, kk[j] * kt);
+    wk[j] = buf_ld<KT>(rw, kk[j] * kt);
   }
   const int L = lab_of(mi);
   const KT wi = L == PORE ? wiv : (KT)0;
@@ -1058,8 +1066,8 @@ __global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* _
     const bool pore_side = L == PORE;
     const uint32_t f = iface ? face_rank(pore_side ? mk[j] : mi, pore_side ? (d ^ 1) : d) : 0u;
     const bool an = (pore_side ? Lk : L) == ANODE;
-    const KT* co = an ? can + 5 * (size_t)f : cca + 3 * (size_t)f;
-    const KT c0 = co[0], c1 = co[1], c3 = co[an ? 3 : 1];
+    const uint32_t co = an ? 5u * f * kt : ca_off + 3u * f * kt;
+    const KT c0 = buf_ld<KT>(rco, co), c1 = buf_ld<KT>(rco, co + kt), c3 = buf_ld<KT>(rco, co + (an ? 3 : 1) * kt);
     const KT vs = pore_side ? vk[j] : vc, vpo = pore_side ? vc : vk[j];
     // interface flux derivative w.r.t. the concentrations (potential part zero)
     const KT q = c0 * vs + c1 * vpo + (an ? c3 * vpo : (KT)0);
@@ -1156,7 +1164,7 @@ static void vcycle(const BatchLaunch& b, int op, int need, hipStream_t s) {
       (op == 0 ? k_mgl_restrict<KT, 0> : k_mgl_restrict<KT, 1>)<<<b.lvlr_nblk[l + 1], kBlock, 0, s>>>(
           b.cells, b.lvlr_blk[l + 1], l, need);
   }
-  (op == 0 ? k_mg_coarse_cycle<KT, 0> : k_mg_coarse_cycle<KT, 1>)<<<b.ncell, kBlock, b.fused_lds * sizeof(KT), s>>>(
+  (op == 0 ? k_mg_coarse_cycle<KT, 0> : k_mg_coarse_cycle<KT, 1>)<<<b.ncell, kFuseBlock, b.fused_lds * sizeof(KT), s>>>(
       b.cells, b.ncell, need);
   for (int l = top - 1; l >= 0; --l) {
     const int nu = l >= 2 ? std::min(b.max_nu, b.max_nu_c) : b.max_nu;
