@@ -537,9 +537,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize_dots(CellDev* cells, int nc
 }
 
 // First Gram-Schmidt pass and the second pass's dot products in one kernel:
-// w -= sum_j H(j,k) V_j, then block partials of V_j . w for j <= k.  The
-// thread's basis entries are read a second time for the dots: holding all
-// of them in registers would cut the occupancy to two waves per SIMD.
+// w -= sum_j H(j,k) V_j, then block partials of V_j . w for j <= k.  FP32
+// basis: the thread's basis entries (at most kMaxRestart pairs) stay in
+// registers between the two, so the basis is read once.  FP64 basis: they
+// are read a second time for the dots (holding them would cut the
+// occupancy to two waves per SIMD).  The arithmetic is the same either way.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2* __restrict__ blk, int k) {
   const int2 bb = block_of(blk);
@@ -558,14 +560,16 @@ __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2
     wp = w[N + i];
   }
   const uint32_t off = in ? (uint32_t)i * (uint32_t)sizeof(KT) : kNoOff, soff = (uint32_t)(N * sizeof(KT));
-  for (int c = 0; c <= k; c += 8) {
-    KT vc[8], vp[8];
+  // eight basis vectors from chunk start c (indices past k clamp to k)
+  auto load8 = [&](int c, KT (&vc)[8], KT (&vp)[8]) {
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
       const BufRes r = basis_buf<KT>(cd, c + jj < k ? c + jj : k);
       vc[jj] = buf_ld<KT>(r, off);
       vp[jj] = buf_ld<KT>(r, off, soff);
     }
+  };
+  auto update8 = [&](int c, const KT (&vc)[8], const KT (&vp)[8]) {
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj)
       if (c + jj <= k) {
@@ -573,28 +577,57 @@ __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2
         wc -= hj * vc[jj];
         wp -= hj * vp[jj];
       }
-  }
-  if (in) {
-    w[i] = wc;
-    w[N + i] = wp;
-  } else {
-    wc = (KT)0;
-    wp = (KT)0;
-  }
-  const double dwc = (double)wc, dwp = (double)wp;
-  for (int c = 0; c <= k; c += 8) {
-    KT vc[8], vp[8];
-#pragma unroll
-    for (int jj = 0; jj < 8; ++jj) {
-      const BufRes r = basis_buf<KT>(cd, c + jj < k ? c + jj : k);
-      vc[jj] = buf_ld<KT>(r, off);
-      vp[jj] = buf_ld<KT>(r, off, soff);
-    }
-    // (the LDS-transposed block_dots8 measured slower here than per-wave
-    // reductions: this kernel's second pass is bandwidth-bound)
+  };
+  auto dots8 = [&](int c, const KT (&vc)[8], const KT (&vp)[8], double dwc, double dwp) {
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj)
       if (c + jj <= k) wave_to_lds((double)vc[jj] * dwc + (double)vp[jj] * dwp, false, lds, kPartStride, c + jj);
+  };
+  auto store_w = [&]() {
+    if (in) {
+      w[i] = wc;
+      w[N + i] = wp;
+    } else {
+      wc = (KT)0;
+      wp = (KT)0;
+    }
+  };
+  if constexpr (sizeof(KT) == sizeof(float)) {
+    constexpr int kCh = kMaxRestart / 8;
+    KT vc[kCh][8], vp[kCh][8];
+#pragma unroll
+    for (int ch = 0; ch < kCh; ++ch)
+      if (8 * ch <= k) load8(8 * ch, vc[ch], vp[ch]);
+#pragma unroll
+    for (int ch = 0; ch < kCh; ++ch)
+      if (8 * ch <= k) update8(8 * ch, vc[ch], vp[ch]);
+    store_w();
+    const double dwc = (double)wc, dwp = (double)wp;
+    // the dots come from registers: the reduction is the critical path here,
+    // so it goes through LDS (block_dots8) rather than per-wave shuffles
+    __shared__ double ldsd[kDotsLds];
+#pragma unroll
+    for (int ch = 0; ch < kCh; ++ch)
+      if (8 * ch <= k) {
+        double t[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) t[jj] = (double)vc[ch][jj] * dwc + (double)vp[ch][jj] * dwp;
+        block_dots8(cd, bb.y, 8 * ch, k, t, ldsd);
+      }
+    return;
+  } else {
+    for (int c = 0; c <= k; c += 8) {
+      KT vc[8], vp[8];
+      load8(c, vc, vp);
+      update8(c, vc, vp);
+    }
+    store_w();
+    const double dwc = (double)wc, dwp = (double)wp;
+    for (int c = 0; c <= k; c += 8) {
+      KT vc[8], vp[8];
+      load8(c, vc, vp);
+      dots8(c, vc, vp, dwc, dwp);
+    }
   }
   __syncthreads();
   for (int j = threadIdx.x; j <= k; j += kBlock)
