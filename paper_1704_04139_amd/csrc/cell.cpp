@@ -363,6 +363,13 @@ void fill_step_constants(CellDev& h, double dt) {
     // the foil's concentration row carries no interface flux
     h.Ks[s] = (s == 1 && h.half) ? 0.0 : dt * mu / (hh * kFaraday * h.cmax[s]);
   }
+  // same-phase couplings of the level-0 smoother per operator and label, in both Krylov types
+  const double gs[2][3] = {{h.Dh, h.Dsh[0], h.Dsh[1]}, {h.Gk, h.Gs[0], h.Gs[1]}};
+  for (int op = 0; op < 2; ++op)
+    for (int l = 0; l < 3; ++l) {
+      h.gsame_d[op][l] = gs[op][l];
+      h.gsame_f[op][l] = (float)gs[op][l];
+    }
 }
 
 // A batch of cells sharing every launch.
@@ -645,9 +652,8 @@ void launch_chunk(const BatchLaunch& bl, int k0, int k1, double* d_gather, int n
     // classical Gram-Schmidt with one re-orthogonalisation (CGS2)
     launch_multidot<KT>(bl, k, 0, s);   // H(:,k) = V^T w
     launch_orth_dots<KT>(bl, k, s);     // w -= V H(:,k); tmp = V^T w
-    launch_orth<KT>(bl, k, 1, s);       // w -= V tmp; H(:,k) += tmp; H(k+1,k) = |w|
-    launch_scale_next<KT>(bl, k, s);
-    launch_givens(bl, k, s);
+    launch_orth<KT>(bl, k, 1, s);       // w -= V tmp; H(:,k) += tmp; H(k+1,k) = |w|; Givens step of column k
+    launch_scale_next<KT>(bl, k, s);    // V_{k+1} = w / |w| (cells still iterating)
   }
   if (copy_out) {
     launch_gather_ctl(bl, d_gather, s);

@@ -674,70 +674,9 @@ __global__ void __launch_bounds__(kBlock) k_orth(CellDev* cells, const int2* __r
   reduce_block<1>(cd, bb.y, vals, 0u);
 }
 
-// Second pass of k_orth: H(k+1,k) = ||w|| (src = 1 also adds tmp to H(:,k)).
-__global__ void __launch_bounds__(kBlock) k_finalize_norm(CellDev* cells, int ncell, int k, int src) {
-  const int ci = blockIdx.x;
-  if (ci >= ncell) return;
-  const CellDev& cd = cells[ci];
-  if (!cd.active || cd.ictl[CTL_DONE]) return;
-  __shared__ double lds4[4];
-  __shared__ double res;
-  const double acc = finalize_column(cd, 0, false, lds4, &res);
-  if (threadIdx.x == 0) {
-    const int m = cd.m;
-    double* H = cd.gm + gm_H(m) + (size_t)(m + 1) * k;
-    if (src == 1) {
-      const double* tmp = cd.gm + gm_tmp(m);
-      for (int j = 0; j <= k; ++j) H[j] += tmp[j];
-    }
-    H[k + 1] = sqrt(acc);
-  }
-}
-
-// Second pass of the voxel-block reductions: partial columns 0..K-1 into
-// red[slot..slot+K) (bit j of maxmask: max, else sum).  need: -3 any active
-// cell, -4 cells whose GMRES cycle just closed (state 1 or 2), otherwise only
-// cells whose GMRES state equals need.
-__global__ void __launch_bounds__(kBlock) k_finalize_red(CellDev* cells, int ncell, int slot, int K, unsigned maxmask,
-                                                         int need) {
-  const int ci = blockIdx.x;
-  if (ci >= ncell) return;
-  const CellDev& cd = cells[ci];
-  if (!cd.active) return;
-  const int st = cd.ictl[CTL_DONE];
-  if (need == -4 ? (st != 1 && st != 2) : (need != -3 && st != need)) return;
-  __shared__ double lds4[4];
-  __shared__ double res;
-  for (int j = 0; j < K; ++j) {
-    const double r = finalize_column(cd, j, (maxmask >> j) & 1u, lds4, &res);
-    if (threadIdx.x == 0) cd.red[slot + j] = r;
-  }
-}
-
-// V_{k+1} = w / H(k+1,k)
-template <typename KT>
-__global__ void __launch_bounds__(kBlock) k_scale_next(CellDev* cells, const int2* __restrict__ blk, int k) {
-  const int2 bb = block_of(blk);
-  const CellDev& cd = cells[bb.x];
-  if (!cd.active || cd.ictl[CTL_DONE]) return;
-  const int i = bb.y * kBlock + threadIdx.x;
-  if (i >= cd.N) return;
-  const int m = cd.m;
-  const double hn = cd.gm[gm_H(m) + (size_t)(m + 1) * k + k + 1];
-  const KT inv = hn > 0.0 ? (KT)(1.0 / hn) : (KT)0;
-  const size_t N = cd.N;
-  const KT* w = (const KT*)cd.w;
-  KT* vn = vec<KT>(cd, k + 1);
-  vn[i] = w[i] * inv;
-  vn[N + i] = w[N + i] * inv;
-}
-
-// Givens rotations of the Hessenberg column k (one thread per cell).
-__global__ void k_givens(CellDev* cells, int ncell, int k) {
-  const int ci = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ci >= ncell) return;
-  const CellDev& cd = cells[ci];
-  if (!cd.active || cd.ictl[CTL_DONE]) return;
+// Givens rotations of the Hessenberg column k of one cell (one thread), and
+// the cell's GMRES state after iteration k.
+__device__ inline void givens_column(const CellDev& cd, int k) {
   const int m = cd.m;
   double* H = cd.gm + gm_H(m) + (size_t)(m + 1) * k;
   double* g = cd.gm + gm_g(m);
@@ -767,6 +706,68 @@ __global__ void k_givens(CellDev* cells, int ncell, int k) {
     cd.ictl[CTL_DONE] = 1;          // converged (or exact breakdown)
   else if (k + 1 >= m)
     cd.ictl[CTL_DONE] = 2;          // cycle full: restart needed
+}
+
+// Second pass of k_orth: H(k+1,k) = ||w|| (src = 1 also adds tmp to H(:,k)),
+// kept in red[RED_HNORM] for k_scale_next; then the Givens step of column k
+// (one thread: givens_column).
+__global__ void __launch_bounds__(kBlock) k_finalize_norm(CellDev* cells, int ncell, int k, int src) {
+  const int ci = blockIdx.x;
+  if (ci >= ncell) return;
+  CellDev& cd = cells[ci];
+  if (!cd.active || cd.ictl[CTL_DONE]) return;
+  __shared__ double lds4[4];
+  __shared__ double res;
+  const double acc = finalize_column(cd, 0, false, lds4, &res);
+  if (threadIdx.x == 0) {
+    const int m = cd.m;
+    double* H = cd.gm + gm_H(m) + (size_t)(m + 1) * k;
+    if (src == 1) {
+      const double* tmp = cd.gm + gm_tmp(m);
+      for (int j = 0; j <= k; ++j) H[j] += tmp[j];
+    }
+    H[k + 1] = sqrt(acc);
+    cd.red[RED_HNORM] = H[k + 1];
+    givens_column(cd, k);
+  }
+}
+
+// Second pass of the voxel-block reductions: partial columns 0..K-1 into
+// red[slot..slot+K) (bit j of maxmask: max, else sum).  need: -3 any active
+// cell, -4 cells whose GMRES cycle just closed (state 1 or 2), otherwise only
+// cells whose GMRES state equals need.
+__global__ void __launch_bounds__(kBlock) k_finalize_red(CellDev* cells, int ncell, int slot, int K, unsigned maxmask,
+                                                         int need) {
+  const int ci = blockIdx.x;
+  if (ci >= ncell) return;
+  const CellDev& cd = cells[ci];
+  if (!cd.active) return;
+  const int st = cd.ictl[CTL_DONE];
+  if (need == -4 ? (st != 1 && st != 2) : (need != -3 && st != need)) return;
+  __shared__ double lds4[4];
+  __shared__ double res;
+  for (int j = 0; j < K; ++j) {
+    const double r = finalize_column(cd, j, (maxmask >> j) & 1u, lds4, &res);
+    if (threadIdx.x == 0) cd.red[slot + j] = r;
+  }
+}
+
+// V_{k+1} = w / ||w|| (red[RED_HNORM]).  Cells whose GMRES cycle ended at
+// iteration k (converged or full) skip it: their V_{k+1} is not used.
+template <typename KT>
+__global__ void __launch_bounds__(kBlock) k_scale_next(CellDev* cells, const int2* __restrict__ blk, int k) {
+  const int2 bb = block_of(blk);
+  const CellDev& cd = cells[bb.x];
+  if (!cd.active || cd.ictl[CTL_DONE]) return;
+  const int i = bb.y * kBlock + threadIdx.x;
+  if (i >= cd.N) return;
+  const double hn = cd.red[RED_HNORM];
+  const KT inv = hn > 0.0 ? (KT)(1.0 / hn) : (KT)0;
+  const size_t N = cd.N;
+  const KT* w = (const KT*)cd.w;
+  KT* vn = vec<KT>(cd, k + 1);
+  vn[i] = w[i] * inv;
+  vn[N + i] = w[N + i] * inv;
 }
 
 // Back substitution R y = g for the iterations of the current cycle.
@@ -1249,9 +1250,6 @@ void launch_orth(const BatchLaunch& b, int k, int src, hipStream_t s) {
 template <typename KT>
 void launch_scale_next(const BatchLaunch& b, int k, hipStream_t s) {
   k_scale_next<KT><<<grid_of(b.nblk), kBlock, 0, s>>>(b.cells, b.blk, k);
-}
-void launch_givens(const BatchLaunch& b, int k, hipStream_t s) {
-  k_givens<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell, k);
 }
 void launch_backsolve(const BatchLaunch& b, hipStream_t s) {
   k_backsolve<<<(b.ncell + 63) / 64, 64, 0, s>>>(b.cells, b.ncell);

@@ -74,7 +74,8 @@ enum {
   RED_TOL = 12,    // GMRES absolute tolerance of the current solve
   RED_BETA0 = 13,  // norm of the first GMRES residual of the current solve
   RED_LTE = 14,    // max over the differential unknowns of |u - u_pred| (scaled), adaptive stepping
-  RED_NSLOT = 15
+  RED_HNORM = 15,  // ||w|| of the current GMRES iteration (H(k+1,k) before its Givens rotation)
+  RED_NSLOT = 16
 };
 // Slots of the per-cell device-written integer array `ictl`.
 enum { CTL_DONE = 0, CTL_K = 1, CTL_ITERS = 2, CTL_NSLOT = 4 };
@@ -148,6 +149,11 @@ struct CellDev {
   double Kd;                         // kappa (1-t+) theta RT/(F h)
   double Gk, tth, Dh, tau, Ke, Gcol;
   double Dsh[2], Gs[2], Ks[2];
+  // the level-0 smoother's same-phase coupling per operator (concentration,
+  // potential) and label (pore, anode, cathode): Dh Dsh, Gk Gs, in both
+  // Krylov types (read as scalars, then selected per voxel)
+  alignas(16) double gsame_d[2][4];
+  alignas(16) float gsame_f[2][4];
 };
 
 // gm layout: H[(m+1)*m] column-major, g[m+1], cs[m], sn[m], y[m], tmp[m+1]
@@ -180,6 +186,25 @@ __device__ inline VoxCoord coord_of(const CellDev& cd, int i) {
   const int t = divmod(i, cd.nx, cd.inv_nx, v.x);
   v.z = divmod(t, cd.ny, cd.inv_ny, v.y);
   return v;
+}
+
+// The three same-phase couplings of operator op (pore, anode, cathode),
+// fetched with one wide load (so that no load waits inside a label branch).
+template <typename KT>
+struct Gsame {
+  KT pore, an, ca;
+};
+template <typename KT>
+__device__ inline Gsame<KT> gsame_of(const CellDev& cd, int op);
+template <>
+__device__ inline Gsame<float> gsame_of<float>(const CellDev& cd, int op) {
+  const float4 v = *(const float4*)cd.gsame_f[op];
+  return {v.x, v.y, v.z};
+}
+template <>
+__device__ inline Gsame<double> gsame_of<double>(const CellDev& cd, int op) {
+  const double2 a = *(const double2*)cd.gsame_d[op], b = *(const double2*)(cd.gsame_d[op] + 2);
+  return {a.x, a.y, b.x};
 }
 
 // Raw buffer loads: the array's base and size sit in a scalar descriptor and

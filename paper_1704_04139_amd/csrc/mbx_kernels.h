@@ -65,7 +65,6 @@ template <typename KT> void launch_orth(const BatchLaunch& b, int k, int src, hi
 // the second pass (into tmp)
 template <typename KT> void launch_orth_dots(const BatchLaunch& b, int k, hipStream_t s);
 template <typename KT> void launch_scale_next(const BatchLaunch& b, int k, hipStream_t s);
-void launch_givens(const BatchLaunch& b, int k, hipStream_t s);
 void launch_backsolve(const BatchLaunch& b, hipStream_t s);
 // x += Z y for the cells whose cycle just closed
 template <typename KT> void launch_update_x(const BatchLaunch& b, hipStream_t s);

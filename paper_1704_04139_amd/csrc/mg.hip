@@ -148,7 +148,7 @@ __device__ inline int fine_nbr(int i, const C3& c, int nx, int ny, int nz, int d
 // odd-x cells.  A red-black half sweep visits one x-parity per row, whose
 // cells are then contiguous (whole cache lines instead of every other
 // element); the +-y and +-z neighbours keep the strides nx and nx*ny.
-__device__ inline int xperm(int x, int nx) { return (x & 1) ? ((nx + 1) >> 1) + (x >> 1) : (x >> 1); }
+__device__ inline int xperm(int x, int nx) { return (x >> 1) + (x & 1) * ((nx + 1) >> 1); }
 __device__ inline int lvl_index(int x, int y, int z, int nx, int ny) { return xperm(x, nx) + nx * (y + ny * z); }
 __device__ inline int lvl_cell(const MGLevel& L, int x, int y, int z) { return lvl_index(x, y, z, L.nx, L.ny); }
 // coordinates of the cell stored at index c
@@ -264,15 +264,9 @@ __device__ inline void voxel_row(const CellDev& cd, int color, int p, const C3& 
   }
   // interface part of the concentration diagonal (per voxel, from the setup)
   const KT dint = OP == 0 ? buf_ld<KT>(buf_of(cd.dint, 2u * (uint32_t)cd.rbH * kt), (uint32_t)p * kt) : (KT)0;
-  // same-phase coupling (the per-cell constants converted before the select)
-  KT gsame;
-  if (OP == 0) {
-    const KT gp = (KT)cd.Dh, ga = (KT)cd.Dsh[0], gc = (KT)cd.Dsh[1];
-    gsame = pore ? gp : (L == CATHODE ? gc : ga);
-  } else {
-    const KT gp = (KT)cd.Gk, ga = (KT)cd.Gs[0], gc = (KT)cd.Gs[1];
-    gsame = pore ? gp : (L == CATHODE ? gc : ga);
-  }
+  // same-phase coupling (per-cell constants in the Krylov type, selected by label)
+  const Gsame<KT> gs = gsame_of<KT>(cd, OP);
+  const KT gsame = pore ? gs.pore : (L == CATHODE ? gs.ca : gs.an);
   KT g[6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
