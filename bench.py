@@ -87,8 +87,9 @@ def run_gpu(w, precision, steps, warmup, stream, prof_steps=4, V_cut=None, to_cu
                     **({"V_cut": V_cut} if V_cut else {}))
     t_start = time.perf_counter()
     infos = []
-    for _ in range(warmup):
+    for k in range(warmup):
         infos.append(cell.step(w.dt))
+        print(f"[bench] {precision}: warm-up step {k + 1}/{warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -99,9 +100,11 @@ def run_gpu(w, precision, steps, warmup, stream, prof_steps=4, V_cut=None, to_cu
     state = cell.get_state()
     mean_solid = cell.mean_solid()
     V_timed = timed[-1]["V"]
+    print(f"[bench] {precision}: {steps} timed steps done", file=sys.stderr, flush=True)
     mbx.profile(PROFILED_KERNEL)
-    for _ in range(prof_steps):
+    for k in range(prof_steps):
         infos.append(cell.step(w.dt))
+        print(f"[bench] {precision}: event-timed step {k + 1}/{prof_steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     launches, ms, nbytes = mbx.profile_read()
     mbx.profile(None)

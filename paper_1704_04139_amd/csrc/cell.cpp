@@ -406,10 +406,11 @@ struct Batch {
       b.bytes_residual[0] += 44.0 * N + 4.0 * (Fa + Fc) + 32.0 * Fa;
       b.bytes_residual[1] += 44.0 * N + 4.0 * (Fa + Fc) + 32.0 * Fa + kt * N + (6.0 * kt + 16.0) * Fa + 4.0 * kt * Fc;
       b.bytes_matvec += (4.0 + 5.0 * kt) * N + 5.0 * kt * Fa + 3.0 * kt * Fc;
-      // one half sweep: meta of all voxels, x of the other colour, b of its own,
-      // the new x; averaged over the two operators: interface conductances
-      // (potential operator) and the per-voxel interface diagonal (concentration)
-      b.bytes_smooth0 += (4.0 + 1.5 * kt) * N + 0.5 * kt * (Fa + Fc) + 0.25 * kt * N;
+      // one half sweep: meta and b of the colour's voxels, x of the other
+      // colour, the new x; averaged over the two operators: the colour's
+      // interface conductances (potential operator, one per face) and its
+      // per-voxel interface diagonal (concentration operator)
+      b.bytes_smooth0 += (2.0 + 1.5 * kt) * N + 0.5 * kt * (Fa + Fc) + 0.25 * kt * N;
     }
     b.cells = d_desc;
     // a single cell needs no block tables: kernels map block b to {0, b}
