@@ -299,7 +299,7 @@ __device__ inline void voxel_row(const CellDev& cd, int color, int p, const C3& 
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     D += g[j];
-    if (!zero) S += g[j] * xk[j];
+    S += g[j] * xk[j];   // xk = 0 from a zero iterate: S stays +0 (the couplings are finite)
   }
 }
 
