@@ -56,7 +56,9 @@ __device__ inline void jv_row(const CellDev& cd, int i, const VT* __restrict__ v
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     const int Lk = lab_of(mk[d]);
-    const bool lo = ui < k[d];
+    // the +x, +y, +z neighbours (odd d) have the higher index: the face's
+    // orientation is known per direction at compile time
+    const bool lo = (d & 1) != 0;
     const AT vk = vck[d], pk = vpk[d];
     // electrolyte face (oriented low index -> high index, as in the residual)
     const AT vca = lo ? vc : vk, vcb = lo ? vk : vc;

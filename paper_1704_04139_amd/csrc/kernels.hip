@@ -308,9 +308,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellDev* cells, const int2*
         }
         continue;
       }
-      const int k = kk[d];
       const int Lk = lab_of(mk[d]);
-      const bool lo = i < k;
+      const bool lo = (d & 1) != 0;   // the +x, +y, +z neighbours (odd d) have the higher index
       const double sgn = lo ? 1.0 : -1.0;
       weight_add(cd, L, Lk, wc, wp);
       if (L == PORE && Lk == PORE) {
