@@ -416,8 +416,8 @@ int mbx_profile_read(int64_t *launches, double *total_ms, double *total_bytes);
  * Outputs: modes (device, n x k_max column-major, leading dimension
  * ldm >= n; columns k.. are not written), sigma (host, all m singular
  * values, descending), *k_out = number of kept modes.  K is formed on the
- * GPU's FP64 matrix cores; its eigen-decomposition runs on the host (cyclic
- * Jacobi).  Singular values below about 1e-8 sigma_1 carry the rounding of
+ * GPU's FP64 matrix cores; its eigen-decomposition runs on the host
+ * (Householder tridiagonalisation and implicit QR, mbx_sym_eig).  Singular values below about 1e-8 sigma_1 carry the rounding of
  * K (the method squares the condition number).  Allocates a device
  * workspace of about 8 (2048 x 1024 + m^2 + 32 m ceil(k/32)) bytes for the
  * call and synchronises the stream.  Errors: MBX_EINVAL, MBX_ENOMEM,
