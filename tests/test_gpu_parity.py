@@ -184,6 +184,26 @@ def test_config0_trajectory_matches_oracle(mbx, prec, bar):
 
 
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-8), ("mixed", 1e-6)])
+@pytest.mark.parametrize("shape,seed", [((17, 9, 33), 3), ((15, 13, 27), 8)])
+def test_odd_grid_steps_match_live_oracle(mbx, prec, bar, shape, seed):
+    """Grids with odd extents (padding slots in the colour-split level-0
+    storage, odd rows in the coarse levels' even-x-first order) stepped at 2C
+    against a live oracle run."""
+    lab = I.sphere_cell(*shape, seed, 2.0, 3.5, 0.35, 0.33)
+    prm = I.CellParams()
+    prm.I_app = 2.0 * I.one_c_current(lab, prm)
+    dt, steps = 5.0, 2
+    say("odd grid", shape, prec)
+    model, ref, _ = oracle.simulate(lab, prm.as_dict(), dt, steps)
+    w = I.Workload("odd grid", lab, prm, dt, steps)
+    cell, states, infos = run_gpu(mbx, w, prec, steps)
+    for k in range(steps):
+        assert abs(infos[k]["V"] - model.voltage(ref[k + 1])) <= 1e-6
+        for f, e in field_errors(model, states[k], ref[k + 1]).items():
+            assert e <= bar, (k, f, e)
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-8), ("mixed", 1e-6)])
 def test_downscaled_config1_matches_live_oracle(mbx, prec, bar):
     """Same recipe as the 64x64x160 workload (2C, 5 s steps) on a 16x16x40 grid,
     oracle computed live."""
