@@ -536,17 +536,18 @@ __global__ void __launch_bounds__(kBlock) k_finalize_dots(CellDev* cells, int nc
 }
 
 // First Gram-Schmidt pass and the second pass's dot products in one kernel:
-// w -= sum_j H(j,k) V_j, then block partials of V_j . w for j <= k.  FP32
-// basis: the thread's basis entries (at most kMaxRestart pairs) stay in
-// registers between the two, so the basis is read once.  FP64 basis: they
-// are read a second time for the dots (holding them would cut the
-// occupancy to two waves per SIMD).  The arithmetic is the same either way.
+// w -= sum_j H(j,k) V_j, then block partials of V_j . w for j <= k.  The
+// thread's basis entries (at most kMaxRestart pairs) stay in registers
+// between the two, so the basis is read once (FP32: 96 VGPRs; FP64: 172, two
+// waves per SIMD, still faster than reading the basis twice).  The dots come
+// from registers, which makes their reduction the critical path: it goes
+// through LDS (block_dots8) rather than per-wave shuffles.
 template <typename KT>
 __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2* __restrict__ blk, int k) {
   const int2 bb = block_of(blk);
   const CellDev& cd = cells[bb.x];
   if (!cd.active || cd.ictl[CTL_DONE]) return;
-  __shared__ double lds[4 * kPartStride];
+  __shared__ double lds[kDotsLds];
   const int m = cd.m;
   const double* hc = cd.gm + gm_H(m) + (size_t)(m + 1) * k;
   const int i = bb.y * kBlock + threadIdx.x;
@@ -559,78 +560,45 @@ __global__ void __launch_bounds__(kBlock) k_orth_dots(CellDev* cells, const int2
     wp = w[N + i];
   }
   const uint32_t off = in ? (uint32_t)i * (uint32_t)sizeof(KT) : kNoOff, soff = (uint32_t)(N * sizeof(KT));
-  // eight basis vectors from chunk start c (indices past k clamp to k)
-  auto load8 = [&](int c, KT (&vc)[8], KT (&vp)[8]) {
+  constexpr int kCh = kMaxRestart / 8;
+  KT vc[kCh][8], vp[kCh][8];
 #pragma unroll
-    for (int jj = 0; jj < 8; ++jj) {
-      const BufRes r = basis_buf<KT>(cd, c + jj < k ? c + jj : k);
-      vc[jj] = buf_ld<KT>(r, off);
-      vp[jj] = buf_ld<KT>(r, off, soff);
-    }
-  };
-  auto update8 = [&](int c, const KT (&vc)[8], const KT (&vp)[8]) {
+  for (int ch = 0; ch < kCh; ++ch)
+    if (8 * ch <= k) {
 #pragma unroll
-    for (int jj = 0; jj < 8; ++jj)
-      if (c + jj <= k) {
-        const KT hj = (KT)hc[c + jj];
-        wc -= hj * vc[jj];
-        wp -= hj * vp[jj];
+      for (int jj = 0; jj < 8; ++jj) {   // indices past k clamp to k (loaded, not used)
+        const BufRes r = basis_buf<KT>(cd, 8 * ch + jj < k ? 8 * ch + jj : k);
+        vc[ch][jj] = buf_ld<KT>(r, off);
+        vp[ch][jj] = buf_ld<KT>(r, off, soff);
       }
-  };
-  auto dots8 = [&](int c, const KT (&vc)[8], const KT (&vp)[8], double dwc, double dwp) {
-#pragma unroll
-    for (int jj = 0; jj < 8; ++jj)
-      if (c + jj <= k) wave_to_lds((double)vc[jj] * dwc + (double)vp[jj] * dwp, false, lds, kPartStride, c + jj);
-  };
-  auto store_w = [&]() {
-    if (in) {
-      w[i] = wc;
-      w[N + i] = wp;
-    } else {
-      wc = (KT)0;
-      wp = (KT)0;
     }
-  };
-  if constexpr (sizeof(KT) == sizeof(float)) {
-    constexpr int kCh = kMaxRestart / 8;
-    KT vc[kCh][8], vp[kCh][8];
 #pragma unroll
-    for (int ch = 0; ch < kCh; ++ch)
-      if (8 * ch <= k) load8(8 * ch, vc[ch], vp[ch]);
+  for (int ch = 0; ch < kCh; ++ch)
+    if (8 * ch <= k) {
 #pragma unroll
-    for (int ch = 0; ch < kCh; ++ch)
-      if (8 * ch <= k) update8(8 * ch, vc[ch], vp[ch]);
-    store_w();
-    const double dwc = (double)wc, dwp = (double)wp;
-    // the dots come from registers: the reduction is the critical path here,
-    // so it goes through LDS (block_dots8) rather than per-wave shuffles
-    __shared__ double ldsd[kDotsLds];
-#pragma unroll
-    for (int ch = 0; ch < kCh; ++ch)
-      if (8 * ch <= k) {
-        double t[8];
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) t[jj] = (double)vc[ch][jj] * dwc + (double)vp[ch][jj] * dwp;
-        block_dots8(cd, bb.y, 8 * ch, k, t, ldsd);
-      }
-    return;
+      for (int jj = 0; jj < 8; ++jj)
+        if (8 * ch + jj <= k) {
+          const KT hj = (KT)hc[8 * ch + jj];
+          wc -= hj * vc[ch][jj];
+          wp -= hj * vp[ch][jj];
+        }
+    }
+  if (in) {
+    w[i] = wc;
+    w[N + i] = wp;
   } else {
-    for (int c = 0; c <= k; c += 8) {
-      KT vc[8], vp[8];
-      load8(c, vc, vp);
-      update8(c, vc, vp);
-    }
-    store_w();
-    const double dwc = (double)wc, dwp = (double)wp;
-    for (int c = 0; c <= k; c += 8) {
-      KT vc[8], vp[8];
-      load8(c, vc, vp);
-      dots8(c, vc, vp, dwc, dwp);
-    }
+    wc = (KT)0;
+    wp = (KT)0;
   }
-  __syncthreads();
-  for (int j = threadIdx.x; j <= k; j += kBlock)
-    cd.part[(size_t)j * cd.nblk + bb.y] = combine4(lds, kPartStride, j, false);
+  const double dwc = (double)wc, dwp = (double)wp;
+#pragma unroll
+  for (int ch = 0; ch < kCh; ++ch)
+    if (8 * ch <= k) {
+      double t[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) t[jj] = (double)vc[ch][jj] * dwc + (double)vp[ch][jj] * dwp;
+      block_dots8(cd, bb.y, 8 * ch, k, t, lds);
+    }
 }
 
 // w -= sum_j h_j V_j with h = H(:,k) (src = 0) or tmp (src = 1); block
