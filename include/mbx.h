@@ -134,7 +134,8 @@ int mbx_params_default(mbx_params *p);
  * interface current vanish.
  * Size limits: nz >= 2, nx*ny*nz below 2^27 voxels (the kernels address
  * the FP64 GMRES iterate, 16 bytes per voxel, with 32-bit byte offsets), fewer
- * than 2^24 interface faces (anode plus cathode).
+ * than 2^24 interface faces (anode plus cathode), nx and ny at most 2^21 and
+ * ny*nz at most 2^23 (the kernels' index division).
  * Errors: MBX_EINVAL (bad sizes/parameters), MBX_ELABEL, MBX_ENOMEM, MBX_EHIP. */
 int mbx_cell_create(const uint8_t *labels, int nx, int ny, int nz,
                     const mbx_params *p, void *stream, mbx_cell **out);

@@ -305,6 +305,15 @@ bool cutoff_reached(const mbx_params& p, double V) {
 
 namespace {
 
+// Smallest double >= 1/d (d >= 1), the reciprocal the kernels' divmod needs:
+// RN(1/d), moved up one step when it lies below 1/d (the fused product
+// r*d - 1 carries the exact sign).
+double rcp_up(int d) {
+  double r = 1.0 / d;
+  if (std::fma(r, (double)d, -1.0) < 0.0) r = std::nextafter(r, 2.0);
+  return r;
+}
+
 int check_params(const mbx_params* p) {
   if (!p) return fail(MBX_EINVAL, "null parameter struct");
   if (!finite_pos(p->T) || !finite_pos(p->h) || !finite_pos(p->c0) || !finite_pos(p->De) ||
@@ -1224,6 +1233,9 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   if (nx < 1 || ny < 1 || nz < 2) return fail(MBX_EINVAL, "grid must be at least 1 x 1 x 2");
   const int64_t N64 = (int64_t)nx * ny * nz;
   if (N64 > (1 << 28)) return fail(MBX_EINVAL, "grid too large (more than 2^28 voxels)");
+  // the kernels' index division (divmod) is exact for divisors up to 2^21 and quotients below 2^24
+  if (nx > (1 << 21) || ny > (1 << 21) || (int64_t)ny * nz > (1 << 23))
+    return fail(MBX_EINVAL, "grid too elongated (nx and ny at most 2^21, ny*nz at most 2^23)");
   if (int e = check_params(pin)) return e;
   mbx_params p = *pin;
   // scaled-update tolerance: 100x below each mode's state-error target (FP64 1e-8, mixed 1e-6)
@@ -1404,8 +1416,9 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   for (int l = 0; l < c->ld.n; ++l) {
     MGLevel& lv = h.lv[l];
     const int lnx = l == 0 ? nx : c->ld.nx[l], lny = l == 0 ? ny : c->ld.ny[l];
-    lv.inv_hx = 1.0 / ((lnx + 1) / 2);
-    lv.inv_ny = 1.0 / lny;
+    lv.inv_hx = rcp_up((lnx + 1) / 2);
+    lv.inv_nx = rcp_up(lnx);
+    lv.inv_ny = rcp_up(lny);
   }
   for (int l = 1; l < c->ld.n; ++l) {
     const int o = 41 + 7 * (l - 1);
@@ -1430,9 +1443,8 @@ int mbx_cell_create(const uint8_t* labels, int nx, int ny, int nz, const mbx_par
   h.Zb = b + L.off[43 + 7 * (c->ld.n - 1)];
   h.rbhx = (nx + 1) / 2;
   h.rbH = h.rbhx * ny * nz;
-  h.inv_nx = 1.0 / nx;
-  h.inv_ny = 1.0 / ny;
-  h.inv_rbhx = 1.0 / h.rbhx;
+  h.inv_nx = rcp_up(nx);
+  h.inv_ny = rcp_up(ny);
   h.meta_rb = (const uint32_t*)(b + L.off[44 + 7 * (c->ld.n - 1)]);
   h.x_rb = b + L.off[45 + 7 * (c->ld.n - 1)];
   h.c_prev = (double*)(b + L.off[46 + 7 * (c->ld.n - 1)]);

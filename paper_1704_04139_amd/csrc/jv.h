@@ -71,7 +71,8 @@ __device__ inline void jv_row(const CellDev& cd, int i, const VT* __restrict__ v
     const bool iface = (L == PORE) != (Lk == PORE);
     const uint32_t f = iface ? face_rank(pore_side ? mk[d] : mi, pore_side ? (d ^ 1) : d) : 0u;
     const bool an = (pore_side ? Lk : L) == ANODE;
-    const uint32_t co = an ? 5u * f * kt : ca_off + 3u * f * kt;
+    // face indices are below 2^24 (checked at creation): 24-bit products
+    const uint32_t co = an ? __umul24(f, 5u * kt) : ca_off + __umul24(f, 3u * kt);
     const AT c0 = (AT)buf_ld<KT>(rco, co), c1 = (AT)buf_ld<KT>(rco, co + kt), c2 = (AT)buf_ld<KT>(rco, co + 2 * kt);
     const AT c3v = (AT)buf_ld<KT>(rco, an ? co + 3 * kt : kNoOff), c4v = (AT)buf_ld<KT>(rco, an ? co + 4 * kt : kNoOff);
     const AT vs = pore_side ? vk : vc, ve = pore_side ? vc : vk;     // solid / pore values

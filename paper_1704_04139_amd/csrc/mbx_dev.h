@@ -39,7 +39,7 @@ constexpr double kToBoundary = 0.1;   // a Newton update leaves at least this fr
 constexpr int kOpStride = 33;   // per coarse cell: E[3], X[3], G[3 dirs][3][3] (SoA)
 struct MGLevel {
   int nx, ny, nz, ncell;
-  double inv_hx, inv_ny;   // 1 / ceil(nx/2) and 1 / ny (red-black thread mapping)
+  double inv_hx, inv_nx, inv_ny;   // smallest doubles >= 1/ceil(nx/2), 1/nx, 1/ny (divmod)
   void* x;       // KT [3*ncell] (slot-major)
   void* b;       // KT [3*ncell]
   void* op[2];   // KT [kOpStride*ncell] for the concentration (0) and potential (1) operators
@@ -132,7 +132,7 @@ struct CellDev {
   // rbhx = ceil(nx/2) and rbH = rbhx*ny*nz (odd nx leaves padding slots), so a
   // half sweep reads and writes whole cache lines of one colour.
   int rbhx, rbH;
-  double inv_nx, inv_ny, inv_rbhx;  // reciprocals for the index arithmetic (divmod)
+  double inv_nx, inv_ny;   // smallest doubles >= 1/nx and 1/ny (divmod)
   const uint32_t* meta_rb;           // meta words in colour-split order; the face-base field (bits 8-31)
                                      // holds the start of the voxel's list in its colour's part of cond_rb
   void *x_rb;                        // KT [2 rbH] level-0 iterate of the V-cycle being run
@@ -169,16 +169,16 @@ __host__ __device__ inline int gm_size(int m) { return (m + 1) * m + 2 * (m + 1)
 struct VoxCoord {
   int x, y, z;
 };
-// Quotient and remainder of n / d (0 <= n < 2^31, d >= 1) from the FP64
-// reciprocal inv = 1/d: the product is within 2^-20 of the exact n/d, so its
-// truncation is off by at most one, and one correction step makes it exact.
-// A few instructions instead of the integer division sequence.
+// Quotient and remainder of n / d for 0 <= n < 2^31, 1 <= d <= 2^21 and
+// n / d < 2^24, from inv = the smallest double >= 1/d.  Then n*inv lies in
+// [n/d, n/d + 2^-20/d], and the rounded product in [floor(n/d),
+// floor(n/d) + 1 - 1/d + 2^-20/d + 2^-22]: below the next integer whenever
+// d <= 2^21, so its truncation is floor(n/d) with no correction step.  The
+// remainder's product fits the 24-bit multiplier (full rate, where the 32-bit
+// one is quarter rate).
 __device__ inline int divmod(int n, int d, double inv, int& r) {
-  int q = (int)((double)n * inv);
-  r = n - q * d;
-  const bool hi = r >= d, lo = r < 0;   // selects, not branches
-  q += hi ? 1 : (lo ? -1 : 0);
-  r += hi ? -d : (lo ? d : 0);
+  const int q = (int)((double)n * inv);
+  r = n - (int)__umul24((unsigned)q, (unsigned)d);
   return q;
 }
 __device__ inline VoxCoord coord_of(const CellDev& cd, int i) {

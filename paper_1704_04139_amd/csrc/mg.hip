@@ -74,12 +74,9 @@ __device__ inline KT* vsel(const CellDev& cd, int sel) {
 struct C3 {
   int x, y, z;
 };
-__device__ inline C3 c3_of(int i, int nx, int ny) {
+__device__ inline C3 c3_of(int i, int nx, int ny, double inv_nx, double inv_ny) {
   C3 c;
-  c.x = i % nx;
-  const int t = i / nx;
-  c.y = t % ny;
-  c.z = t / ny;
+  c.z = divmod(divmod(i, nx, inv_nx, c.x), ny, inv_ny, c.y);
   return c;
 }
 
@@ -149,12 +146,16 @@ __device__ inline int fine_nbr(int i, const C3& c, int nx, int ny, int nz, int d
 // cells are then contiguous (whole cache lines instead of every other
 // element); the +-y and +-z neighbours keep the strides nx and nx*ny.
 __device__ inline int xperm(int x, int nx) { return (x >> 1) + (x & 1) * ((nx + 1) >> 1); }
-__device__ inline int lvl_index(int x, int y, int z, int nx, int ny) { return xperm(x, nx) + nx * (y + ny * z); }
+// (non-negative coordinates inside the level; the products fit the 24-bit
+// multiplier under the grid limits nx, ny <= 2^21 and ny*nz <= 2^23)
+__device__ inline int lvl_index(int x, int y, int z, int nx, int ny) {
+  return xperm(x, nx) + (int)__umul24((unsigned)nx, (unsigned)(y + (int)__umul24((unsigned)ny, (unsigned)z)));
+}
 __device__ inline int lvl_cell(const MGLevel& L, int x, int y, int z) { return lvl_index(x, y, z, L.nx, L.ny); }
 // coordinates of the cell stored at index c
-__device__ inline C3 lvl_coords(int c, int nx, int ny) {
-  C3 q = c3_of(c, nx, ny);   // q.x: position in the row
-  const int he = (nx + 1) >> 1;
+__device__ inline C3 lvl_coords(int c, const MGLevel& G) {
+  C3 q = c3_of(c, G.nx, G.ny, G.inv_nx, G.inv_ny);   // q.x: position in the row
+  const int he = (G.nx + 1) >> 1;
   q.x = q.x < he ? 2 * q.x : 2 * (q.x - he) + 1;
   return q;
 }
@@ -224,9 +225,10 @@ __device__ inline void voxel_row(const CellDev& cd, int color, int p, const C3& 
                                  const KT* __restrict__ xsrc, bool zero, bool corr, KT& D, KT& S) {
   constexpr uint32_t kt = sizeof(KT);
   // colour-split neighbours (+x, -x, +y, -y, +z, -z): the other colour, at
-  // q0 = the slot of (x, y, z) in that colour's rows
-  const int row = c.y + cd.ny * c.z, hx = cd.rbhx;
-  const int q0 = (1 - color) * cd.rbH + row * hx + (c.x >> 1);
+  // q0 = the slot of (x, y, z) in that colour's rows (p's slot, moved by
+  // one colour block: both colours index rows and columns alike)
+  const int hx = cd.rbhx;
+  const int q0 = p + (1 - 2 * color) * cd.rbH;
   const int odd = c.x & 1;
   bool ex[6];
   ex[0] = c.x + 1 < cd.nx; ex[1] = c.x > 0;
@@ -419,7 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_cond_rb(CellDev* cells, const int2* 
   const uint32_t mi = cd.meta[i];
   const uint32_t msk = mask_of(mi);
   if (!msk) return;
-  const C3 c = c3_of(i, cd.nx, cd.ny);
+  const C3 c = c3_of(i, cd.nx, cd.ny, cd.inv_nx, cd.inv_ny);
   const int color = (c.x + c.y + c.z) & 1;
   KT* out = (KT*)cd.cond_rb + (size_t)color * (cd.F_an + cd.F_ca) + base_of(cd.meta_rb[rb_index(cd, c.x, c.y, c.z)]);
   const int L = lab_of(mi);
@@ -451,7 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_assemble0(CellDev* cells, const i
   const MGLevel& L1 = cd.lv[1];
   const int C = bb.y * kBlock + threadIdx.x;
   if (C >= L1.ncell) return;
-  const C3 q = lvl_coords(C, L1.nx, L1.ny);
+  const C3 q = lvl_coords(C, L1);
   KT E[3] = {0, 0, 0}, X[3] = {0, 0, 0}, G[27];
   for (int k = 0; k < 27; ++k) G[k] = (KT)0;
   for (int dz = 0; dz < 2; ++dz)
@@ -510,7 +512,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_assemble(CellDev* cells, const in
   const MGLevel& Lp = cd.lv[l + 1];
   const int P = bb.y * kBlock + threadIdx.x;
   if (P >= Lp.ncell) return;
-  const C3 q = lvl_coords(P, Lp.nx, Lp.ny);
+  const C3 q = lvl_coords(P, Lp);
   const OpV<KT> A{(const KT*)Lc.op[op], Lc.ncell};
   KT E[3] = {0, 0, 0}, X[3] = {0, 0, 0}, G[27];
   for (int k = 0; k < 27; ++k) G[k] = (KT)0;
@@ -557,7 +559,7 @@ __device__ inline void coarse_assemble(const MGLevel& L, const OpV<KT>& A, doubl
   __syncthreads();
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     const int c = r / 3, s = r % 3;
-    const C3 q = lvl_coords(c, L.nx, L.ny);
+    const C3 q = lvl_coords(c, L);
     double D = (double)A.E(c, s);
     for (int t = 0; t < 3; ++t)
       if (t != s) {
@@ -666,7 +668,8 @@ __global__ void __launch_bounds__(BS) k_mg0_smooth(CellDev* cells, const int2* _
   if (!gate_state(cd, need)) return;
   const KT xn = D > (KT)0 ? (bi + S) / D : (KT)0;
   buf_st(buf_of(x0, nrb * (uint32_t)sizeof(KT)), (uint32_t)p * (uint32_t)sizeof(KT), xn);
-  if (post && it == cd.nu - 1) ((KT*)cd.z)[(size_t)OP * cd.N + c.x + cd.nx * (c.y + cd.ny * c.z)] = xn;
+  if (post && it == cd.nu - 1)
+    ((KT*)cd.z)[(size_t)OP * cd.N + c.x + __umul24((unsigned)cd.nx, (unsigned)(c.y + (int)__umul24((unsigned)cd.ny, (unsigned)c.z)))] = xn;
 }
 
 // Sum over the 4 lanes of an aligned lane group (xor butterfly: every lane
@@ -702,7 +705,7 @@ __global__ void __launch_bounds__(kBlock) k_mg0_restrict(CellDev* cells, const i
   const bool live = C < L1.ncell;   // whole 4-lane groups share C: shuffles stay within live groups
   KT rs[3] = {0, 0, 0};
   if (live) {
-    const C3 fc = red_child(lvl_coords(C, L1.nx, L1.ny), ch);
+    const C3 fc = red_child(lvl_coords(C, L1), ch);
     if (fc.x < cd.nx && fc.y < cd.ny && fc.z < cd.nz) {
       const KT* x0 = (const KT*)cd.x_rb;
       const int p = rb_index(cd, fc.x, fc.y, fc.z);
@@ -818,7 +821,7 @@ __global__ void __launch_bounds__(kBlock) k_mgl_restrict(CellDev* cells, const i
   const bool live = P < Lp.ncell;   // whole 4-lane groups share P
   KT rs[3] = {0, 0, 0};
   if (live) {
-    const C3 c = red_child(lvl_coords(P, Lp.nx, Lp.ny), ch);
+    const C3 c = red_child(lvl_coords(P, Lp), ch);
     if (c.x < L.nx && c.y < L.ny && c.z < L.nz) residual_cell<KT, OP>(view<KT>(L, OP), lvl_cell(L, c.x, c.y, c.z), c, rs);
   }
   for (int s = 0; s < 3; ++s) rs[s] = lane4_sum(rs[s]);
@@ -875,7 +878,7 @@ __global__ void __launch_bounds__(kFuseBlock) k_mg_coarse_cycle(CellDev* cells, 
     }
     // red children only, summed as the 4-lane restriction kernel sums them
     for (int P = threadIdx.x; P < Lp.ncell; P += blockDim.x) {
-      const C3 q = lvl_coords(P, Lp.nx, Lp.ny);
+      const C3 q = lvl_coords(P, cd.lv[l + 1]);
       KT r[4][3];
       for (int ch = 0; ch < 4; ++ch) {
         const C3 c = red_child(q, ch);
@@ -931,7 +934,7 @@ __global__ void __launch_bounds__(kFuseBlock) k_mg_coarse_cycle(CellDev* cells, 
         __syncthreads();
       }
     for (int P = threadIdx.x; P < Lp.ncell; P += blockDim.x) {
-      const C3 q = lvl_coords(P, Lp.nx, Lp.ny);
+      const C3 q = lvl_coords(P, cd.lv[l + 1]);
       KT acc[3] = {0, 0, 0};
       for (int ch = 0; ch < 8; ++ch) {
         const int cx = 2 * q.x + (ch & 1), cy = 2 * q.y + ((ch >> 1) & 1), cz = 2 * q.z + (ch >> 2);
@@ -1004,7 +1007,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_pre(CellDev* cells, const int2* _
   const KT vc = v[i], vp = v[(size_t)cd.N + i];
   const KT r = lab_of(mi) == PORE ? vc - (KT)cd.tau * vp : vc;
   if (!gate_state(cd, need)) return;
-  const C3 c = c3_of(i, cd.nx, cd.ny);
+  const C3 c = c3_of(i, cd.nx, cd.ny, cd.inv_nx, cd.inv_ny);
   ((KT*)cd.b0)[rb_index(cd, c.x, c.y, c.z)] = r;
 }
 
@@ -1028,7 +1031,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* _
   const BufRes rv = buf_of(vsel<KT>(cd, src), 2u * N * kt);
   const uint32_t ca_off = (uint32_t)((const char*)cd.coef_ca - (const char*)cd.coef_an);
   const BufRes rco = buf_of(cd.coef_an, ca_off + 3u * (uint32_t)(cd.F_ca > 0 ? cd.F_ca : 1) * kt);
-  const C3 c = c3_of(i, cd.nx, cd.ny);
+  const C3 c = c3_of(i, cd.nx, cd.ny, cd.inv_nx, cd.inv_ny);
   int k[6];
   bool ex[6];
   neighbours6(i, c, cd.nx, cd.ny, cd.nz, k, ex);
@@ -1060,7 +1063,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_mid(CellDev* cells, const int2* _
     const bool pore_side = L == PORE;
     const uint32_t f = iface ? face_rank(pore_side ? mk[j] : mi, pore_side ? (d ^ 1) : d) : 0u;
     const bool an = (pore_side ? Lk : L) == ANODE;
-    const uint32_t co = an ? 5u * f * kt : ca_off + 3u * f * kt;
+    const uint32_t co = an ? __umul24(f, 5u * kt) : ca_off + __umul24(f, 3u * kt);   // f < 2^24
     const KT c0 = buf_ld<KT>(rco, co), c1 = buf_ld<KT>(rco, co + kt), c3 = buf_ld<KT>(rco, co + (an ? 3 : 1) * kt);
     const KT vs = pore_side ? vk[j] : vc, vpo = pore_side ? vc : vk[j];
     // interface flux derivative w.r.t. the concentrations (potential part zero)
