@@ -450,7 +450,8 @@ int mbx_pod_noalloc(const double *S, int64_t n, int m, int64_t lds, const double
  * convergence). */
 int mbx_sym_eig(int m, const double *A, double *lam, double *V);
 
-/* Device bytes a cell of this size would allocate (for admission control). */
+/* Device bytes a cell of this size would allocate (for admission control);
+ * -1 for a shape mbx_cell_create refuses by its size limits. */
 int64_t mbx_cell_footprint(int nx, int ny, int nz, int precision, int n_an_faces, int n_ca_faces);
 
 /* Message for the last failure on this thread ("" if none). */

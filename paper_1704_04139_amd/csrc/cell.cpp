@@ -1220,6 +1220,7 @@ int mbx_params_default(mbx_params* p) {
 int64_t mbx_cell_footprint(int nx, int ny, int nz, int precision, int n_an_faces, int n_ca_faces) {
   const int64_t N = (int64_t)nx * ny * nz;
   if (N <= 0 || N > (1 << 28)) return -1;
+  if (nx > (1 << 21) || ny > (1 << 21) || (int64_t)ny * nz > (1 << 23)) return -1;
   const int nblk = (int)((N + kBlock - 1) / kBlock);
   Layout L = make_layout((int)N, n_an_faces, n_ca_faces, nblk, restart_len(), kt_size(precision),
                          level_dims(nx, ny, nz, kt_size(precision)));

@@ -3,8 +3,10 @@ every entry point that include/mbx.h declares, and the binding knows them."""
 import os
 import re
 
+import numpy as np
 import pytest
 
+from paper_1704_04139_amd import inputs as I
 from paper_1704_04139_amd import mbx
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -41,6 +43,19 @@ def test_params_default_and_footprint():
     f32 = mbx.footprint(64, 64, 160, "mixed", 90000, 90000)
     assert 0 < f32 < f64 < 2e9
     assert mbx.footprint(0, 4, 4) == -1
+
+
+def test_create_rejects_grids_beyond_the_index_division_limits():
+    # the kernels divide voxel and thread indices by nx, ny and ceil(nx/2)
+    # exactly only for extents up to 2^21 and ny*nz up to 2^23: creation
+    # refuses other shapes before it touches the device
+    prm = mbx.make_params(I.config0().params, "mixed")
+    for nz, ny, nx in [(2, 1, 2 ** 21 + 1), (2, 2 ** 21 + 1, 1), (2 ** 11 + 1, 2 ** 12, 1)]:
+        with pytest.raises(mbx.MbxError) as e:
+            mbx.Cell(np.zeros((nz, ny, nx), np.uint8), prm)
+        assert e.value.code == mbx.MBX_EINVAL and "elongated" in str(e.value)
+        assert mbx.footprint(nx, ny, nz, "mixed") == -1
+    assert mbx.footprint(2 ** 21, 1, 2, "mixed") > 0
 
 
 def test_missing_library_fails_loudly(tmp_path):
