@@ -90,6 +90,7 @@ template <typename KT> void launch_precond(const BatchLaunch& b, int src, int ne
 
 // POD by the method of snapshots (pod.hip).  Snapshots S: n x m column-major.
 int gram_tile();               // edge of the Gram tiles (pairs index tiles of this size)
+int gram_all_cols();           // sets at most this wide: one workgroup per row slice computes every pair
 int gram_rows_step();          // rows per split are a multiple of this
 int modes_cols_per_thread();   // kpad is a multiple of this
 // partial Gram tiles part[(y npairs + p) tile^2] of W S[:, ti] ^T S[:, tj] over row slice y

@@ -224,10 +224,11 @@ PodPlan pod_plan(int64_t n, int m, int k_cap) {
   for (int ti = 0; ti < nt; ++ti)
     for (int tj = ti; tj < nt; ++tj) P.pairs.push_back(make_int2(ti, tj));
   P.np = (int)P.pairs.size();
-  // row slices: about 2048 workgroups in all, each slice a multiple of the
-  // staging step
+  // row slices, each a multiple of the staging step: about 2048 workgroups in
+  // all when each owns one tile pair; one per compute unit (256) when each
+  // owns a slice of every pair (sets at most gram_all_cols() wide)
   const int step = gram_rows_step();
-  const int64_t want = std::max<int64_t>(1, 2048 / P.np);
+  const int64_t want = m <= gram_all_cols() ? 256 : std::max<int64_t>(1, 2048 / P.np);
   int64_t R = (n + want - 1) / want;
   P.R = (R + step - 1) / step * step;
   P.nsplit = (int)((n + P.R - 1) / P.R);

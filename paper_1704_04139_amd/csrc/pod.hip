@@ -96,6 +96,112 @@ __global__ void __launch_bounds__(kGThreads)
   for (int r = 0; r < 4; ++r) out[(wr + lk + 4 * r) * kGT + wc + li] = acc[r];
 }
 
+// The same partial tiles when the whole snapshot set is at most kGAllCols
+// columns wide: one workgroup per row slice stages each row chunk of all m
+// columns in LDS once (two buffers: the next chunk is stored while the
+// current one is consumed, one barrier per chunk) and computes every tile
+// pair from it, so each snapshot entry is fetched once (the pair-per-workgroup
+// kernel above fetches a column tile once for every pair that holds it).
+// Wavefront v takes the NU 16x16 blocks u = v, v + 8, ... (tile pair u / 4,
+// quarter u % 4), every one of them in the multiply loop (no branches there:
+// blocks below the diagonal or past m read staged columns and write zeros).
+// Each block is accumulated over the rows in the same order as above, so the
+// reduction reads the same partial layout.
+constexpr int kGAllCols = 128;                              // widest set staged whole (4 tiles, 10 pairs)
+constexpr int kGAllThreads = 512;                           // 8 wavefronts
+constexpr int kGAllPer = (kGK * kGAllCols) / kGAllThreads;  // staged values per thread at most
+
+template <bool kW, int NU>
+__global__ void __launch_bounds__(kGAllThreads)
+    k_gram_all(const double* __restrict__ S, int64_t n, int m, int64_t lds, const double* __restrict__ w, int64_t R,
+               const int2* __restrict__ pairs, int npairs, double* __restrict__ part) {
+  __shared__ double Ss[2][kGK][kGAllCols + 1];
+  __shared__ double Ws[2][kGK];
+  const int y = blockIdx.x;
+  const int t = threadIdx.x;
+  const int wv = t >> 6, l = t & 63;
+  const int li = l & 15, lk = l >> 4;
+  const int mp = (m + kGT - 1) / kGT * kGT;   // staged columns: whole tiles
+  const int nst = kGK * mp;                   // staged values per chunk
+  int ca[NU], cb[NU];
+  bool live[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int b = wv + 8 * u, pp = b >> 2, q = b & 3;
+    const int wr = (q >> 1) * 16, wc = (q & 1) * 16;
+    const int2 tt = pp < npairs ? pairs[pp] : make_int2(0, 0);
+    ca[u] = tt.x * kGT + wr + li;
+    cb[u] = tt.y * kGT + wc + li;
+    live[u] = pp < npairs && tt.x * kGT + wr < m && tt.y * kGT + wc < m && !(tt.x == tt.y && wr > wc);
+  }
+  dbl4 acc[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int64_t r_begin = (int64_t)y * R;
+  const int64_t r_end = r_begin + R < n ? r_begin + R : n;
+  double pv[kGAllPer], pw = 0.0;
+  auto fetch = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < kGAllPer; ++q) {
+      const int e = q * kGAllThreads + t;
+      const int row = e % kGK, col = e / kGK;
+      const int64_t rg = r0 + row;
+      pv[q] = (e < nst && rg < r_end && col < m) ? S[rg + (int64_t)col * lds] : 0.0;
+    }
+    if (kW && t < kGK) pw = r0 + t < r_end ? w[r0 + t] : 0.0;
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < kGAllPer; ++q) {
+      const int e = q * kGAllThreads + t;
+      if (e < nst) Ss[buf][e % kGK][e / kGK] = pv[q];
+    }
+    if (kW && t < kGK) Ws[buf][t] = pw;
+  };
+  if (r_begin < r_end) {
+    fetch(r_begin);
+    stage(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGK, cur ^= 1) {
+    const bool more = r0 + kGK < r_end;
+    if (more) fetch(r0 + kGK);
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 4)
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        double a = Ss[cur][kk + lk][ca[u]];
+        if (kW) a *= Ws[cur][kk + lk];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ss[cur][kk + lk][cb[u]], acc[u], 0, 0, 0);
+      }
+    if (more) stage(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int b = wv + 8 * u, pp = b >> 2, q = b & 3;
+    if (pp >= npairs) break;
+    const int wr = (q >> 1) * 16, wc = (q & 1) * 16;
+    double* out = part + ((int64_t)y * npairs + pp) * (kGT * kGT);
+    for (int r = 0; r < 4; ++r) out[(wr + lk + 4 * r) * kGT + wc + li] = live[u] ? acc[u][r] : 0.0;
+  }
+}
+
+template <bool kW>
+void launch_gram_all(const double* S, int64_t n, int m, int64_t lds, const double* w, int64_t R, int nsplit,
+                     const int2* pairs, int npairs, double* part, hipStream_t s) {
+  const int nu = (4 * npairs + 7) / 8;   // blocks per wavefront: 1, 2, 3 or 5 for 1, 3, 6 or 10 pairs
+  if (nu <= 1)
+    k_gram_all<kW, 1><<<nsplit, kGAllThreads, 0, s>>>(S, n, m, lds, w, R, pairs, npairs, part);
+  else if (nu == 2)
+    k_gram_all<kW, 2><<<nsplit, kGAllThreads, 0, s>>>(S, n, m, lds, w, R, pairs, npairs, part);
+  else if (nu == 3)
+    k_gram_all<kW, 3><<<nsplit, kGAllThreads, 0, s>>>(S, n, m, lds, w, R, pairs, npairs, part);
+  else
+    k_gram_all<kW, 5><<<nsplit, kGAllThreads, 0, s>>>(S, n, m, lds, w, R, pairs, npairs, part);
+}
+
 // K from the partial tiles.  A block of kRGroups wavefronts owns 64 entries:
 // wavefront g sums the slices y = g, g + kRGroups, ... (two running sums, so
 // two loads are in flight), and the group sums are added in group order, so
@@ -152,11 +258,19 @@ __global__ void __launch_bounds__(256)
 }  // namespace
 
 int gram_tile() { return kGT; }
+int gram_all_cols() { return kGAllCols; }
 int gram_rows_step() { return kGK; }
 int modes_cols_per_thread() { return kMQ; }
 
 void launch_gram(const double* S, int64_t n, int m, int64_t lds, const double* w, int64_t rows_per_split, int nsplit,
                  const int2* pairs, int npairs, double* part, hipStream_t s) {
+  if (m <= kGAllCols) {
+    if (w)
+      launch_gram_all<true>(S, n, m, lds, w, rows_per_split, nsplit, pairs, npairs, part, s);
+    else
+      launch_gram_all<false>(S, n, m, lds, w, rows_per_split, nsplit, pairs, npairs, part, s);
+    return;
+  }
   if (w)
     k_gram<true><<<dim3(npairs, nsplit), kGThreads, 0, s>>>(S, n, m, lds, w, rows_per_split, pairs, npairs, part);
   else

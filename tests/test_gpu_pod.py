@@ -130,7 +130,7 @@ def test_pod_edge_cases(mbx, torch):
     S = np.stack([y] * 5, axis=1)
     modes, sigma, k = gpu_pod(mbx, torch, S)
     assert k == 1 and abs(sigma[0] - np.sqrt(5.0) * np.linalg.norm(y)) <= 1e-12 * sigma[0]
-    # k_max below the tolerance count; three column tiles (m = 150)
+    # k_max below the tolerance count; five column tiles (m = 150)
     S = prescribed(2000, 150, 0.8 ** np.arange(40), 3)
     modes, sigma, k = gpu_pod(mbx, torch, S, rtol=1e-7, k_max=9)
     assert k == 9
@@ -138,6 +138,19 @@ def test_pod_edge_cases(mbx, torch):
     # all-zero snapshots: nothing kept
     modes, sigma, k = gpu_pod(mbx, torch, np.zeros((40, 3)))
     assert k == 0 and np.all(sigma == 0.0)
+
+
+def test_pod_widths_at_the_staged_set_limit(mbx, torch):
+    """Set widths at the edge of the Gram kernel that stages whole row chunks:
+    128 columns (four tiles, ten tile pairs, five 16x16 blocks per wavefront)
+    and 129 (the first width the pair-per-workgroup kernel takes), weighted,
+    with a ragged last row slice."""
+    rng = np.random.default_rng(21)
+    for m, seed in ((128, 22), (129, 23)):
+        w = rng.uniform(0.5, 2.0, 3001)
+        S = prescribed(3001, m, 0.7 ** np.arange(30), seed, w)
+        modes, sigma, k = gpu_pod(mbx, torch, S, w=w, rtol=1e-5, lds_pad=2)
+        compare(S, w, modes, sigma, k, 1e-5, label=f"m={m} weighted")
 
 
 def test_pod_argument_checks(mbx, torch):
