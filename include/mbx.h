@@ -420,8 +420,9 @@ int mbx_profile_read(int64_t *launches, double *total_ms, double *total_bytes);
  * GPU's FP64 matrix cores; its eigen-decomposition runs on the host
  * (Householder tridiagonalisation and implicit QR, mbx_sym_eig).  Singular values below about 1e-8 sigma_1 carry the rounding of
  * K (the method squares the condition number).  Allocates a device
- * workspace of about 8 (2048 x 1024 + m^2 + 32 m ceil(k/32)) bytes for the
- * call and synchronises the stream.  Errors: MBX_EINVAL, MBX_ENOMEM,
+ * workspace of at most about 8 (2560 x 1024 + m^2 + 32 m ceil(k/32)) bytes
+ * (the partial Gram tiles of the row slices, K, the eigenvector
+ * coefficients) for the call and synchronises the stream.  Errors: MBX_EINVAL, MBX_ENOMEM,
  * MBX_ENAN (non-finite Gram matrix), MBX_EHIP. */
 int mbx_pod(const double *S, int64_t n, int m, int64_t lds, const double *w, double rtol, int k_max,
             double *modes, int64_t ldm, double *sigma, int *k_out, void *stream);
