@@ -49,8 +49,9 @@ def test_pod_noalloc_matches_pod_on_two_calls():
     from paper_1704_04139_amd import mbx
     assert torch.cuda.is_available()
     mbx.load()
-    cases = [  # (n, m, weighted, rtol, k_max, lds pad, ldm pad): the second call is smaller
+    cases = [  # (n, m, weighted, rtol, k_max, lds pad, ldm pad): each call smaller than the one before
         (40_003, 200, True, 1e-6, 64, 5, 3),
+        (20_011, 128, True, 1e-6, 128, 0, 2),   # the largest workspace: 256 row slices x 10 tile pairs
         (5_003, 70, False, 1e-5, 70, 0, 1),
     ]
     for n, m, weighted, rtol, k_max, lp, mp in cases:
