@@ -238,7 +238,9 @@ __global__ void __launch_bounds__(64 * kRGroups)
 }
 
 // Modes U[:, q] = S C[:, q]: one thread per snapshot row and kMQ columns of
-// C, whose entries all lanes share (C row-major, kpad columns).
+// C, whose entries all lanes share (C row-major, kpad columns).  The row's
+// snapshot values are loaded 8 columns at a time before their products, so
+// 8 loads are in flight per thread; each sum still runs over j in order.
 __global__ void __launch_bounds__(256)
     k_modes(const double* __restrict__ S, int64_t n, int m, int64_t lds, const double* __restrict__ C, int kpad,
             int k, double* __restrict__ U, int64_t ldu) {
@@ -247,7 +249,19 @@ __global__ void __launch_bounds__(256)
   if (i >= n) return;
   double acc[kMQ];
   for (int q = 0; q < kMQ; ++q) acc[q] = 0.0;
-  for (int j = 0; j < m; ++j) {
+  int j = 0;
+  for (; j + 8 <= m; j += 8) {
+    double s8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s8[u] = S[i + (int64_t)(j + u) * lds];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double* c = C + (int64_t)(j + u) * kpad + q0;
+#pragma unroll
+      for (int q = 0; q < kMQ; ++q) acc[q] = fma(s8[u], c[q], acc[q]);
+    }
+  }
+  for (; j < m; ++j) {
     const double s = S[i + (int64_t)j * lds];
     const double* c = C + (int64_t)j * kpad + q0;
     for (int q = 0; q < kMQ; ++q) acc[q] = fma(s, c[q], acc[q]);
